@@ -1,0 +1,192 @@
+/*
+ * dt.h - C ABI of libdt, an MI355X (gfx950) library for the fast convolution
+ * approximation of the signed Euclidean distance function of
+ * Gurumoorthy and Rangarajan, "Fast convolution based method for computing
+ * the signed distance function and its derivatives" (arXiv:1112.3010).
+ *
+ * What the library computes (paper references in brackets):
+ *   phi(X) = sum_k exp(-||X - Y_k|| / tau)       [Sec. 2.3, eq. wavefunc]
+ *   S(X)   = -tau log phi(X)                      [Sec. 2.3, eq. STilde]
+ * on every node X of a regular 2D or 3D grid, as a zero-padded discrete
+ * convolution of the source indicator g with the kernel f = exp(-r/tau),
+ * evaluated with FFTs                             [Sec. 3, Table 1];
+ * the gradient and Hessian of S as ratios of further kernel convolutions
+ *                                                 [Sec. 5, eqs. SxSyconv, Sxx, Syy, Sxy];
+ * the sign from the discrete winding number (2D) [Sec. 4.1, eq. kappadiscretefinal]
+ * or topological degree (3D)                      [Sec. 4.2, eq. mudef];
+ * and the adjoint (gradients of a grid loss with respect to the sources
+ * and tau), which the paper does not give; it is derived from eq. STilde.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.   ndim = 2 or 3.  dims[] = (nx, ny[, nz]) nodes, spacing[] = h per
+ *         axis, origin[] = o per axis.  Node i sits at o + (i + 1/2) h
+ *         (cell centred).  Fields are C-ordered [z][y][x] (x fastest).
+ * Sources. Y is a device pointer to K x ndim float32, row-major (x, y[, z])
+ *         per point.  The paper places sources on grid nodes (Sec. 3); a
+ *         source is assigned to node idx_d = floor((y_d - o_d) / h_d),
+ *         evaluated in float64.  Coincident sources count with multiplicity.
+ *         A source outside the grid, or non-finite, is skipped and raises
+ *         a sticky device error (DT_E_RANGE) reported by dt_last_error().
+ * Padding. Every axis is zero-padded to M_d >= 2 n_d (a power of two), so
+ *         the FFT evaluates the linear (not circular) convolution.
+ * Precision. DT_FP32_SCALED works in float32 with power-of-two scaling of
+ *         the source image and kernel spectra (exact, so only the range is
+ *         affected); DT_FP64 works in float64.  Output fields have the
+ *         plan's working type (float or double).
+ * Validity. An FFT convolution in finite precision has an absolute error
+ *         floor; nodes where phi falls below the threshold
+ *           Theta = c_theta * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
+ *         (u = 2^-24 or 2^-53, N_pad = prod M_d, ||f||_1 = sum of the padded
+ *         kernel, ||g||_2 = sqrt(sum of squared multiplicities)) report
+ *         S = S_max = -tau log Theta and zero derivatives.  The paper notes
+ *         the effect (Sec. 3.2) but gives no rule; this threshold is the
+ *         library's contract.
+ * Streams. Every compute call is enqueued on the given HIP stream (NULL =
+ *         the default stream) and returns without synchronising.  Argument
+ *         errors are detected on the host, return at once and enqueue
+ *         nothing.  A plan is not thread-safe; distinct plans are.
+ * Memory. The library never allocates device memory: the caller provides
+ *         one workspace per plan (dt_plan_workspace_size) and owns all
+ *         inputs and outputs.  Kernel spectra live in the workspace.
+ */
+#ifndef DT_H
+#define DT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dt_plan_s* dt_plan;
+
+typedef enum {
+  DT_OK = 0,
+  DT_E_ARG = 1,          /* invalid argument (host check; nothing enqueued) */
+  DT_E_RANGE = 2,        /* a source fell outside the grid or was non-finite (sticky) */
+  DT_E_PRECISION = 3,    /* DT_AUTO: the requested distance is not representable */
+  DT_E_WORKSPACE = 4,    /* workspace missing, too small or misaligned */
+  DT_E_HIP = 5,          /* a HIP runtime call failed */
+  DT_E_UNSUPPORTED = 6   /* valid request this build does not implement */
+} dt_status;
+
+typedef enum { DT_FP32_SCALED = 0, DT_FP64 = 1, DT_AUTO = 2 } dt_precision;
+
+/* Kernel families a plan prepares (bit mask for dt_create_plan). */
+enum {
+  DT_OUT_S = 1,          /* distance S (kernel f)                         */
+  DT_OUT_GRAD = 2,       /* gradient of S (kernels (X_i/r) f)             */
+  DT_OUT_HESS = 4,       /* Hessian of S (kernels H_ij)                    */
+  DT_OUT_SIGN = 8,       /* winding number / topological degree kernels   */
+  DT_OUT_BACKWARD = 16   /* adjoint: gradient kernels and r f for d/dtau  */
+};
+
+/* Closed boundary for the sign (and, optionally, the sources). */
+typedef struct {
+  int kind;              /* DT_SHAPE_POLYGON (2D) or DT_SHAPE_MESH (3D) */
+  /* polygon: ordered closed polyline, point k+1 follows k, K+1 wraps to 1.
+   * Counter-clockwise order gives mu ~ +1 inside. Device, K x 2 float32. */
+  const float* points;
+  int64_t n_points;
+  /* mesh: closed, consistently outward-wound triangle mesh.
+   * vertices: device nv x 3 float32; faces: device nf x 3 int32. */
+  const float* vertices;
+  int64_t n_vertices;
+  const int32_t* faces;
+  int64_t n_faces;
+} dt_shape;
+enum { DT_SHAPE_POLYGON = 1, DT_SHAPE_MESH = 2 };
+
+/* Output buffers for dt_forward (device pointers; NULL = not wanted).
+ * S: N values; grad: ndim x N (channel first); hess: ndim(ndim+1)/2 x N in
+ * the order xx, xy, [xz,] yy, [yz,] zz; label: N int8 (+1 inside, -1
+ * outside); mu: N values.  N = prod dims.  Value type = plan type. */
+typedef struct {
+  void* S;
+  void* grad;
+  void* hess;
+  int8_t* label;
+  void* mu;
+  int signed_outputs;    /* nonzero: S and grad are multiplied by the label */
+} dt_outputs;
+
+typedef struct {
+  int ndim;
+  int64_t dims[3];
+  int64_t padded[3];     /* M_d */
+  double spacing[3];
+  double origin[3];
+  double tau;
+  int precision;         /* DT_FP32_SCALED or DT_FP64 after DT_AUTO resolves */
+  unsigned out_mask;
+  double c_theta;
+  double kernel_l1;      /* ||f||_1 over the padded grid (after set_workspace) */
+  double unit_roundoff;
+  size_t workspace_bytes;
+  int n_tables;
+} dt_plan_info_t;
+
+typedef struct {
+  double g_l2;           /* sqrt(sum of squared multiplicities) of the last call */
+  double theta;          /* validity threshold of the last call */
+  double s_max;          /* -tau log theta */
+  double dL_dtau;        /* last backward's d/dtau (also written to the user pointer) */
+  uint32_t error_bits;   /* sticky device error bits (1 = range, 2 = non-finite) */
+} dt_call_stats;
+
+/* Create a plan.  dims/spacing/origin have ndim entries (x first); tau > 0.
+ * out_mask selects the kernel families to prepare.  trunc_dist and k_hint
+ * only matter for DT_AUTO: the plan uses float32 if a node at distance
+ * trunc_dist from an isolated source stays valid for k_hint distinct
+ * sources, else float64 if that holds in float64, else DT_E_PRECISION.
+ * c_theta <= 0 selects the default safety factor 1024. Host only. */
+dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                         const double* origin, double tau, int precision, unsigned out_mask,
+                         double trunc_dist, int64_t k_hint, double c_theta);
+
+/* Bytes of device workspace the plan needs (256-byte aligned pointer). */
+dt_status dt_plan_workspace_size(dt_plan plan, size_t* bytes);
+
+/* Attach the workspace and build the kernel spectra on `stream` (this call
+ * synchronises the stream once: plan set-up is not a hot path). */
+dt_status dt_plan_set_workspace(dt_plan plan, void* dev_ptr, size_t bytes, void* stream);
+
+dt_status dt_plan_info(dt_plan plan, dt_plan_info_t* info);
+dt_status dt_destroy_plan(dt_plan plan);
+
+/* Distance S only (needs DT_OUT_S). */
+dt_status dt_distance(dt_plan plan, const float* Y, int64_t K, void* S, void* stream);
+/* S (optional, may be NULL) and grad S (needs DT_OUT_GRAD). */
+dt_status dt_gradient(dt_plan plan, const float* Y, int64_t K, void* S_or_null, void* grad, void* stream);
+/* Hessian of S (needs DT_OUT_HESS). */
+dt_status dt_hessian(dt_plan plan, const float* Y, int64_t K, void* hess, void* stream);
+/* Sign labels (and mu if non-NULL) of the closed shape (needs DT_OUT_SIGN). */
+dt_status dt_sign(dt_plan plan, const dt_shape* shape, int8_t* label, void* mu_or_null, void* stream);
+/* Any subset of outputs in one pipeline.  Sources: Y (K points) if Y is
+ * non-NULL, else the shape's points (polygon) or triangle incenters (mesh).
+ * The sign needs a shape. */
+dt_status dt_forward(dt_plan plan, const float* Y, int64_t K, const dt_shape* shape_or_null,
+                     const dt_outputs* out, void* stream);
+/* Adjoint of dt_distance (needs DT_OUT_BACKWARD).  S: the forward's output
+ * for the same Y; dL_dS: upstream gradient (plan type, N values).  Writes
+ * dL/dY (device K x ndim float32) and, if non-NULL, dL/dtau (device
+ * double).  Nodes with S >= S_max are treated as truncated (zero weight).
+ * The tau derivative holds the kernel spectra and Theta fixed. */
+dt_status dt_backward(dt_plan plan, const float* Y, int64_t K, const void* S, const void* dL_dS,
+                      float* dL_dY, double* dL_dtau_or_null, void* stream);
+
+/* Synchronise the plan's last stream; return DT_E_RANGE if a source of any
+ * call since the previous dt_last_error was skipped, and clear the flag. */
+dt_status dt_last_error(dt_plan plan);
+/* Synchronise and report the per-call scalars of the last call. */
+dt_status dt_last_stats(dt_plan plan, dt_call_stats* stats);
+
+const char* dt_status_str(dt_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DT_H */

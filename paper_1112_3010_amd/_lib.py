@@ -1,0 +1,130 @@
+"""ctypes view of libdt.so (the C ABI declared in include/dt.h).
+
+Only argument marshalling lives here.  The library is loaded from this
+package's directory; if it is missing the import fails loudly (there is no
+CPU fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdt.so")
+
+DT_OK, DT_E_ARG, DT_E_RANGE, DT_E_PRECISION, DT_E_WORKSPACE, DT_E_HIP, DT_E_UNSUPPORTED = range(7)
+DT_FP32_SCALED, DT_FP64, DT_AUTO = 0, 1, 2
+DT_OUT_S, DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_SIGN, DT_OUT_BACKWARD = 1, 2, 4, 8, 16
+DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
+
+EXPORTED = (
+    "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_info", "dt_destroy_plan",
+    "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
+    "dt_last_error", "dt_last_stats", "dt_status_str",
+)
+
+
+class DtShape(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("points", ctypes.c_void_p),
+        ("n_points", ctypes.c_int64),
+        ("vertices", ctypes.c_void_p),
+        ("n_vertices", ctypes.c_int64),
+        ("faces", ctypes.c_void_p),
+        ("n_faces", ctypes.c_int64),
+    ]
+
+
+class DtOutputs(ctypes.Structure):
+    _fields_ = [
+        ("S", ctypes.c_void_p),
+        ("grad", ctypes.c_void_p),
+        ("hess", ctypes.c_void_p),
+        ("label", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p),
+        ("signed_outputs", ctypes.c_int),
+    ]
+
+
+class DtPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("dims", ctypes.c_int64 * 3),
+        ("padded", ctypes.c_int64 * 3),
+        ("spacing", ctypes.c_double * 3),
+        ("origin", ctypes.c_double * 3),
+        ("tau", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("out_mask", ctypes.c_uint),
+        ("c_theta", ctypes.c_double),
+        ("kernel_l1", ctypes.c_double),
+        ("unit_roundoff", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("n_tables", ctypes.c_int),
+    ]
+
+
+class DtCallStats(ctypes.Structure):
+    _fields_ = [
+        ("g_l2", ctypes.c_double),
+        ("theta", ctypes.c_double),
+        ("s_max", ctypes.c_double),
+        ("dL_dtau", ctypes.c_double),
+        ("error_bits", ctypes.c_uint32),
+    ]
+
+
+class DtError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+_lib = None
+
+
+def load():
+    """Load libdt.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1112_3010_amd.build` "
+                          "(the distance-field path has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.dt_create_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                   ctypes.POINTER(dbl), dbl, ctypes.c_int, ctypes.c_uint, dbl, i64, dbl]
+    lib.dt_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dt_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.dt_plan_info.argtypes = [vp, ctypes.POINTER(DtPlanInfo)]
+    lib.dt_destroy_plan.argtypes = [vp]
+    lib.dt_distance.argtypes = [vp, vp, i64, vp, vp]
+    lib.dt_gradient.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.dt_hessian.argtypes = [vp, vp, i64, vp, vp]
+    lib.dt_sign.argtypes = [vp, ctypes.POINTER(DtShape), vp, vp, vp]
+    lib.dt_forward.argtypes = [vp, vp, i64, ctypes.POINTER(DtShape), ctypes.POINTER(DtOutputs), vp]
+    lib.dt_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.dt_last_error.argtypes = [vp]
+    lib.dt_last_stats.argtypes = [vp, ctypes.POINTER(DtCallStats)]
+    lib.dt_status_str.argtypes = [st]
+    lib.dt_status_str.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "dt_status_str":
+            getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+def status_str(status):
+    try:
+        return load().dt_status_str(int(status)).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def check(status, where):
+    if status != DT_OK:
+        raise DtError(status, where)

@@ -1,0 +1,413 @@
+// FFT passes of the zero-padded convolution (Sec. 3, Table 1 steps 3-6):
+//
+//   row_r2c      x pass, real -> half spectrum (input rows zero-padded from
+//                n_x to M_x; a length-M_x real transform done as a length
+//                M_x/2 complex transform of packed even/odd samples).
+//   col_c2c      strided pass along y (3D forward or inverse), with the
+//                zero input rows (forward) or unused output rows (inverse)
+//                pruned.
+//   col_fused    last axis: forward transform of the source images, pointwise
+//                product with the kernel spectra (Table 1 step 4) for every
+//                output channel, inverse transform, keep only the n rows of
+//                the unpadded grid.  The source spectrum never leaves
+//                registers.
+//   row_c2r_epi  x pass, half spectrum -> real, fused with the epilogue:
+//                S = -tau log phi (step 6), the derivative ratios of Sec. 5
+//                and the winding number / degree label of Sec. 4.
+#include <math.h>
+
+#include "dt_launch.hpp"
+#include "fft_engine.hpp"
+
+namespace dt {
+
+// ---------------------------------------------------------------------------
+// Row pass: real -> half spectrum
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>* __restrict__ out, RowParams p) {
+  using V = Cx<T>;
+  constexpr int E = 8;
+  constexpr int Q = N / E;
+  constexpr int LPB = Q >= 256 ? 1 : 256 / Q;
+  constexpr int LP = N + 1;
+  constexpr int R0 = fft_radix(N, 0);
+  using F = Stockham<T, N, E, +1>;
+  __shared__ V lds[LPB * LP];
+  const int tid = threadIdx.x;
+  const int q = tid % Q, b = tid / Q;
+  const int64_t line = (int64_t)blockIdx.x * LPB + b;
+  const bool active = line < p.n_lines;
+  const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
+  const T* src = in + (active ? line : 0) * (int64_t)p.nx;
+  V v[E];
+#pragma unroll
+  for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int i = F::template in_index<0>(q, s, r);
+      const int m = 2 * i;
+      const T a = (active && m < p.nx) ? src[m] : T(0);
+      const T c = (active && m + 1 < p.nx) ? src[m + 1] : T(0);
+      v[s * R0 + r] = mk<V>(a, c);
+    }
+  auto addr = [b](int i) { return b * LP + i; };
+  F::run(v, lds, q, tw, 2, addr);
+  __syncthreads();
+  F::store_last(lds, v, q, addr);
+  __syncthreads();
+  if (!active) return;
+  V* dst = out + line * (int64_t)p.pitch;
+  for (int k = q; k <= N; k += Q) {
+    const V zk = lds[b * LP + (k & (N - 1))];
+    const V zc = cconj(lds[b * LP + ((N - k) & (N - 1))]);
+    const V ev = cscale(cadd(zk, zc), T(0.5));
+    const V od = cscale(mul_mi(csub(zk, zc)), T(0.5));
+    dst[k] = cadd(ev, cmul(tw[k], od));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass (C2C along a strided axis), tiles of NB consecutive kx bins
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NB, int NT, int DIR>
+__global__ void __launch_bounds__(NT) k_col_c2c(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out,
+                                                ColParams p) {
+  using V = Cx<T>;
+  constexpr int E = N * NB / NT;
+  constexpr int R0 = fft_radix(N, 0);
+  constexpr int S = fft_stages(N);
+  constexpr int RL = fft_radix(N, S - 1);
+  using F = Stockham<T, N, E, DIR>;
+  static_assert(F::Q * NB == NT, "block shape");
+  __shared__ V lds[N * NB];
+  const int tid = threadIdx.x;
+  const int b = tid % NB, q = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const V* src = in + blockIdx.z * p.in_ch + blockIdx.y * p.in_outer + (active ? kx : 0);
+  V v[E];
+#pragma unroll
+  for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int i = F::template in_index<0>(q, s, r);
+      v[s * R0 + r] = (active && i < p.n_in) ? src[(int64_t)i * p.in_line] : mk<V>(T(0), T(0));
+    }
+  auto addr = [b](int i) { return i * NB + b; };
+  F::run(v, lds, q, (const V*)p.tw, p.tw_stride, addr);
+  if (!active) return;
+  V* dst = out + blockIdx.z * p.out_ch + blockIdx.y * p.out_outer + kx;
+#pragma unroll
+  for (int s = 0; s < E / RL; ++s)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int i = F::template in_index<S - 1>(q, s, r);
+      if (i < p.n_out) dst[(int64_t)i * p.out_line] = v[s * RL + r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused last-axis pass: forward, multiply by kernel spectra, inverse
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NB, int NT>
+__global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out,
+                                                  ColParams p, FusedSpec fs) {
+  using V = Cx<T>;
+  constexpr int E = N * NB / NT;
+  constexpr int S = fft_stages(N);
+  constexpr int R0 = fft_radix(N, 0);
+  constexpr int RL = fft_radix(N, S - 1);
+  static_assert(R0 == RL, "forward output slots must be the inverse input slots");
+  using Fw = Stockham<T, N, E, +1>;
+  using Bw = Stockham<T, N, E, -1>;
+  __shared__ V lds[N * NB];
+  const int tid = threadIdx.x;
+  const int b = tid % NB, q = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const int kxs = active ? kx : 0;
+  const int o = blockIdx.y;
+  const bool o_neg = 2 * o > p.outer_len;
+  const int of = o_neg ? p.outer_len - o : o;
+  const FusedGroup& G = fs.g[blockIdx.z];
+  const V* tw = (const V*)p.tw;
+  auto addr = [b](int i) { return i * NB + b; };
+
+  auto load_fwd = [&](int ch, V* v) {
+    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
+#pragma unroll
+    for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int i = Fw::template in_index<0>(q, s, r);
+        v[s * R0 + r] = (active && i < p.n_in) ? src[(int64_t)i * p.in_line] : mk<V>(T(0), T(0));
+      }
+    Fw::run(v, lds, q, tw, p.tw_stride, addr);
+  };
+  // v *= kernel spectrum of table t at this block's (kx, outer, line) slots
+  auto times_table = [&](const TabRef& t, const V* v, V* res, bool accumulate) {
+    const T* tab = (const T*)t.ptr + (int64_t)of * fs.tab_outer_stride + kxs;
+    const bool flip_o = t.odd_outer && o_neg;
+#pragma unroll
+    for (int s = 0; s < E / RL; ++s)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int l = Fw::template in_index<S - 1>(q, s, r);
+        const bool l_neg = 2 * l > N;
+        const int lf = l_neg ? N - l : l;
+        T tv = active ? tab[(int64_t)lf * fs.tab_line_stride] : T(0);
+        if (flip_o != (t.odd_line && l_neg)) tv = -tv;
+        const V prod = mul_mi_pow(cscale(v[s * RL + r], tv), t.phase);
+        res[s * RL + r] = accumulate ? cadd(res[s * RL + r], prod) : prod;
+      }
+  };
+  auto inv_store = [&](V* v, int ch) {
+    Bw::run(v, lds, q, tw, p.tw_stride, addr);
+    if (!active) return;
+    V* dst = out + (int64_t)ch * p.out_ch + (int64_t)o * p.out_outer + kx;
+#pragma unroll
+    for (int s = 0; s < E / RL; ++s)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int i = Bw::template in_index<S - 1>(q, s, r);
+        if (i < p.n_out) dst[(int64_t)i * p.out_line] = v[s * RL + r];
+      }
+  };
+
+  if (G.mode == 0) {
+    V spec[E];
+    load_fwd(G.in_ch[0], spec);
+    for (int c = 0; c < G.n_out; ++c) {
+      V v[E];
+      times_table(fs.tabs[G.tab[c]], spec, v, false);
+      inv_store(v, G.out_ch[c]);
+    }
+  } else {
+    V acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = mk<V>(T(0), T(0));
+    for (int i = 0; i < G.n_in; ++i) {
+      V v[E];
+      load_fwd(G.in_ch[i], v);
+      times_table(fs.tabs[G.tab[i]], v, acc, true);
+    }
+    inv_store(acc, G.out_ch[0]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass: half spectrum -> real, fused with the epilogue
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void hess_pair(int ndim, int h, int& i, int& j) {
+  if (ndim == 2) {
+    const int a[3] = {0, 0, 1}, c[3] = {0, 1, 1};
+    i = a[h]; j = c[h];
+  } else {
+    const int a[6] = {0, 0, 0, 1, 1, 2}, c[6] = {0, 1, 2, 1, 2, 2};
+    i = a[h]; j = c[h];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void epilogue_cell(const EpiParams& e, const T* vals, int64_t node) {
+  const T theta = (T)e.theta[0];
+  const T smax = (T)e.theta[1];
+  const T tau = (T)e.tau;
+  T label = T(1);
+  if (e.ch_mu >= 0) {
+    const T mu = vals[e.ch_mu] * (T)e.scale_mu;
+    label = mu >= T(0.5) ? T(1) : T(-1);
+    if (e.label) e.label[node] = (int8_t)(mu >= T(0.5) ? 1 : -1);
+    if (e.mu) ((T*)e.mu)[node] = mu;
+  }
+  if (e.ch_phi < 0) return;
+  const T cphi = vals[e.ch_phi];
+  const T phi = cphi * (T)e.scale_phi;
+  const bool valid = phi >= theta;
+  const T sgn = (e.signed_out && e.ch_mu >= 0) ? label : T(1);
+  if (e.S) ((T*)e.S)[node] = sgn * (valid ? -tau * log(phi) : smax);
+  if (e.ch_u[0] < 0) return;
+  T g[3] = {T(0), T(0), T(0)};
+  const T inv = valid ? T(1) / cphi : T(0);
+  for (int a = 0; a < e.ndim; ++a) g[a] = valid ? vals[e.ch_u[a]] * inv * (T)e.scale_u[a] : T(0);
+  if (e.grad)
+    for (int a = 0; a < e.ndim; ++a) ((T*)e.grad)[a * e.plane + node] = sgn * g[a];
+  if (e.hess && e.ch_h[0] >= 0) {
+    const int nh = e.ndim == 2 ? 3 : 6;
+    for (int h = 0; h < nh; ++h) {
+      int i, j;
+      hess_pair(e.ndim, h, i, j);
+      const T hv = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
+      ((T*)e.hess)[h * e.plane + node] = hv;
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
+  using V = Cx<T>;
+  constexpr int E = 8;
+  constexpr int Q = N / E;
+  constexpr int LP = N + 1;
+  constexpr int R0 = fft_radix(N, 0);
+  constexpr int S = fft_stages(N);
+  constexpr int RL = fft_radix(N, S - 1);
+  using B = Stockham<T, N, E, -1>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int C = e.C;
+  const int lines = blockDim.x / Q;
+  const int RPB = lines / C;
+  const int tid = threadIdx.x;
+  const int q = tid % Q, b = tid / Q;
+  const int rl = b / C, c = b % C;
+  const int64_t row = (int64_t)blockIdx.x * RPB + rl;
+  const bool active = row < e.n_rows;
+  const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
+  const V* src = in + (int64_t)c * e.ch_stride + (active ? row : 0) * (int64_t)p.pitch;
+  V v[E];
+#pragma unroll
+  for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int k = B::template in_index<0>(q, s, r);
+      V z = mk<V>(T(0), T(0));
+      if (active) {
+        const V xk = src[k];
+        const V xc = cconj(src[N - k]);
+        const V ev = cadd(xk, xc);
+        const V od = cmul(csub(xk, xc), cconj(tw[k]));
+        z = mk<V>(ev.x - od.y, ev.y + od.x);  // ev + i * od
+      }
+      v[s * R0 + r] = z;
+    }
+  auto addr = [b](int i) { return b * LP + i; };
+  B::run(v, lds, q, tw, 2, addr);
+  __syncthreads();
+  T* ldr = reinterpret_cast<T*>(lds);
+#pragma unroll
+  for (int s = 0; s < E / RL; ++s)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int j = B::template in_index<S - 1>(q, s, r);
+      ldr[(int64_t)b * 2 * LP + 2 * j] = v[s * RL + r].x;
+      ldr[(int64_t)b * 2 * LP + 2 * j + 1] = v[s * RL + r].y;
+    }
+  __syncthreads();
+  const int nx = p.nx;
+  for (int t = tid; t < RPB * nx; t += blockDim.x) {
+    const int r2 = t / nx, x = t % nx;
+    const int64_t row2 = (int64_t)blockIdx.x * RPB + r2;
+    if (row2 >= e.n_rows) continue;
+    T vals[kMaxChan];
+    for (int cc = 0; cc < C; ++cc) vals[cc] = ldr[(int64_t)(r2 * C + cc) * 2 * LP + x];
+    epilogue_cell<T>(e, vals, row2 * nx + x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T> struct ColShape;
+template <> struct ColShape<float> {
+  static constexpr int nb(int N) { return N <= 512 ? 16 : (N == 1024 ? 8 : 4); }
+  static constexpr int nt(int N) { return N * nb(N) / 8 < 256 ? N * nb(N) / 8 : 256; }
+};
+template <> struct ColShape<double> {
+  static constexpr int nb(int N) { return N <= 512 ? 8 : (N == 1024 ? 4 : 2); }
+  static constexpr int nt(int N) { return N * nb(N) / 8 < 256 ? N * nb(N) / 8 : 256; }
+};
+
+int col_tile_width(int N, bool fp64) { return fp64 ? ColShape<double>::nb(N) : ColShape<float>::nb(N); }
+
+// Row passes transform M_x/2 complex points, column passes M points; M >= 64.
+#define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define DT_FOR_EACH_COL_N(X) X(64) X(128) X(256) X(512) X(1024) X(2048)
+
+template <typename T> bool launch_row_r2c(const T* in, void* out, const RowParams& p, int N, hipStream_t st) {
+  const int Q = N / 8;
+  const int lpb = Q >= 256 ? 1 : 256 / Q;
+  const int64_t blocks = (p.n_lines + lpb - 1) / lpb;
+  if (blocks <= 0) return true;
+  switch (N) {
+#define CASE(NN)                                                                                  \
+  case NN:                                                                                        \
+    hipLaunchKernelGGL((k_row_r2c<T, NN>), dim3((unsigned)blocks), dim3(lpb * Q), 0, st, in, (Cx<T>*)out, p); \
+    return true;
+    DT_FOR_EACH_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template <typename T> bool launch_col_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
+                                          int outer, int chans, hipStream_t st) {
+  const dim3 grid(tiles, outer, chans);
+  switch (N) {
+#define CASE(NN)                                                                                         \
+  case NN: {                                                                                             \
+    constexpr int NB = ColShape<T>::nb(NN), NT = ColShape<T>::nt(NN);                                    \
+    if (dir > 0)                                                                                         \
+      hipLaunchKernelGGL((k_col_c2c<T, NN, NB, NT, 1>), grid, dim3(NT), 0, st, (const Cx<T>*)in, (Cx<T>*)out, p); \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_col_c2c<T, NN, NB, NT, -1>), grid, dim3(NT), 0, st, (const Cx<T>*)in, (Cx<T>*)out, p); \
+    return true;                                                                                         \
+  }
+    DT_FOR_EACH_COL_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template <typename T> bool launch_col_fused(const void* in, void* out, const ColParams& p, const FusedSpec& fs,
+                                            int N, int tiles, int outer, hipStream_t st) {
+  const dim3 grid(tiles, outer, fs.n_groups);
+  switch (N) {
+#define CASE(NN)                                                                                         \
+  case NN: {                                                                                             \
+    constexpr int NB = ColShape<T>::nb(NN), NT = ColShape<T>::nt(NN);                                    \
+    hipLaunchKernelGGL((k_col_fused<T, NN, NB, NT>), grid, dim3(NT), 0, st, (const Cx<T>*)in, (Cx<T>*)out, p, fs); \
+    return true;                                                                                         \
+  }
+    DT_FOR_EACH_COL_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p, const EpiParams& e, int N,
+                                              hipStream_t st) {
+  const int Q = N / 8;
+  int rpb = 256 / (e.C * Q);
+  if (rpb < 1) rpb = 1;
+  const int threads = rpb * e.C * Q;
+  if (threads > 1024) return false;
+  const int64_t blocks = (e.n_rows + rpb - 1) / rpb;
+  const size_t shmem = (size_t)rpb * e.C * (N + 1) * sizeof(Cx<T>);
+  if (shmem > 65536) return false;
+  if (blocks <= 0) return true;
+  switch (N) {
+#define CASE(NN)                                                                                         \
+  case NN:                                                                                               \
+    hipLaunchKernelGGL((k_row_c2r_epi<T, NN>), dim3((unsigned)blocks), dim3(threads), shmem, st,         \
+                       (const Cx<T>*)in, p, e);                                                          \
+    return true;
+    DT_FOR_EACH_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template bool launch_row_r2c<float>(const float*, void*, const RowParams&, int, hipStream_t);
+template bool launch_row_r2c<double>(const double*, void*, const RowParams&, int, hipStream_t);
+template bool launch_col_c2c<float>(const void*, void*, const ColParams&, int, int, int, int, int, hipStream_t);
+template bool launch_col_c2c<double>(const void*, void*, const ColParams&, int, int, int, int, int, hipStream_t);
+template bool launch_col_fused<float>(const void*, void*, const ColParams&, const FusedSpec&, int, int, int,
+                                      hipStream_t);
+template bool launch_col_fused<double>(const void*, void*, const ColParams&, const FusedSpec&, int, int, int,
+                                       hipStream_t);
+template bool launch_row_c2r_epi<float>(const void*, const RowParams&, const EpiParams&, int, hipStream_t);
+template bool launch_row_c2r_epi<double>(const void*, const RowParams&, const EpiParams&, int, hipStream_t);
+
+}  // namespace dt

@@ -1,0 +1,369 @@
+// Source images, validity scalars and plan-time kernel spectra.
+//
+//  * splat: sources are snapped to grid nodes (the method works with sources
+//    on the grid, Sec. 3, eqs. function_g and krondelta; sampled inputs are
+//    rounded to nodes, Sec. 6) and accumulated with multiplicity into the
+//    count image g.  For the sign, the weight images g_1, g_2 (2D, tangents
+//    Z_k, Sec. 4.1 eq. tangentVec) or g_1..g_3 (3D, area vectors P_k at the
+//    triangle incenters, Sec. 4.2) are accumulated the same way.
+//  * validity: ||g||_2 and the threshold Theta of the library's contract.
+//  * kernel spectra (plan time): every kernel has a definite parity on every
+//    axis, so its DFT is (-i)^(#odd axes) times a real table that is a
+//    cosine/sine transform over the folded displacement range; it is
+//    evaluated in float64 by three separable direct sums.
+#include "dt_launch.hpp"
+
+#include <math.h>
+
+namespace dt {
+
+// ---------------------------------------------------------------------------
+// Fill
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_zero(T* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = T(0);
+}
+
+template <typename T> void launch_fill_zero(T* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+template void launch_fill_zero<float>(float*, int64_t, hipStream_t);
+template void launch_fill_zero<double>(double*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Snapping (float64, IEEE division and floor)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool snap_node(const GridGeom& g, const double* y, int64_t& lin, int* idx,
+                                          uint32_t* err) {
+  bool finite = true, inside = true;
+  for (int d = 0; d < g.ndim; ++d) {
+    if (!isfinite(y[d])) { finite = false; break; }
+    const double q = floor((y[d] - g.o[d]) / g.h[d]);
+    if (!(q >= 0.0 && q < (double)g.n[d])) { inside = false; break; }
+    idx[d] = (int)q;
+  }
+  if (!finite || !inside) {
+    if (err) atomicOr(err, finite ? kErrRange : kErrNonFinite);
+    return false;
+  }
+  lin = idx[0] + (int64_t)g.n[0] * (idx[1] + (g.ndim == 3 ? (int64_t)g.n[1] * idx[2] : 0));
+  return true;
+}
+
+// Point sources: count image only.
+template <typename T>
+__global__ void __launch_bounds__(256) k_splat_points(const float* __restrict__ Y, int64_t K, GridGeom g,
+                                                      T* __restrict__ cnt, T cval, uint32_t* err) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double y[3];
+  for (int d = 0; d < g.ndim; ++d) y[d] = (double)Y[k * g.ndim + d];
+  int idx[3];
+  int64_t lin;
+  if (!snap_node(g, y, lin, idx, err)) return;
+  atomicAdd(&cnt[lin], cval);
+}
+
+// Closed polygon: optional count image, tangent images g1 (Z^1) and g2 (Z^2)
+// with Z_k = Yhat_{k+1} - Yhat_k on the snapped points (wrapping at K).
+template <typename T>
+__global__ void __launch_bounds__(256) k_splat_polygon(const float* __restrict__ P, int64_t K, GridGeom g,
+                                                       T* __restrict__ cnt, T cval, T* __restrict__ g1,
+                                                       T* __restrict__ g2, double w1, double w2, uint32_t* err) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int64_t kn = (k + 1 == K) ? 0 : k + 1;
+  double y[2] = {(double)P[2 * k], (double)P[2 * k + 1]};
+  double yn[2] = {(double)P[2 * kn], (double)P[2 * kn + 1]};
+  int idx[3], idn[3];
+  int64_t lin, linn;
+  if (!snap_node(g, y, lin, idx, err)) return;
+  if (cnt) atomicAdd(&cnt[lin], cval);
+  if (!g1) return;
+  if (!snap_node(g, yn, linn, idn, nullptr)) return;  // the next point reports its own error
+  const double zx = (double)(idn[0] - idx[0]) * g.h[0];
+  const double zy = (double)(idn[1] - idx[1]) * g.h[1];
+  atomicAdd(&g1[lin], (T)(zx * w1));
+  atomicAdd(&g2[lin], (T)(zy * w2));
+}
+
+// Incenter and area vector of one triangle.  The incenter order of
+// operations is fixed (the snapped node must not depend on contraction):
+// a = |v1 - v2|, b = |v2 - v0|, c = |v0 - v1|, |u| = sqrt((ux*ux + uy*uy) + uz*uz),
+// incenter = ((a*v0 + b*v1) + c*v2) / ((a + b) + c).
+__device__ __forceinline__ void triangle_sources(const double* v0, const double* v1, const double* v2,
+                                                 double* inc, double* area) {
+#pragma clang fp contract(off)
+  double e12[3], e20[3], e01[3];
+  for (int d = 0; d < 3; ++d) {
+    e12[d] = v1[d] - v2[d];
+    e20[d] = v2[d] - v0[d];
+    e01[d] = v0[d] - v1[d];
+  }
+  const double a = sqrt((e12[0] * e12[0] + e12[1] * e12[1]) + e12[2] * e12[2]);
+  const double b = sqrt((e20[0] * e20[0] + e20[1] * e20[1]) + e20[2] * e20[2]);
+  const double c = sqrt((e01[0] * e01[0] + e01[1] * e01[1]) + e01[2] * e01[2]);
+  const double den = (a + b) + c;
+  for (int d = 0; d < 3; ++d) inc[d] = ((a * v0[d] + b * v1[d]) + c * v2[d]) / den;
+  double u[3], w[3];
+  for (int d = 0; d < 3; ++d) {
+    u[d] = v1[d] - v0[d];
+    w[d] = v2[d] - v0[d];
+  }
+  area[0] = 0.5 * (u[1] * w[2] - u[2] * w[1]);
+  area[1] = 0.5 * (u[2] * w[0] - u[0] * w[2]);
+  area[2] = 0.5 * (u[0] * w[1] - u[1] * w[0]);
+}
+
+// Closed triangle mesh: optional count image at the snapped incenters and
+// area-vector images gp[0..2].
+template <typename T>
+__global__ void __launch_bounds__(256) k_splat_mesh(const float* __restrict__ V, int64_t nv,
+                                                    const int32_t* __restrict__ F, int64_t nf, GridGeom g,
+                                                    T* __restrict__ cnt, T cval, T* __restrict__ gp0,
+                                                    T* __restrict__ gp1, T* __restrict__ gp2, double w0,
+                                                    double w1, double w2, uint32_t* err) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double v[3][3];
+  for (int c = 0; c < 3; ++c) {
+    const int32_t vi = F[3 * f + c];
+    if (vi < 0 || (int64_t)vi >= nv) {
+      atomicOr(err, kErrRange);
+      return;
+    }
+    for (int d = 0; d < 3; ++d) v[c][d] = (double)V[3 * (int64_t)vi + d];
+  }
+  double inc[3], area[3];
+  triangle_sources(v[0], v[1], v[2], inc, area);
+  int idx[3];
+  int64_t lin;
+  if (!snap_node(g, inc, lin, idx, err)) return;
+  if (cnt) atomicAdd(&cnt[lin], cval);
+  if (gp0) {
+    atomicAdd(&gp0[lin], (T)(area[0] * w0));
+    atomicAdd(&gp1[lin], (T)(area[1] * w1));
+    atomicAdd(&gp2[lin], (T)(area[2] * w2));
+  }
+}
+
+template <typename T> void launch_splat_points(const float* Y, int64_t K, const GridGeom& g, T* cnt, T cval,
+                                               uint32_t* err, hipStream_t st) {
+  if (K <= 0) return;
+  hipLaunchKernelGGL(k_splat_points<T>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, Y, K, g, cnt, cval,
+                     err);
+}
+template <typename T> void launch_splat_polygon(const float* P, int64_t K, const GridGeom& g, T* cnt, T cval,
+                                                T* g1, T* g2, double w1, double w2, uint32_t* err, hipStream_t st) {
+  if (K <= 0) return;
+  hipLaunchKernelGGL(k_splat_polygon<T>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, P, K, g, cnt,
+                     cval, g1, g2, w1, w2, err);
+}
+template <typename T> void launch_splat_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
+                                             const GridGeom& g, T* cnt, T cval, T* gp0, T* gp1, T* gp2,
+                                             double w0, double w1, double w2, uint32_t* err, hipStream_t st) {
+  if (nf <= 0) return;
+  hipLaunchKernelGGL(k_splat_mesh<T>, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, V, nv, F, nf, g,
+                     cnt, cval, gp0, gp1, gp2, w0, w1, w2, err);
+}
+#define DT_INST_SPLAT(T)                                                                                   \
+  template void launch_splat_points<T>(const float*, int64_t, const GridGeom&, T*, T, uint32_t*,          \
+                                       hipStream_t);                                                      \
+  template void launch_splat_polygon<T>(const float*, int64_t, const GridGeom&, T*, T, T*, T*, double,    \
+                                        double, uint32_t*, hipStream_t);                                  \
+  template void launch_splat_mesh<T>(const float*, int64_t, const int32_t*, int64_t, const GridGeom&, T*, \
+                                     T, T*, T*, T*, double, double, double, uint32_t*, hipStream_t);
+DT_INST_SPLAT(float)
+DT_INST_SPLAT(double)
+
+// ---------------------------------------------------------------------------
+// Validity scalars: Theta = c * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
+// ---------------------------------------------------------------------------
+// Sum of squared multiplicities over a count image (values m * inv_scale^-1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_grid_msq(const T* __restrict__ cnt, int64_t n, double inv_cval,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double m = (double)cnt[i] * inv_cval;
+    acc += m * m;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+template <typename T> int launch_grid_msq(const T* cnt, int64_t n, double inv_cval, double* partials,
+                                          hipStream_t st) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_grid_msq<T>, dim3(blocks), dim3(256), 0, st, cnt, n, inv_cval, partials);
+  return blocks;
+}
+template int launch_grid_msq<float>(const float*, int64_t, double, double*, hipStream_t);
+template int launch_grid_msq<double>(const double*, int64_t, double, double*, hipStream_t);
+
+// scal[0] = Theta, scal[1] = S_max, scal[2] = ||g||_2, scal[3] = 2^floor(log2 Theta)
+__global__ void __launch_bounds__(256) k_finalize_theta(const double* __restrict__ partials, int n_partials,
+                                                        double coef, double tau, double* __restrict__ scal) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n_partials; i += blockDim.x) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double gl2 = sqrt(red[0]);
+    const double theta = coef * gl2;
+    scal[0] = theta;
+    scal[1] = -tau * log(theta);
+    scal[2] = gl2;
+    int e;
+    frexp(theta, &e);              // theta = f * 2^e with f in [0.5, 1)
+    scal[3] = ldexp(1.0, e - 1);   // largest power of two <= theta
+  }
+}
+
+void launch_finalize_theta(const double* partials, int n_partials, double coef, double tau, double* scal,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_theta, dim3(1), dim3(256), 0, st, partials, n_partials, coef, tau, scal);
+}
+
+// ---------------------------------------------------------------------------
+// Plan-time kernel spectra
+// ---------------------------------------------------------------------------
+// Kernel values at physical displacement D (kind, axes i, j); all are 0 at
+// D = 0 except f (1 there).
+__device__ double kernel_value(const TabKernel& kd, const double* D, int ndim) {
+  double r2 = 0.0;
+  for (int a = 0; a < ndim; ++a) r2 += D[a] * D[a];
+  const double r = sqrt(r2);
+  const double tau = kd.tau;
+  if (r == 0.0) return kd.kind == KER_F ? 1.0 : 0.0;
+  const double f = exp(-r / tau);
+  switch (kd.kind) {
+    case KER_F: return f;
+    case KER_U: return D[kd.i] / r * f;
+    case KER_H: {
+      const double ni = D[kd.i] / r, nj = D[kd.j] / r;
+      const double delta = kd.i == kd.j ? 1.0 : 0.0;
+      return (-ni * nj / tau + (delta - ni * nj) / r) * f;
+    }
+    case KER_W2: return kd.coef * D[kd.i] / r2;             // winding-number kernels
+    case KER_D3: return kd.coef * D[kd.i] / (r2 * r);       // topological-degree kernels
+    case KER_RF: return r * f;
+  }
+  return 0.0;
+}
+
+// Sample on the folded range d_a in [0, Mh_a) (d_a = M_a/2 set to zero) and
+// accumulate the l1 norm over the full padded grid (weights 1 at d = 0, 2 else).
+__global__ void __launch_bounds__(256) k_tab_sample(TabKernel kd, TabGeom tg, double* __restrict__ out,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[256];
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    int d[3];
+    d[0] = (int)(i % tg.H[0]);
+    d[1] = (int)((i / tg.H[0]) % tg.H[1]);
+    d[2] = (int)(i / ((int64_t)tg.H[0] * tg.H[1]));
+    bool nyq = false;
+    double w = 1.0, D[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < tg.ndim; ++a) {
+      if (2 * d[a] == tg.M[a]) nyq = true;
+      if (d[a] > 0) w *= 2.0;
+      D[a] = (double)d[a] * tg.h[a];
+    }
+    const double val = nyq ? 0.0 : kernel_value(kd, D, tg.ndim);
+    out[i] = val;
+    acc += w * fabs(val);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// One separable stage along `axis`: out(k) = sum_{d < M/2} c_d in(d) trig(2 pi k d / M),
+// trig = cos for an even axis, sin for an odd one, c_0 = 1, c_d = 2.
+__global__ void __launch_bounds__(256) k_tab_axis(TabGeom tg, int axis, int odd, const double2* __restrict__ trig,
+                                                  const double* __restrict__ in, double* __restrict__ out) {
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int c[3];
+  c[0] = (int)(i % tg.H[0]);
+  c[1] = (int)((i / tg.H[0]) % tg.H[1]);
+  c[2] = (int)(i / ((int64_t)tg.H[0] * tg.H[1]));
+  const int k = c[axis];
+  const int M = tg.M[axis];
+  int64_t astride = 1;
+  for (int a = 0; a < axis; ++a) astride *= tg.H[a];
+  const int64_t base = i - (int64_t)k * astride;
+  double acc = 0.0;
+  int m = 0;  // (k * d) mod M
+  for (int d = 0; d < M / 2; ++d) {
+    const double2 w = trig[m];            // (cos, -sin) of 2 pi m / M
+    const double t = odd ? -w.y : w.x;
+    const double cd = d == 0 ? 1.0 : 2.0;
+    acc += cd * in[base + (int64_t)d * astride] * t;
+    m += k;
+    if (m >= M) m -= M;
+  }
+  out[i] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tab_store(TabGeom tg, const double* __restrict__ in, double scale,
+                                                   T* __restrict__ out, int64_t pitch) {
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t x = i % tg.H[0];
+  const int64_t row = i / tg.H[0];
+  out[row * pitch + x] = (T)(in[i] * scale);
+}
+
+int launch_tab_sample(const TabKernel& kd, const TabGeom& tg, double* out, double* partials, hipStream_t st) {
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_tab_sample, dim3(blocks), dim3(256), 0, st, kd, tg, out, partials);
+  return blocks;
+}
+void launch_tab_axis(const TabGeom& tg, int axis, int odd, const void* trig, const double* in, double* out,
+                     hipStream_t st) {
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  hipLaunchKernelGGL(k_tab_axis, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tg, axis, odd,
+                     (const double2*)trig, in, out);
+}
+template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out,
+                                            int64_t pitch, hipStream_t st) {
+  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
+  hipLaunchKernelGGL(k_tab_store<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tg, in, scale, out,
+                     pitch);
+}
+template void launch_tab_store<float>(const TabGeom&, const double*, double, float*, int64_t, hipStream_t);
+template void launch_tab_store<double>(const TabGeom&, const double*, double, double*, int64_t, hipStream_t);
+
+}  // namespace dt

@@ -1,0 +1,824 @@
+// Host side of libdt: plan creation and validation, workspace layout,
+// plan-time kernel spectra, and the launch sequences of the C ABI calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dt.h"
+#include "dt_launch.hpp"
+
+using namespace dt;
+
+namespace dt {
+int col_tile_width(int N, bool fp64);
+}
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kPartials = 4096;     // per-block partial sums (each region)
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int64_t pad_length(int64_t n) {
+  int64_t m = 64;
+  while (m < 2 * n) m *= 2;
+  return m;
+}
+
+int ceil_log2(double v) {
+  if (!(v > 0)) return 0;
+  int e;
+  const double f = std::frexp(v, &e);  // v = f 2^e, f in [0.5, 1)
+  return f == 0.5 ? e - 1 : e;
+}
+
+struct Table {
+  TabKernel kd;
+  int par[3];   // odd (1) / even (0) per axis x, y, z
+  int phase;
+  double l1;
+  int e;        // table scaled by 2^-e / N_pad
+  size_t off;
+};
+
+}  // namespace
+
+struct dt_plan_s {
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};
+  int64_t M[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  double o[3] = {0, 0, 0};
+  double tau = 0;
+  int prec = DT_FP32_SCALED;
+  unsigned mask = 0;
+  double c_theta = 1024.0;
+  bool fp64 = false;
+  size_t w = 4;          // bytes per real
+  int Mh = 0, MhP = 0;   // half spectrum length and pitch along x
+  int NB = 16;           // column tile width
+  std::vector<Table> tabs;
+  int t_f = -1, t_u[3] = {-1, -1, -1}, t_h[6] = {-1, -1, -1, -1, -1, -1}, t_sign[3] = {-1, -1, -1}, t_rf = -1;
+  int e_sign_tab = 0;
+  int in_max = 0, out_max = 0;
+  size_t off_scal = 0, off_err = 0, off_partA = 0, off_partB = 0, off_tw[3] = {0, 0, 0}, off_tw64[3] = {0, 0, 0};
+  size_t off_tabs = 0, tab_elems = 0, off_R1 = 0, off_R2 = 0, R1 = 0, R2 = 0, ws_bytes = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  double kernel_l1 = 0;
+  bool ready = false;
+
+  int64_t nodes() const { return n[0] * n[1] * n[2]; }
+  int64_t rows() const { return n[1] * n[2]; }
+  double npad() const { return (double)M[0] * (double)M[1] * (double)M[2]; }
+  double unit() const { return fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24); }
+  double* scal() const { return (double*)(ws + off_scal); }
+  uint32_t* err() const { return (uint32_t*)(ws + off_err); }
+  double* partA() const { return (double*)(ws + off_partA); }
+  double* partB() const { return (double*)(ws + off_partB); }
+  char* R1p() const { return ws + off_R1; }
+  char* R2p() const { return ws + off_R2; }
+  const void* tab_ptr(int t) const { return ws + off_tabs + tabs[t].off; }
+  GridGeom geom() const {
+    GridGeom g;
+    g.ndim = ndim;
+    for (int a = 0; a < 3; ++a) {
+      g.n[a] = (int)n[a];
+      g.o[a] = o[a];
+      g.h[a] = h[a];
+    }
+    return g;
+  }
+};
+
+namespace {
+
+// Twiddles exp(-2 pi i m / M) in float64 with octant reduction of the angle.
+void make_twiddles(int M, std::vector<double>& out) {
+  out.resize(2 * (size_t)M);
+  for (int m = 0; m < M; ++m) {
+    // angle = 2 pi m / M; reduce to [0, pi/4] by symmetry for accuracy
+    const int64_t e8 = (int64_t)m * 8;
+    const int oct = (int)(e8 / M);
+    const int64_t rem = e8 % M;  // angle within octant = (pi/4) * rem / M
+    double c, s;
+    auto cs = [&](int64_t num, double& cc, double& ss) {  // angle = (pi/4) num / M
+      const double a = (kPi / 4.0) * (double)num / (double)M;
+      cc = std::cos(a);
+      ss = std::sin(a);
+    };
+    double ca, sa;
+    switch (oct) {
+      case 0: cs(rem, ca, sa); c = ca; s = sa; break;
+      case 1: cs(M - rem, ca, sa); c = sa; s = ca; break;
+      case 2: cs(rem, ca, sa); c = -sa; s = ca; break;
+      case 3: cs(M - rem, ca, sa); c = -ca; s = sa; break;
+      case 4: cs(rem, ca, sa); c = -ca; s = -sa; break;
+      case 5: cs(M - rem, ca, sa); c = -sa; s = -ca; break;
+      case 6: cs(rem, ca, sa); c = sa; s = -ca; break;
+      default: cs(M - rem, ca, sa); c = ca; s = -sa; break;
+    }
+    out[2 * (size_t)m] = c;
+    out[2 * (size_t)m + 1] = -s;
+  }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+int add_table(dt_plan p, int kind, int i, int j, double coef) {
+  Table t{};
+  t.kd.kind = kind;
+  t.kd.i = i;
+  t.kd.j = j;
+  t.kd.tau = p->tau;
+  t.kd.coef = coef;
+  t.par[0] = t.par[1] = t.par[2] = 0;
+  switch (kind) {
+    case KER_U: case KER_W2: case KER_D3: t.par[i] ^= 1; break;
+    case KER_H: if (i != j) { t.par[i] ^= 1; t.par[j] ^= 1; } break;
+    default: break;
+  }
+  t.phase = (t.par[0] + t.par[1] + t.par[2]) & 3;
+  p->tabs.push_back(t);
+  return (int)p->tabs.size() - 1;
+}
+
+// Host estimate of ||f||_1 over the padded grid (used by DT_AUTO only).
+double host_kernel_l1(const int64_t* M, const double* h, int ndim, double tau) {
+  double total = 0.0;
+  const int64_t hz = ndim == 3 ? M[2] / 2 : 1;
+  for (int64_t z = 0; z < hz; ++z)
+    for (int64_t y = 0; y < M[1] / 2; ++y) {
+      const double wzy = (z > 0 ? 2.0 : 1.0) * (y > 0 ? 2.0 : 1.0);
+      const double dz = ndim == 3 ? z * h[2] : 0.0, dy = y * h[1];
+      for (int64_t x = 0; x < M[0] / 2; ++x) {
+        const double dx = x * h[0];
+        total += wzy * (x > 0 ? 2.0 : 1.0) * std::exp(-std::sqrt(dx * dx + dy * dy + dz * dz) / tau);
+      }
+    }
+  return total;
+}
+
+dt_status hip_status(hipError_t e) { return e == hipSuccess ? DT_OK : DT_E_HIP; }
+
+template <typename T> size_t complex_bytes() { return 2 * sizeof(T); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan creation
+// ---------------------------------------------------------------------------
+extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                                    const double* origin, double tau, int precision, unsigned out_mask,
+                                    double trunc_dist, int64_t k_hint, double c_theta) {
+  if (!out) return DT_E_ARG;
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return DT_E_ARG;
+  if (!dims || !spacing || !origin) return DT_E_ARG;
+  if (!finite_pos(tau)) return DT_E_ARG;
+  if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO) return DT_E_ARG;
+  const unsigned known = DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_SIGN | DT_OUT_BACKWARD;
+  if (out_mask == 0 || (out_mask & ~known)) return DT_E_ARG;
+  if (!(c_theta <= 0) && !finite_pos(c_theta)) return DT_E_ARG;
+  for (int a = 0; a < ndim; ++a) {
+    if (dims[a] < 2) return DT_E_ARG;
+    if (!finite_pos(spacing[a]) || !std::isfinite(origin[a])) return DT_E_ARG;
+    if (dims[a] > 1024) return DT_E_UNSUPPORTED;
+  }
+  dt_plan p = new (std::nothrow) dt_plan_s();
+  if (!p) return DT_E_ARG;
+  p->ndim = ndim;
+  for (int a = 0; a < ndim; ++a) {
+    p->n[a] = dims[a];
+    p->h[a] = spacing[a];
+    p->o[a] = origin[a];
+    p->M[a] = pad_length(dims[a]);
+  }
+  p->tau = tau;
+  p->mask = out_mask;
+  p->c_theta = c_theta > 0 ? c_theta : 1024.0;
+
+  if (precision == DT_AUTO) {
+    if (!(trunc_dist >= 0) || !std::isfinite(trunc_dist) || k_hint < 1) {
+      delete p;
+      return DT_E_ARG;
+    }
+    const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
+    const double np = p->npad();
+    int chosen = -1;
+    for (int cand = 0; cand < 2 && chosen < 0; ++cand) {
+      const double u = cand == 0 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+      const double theta = p->c_theta * u * std::log2(np) * l1 * std::sqrt((double)k_hint) / std::sqrt(np);
+      if (trunc_dist <= -tau * std::log(theta)) chosen = cand == 0 ? DT_FP32_SCALED : DT_FP64;
+    }
+    if (chosen < 0) {
+      delete p;
+      return DT_E_PRECISION;
+    }
+    precision = chosen;
+  }
+  p->prec = precision;
+  p->fp64 = precision == DT_FP64;
+  p->w = p->fp64 ? 8 : 4;
+  p->Mh = (int)(p->M[0] / 2 + 1);
+  p->NB = col_tile_width((int)p->M[1], p->fp64);
+  for (int a = 2; a < ndim; ++a) p->NB = std::max(p->NB, col_tile_width((int)p->M[a], p->fp64));
+  p->MhP = (p->Mh + p->NB - 1) / p->NB * p->NB;
+
+  // kernel tables
+  const int D = ndim;
+  const bool dist = out_mask & (DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS);
+  const bool grad = out_mask & (DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_BACKWARD);
+  if (dist) p->t_f = add_table(p, KER_F, 0, 0, 1.0);
+  if (grad)
+    for (int a = 0; a < D; ++a) p->t_u[a] = add_table(p, KER_U, a, 0, 1.0);
+  if (out_mask & DT_OUT_HESS) {
+    int hcount = 0;
+    for (int i = 0; i < D; ++i)
+      for (int j = i; j < D; ++j) p->t_h[hcount++] = add_table(p, KER_H, i, j, 1.0);
+  }
+  if (out_mask & DT_OUT_SIGN) {
+    if (D == 2) {
+      p->t_sign[0] = add_table(p, KER_W2, 1, 0, 1.0 / (2 * kPi));   // applied to Z^1 weights
+      p->t_sign[1] = add_table(p, KER_W2, 0, 0, -1.0 / (2 * kPi));  // applied to Z^2 weights
+    } else {
+      for (int a = 0; a < 3; ++a) p->t_sign[a] = add_table(p, KER_D3, a, 0, -1.0 / (4 * kPi));
+    }
+  }
+  if (out_mask & DT_OUT_BACKWARD) p->t_rf = add_table(p, KER_RF, 0, 0, 1.0);
+
+  // channel counts
+  const int nh = D == 2 ? 3 : 6;
+  const int in_fwd = (dist ? 1 : 0) + ((out_mask & DT_OUT_SIGN) ? D : 0);
+  const int out_fwd = (dist ? 1 : 0) + ((out_mask & (DT_OUT_GRAD | DT_OUT_HESS)) ? D : 0) +
+                      ((out_mask & DT_OUT_HESS) ? nh : 0) + ((out_mask & DT_OUT_SIGN) ? 1 : 0);
+  p->in_max = std::max(in_fwd, (out_mask & DT_OUT_BACKWARD) ? 1 : 0);
+  p->out_max = std::max(out_fwd, (out_mask & DT_OUT_BACKWARD) ? D + 1 : 0);
+  p->in_max = std::max(p->in_max, 1);  // the backward's count image needs one channel
+
+  // workspace layout
+  const size_t cs = 2 * p->w;
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t My = p->M[1];
+  size_t R1, R2;
+  const size_t splat = (size_t)p->in_max * nx * ny * nz * p->w;
+  if (D == 2) {
+    const size_t A = (size_t)p->in_max * ny * p->MhP * cs;
+    const size_t C = (size_t)p->out_max * ny * p->MhP * cs;
+    R1 = std::max(splat, C);
+    R2 = A;
+  } else {
+    const size_t A = (size_t)p->in_max * nz * ny * p->MhP * cs;
+    const size_t B = (size_t)p->in_max * nz * My * p->MhP * cs;
+    const size_t C = (size_t)p->out_max * nz * My * p->MhP * cs;
+    const size_t Dd = (size_t)p->out_max * nz * ny * p->MhP * cs;
+    R1 = std::max({splat, B, Dd});
+    R2 = std::max(A, C);
+  }
+  // plan-time float64 scratch for the folded kernel samples
+  const int64_t H0 = p->M[0] / 2 + 1, H1 = p->M[1] / 2 + 1, H2 = D == 3 ? p->M[2] / 2 + 1 : 1;
+  const size_t fold = (size_t)H0 * H1 * H2 * sizeof(double);
+  R1 = std::max(R1, fold);
+  R2 = std::max(R2, fold);
+  p->tab_elems = (size_t)p->MhP * H1 * H2;
+
+  size_t off = 0;
+  p->off_scal = off; off = align_up(off + 64 * sizeof(double));
+  p->off_err = off; off = align_up(off + sizeof(uint32_t));
+  p->off_partA = off; off = align_up(off + kPartials * sizeof(double));
+  p->off_partB = off; off = align_up(off + kPartials * sizeof(double));
+  for (int a = 0; a < D; ++a) {
+    p->off_tw[a] = off; off = align_up(off + (size_t)p->M[a] * cs);
+    p->off_tw64[a] = off; off = align_up(off + (size_t)p->M[a] * 16);
+  }
+  p->off_tabs = off;
+  for (auto& t : p->tabs) {
+    t.off = off - p->off_tabs;
+    off = align_up(off + p->tab_elems * p->w);
+  }
+  p->off_R1 = off; off = align_up(off + R1);
+  p->off_R2 = off; off = align_up(off + R2);
+  p->R1 = R1;
+  p->R2 = R2;
+  p->ws_bytes = off;
+  *out = p;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_plan_workspace_size(dt_plan p, size_t* bytes) {
+  if (!p || !bytes) return DT_E_ARG;
+  *bytes = p->ws_bytes;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_destroy_plan(dt_plan p) {
+  if (!p) return DT_E_ARG;
+  delete p;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_plan_info(dt_plan p, dt_plan_info_t* info) {
+  if (!p || !info) return DT_E_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->ndim = p->ndim;
+  for (int a = 0; a < 3; ++a) {
+    info->dims[a] = p->n[a];
+    info->padded[a] = p->M[a];
+    info->spacing[a] = p->h[a];
+    info->origin[a] = p->o[a];
+  }
+  info->tau = p->tau;
+  info->precision = p->prec;
+  info->out_mask = p->mask;
+  info->c_theta = p->c_theta;
+  info->kernel_l1 = p->kernel_l1;
+  info->unit_roundoff = p->unit();
+  info->workspace_bytes = p->ws_bytes;
+  info->n_tables = (int)p->tabs.size();
+  return DT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace attach and plan-time spectra
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T> dt_status build_tables(dt_plan p, hipStream_t st) {
+  const int D = p->ndim;
+  // twiddles
+  for (int a = 0; a < D; ++a) {
+    std::vector<double> tw;
+    make_twiddles((int)p->M[a], tw);
+    std::vector<T> twt(tw.size());
+    for (size_t i = 0; i < tw.size(); ++i) twt[i] = (T)tw[i];
+    if (hipMemcpyAsync(p->ws + p->off_tw[a], twt.data(), twt.size() * sizeof(T), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return DT_E_HIP;
+    if (hipMemcpyAsync(p->ws + p->off_tw64[a], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return DT_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
+  }
+  TabGeom tg{};
+  tg.ndim = D;
+  for (int a = 0; a < 3; ++a) {
+    tg.M[a] = a < D ? (int)p->M[a] : 1;
+    tg.H[a] = a < D ? (int)(p->M[a] / 2 + 1) : 1;
+    tg.h[a] = a < D ? p->h[a] : 1.0;
+  }
+  double* buf0 = (double*)p->R1p();
+  double* buf1 = (double*)p->R2p();
+  std::vector<double> part(kPartials);
+  // sample every kernel, record l1
+  for (auto& t : p->tabs) {
+    const int nb = launch_tab_sample(t.kd, tg, buf0, p->partA(), st);
+    if (hipMemcpyAsync(part.data(), p->partA(), nb * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return DT_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
+    double l1 = 0.0;
+    for (int i = 0; i < nb; ++i) l1 += part[i];
+    t.l1 = l1;
+    t.e = ceil_log2(l1);
+  }
+  // the sign tables share one exponent (their products are summed)
+  int es = -1000000;
+  for (int a = 0; a < 3; ++a)
+    if (p->t_sign[a] >= 0) es = std::max(es, p->tabs[p->t_sign[a]].e);
+  for (int a = 0; a < 3; ++a)
+    if (p->t_sign[a] >= 0) p->tabs[p->t_sign[a]].e = es;
+  p->e_sign_tab = es;
+  if (p->t_f >= 0) p->kernel_l1 = p->tabs[p->t_f].l1;
+  else {
+    // the validity threshold needs ||f||_1 even when f itself is not tabulated
+    TabKernel kf{};
+    kf.kind = KER_F;
+    kf.tau = p->tau;
+    const int nb = launch_tab_sample(kf, tg, buf0, p->partA(), st);
+    if (hipMemcpyAsync(part.data(), p->partA(), nb * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return DT_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
+    double l1 = 0.0;
+    for (int i = 0; i < nb; ++i) l1 += part[i];
+    p->kernel_l1 = l1;
+  }
+  // transform and store
+  for (auto& t : p->tabs) {
+    launch_tab_sample(t.kd, tg, buf0, p->partA(), st);
+    double* cur = buf0;
+    double* nxt = buf1;
+    for (int a = 0; a < D; ++a) {
+      launch_tab_axis(tg, a, t.par[a], p->ws + p->off_tw64[a], cur, nxt, st);
+      std::swap(cur, nxt);
+    }
+    const double scale = std::ldexp(1.0, -t.e) / p->npad();
+    launch_tab_store<T>(tg, cur, scale, (T*)(p->ws + p->off_tabs + t.off), p->MhP, st);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t bytes, void* stream) {
+  if (!p || !dev_ptr) return DT_E_ARG;
+  if (bytes < p->ws_bytes || ((uintptr_t)dev_ptr % kAlign) != 0) return DT_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  p->ws = (char*)dev_ptr;
+  p->stream = st;
+  p->ready = false;
+  // clear the scalars, the error word and the pitch padding of the table region
+  launch_fill_zero<double>((double*)p->ws, (int64_t)(p->off_R1 / sizeof(double)), st);
+  const dt_status s = p->fp64 ? build_tables<double>(p, st) : build_tables<float>(p, st);
+  if (s != DT_OK) return s;
+  p->ready = true;
+  return DT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Calls
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Request {
+  bool dist = false, grad = false, hess = false, sign = false;
+};
+
+dt_status check_shape(dt_plan p, const dt_shape* s) {
+  if (!s) return DT_E_ARG;
+  if (p->ndim == 2) {
+    if (s->kind != DT_SHAPE_POLYGON || !s->points || s->n_points < 3) return DT_E_ARG;
+  } else {
+    if (s->kind != DT_SHAPE_MESH || !s->vertices || !s->faces || s->n_vertices < 3 || s->n_faces < 1)
+      return DT_E_ARG;
+  }
+  return DT_OK;
+}
+
+struct Layout3 {
+  int64_t lineA, zA, chA;   // after the x pass  [ch][z][y][kx]
+  int64_t lineB, zB, chB;   // after the y pass  [ch][z][ky][kx]
+  int64_t lineD, zD, chD;   // after the inverse y pass [c][z][y][kx]
+};
+
+template <typename T>
+dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStream_t st) {
+  const int D = p->ndim;
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t My = p->M[1];
+  const int MhP = p->MhP;
+  auto tiles_for = [&](int64_t len) {
+    const int nb = col_tile_width((int)len, p->fp64);
+    return (p->Mh + nb - 1) / nb;
+  };
+  RowParams rp{};
+  rp.n_lines = (int64_t)n_in * ny * nz;
+  rp.nx = (int)nx;
+  rp.pitch = MhP;
+  rp.inner = p->Mh;
+  rp.tw = p->ws + p->off_tw[0];
+  if (!launch_row_r2c<T>((const T*)p->R1p(), p->R2p(), rp, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  if (D == 2) {
+    ColParams cp{};
+    cp.in_line = MhP; cp.in_outer = 0; cp.in_ch = ny * MhP;
+    cp.out_line = MhP; cp.out_outer = 0; cp.out_ch = ny * MhP;
+    cp.inner = p->Mh; cp.n_in = (int)ny; cp.n_out = (int)ny; cp.outer_len = 1;
+    cp.tw = p->ws + p->off_tw[1]; cp.tw_stride = 1;
+    if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My), 1, st)) return DT_E_UNSUPPORTED;
+  } else {
+    const int64_t Mz = p->M[2];
+    ColParams c2{};
+    c2.in_line = MhP; c2.in_outer = ny * MhP; c2.in_ch = nz * ny * MhP;
+    c2.out_line = MhP; c2.out_outer = My * MhP; c2.out_ch = nz * My * MhP;
+    c2.inner = p->Mh; c2.n_in = (int)ny; c2.n_out = (int)My; c2.outer_len = (int)nz;
+    c2.tw = p->ws + p->off_tw[1]; c2.tw_stride = 1;
+    if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My), (int)nz, n_in, st)) return DT_E_UNSUPPORTED;
+    ColParams c3{};
+    c3.in_line = My * MhP; c3.in_outer = MhP; c3.in_ch = nz * My * MhP;
+    c3.out_line = My * MhP; c3.out_outer = MhP; c3.out_ch = nz * My * MhP;
+    c3.inner = p->Mh; c3.n_in = (int)nz; c3.n_out = (int)nz; c3.outer_len = (int)My;
+    c3.tw = p->ws + p->off_tw[2]; c3.tw_stride = 1;
+    if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz), (int)My, st)) return DT_E_UNSUPPORTED;
+    ColParams c4{};
+    c4.in_line = MhP; c4.in_outer = My * MhP; c4.in_ch = nz * My * MhP;
+    c4.out_line = MhP; c4.out_outer = ny * MhP; c4.out_ch = nz * ny * MhP;
+    c4.inner = p->Mh; c4.n_in = (int)My; c4.n_out = (int)ny; c4.outer_len = (int)nz;
+    c4.tw = p->ws + p->off_tw[1]; c4.tw_stride = 1;
+    if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My), (int)nz, n_out, st)) return DT_E_UNSUPPORTED;
+  }
+  return DT_OK;
+}
+
+void fill_tabrefs(dt_plan p, FusedSpec& fs) {
+  for (size_t t = 0; t < p->tabs.size() && t < (size_t)kMaxTables; ++t) {
+    TabRef& r = fs.tabs[t];
+    r.ptr = p->tab_ptr((int)t);
+    r.phase = p->tabs[t].phase;
+    const int line_axis = p->ndim == 3 ? 2 : 1;
+    r.odd_line = p->tabs[t].par[line_axis];
+    r.odd_outer = p->ndim == 3 ? p->tabs[t].par[1] : 0;
+  }
+  const int64_t H1 = p->M[1] / 2 + 1;
+  if (p->ndim == 3) {
+    fs.tab_line_stride = H1 * p->MhP;
+    fs.tab_outer_stride = p->MhP;
+  } else {
+    fs.tab_line_stride = p->MhP;
+    fs.tab_outer_stride = 0;
+  }
+}
+
+template <typename T>
+dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
+                      hipStream_t st) {
+  const int D = p->ndim;
+  Request rq;
+  rq.hess = out->hess != nullptr;
+  rq.grad = out->grad != nullptr || rq.hess;
+  rq.dist = out->S != nullptr || rq.grad;
+  rq.sign = out->label != nullptr || out->mu != nullptr;
+  if (!rq.dist && !rq.sign) return DT_E_ARG;
+  if (out->signed_outputs && !rq.sign) return DT_E_ARG;
+  if (rq.dist && p->t_f < 0) return DT_E_ARG;
+  if (rq.grad && p->t_u[0] < 0) return DT_E_ARG;
+  if (rq.hess && p->t_h[0] < 0) return DT_E_ARG;
+  if (rq.sign && p->t_sign[0] < 0) return DT_E_ARG;
+  if (rq.sign || (rq.dist && !Y)) {
+    const dt_status s = check_shape(p, shape);
+    if (s != DT_OK) return s;
+  }
+  if (rq.dist && Y && K < 1) return DT_E_ARG;
+  if (!p->ready) return DT_E_WORKSPACE;
+
+  const int nh = D == 2 ? 3 : 6;
+  const int n_in = (rq.dist ? 1 : 0) + (rq.sign ? D : 0);
+  const int sign_in0 = rq.dist ? 1 : 0;
+  int n_out = 0;
+  FusedSpec fs{};
+  fill_tabrefs(p, fs);
+  EpiParams ep{};
+  ep.ch_phi = -1;
+  ep.ch_mu = -1;
+  for (int a = 0; a < 3; ++a) ep.ch_u[a] = -1;
+  for (int a = 0; a < 6; ++a) ep.ch_h[a] = -1;
+  const GridGeom g = p->geom();
+  const int64_t N = p->nodes();
+  T* img = (T*)p->R1p();
+  launch_fill_zero<T>(img, (int64_t)n_in * N, st);
+
+  // source counts
+  int64_t Kc = 0;
+  if (rq.dist) Kc = Y ? K : (D == 2 ? shape->n_points : shape->n_faces);
+  const int e_g = rq.dist ? ceil_log2((double)Kc) : 0;
+  const T cval = (T)std::ldexp(1.0, -e_g);
+  // sign weight scale: |Z^i| <= extent, |P^i| <= extent^2 / 2
+  double ext = 0.0;
+  for (int a = 0; a < D; ++a) ext = std::max(ext, (double)p->n[a] * p->h[a]);
+  int64_t Ks = rq.sign ? (D == 2 ? shape->n_points : shape->n_faces) : 0;
+  const int e_s = rq.sign ? ceil_log2((double)Ks * (D == 2 ? ext : 0.5 * ext * ext)) : 0;
+  const double ws_scale = std::ldexp(1.0, -e_s);
+
+  T* cnt = rq.dist ? img : nullptr;
+  T* sg[3] = {nullptr, nullptr, nullptr};
+  if (rq.sign)
+    for (int a = 0; a < D; ++a) sg[a] = img + (int64_t)(sign_in0 + a) * N;
+  if (rq.dist && Y) launch_splat_points<T>(Y, K, g, cnt, cval, p->err(), st);
+  if (D == 2 && shape && (rq.sign || (rq.dist && !Y)))
+    launch_splat_polygon<T>(shape->points, shape->n_points, g, (rq.dist && !Y) ? cnt : nullptr, cval,
+                            rq.sign ? sg[0] : nullptr, rq.sign ? sg[1] : nullptr, ws_scale, ws_scale, p->err(), st);
+  if (D == 3 && shape && (rq.sign || (rq.dist && !Y)))
+    launch_splat_mesh<T>(shape->vertices, shape->n_vertices, shape->faces, shape->n_faces, g,
+                         (rq.dist && !Y) ? cnt : nullptr, cval, sg[0], sg[1], sg[2], ws_scale, ws_scale, ws_scale,
+                         p->err(), st);
+
+  // validity scalars
+  if (rq.dist) {
+    const int nb = launch_grid_msq<T>(cnt, N, std::ldexp(1.0, e_g), p->partA(), st);
+    const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
+    launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+  }
+
+  // fused groups and epilogue channel map
+  int gi = 0;
+  if (rq.dist) {
+    FusedGroup& G = fs.g[gi++];
+    G.mode = 0;
+    G.n_in = 1;
+    G.in_ch[0] = 0;
+    G.n_out = 0;
+    auto push = [&](int tab) {
+      G.out_ch[G.n_out] = n_out;
+      G.tab[G.n_out] = tab;
+      ++G.n_out;
+      return n_out++;
+    };
+    const int ef = p->tabs[p->t_f].e;
+    ep.ch_phi = push(p->t_f);
+    ep.scale_phi = std::ldexp(1.0, e_g + ef);
+    if (rq.grad)
+      for (int a = 0; a < D; ++a) {
+        ep.ch_u[a] = push(p->t_u[a]);
+        ep.scale_u[a] = std::ldexp(1.0, p->tabs[p->t_u[a]].e - ef);
+      }
+    if (rq.hess)
+      for (int hh = 0; hh < nh; ++hh) {
+        ep.ch_h[hh] = push(p->t_h[hh]);
+        ep.scale_h[hh] = std::ldexp(1.0, p->tabs[p->t_h[hh]].e - ef);
+      }
+  }
+  if (rq.sign) {
+    FusedGroup& G = fs.g[gi++];
+    G.mode = 1;
+    G.n_in = D;
+    for (int a = 0; a < D; ++a) {
+      G.in_ch[a] = sign_in0 + a;
+      G.tab[a] = p->t_sign[a];
+    }
+    G.n_out = 1;
+    G.out_ch[0] = n_out;
+    ep.ch_mu = n_out++;
+    ep.scale_mu = std::ldexp(1.0, e_s + p->e_sign_tab);
+  }
+  fs.n_groups = gi;
+
+  dt_status s = run_passes<T>(p, n_in, fs, n_out, st);
+  if (s != DT_OK) return s;
+
+  // final x pass with the epilogue
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  RowParams rp{};
+  rp.n_lines = ny * nz;
+  rp.nx = (int)nx;
+  rp.pitch = p->MhP;
+  rp.inner = p->Mh;
+  rp.tw = p->ws + p->off_tw[0];
+  ep.C = n_out;
+  ep.ch_stride = (int64_t)nz * ny * p->MhP;
+  ep.tau = p->tau;
+  ep.theta = p->scal();
+  ep.ndim = D;
+  ep.n_rows = ny * nz;
+  ep.nx = (int)nx;
+  ep.plane = N;
+  ep.S = out->S;
+  ep.grad = out->grad;
+  ep.hess = out->hess;
+  ep.label = out->label;
+  ep.mu = out->mu;
+  ep.signed_out = out->signed_outputs;
+  if (!launch_row_c2r_epi<T>(p->R1p(), rp, ep, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
+dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, const void* G, float* dY, double* dtau,
+                       hipStream_t st) {
+  const int D = p->ndim;
+  const int64_t N = p->nodes();
+  const GridGeom g = p->geom();
+  T* img = (T*)p->R1p();
+  // validity threshold of the forward call with the same sources
+  launch_fill_zero<T>(img, N, st);
+  const int e_g = ceil_log2((double)K);
+  const T cval = (T)std::ldexp(1.0, -e_g);
+  launch_splat_points<T>(Y, K, g, img, cval, p->err(), st);
+  const int nb = launch_grid_msq<T>(img, N, std::ldexp(1.0, e_g), p->partA(), st);
+  const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
+  launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+  // w = G exp(S/tau) on valid nodes (overwrites the count image)
+  const int ngs = launch_prep_w<T>((const T*)S, (const T*)G, N, p->scal(), p->tau, img, p->partA(), st);
+  // w * u_i and w * (r f)
+  FusedSpec fs{};
+  fill_tabrefs(p, fs);
+  fs.n_groups = 1;
+  FusedGroup& Gr = fs.g[0];
+  Gr.mode = 0;
+  Gr.n_in = 1;
+  Gr.in_ch[0] = 0;
+  Gr.n_out = D + 1;
+  for (int a = 0; a < D; ++a) {
+    Gr.out_ch[a] = a;
+    Gr.tab[a] = p->t_u[a];
+  }
+  Gr.out_ch[D] = D;
+  Gr.tab[D] = p->t_rf;
+  dt_status s = run_passes<T>(p, 1, fs, D + 1, st);
+  if (s != DT_OK) return s;
+  GatherParams gp{};
+  gp.g = g;
+  gp.Y = Y;
+  gp.K = K;
+  gp.spec = p->R1p();
+  gp.ch_stride = (int64_t)p->n[2] * p->n[1] * p->MhP;
+  gp.pitch = p->MhP;
+  gp.inner = p->Mh;
+  gp.Mx = (int)p->M[0];
+  gp.tw = p->ws + p->off_tw[0];
+  gp.nu = D;
+  gp.has_rf = 1;
+  for (int a = 0; a < D; ++a) gp.ch_scale[a] = std::ldexp(1.0, p->tabs[p->t_u[a]].e);
+  gp.ch_scale[D] = std::ldexp(1.0, p->tabs[p->t_rf].e);
+  gp.scal = p->scal();
+  gp.dY = dY;
+  gp.partials = p->partB();
+  const int nrf = launch_gather<T>(gp, st);
+  launch_finalize_dtau(p->partA(), ngs, p->partB(), nrf, 1.0, p->tau, p->scal(), dtau, st);
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" dt_status dt_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
+                                void* stream) {
+  if (!p || !out) return DT_E_ARG;
+  if (!Y && K != 0) return DT_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
+  return p->fp64 ? run_forward<double>(p, Y, K, shape, out, st) : run_forward<float>(p, Y, K, shape, out, st);
+}
+
+extern "C" dt_status dt_distance(dt_plan p, const float* Y, int64_t K, void* S, void* stream) {
+  if (!p || !Y || !S || K < 1) return DT_E_ARG;
+  dt_outputs o{};
+  o.S = S;
+  return dt_forward(p, Y, K, nullptr, &o, stream);
+}
+
+extern "C" dt_status dt_gradient(dt_plan p, const float* Y, int64_t K, void* S_or_null, void* grad, void* stream) {
+  if (!p || !Y || !grad || K < 1) return DT_E_ARG;
+  dt_outputs o{};
+  o.S = S_or_null;
+  o.grad = grad;
+  return dt_forward(p, Y, K, nullptr, &o, stream);
+}
+
+extern "C" dt_status dt_hessian(dt_plan p, const float* Y, int64_t K, void* hess, void* stream) {
+  if (!p || !Y || !hess || K < 1) return DT_E_ARG;
+  dt_outputs o{};
+  o.hess = hess;
+  return dt_forward(p, Y, K, nullptr, &o, stream);
+}
+
+extern "C" dt_status dt_sign(dt_plan p, const dt_shape* shape, int8_t* label, void* mu, void* stream) {
+  if (!p || !shape || (!label && !mu)) return DT_E_ARG;
+  dt_outputs o{};
+  o.label = label;
+  o.mu = mu;
+  return dt_forward(p, nullptr, 0, shape, &o, stream);
+}
+
+extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const void* S, const void* dL_dS,
+                                 float* dL_dY, double* dL_dtau, void* stream) {
+  if (!p || !Y || K < 1 || !S || !dL_dS || !dL_dY) return DT_E_ARG;
+  if (!(p->mask & DT_OUT_BACKWARD)) return DT_E_ARG;
+  if (!p->ready) return DT_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
+  return p->fp64 ? run_backward<double>(p, Y, K, S, dL_dS, dL_dY, dL_dtau, st)
+                 : run_backward<float>(p, Y, K, S, dL_dS, dL_dY, dL_dtau, st);
+}
+
+extern "C" dt_status dt_last_error(dt_plan p) {
+  if (!p) return DT_E_ARG;
+  if (!p->ws) return DT_E_WORKSPACE;
+  uint32_t bits = 0;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return DT_E_HIP;
+  if (hipMemcpy(&bits, p->err(), sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) return DT_E_HIP;
+  const uint32_t zero = 0;
+  if (hipMemcpy(p->err(), &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return DT_E_HIP;
+  return bits ? DT_E_RANGE : DT_OK;
+}
+
+extern "C" dt_status dt_last_stats(dt_plan p, dt_call_stats* st) {
+  if (!p || !st) return DT_E_ARG;
+  if (!p->ws) return DT_E_WORKSPACE;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return DT_E_HIP;
+  double s[5];
+  if (hipMemcpy(s, p->scal(), sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return DT_E_HIP;
+  uint32_t bits = 0;
+  if (hipMemcpy(&bits, p->err(), sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) return DT_E_HIP;
+  st->theta = s[0];
+  st->s_max = s[1];
+  st->g_l2 = s[2];
+  st->dL_dtau = s[4];
+  st->error_bits = bits;
+  return DT_OK;
+}
+
+extern "C" const char* dt_status_str(dt_status s) {
+  switch (s) {
+    case DT_OK: return "ok";
+    case DT_E_ARG: return "invalid argument";
+    case DT_E_RANGE: return "a source was outside the grid or non-finite";
+    case DT_E_PRECISION: return "requested distance not representable in any supported precision";
+    case DT_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case DT_E_HIP: return "HIP runtime error";
+    case DT_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}

@@ -1,0 +1,72 @@
+"""Oracle-side helpers for the GPU parity tests.
+
+Everything here is computed by the CPU oracle from the same seeded inputs
+the GPU receives.  The padded sizes follow the library's documented rule
+(next power of two >= 2n, at least 64), recomputed here and checked against
+the plan.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+# Tolerances (absolute).  S: on every node against min(S_exact, S_max).
+# Derivatives: on nodes with phi_exact >= 2 Theta ("deep valid").
+TOL_S_TAU = 0.02            # |dS| <= 0.02 tau
+TOL_GRAD = 0.02             # per component
+TOL_HESS = 0.05             # times (1/tau + 1/h_min)
+TOL_MU = 1e-3
+TOL_S_TAU_FP64 = 1e-8       # float64 path: |dS| <= 1e-8 tau on deep-valid nodes
+TOL_GRAD_FP64 = 1e-8
+
+
+def padded(n):
+    m = 64
+    while m < 2 * n:
+        m *= 2
+    return m
+
+
+def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=False, cells=None,
+              c_theta=oracle.C_THETA):
+    """Oracle fields at all nodes (or at the given flat node indices)."""
+    D = len(dims)
+    idx, valid = oracle.snap(pts, origin, spacing, dims)
+    Yh = oracle.node_coords(idx[valid], origin, spacing)
+    _, mult = oracle.cell_multiplicities(idx[valid], dims)
+    g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
+    Mp = tuple(padded(n) for n in dims)
+    l1 = oracle.kernel_l1(Mp, spacing, tau)
+    theta = oracle.theta(precision, Mp, l1, g_l2, c_theta)
+    smax = oracle.s_max(tau, theta)
+    X = oracle.grid_nodes(dims, origin, spacing, cells)
+    f = oracle.fields(X, Yh, tau, grad=grad, hess=hess)
+    lnphi = f["lnphi"]
+    out = {
+        "S_exact": f["S"],
+        "S_ref": np.minimum(f["S"], smax),
+        "R": f["R"],
+        "valid": lnphi >= np.log(theta),
+        "deep": lnphi >= np.log(2 * theta),
+        "theta": theta,
+        "s_max": smax,
+        "g_l2": g_l2,
+        "padded": Mp,
+        "kernel_l1": l1,
+        "Yhat": Yh,
+        "X": X,
+    }
+    if grad or hess:
+        out["grad"] = f["grad"]
+    if hess:
+        out["hess"] = f["hess"]
+    return out
+
+
+def hess_components(H, D):
+    """Stack an N x D x D Hessian in the library's channel order
+    xx, xy, [xz,] yy, [yz,] zz."""
+    pairs = [(0, 0), (0, 1), (1, 1)] if D == 2 else [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    return np.stack([H[:, i, j] for i, j in pairs], axis=0)

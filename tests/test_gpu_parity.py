@@ -1,0 +1,137 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Sizes are small enough for the oracle's direct sums to finish in seconds but
+span several column tiles and leave ragged tails (non-power-of-two n, tiles
+of 8 or 16 half-spectrum bins).  Each test prints its measured maxima.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1112_3010_amd as dtm
+    dtm.load_library()
+    return dtm
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _run_fields(dt, dims, pts, tau_h, prec, grad=True, hess=False):
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    outs = ["S", "grad"] + (["hess"] if hess else [])
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=outs)
+    assert plan.padded == tuple(parity.padded(n) for n in dims)
+    Y = torch.from_numpy(pts).cuda()
+    res = plan.forward(Y, S=True, grad=grad, hess=hess)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    ref = parity.reference(dims, h, (0.0,) * len(dims), tau, pts, prec, grad=grad, hess=hess)
+    stats = plan.last_stats()
+    return plan, res, ref, stats, tau, h
+
+
+CASES_2D = [
+    ((128, 128), 64, 2.0, "fp64", "c1"),      # the 2D float64 workload
+    ((100, 77), 50, 1.5, "fp32", "ragged"),
+    ((100, 77), 50, 1.5, "fp64", "ragged"),
+    ((200, 130), 300, 3.0, "fp32", "ragged_big"),
+]
+
+
+@pytest.mark.parametrize("dims,K,tau_h,prec,name", CASES_2D)
+def test_distance_gradient_2d(dt, dims, K, tau_h, prec, name):
+    if name == "c1":
+        w = synth.workload("c1_2d_128")
+        pts = w.points
+    else:
+        pts = synth.generators.uniform_points(2, K, seed=101 + K)
+    plan, res, ref, stats, tau, h = _run_fields(dt, dims, pts, tau_h, prec)
+    S = _np(res["S"]).ravel()
+    g = _np(res["grad"]).reshape(2, -1)
+    assert stats["g_l2"] == pytest.approx(ref["g_l2"], rel=1e-12)
+    assert stats["theta"] == pytest.approx(ref["theta"], rel=1e-9)
+    dS = np.abs(S - ref["S_ref"])
+    deep = ref["deep"]
+    dG = np.abs(g - ref["grad"].T)[:, deep]
+    print(f"\n[{name} {prec}] max|dS|/tau all={dS.max() / tau:.3e} deep={dS[deep].max() / tau:.3e} "
+          f"max|dgrad| deep={dG.max():.3e} valid={ref['valid'].mean():.3f} S_max/tau={ref['s_max'] / tau:.2f}")
+    assert dS.max() <= parity.TOL_S_TAU * tau
+    assert dG.max() <= parity.TOL_GRAD
+    if prec == "fp64":
+        assert dS[deep].max() <= parity.TOL_S_TAU_FP64 * tau
+        assert dG.max() <= parity.TOL_GRAD_FP64
+    # invalid nodes report S_max and zero gradient
+    inval = ~ref["valid"] & (ref["S_exact"] > ref["s_max"] + 0.05 * tau)
+    if inval.any():
+        np.testing.assert_allclose(S[inval], ref["s_max"], rtol=1e-6)
+        assert np.all(g[:, inval] == 0)
+
+
+CASES_3D = [
+    ((40, 36, 33), 30, 1.5, "fp32"),
+    ((40, 36, 33), 30, 1.5, "fp64"),
+    ((64, 64, 64), 200, 1.0, "fp32"),
+]
+
+
+@pytest.mark.parametrize("dims,K,tau_h,prec", CASES_3D)
+def test_distance_gradient_3d(dt, dims, K, tau_h, prec):
+    pts = synth.generators.uniform_points(3, K, seed=201 + K)
+    plan, res, ref, stats, tau, h = _run_fields(dt, dims, pts, tau_h, prec)
+    S = _np(res["S"]).ravel()
+    g = _np(res["grad"]).reshape(3, -1)
+    dS = np.abs(S - ref["S_ref"])
+    deep = ref["deep"]
+    dG = np.abs(g - ref["grad"].T)[:, deep]
+    print(f"\n[3d {dims} {prec}] max|dS|/tau all={dS.max() / tau:.3e} deep={dS[deep].max() / tau:.3e} "
+          f"max|dgrad| deep={dG.max():.3e} valid={ref['valid'].mean():.3f} S_max/tau={ref['s_max'] / tau:.2f}")
+    assert dS.max() <= parity.TOL_S_TAU * tau
+    assert dG.max() <= parity.TOL_GRAD
+    if prec == "fp64":
+        assert dS[deep].max() <= parity.TOL_S_TAU_FP64 * tau
+        assert dG.max() <= parity.TOL_GRAD_FP64
+
+
+@pytest.mark.parametrize("dims,prec", [((90, 70), "fp32"), ((90, 70), "fp64"), ((34, 30, 28), "fp32"),
+                                       ((34, 30, 28), "fp64")])
+def test_hessian(dt, dims, prec):
+    D = len(dims)
+    pts = synth.generators.uniform_points(D, 40, seed=301 + D)
+    plan, res, ref, stats, tau, h = _run_fields(dt, dims, pts, 2.0, prec, hess=True)
+    H = _np(res["hess"]).reshape(3 if D == 2 else 6, -1)
+    Href = parity.hess_components(ref["hess"], D)
+    deep = ref["deep"]
+    dH = np.abs(H - Href)[:, deep]
+    scale = 1.0 / tau + 1.0 / min(h)
+    print(f"\n[hess {dims} {prec}] max|dH|/(1/tau+1/h) deep={dH.max() / scale:.3e}")
+    assert dH.max() <= parity.TOL_HESS * scale
+    if prec == "fp64":
+        assert dH.max() <= 1e-7 * scale
+
+
+def test_source_outside_grid_sets_sticky_error(dt):
+    dims = (64, 48)
+    pts = synth.generators.uniform_points(2, 20, seed=7)
+    bad = np.concatenate([pts, np.array([[1.5, 0.5], [np.nan, 0.2]], dtype=np.float32)])
+    plan = dt.Plan(dims, None, None, 2.0 / 64, precision="fp64", outputs=["S"])
+    S = plan.distance(torch.from_numpy(bad).cuda())
+    torch.cuda.synchronize()
+    assert plan.last_error() == 2       # DT_E_RANGE
+    assert plan.last_error() == 0       # cleared
+    ref = parity.reference(dims, (1 / 64, 1 / 48), (0.0, 0.0), 2.0 / 64, pts, "fp64")
+    np.testing.assert_allclose(_np(S).ravel(), ref["S_ref"], atol=1e-9)
