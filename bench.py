@@ -1,0 +1,239 @@
+"""Throughput of the distance-field hot path on one MI355X.
+
+Default workload (the headline metric): 3D grid 256^3 on [0,1]^3 (h = 1/256,
+padded to 512^3), sources = the 60 000 snapped triangle incenters of a
+closed mesh (a sphere perturbed by random spherical harmonics of degree
+1-6, amplitude 0.1, scaled to 0.8 of the box), tau = h, outputs S and grad S.
+One step = one dt_forward call (splat -> FFT passes -> epilogue) with the
+mesh already resident in device memory.  The float32-with-scaling path is
+the headline value; the float64 path is reported beside it.
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (algorithmic bytes per launch over its average duration, measured
+with HIP events on the launch stream), and a CPU baseline (the FP64 oracle
+on a bounded sample of grid nodes of the same workload, single core).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid pts/s for S+∇S at 256^3: FP64 plain vs FP32-scaled; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(dims, Mp, w, c_in, c_out, n_tab, out_fields):
+    """Algorithmic HBM bytes per launch of each pass (each array read or
+    written once; kernel tables counted once at their folded size)."""
+    D = len(dims)
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if D == 3 else 1
+    Mx, My = Mp[0], Mp[1]
+    Mz = Mp[2] if D == 3 else 1
+    Mh = Mx // 2 + 1
+    cs = 2 * w
+    N = nx * ny * nz
+    tab = n_tab * Mh * (My // 2 + 1) * ((Mz // 2 + 1) if D == 3 else 1) * w
+    b = {
+        "fill": c_in * N * w,
+        "validity": N * w,
+        "row_r2c": c_in * N * w + c_in * ny * nz * Mh * cs,
+    }
+    if D == 3:
+        b["col_fwd_y"] = c_in * nz * ny * Mh * cs + c_in * nz * My * Mh * cs
+        b["col_fused"] = c_in * nz * My * Mh * cs + tab + c_out * nz * My * Mh * cs
+        b["col_inv_y"] = c_out * nz * My * Mh * cs + c_out * nz * ny * Mh * cs
+    else:
+        b["col_fused"] = c_in * ny * Mh * cs + tab + c_out * ny * Mh * cs
+    b["row_c2r_epi"] = c_out * nz * ny * Mh * cs + out_fields * N * w
+    return b
+
+
+def counters_for(kernel_file_hash, precision, pass_name):
+    """HBM traffic measured by rocprofv3 counters for this kernel source, if
+    the committed measurement matches the current source."""
+    try:
+        with open(COUNTERS) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_sha256") != kernel_file_hash:
+        return None
+    return data.get(precision, {}).get(pass_name)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("fft_engine.hpp", "k_fft.hip"):
+        with open(os.path.join(ROOT, "paper_1112_3010_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls):
+    import torch
+    import paper_1112_3010_amd as dt
+    t0 = time.time()
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "grad"])
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    Vd = torch.from_numpy(V).cuda()
+    Fd = torch.from_numpy(F).cuda()
+    out = {"S": plan._empty(), "grad": plan._empty(len(dims))}
+    for _ in range(warmup):
+        plan.forward_into(out, vertices=Vd, faces=Fd)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.forward_into(out, vertices=Vd, faces=Fd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per-pass timing in a separate set of calls (events inside the library)
+    plan.set_timing(True)
+    plan.timings(reset=True)
+    for _ in range(timing_calls):
+        plan.forward_into(out, vertices=Vd, faces=Fd)
+    per = plan.timings(reset=True)
+    plan.set_timing(False)
+    stats = plan.last_stats()
+    w = 8 if prec == "fp64" else 4
+    Mp = plan.padded
+    nbytes = pass_bytes(dims, Mp, w, c_in=1, c_out=1 + len(dims), n_tab=1 + len(dims), out_fields=1 + len(dims))
+    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
+    achieved = nbytes[dom] / (avg[dom] * 1e-3) / 1e9
+    total_model = sum(nbytes.values())
+    N = int(np.prod(dims))
+    res = {
+        "value": N / (ms * 1e-3),
+        "ms_per_step": ms,
+        "plan_setup_s": plan_s,
+        "dominant": dom,
+        "achieved": achieved,
+        "pass_ms": {k: round(v, 4) for k, v in avg.items()},
+        "pass_gbs": {k: round(nbytes[k] / (avg[k] * 1e-3) / 1e9, 1) for k in avg if k in nbytes},
+        "dom_bytes": nbytes[dom],
+        "model_bytes": total_model,
+        "path_gbs": total_model / (ms * 1e-3) / 1e9,
+        "s_max_over_tau": stats["s_max"] / tau,
+        "padded": list(Mp),
+    }
+    del plan
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(V, F, dims, tau, n_cells, seed=0):
+    """The oracle (FP64 direct sums, S and grad S) on a bounded random sample
+    of nodes of the same workload, one core."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    inc, _ = oracle.mesh_sources(V, F)
+    h = tuple(1.0 / n for n in dims)
+    o = (0.0,) * len(dims)
+    idx, valid = oracle.sign.snap_f64(inc, o, h, dims)
+    Yh = oracle.node_coords(idx[valid], o, h)
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(int(np.prod(dims)), n_cells, replace=False)
+    X = oracle.grid_nodes(dims, o, h, cells)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.fields(X, Yh, tau, grad=True)
+        dt_s = time.perf_counter() - t0
+    return {"value": n_cells / dt_s, "unit": "grid pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cells} random nodes of the 256^3 grid, all {int(valid.sum())} sources each, "
+                      f"S and grad S in float64 ({dt_s:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--timing-calls", type=int, default=10)
+    ap.add_argument("--cpu-cells", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import synth
+    n = 256
+    dims = (n, n, n)
+    tau = 1.0 / n
+    V, F = synth.harmonic_star_mesh(seed=3)
+    log(f"workload: 256^3, {len(F)} triangles, tau = h")
+    r32 = run_gpu("fp32", V, F, dims, tau, args.steps, args.warmup, args.timing_calls)
+    log("fp32:", json.dumps(r32))
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
+        log("fp64:", json.dumps(r64))
+    khash = kernel_hash()
+
+    def roof(r, prec):
+        traffic = counters_for(khash, prec, r["dominant"])
+        return {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": r["dominant"],
+                "bytes_per_launch": r["dom_bytes"]}
+
+    line = {
+        "metric": METRIC,
+        "value": round(r32["value"], 1),
+        "unit": "grid pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3d_256cube_mesh60000_tau1h_S_gradS", "grid": list(dims), "padded": r32["padded"],
+                   "sources": int(len(F)), "tau_over_h": 1.0, "precision": "fp32_scaled"},
+        "roofline": roof(r32, "fp32"),
+        "path": {"model_bytes": r32["model_bytes"], "achieved_gbs": round(r32["path_gbs"], 1),
+                 "frac": round(r32["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r32["pass_ms"],
+                 "pass_gbs": r32["pass_gbs"], "s_max_over_tau": round(r32["s_max_over_tau"], 3),
+                 "plan_setup_s": round(r32["plan_setup_s"], 3)},
+    }
+    if r64 is not None:
+        line["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
+                        "dtype": "f64", "roofline": roof(r64, "fp64"),
+                        "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
+                                 "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
+                                 "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3)}}
+    if not args.no_cpu:
+        cb = cpu_baseline(V, F, dims, tau, args.cpu_cells)
+        cb["value"] = round(cb["value"], 2)
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,19 @@ dt_status dt_last_error(dt_plan plan);
 /* Synchronise and report the per-call scalars of the last call. */
 dt_status dt_last_stats(dt_plan plan, dt_call_stats* stats);
 
+/* Optional per-pass timing (for profiling; off by default).  When enabled,
+ * every kernel launch of a call is bracketed by HIP events recorded on the
+ * call's stream; dt_plan_timings synchronises and reports, per pass name,
+ * the number of launches and their summed duration since the last reset. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} dt_pass_timing;
+dt_status dt_plan_set_timing(dt_plan plan, int enable);
+dt_status dt_plan_timings(dt_plan plan, dt_pass_timing* out, int max_entries, int* n_entries);
+dt_status dt_plan_reset_timings(dt_plan plan);
+
 const char* dt_status_str(dt_status status);
 
 #ifdef __cplusplus

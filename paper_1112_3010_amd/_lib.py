@@ -21,7 +21,8 @@ DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
 EXPORTED = (
     "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_info", "dt_destroy_plan",
     "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
-    "dt_last_error", "dt_last_stats", "dt_status_str",
+    "dt_last_error", "dt_last_stats", "dt_plan_set_timing", "dt_plan_timings", "dt_plan_reset_timings",
+    "dt_status_str",
 )
 
 
@@ -76,6 +77,10 @@ class DtCallStats(ctypes.Structure):
     ]
 
 
+class DtPassTiming(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 class DtError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -109,6 +114,9 @@ def load():
     lib.dt_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     lib.dt_last_error.argtypes = [vp]
     lib.dt_last_stats.argtypes = [vp, ctypes.POINTER(DtCallStats)]
+    lib.dt_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.dt_plan_timings.argtypes = [vp, ctypes.POINTER(DtPassTiming), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.dt_plan_reset_timings.argtypes = [vp]
     lib.dt_status_str.argtypes = [st]
     lib.dt_status_str.restype = ctypes.c_char_p
     for name in EXPORTED:

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "dt.h"
@@ -73,6 +74,29 @@ struct dt_plan_s {
   hipStream_t stream = nullptr;
   double kernel_l1 = 0;
   bool ready = false;
+  // optional per-pass timing
+  bool timing = false;
+  struct Pending { std::string name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<std::string, std::pair<int64_t, double>>> acc;
+  hipEvent_t take_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~dt_plan_s() {
+    for (auto& q : pending) {
+      if (q.a) (void)hipEventDestroy(q.a);
+      if (q.b) (void)hipEventDestroy(q.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 
   int64_t nodes() const { return n[0] * n[1] * n[2]; }
   int64_t rows() const { return n[1] * n[2]; }
@@ -98,6 +122,27 @@ struct dt_plan_s {
 };
 
 namespace {
+
+// Brackets one pass with events when timing is enabled.
+struct PassTimer {
+  dt_plan p;
+  hipStream_t st;
+  std::string name;
+  hipEvent_t a = nullptr;
+  PassTimer(dt_plan p_, hipStream_t st_, const char* n) : p(p_), st(st_), name(n) {
+    if (p->timing) {
+      a = p->take_event();
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~PassTimer() {
+    if (!a) return;
+    hipEvent_t b = p->take_event();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    p->pending.push_back({name, a, b});
+  }
+};
 
 // Twiddles exp(-2 pi i m / M) in float64 with octant reduction of the angle.
 void make_twiddles(int M, std::vector<double>& out) {
@@ -482,13 +527,17 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
   rp.pitch = MhP;
   rp.inner = p->Mh;
   rp.tw = p->ws + p->off_tw[0];
-  if (!launch_row_r2c<T>((const T*)p->R1p(), p->R2p(), rp, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  {
+    PassTimer t(p, st, "row_r2c");
+    if (!launch_row_r2c<T>((const T*)p->R1p(), p->R2p(), rp, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  }
   if (D == 2) {
     ColParams cp{};
     cp.in_line = MhP; cp.in_outer = 0; cp.in_ch = ny * MhP;
     cp.out_line = MhP; cp.out_outer = 0; cp.out_ch = ny * MhP;
     cp.inner = p->Mh; cp.n_in = (int)ny; cp.n_out = (int)ny; cp.outer_len = 1;
     cp.tw = p->ws + p->off_tw[1]; cp.tw_stride = 1;
+    PassTimer t(p, st, "col_fused");
     if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My), 1, st)) return DT_E_UNSUPPORTED;
   } else {
     const int64_t Mz = p->M[2];
@@ -497,19 +546,31 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     c2.out_line = MhP; c2.out_outer = My * MhP; c2.out_ch = nz * My * MhP;
     c2.inner = p->Mh; c2.n_in = (int)ny; c2.n_out = (int)My; c2.outer_len = (int)nz;
     c2.tw = p->ws + p->off_tw[1]; c2.tw_stride = 1;
-    if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My), (int)nz, n_in, st)) return DT_E_UNSUPPORTED;
+    {
+      PassTimer t(p, st, "col_fwd_y");
+      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My), (int)nz, n_in, st))
+        return DT_E_UNSUPPORTED;
+    }
     ColParams c3{};
     c3.in_line = My * MhP; c3.in_outer = MhP; c3.in_ch = nz * My * MhP;
     c3.out_line = My * MhP; c3.out_outer = MhP; c3.out_ch = nz * My * MhP;
     c3.inner = p->Mh; c3.n_in = (int)nz; c3.n_out = (int)nz; c3.outer_len = (int)My;
     c3.tw = p->ws + p->off_tw[2]; c3.tw_stride = 1;
-    if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz), (int)My, st)) return DT_E_UNSUPPORTED;
+    {
+      PassTimer t(p, st, "col_fused");
+      if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz), (int)My, st))
+        return DT_E_UNSUPPORTED;
+    }
     ColParams c4{};
     c4.in_line = MhP; c4.in_outer = My * MhP; c4.in_ch = nz * My * MhP;
     c4.out_line = MhP; c4.out_outer = ny * MhP; c4.out_ch = nz * ny * MhP;
     c4.inner = p->Mh; c4.n_in = (int)My; c4.n_out = (int)ny; c4.outer_len = (int)nz;
     c4.tw = p->ws + p->off_tw[1]; c4.tw_stride = 1;
-    if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My), (int)nz, n_out, st)) return DT_E_UNSUPPORTED;
+    {
+      PassTimer t(p, st, "col_inv_y");
+      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My), (int)nz, n_out, st))
+        return DT_E_UNSUPPORTED;
+    }
   }
   return DT_OK;
 }
@@ -569,7 +630,10 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
   const GridGeom g = p->geom();
   const int64_t N = p->nodes();
   T* img = (T*)p->R1p();
-  launch_fill_zero<T>(img, (int64_t)n_in * N, st);
+  {
+    PassTimer t(p, st, "fill");
+    launch_fill_zero<T>(img, (int64_t)n_in * N, st);
+  }
 
   // source counts
   int64_t Kc = 0;
@@ -587,6 +651,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
   T* sg[3] = {nullptr, nullptr, nullptr};
   if (rq.sign)
     for (int a = 0; a < D; ++a) sg[a] = img + (int64_t)(sign_in0 + a) * N;
+  PassTimer* splat_t = new PassTimer(p, st, "splat");
   if (rq.dist && Y) launch_splat_points<T>(Y, K, g, cnt, cval, p->err(), st);
   if (D == 2 && shape && (rq.sign || (rq.dist && !Y)))
     launch_splat_polygon<T>(shape->points, shape->n_points, g, (rq.dist && !Y) ? cnt : nullptr, cval,
@@ -595,9 +660,11 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
     launch_splat_mesh<T>(shape->vertices, shape->n_vertices, shape->faces, shape->n_faces, g,
                          (rq.dist && !Y) ? cnt : nullptr, cval, sg[0], sg[1], sg[2], ws_scale, ws_scale, ws_scale,
                          p->err(), st);
+  delete splat_t;
 
   // validity scalars
   if (rq.dist) {
+    PassTimer t(p, st, "validity");
     const int nb = launch_grid_msq<T>(cnt, N, std::ldexp(1.0, e_g), p->partA(), st);
     const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
     launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
@@ -671,7 +738,10 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
   ep.label = out->label;
   ep.mu = out->mu;
   ep.signed_out = out->signed_outputs;
-  if (!launch_row_c2r_epi<T>(p->R1p(), rp, ep, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  {
+    PassTimer t(p, st, "row_c2r_epi");
+    if (!launch_row_c2r_epi<T>(p->R1p(), rp, ep, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;
+  }
   return hip_status(hipGetLastError());
 }
 
@@ -683,15 +753,28 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
   const GridGeom g = p->geom();
   T* img = (T*)p->R1p();
   // validity threshold of the forward call with the same sources
-  launch_fill_zero<T>(img, N, st);
   const int e_g = ceil_log2((double)K);
   const T cval = (T)std::ldexp(1.0, -e_g);
-  launch_splat_points<T>(Y, K, g, img, cval, p->err(), st);
-  const int nb = launch_grid_msq<T>(img, N, std::ldexp(1.0, e_g), p->partA(), st);
-  const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
-  launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+  {
+    PassTimer t(p, st, "fill");
+    launch_fill_zero<T>(img, N, st);
+  }
+  {
+    PassTimer t(p, st, "splat");
+    launch_splat_points<T>(Y, K, g, img, cval, p->err(), st);
+  }
+  {
+    PassTimer t(p, st, "validity");
+    const int nb = launch_grid_msq<T>(img, N, std::ldexp(1.0, e_g), p->partA(), st);
+    const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
+    launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+  }
   // w = G exp(S/tau) on valid nodes (overwrites the count image)
-  const int ngs = launch_prep_w<T>((const T*)S, (const T*)G, N, p->scal(), p->tau, img, p->partA(), st);
+  int ngs;
+  {
+    PassTimer t(p, st, "prep_w");
+    ngs = launch_prep_w<T>((const T*)S, (const T*)G, N, p->scal(), p->tau, img, p->partA(), st);
+  }
   // w * u_i and w * (r f)
   FusedSpec fs{};
   fill_tabrefs(p, fs);
@@ -726,8 +809,10 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
   gp.scal = p->scal();
   gp.dY = dY;
   gp.partials = p->partB();
+  PassTimer* gt = new PassTimer(p, st, "gather");
   const int nrf = launch_gather<T>(gp, st);
   launch_finalize_dtau(p->partA(), ngs, p->partB(), nrf, 1.0, p->tau, p->scal(), dtau, st);
+  delete gt;
   return hip_status(hipGetLastError());
 }
 
@@ -808,6 +893,52 @@ extern "C" dt_status dt_last_stats(dt_plan p, dt_call_stats* st) {
   st->dL_dtau = s[4];
   st->error_bits = bits;
   return DT_OK;
+}
+
+extern "C" dt_status dt_plan_set_timing(dt_plan p, int enable) {
+  if (!p) return DT_E_ARG;
+  p->timing = enable != 0;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_plan_timings(dt_plan p, dt_pass_timing* out, int max_entries, int* n_entries) {
+  if (!p || !n_entries || (max_entries > 0 && !out)) return DT_E_ARG;
+  if (!p->pending.empty() && hipStreamSynchronize(p->stream) != hipSuccess) return DT_E_HIP;
+  for (auto& q : p->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, q.a, q.b) != hipSuccess) return DT_E_HIP;
+    bool found = false;
+    for (auto& e : p->acc)
+      if (e.first == q.name) {
+        e.second.first += 1;
+        e.second.second += ms;
+        found = true;
+      }
+    if (!found) p->acc.push_back({q.name, {1, (double)ms}});
+    p->pool.push_back(q.a);
+    p->pool.push_back(q.b);
+  }
+  p->pending.clear();
+  int n = 0;
+  for (auto& e : p->acc) {
+    if (n < max_entries) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, e.first.c_str(), sizeof(out[n].name) - 1);
+      out[n].launches = e.second.first;
+      out[n].total_ms = e.second.second;
+    }
+    ++n;
+  }
+  *n_entries = n;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_plan_reset_timings(dt_plan p) {
+  if (!p) return DT_E_ARG;
+  int n = 0;
+  const dt_status s = dt_plan_timings(p, nullptr, 0, &n);
+  p->acc.clear();
+  return s;
 }
 
 extern "C" const char* dt_status_str(dt_status s) {

@@ -160,6 +160,22 @@ class Plan:
         del keep
         return out
 
+    def forward_into(self, out, Y=None, *, polygon=None, vertices=None, faces=None, signed=False):
+        """Like forward() but writes into preallocated tensors in ``out``
+        (keys among S, grad, hess, label, mu)."""
+        Yc = self._points(Y)
+        sh, keep = self._shape(polygon, vertices, faces)
+        o = L.DtOutputs()
+        for key in ("S", "grad", "hess", "label", "mu"):
+            t = out.get(key)
+            setattr(o, key, None if t is None else t.data_ptr())
+        o.signed_outputs = 1 if signed else 0
+        K = 0 if Yc is None else Yc.shape[0]
+        L.check(L.load().dt_forward(self._h, _ptr(Yc), K, ctypes.byref(sh) if sh is not None else None,
+                                    ctypes.byref(o), _stream(self.device)), "dt_forward")
+        del keep
+        return out
+
     def distance(self, Y):
         Yc = self._points(Y)
         S = self._empty()
@@ -199,6 +215,20 @@ class Plan:
         L.check(L.load().dt_backward(self._h, _ptr(Yc), Yc.shape[0], _ptr(S), _ptr(G), _ptr(dY), _ptr(dtau),
                                      _stream(self.device)), "dt_backward")
         return dY, dtau
+
+    def set_timing(self, enable=True):
+        L.check(L.load().dt_plan_set_timing(self._h, 1 if enable else 0), "dt_plan_set_timing")
+
+    def timings(self, reset=False):
+        """{pass name: (launches, total ms)} since the last reset (synchronises)."""
+        lib = L.load()
+        arr = (L.DtPassTiming * 64)()
+        n = ctypes.c_int()
+        L.check(lib.dt_plan_timings(self._h, arr, 64, ctypes.byref(n)), "dt_plan_timings")
+        out = {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 64))}
+        if reset:
+            L.check(lib.dt_plan_reset_timings(self._h), "dt_plan_reset_timings")
+        return out
 
     def last_error(self):
         return L.load().dt_last_error(self._h)
