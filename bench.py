@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "grid pts/s for S+∇S at 256^3: FP64 plain vs FP32-scaled; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_3d_256.txt")
 
 
 def log(*a):
@@ -66,23 +66,32 @@ def pass_bytes(dims, Mp, w, c_in, c_out, n_tab, out_fields):
 
 
 def counters_for(kernel_file_hash, precision, pass_name):
-    """HBM traffic measured by rocprofv3 counters for this kernel source, if
-    the committed measurement matches the current source."""
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) measured by
+    rocprofv3 for the current kernel sources, else None.  The summary file
+    holds lines `sources <sha256>` and `<precision> <pass> fetch=<B> write=<B>`."""
     try:
-        with open(COUNTERS) as fh:
-            data = json.load(fh)
-    except (OSError, ValueError):
+        lines = open(COUNTERS).read().splitlines()
+    except OSError:
         return None
-    if data.get("kernel_source_sha256") != kernel_file_hash:
-        return None
-    return data.get(precision, {}).get(pass_name)
+    src = None
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 2 and f[0] == "sources":
+            src = f[1]
+        if src == kernel_file_hash and len(f) >= 4 and f[0] == precision and f[1] == pass_name:
+            kv = dict(x.split("=") for x in f[2:])
+            return int(kv["fetch"]) + int(kv["write"])
+    return None
 
 
 def kernel_hash():
+    """Hash of every kernel and host source of the library."""
     h = hashlib.sha256()
-    for f in ("fft_engine.hpp", "k_fft.hip"):
-        with open(os.path.join(ROOT, "paper_1112_3010_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1112_3010_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 
@@ -176,7 +185,19 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy (3 times) to calibrate HBM traffic counters, then exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {a.numel() * 4} bytes x 3")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}).",
               file=sys.stderr)

@@ -38,12 +38,24 @@ struct FusedGroup {
   int tab[kMaxOut];
 };
 
+// One block column of the fused pass computes group `group`'s outputs
+// [c0, c1) (mode 0) or its single output (mode 1).
+struct FusedItem {
+  int group, c0, c1;
+};
+
 struct FusedSpec {
   int n_groups;
   FusedGroup g[2];
+  int n_items;               // grid.z of the fused pass
+  FusedItem items[kMaxOut + 1];
   TabRef tabs[kMaxTables];
-  int64_t tab_line_stride;   // elements between folded k along the transform axis
-  int64_t tab_outer_stride;  // elements between folded k along the outer axis
+  // Table element (folded outer k, kx tile, folded line k, bin in tile) sits at
+  // of * tab_outer_stride + tile * tab_tile_stride + lf * tab_line_stride + b:
+  // each block's slice is one contiguous run.
+  int64_t tab_line_stride;
+  int64_t tab_outer_stride;
+  int64_t tab_tile_stride;
 };
 
 // Strided column pass over tiles of consecutive kx bins.

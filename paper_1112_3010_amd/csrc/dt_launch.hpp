@@ -45,8 +45,8 @@ void launch_finalize_theta(const double* partials, int n_partials, double coef, 
 int launch_tab_sample(const TabKernel& kd, const TabGeom& tg, double* out, double* partials, hipStream_t st);
 void launch_tab_axis(const TabGeom& tg, int axis, int odd, const void* trig, const double* in, double* out,
                      hipStream_t st);
-template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out,
-                                            int64_t pitch, hipStream_t st);
+template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out, int nb,
+                                            int tiles, hipStream_t st);
 
 // FFT passes (return false if the length is not supported).
 template <typename T> bool launch_row_r2c(const T* in, void* out, const RowParams& p, int N, hipStream_t st);

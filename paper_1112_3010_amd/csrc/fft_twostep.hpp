@@ -1,0 +1,235 @@
+// Two-step register FFT for column tiles (gfx950).
+//
+// A length-N transform with N = E * P is split the classic four-step way:
+// each of the P threads that share a column holds the E samples
+// x[p + P e] (e < E) and transforms them in registers (size-E DFT with
+// compile-time twiddles), multiplies by the thread twiddles W_N^(p k1),
+// exchanges through LDS once, and finishes with E/P register DFTs of size P.
+// Output slot (t, k2) of thread p holds X[(p + P t) + E k2].  The inverse
+// runs the same steps backwards from those slots and ends with the natural
+// sample order x[p + P n2] in registers, so a forward transform's outputs are
+// exactly the inverse's inputs (used by the fused multiply pass).
+//
+// Compared with a radix-8 Stockham sequence this needs one LDS exchange per
+// transform instead of N's stage count minus one, all LDS offsets are
+// compile-time immediates, and only E/8 + 7 thread twiddles are loaded per
+// kernel.
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace dt {
+
+// ---------------------------------------------------------------------------
+// Compile-time cos/sin of 2 pi m / R (octant reduction in exact integer
+// arithmetic, then a Taylor series on [0, pi/4] in double precision).
+// ---------------------------------------------------------------------------
+constexpr double kPiCT = 3.14159265358979323846264338327950288;
+
+constexpr double ct_taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 14; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi m / R for integers m, R > 0
+constexpr double ct_cos2pi(long m, long R) {
+  m = ((m % R) + R) % R;
+  const long e8 = m * 8;
+  const long oct = e8 / R;
+  const long rem = e8 % R;
+  const double a = (kPiCT / 4.0) * (double)rem / (double)R;
+  const double b = (kPiCT / 4.0) * (double)(R - rem) / (double)R;
+  switch (oct) {
+    case 0: return ct_taylor_cos(a);
+    case 1: return ct_taylor_sin(b);
+    case 2: return -ct_taylor_sin(a);
+    case 3: return -ct_taylor_cos(b);
+    case 4: return -ct_taylor_cos(a);
+    case 5: return -ct_taylor_sin(b);
+    case 6: return ct_taylor_sin(a);
+    default: return ct_taylor_cos(b);
+  }
+}
+constexpr double ct_sin2pi(long m, long R) {
+  m = ((m % R) + R) % R;
+  const long e8 = m * 8;
+  const long oct = e8 / R;
+  const long rem = e8 % R;
+  const double a = (kPiCT / 4.0) * (double)rem / (double)R;
+  const double b = (kPiCT / 4.0) * (double)(R - rem) / (double)R;
+  switch (oct) {
+    case 0: return ct_taylor_sin(a);
+    case 1: return ct_taylor_cos(b);
+    case 2: return ct_taylor_cos(a);
+    case 3: return ct_taylor_sin(b);
+    case 4: return -ct_taylor_sin(a);
+    case 5: return -ct_taylor_cos(b);
+    case 6: return -ct_taylor_cos(a);
+    default: return -ct_taylor_sin(b);
+  }
+}
+
+// a * exp(-2 pi i DIR m / R) with m, R compile-time; trivial angles are
+// rotations and cost no multiplications.
+template <int DIR, int M, int R, typename V> __device__ __forceinline__ V cmul_w(V a) {
+  using T = decltype(V::x);
+  constexpr int m = ((M % R) + R) % R;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr ((4 * m) % R == 0) {
+    constexpr int q = (4 * m) / R;  // multiple of a quarter turn
+    return mul_mi_pow(a, DIR > 0 ? q : (4 - q) & 3);
+  } else if constexpr ((8 * m) % R == 0 && ((8 * m) / R) % 2 == 1) {
+    constexpr int o = (8 * m) / R;  // odd multiple of an eighth turn
+    const V r = (o == 1 || o == 5) ? rot8_1<DIR>(a) : rot8_3<DIR>(a);
+    return (o >= 4) ? mk<V>(-r.x, -r.y) : r;
+  } else {
+    constexpr T c = (T)ct_cos2pi(m, R);
+    constexpr T s = (T)(DIR > 0 ? -ct_sin2pi(m, R) : ct_sin2pi(m, R));
+    return mk<V>(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// In-register DFT of size R, natural order in and out (R = 2..64, power of
+// two): R = R1 x R2 Cooley-Tukey with compile-time twiddles W_R^(n1 k2).
+template <int R, int DIR, typename V> struct RegDFT {
+  static constexpr int R1 = R >= 32 ? 8 : 4;  // 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
+  static constexpr int R2 = R / R1;
+
+  template <int N1, int K2> static __device__ __forceinline__ void twiddle(const V* t, V* b) {
+    if constexpr (K2 < R2) {
+      b[N1 * R2 + K2] = cmul_w<DIR, N1 * K2, R>(t[K2]);
+      twiddle<N1, K2 + 1>(t, b);
+    }
+  }
+  template <int N1> static __device__ __forceinline__ void step1(const V* a, V* b) {
+    if constexpr (N1 < R1) {
+      V t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[N1 + R1 * n2];
+      RegDFT<R2, DIR, V>::run(t);
+      twiddle<N1, 0>(t, b);
+      step1<N1 + 1>(a, b);
+    }
+  }
+  static __device__ __forceinline__ void run(V* a) {
+    if constexpr (R <= 8) {
+      Bfly<R, DIR, V>::run(a);
+    } else {
+      V b[R];
+      step1<0>(a, b);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        V t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = b[n1 * R2 + k2];
+        RegDFT<R1, DIR, V>::run(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) a[k2 + R2 * k1] = t[k1];
+      }
+    }
+  }
+};
+
+// Thread twiddles W_N^(DIR p k) for k < E from two small sets:
+// k = a + 8 b, W^(p k) = W^(p a) W^(8 p b).
+template <typename T, int N, int E> struct ThreadTwiddles {
+  using V = Cx<T>;
+  static constexpr int NB8 = E / 8;
+  V A[8];
+  V B[NB8 > 0 ? NB8 : 1];
+  __device__ __forceinline__ void load(const V* tw, int p) {
+    A[0] = mk<V>(T(1), T(0));
+#pragma unroll
+    for (int a = 1; a < 8; ++a) A[a] = tw[(p * a) % N];
+    B[0] = mk<V>(T(1), T(0));
+#pragma unroll
+    for (int b = 1; b < NB8; ++b) B[b] = tw[(p * 8 * b) % N];
+  }
+  // W_N^(p k) (forward sign); the inverse uses the conjugate
+  __device__ __forceinline__ V get(int k) const {
+    const int a = k & 7, b = k >> 3;
+    if (b == 0) return A[a];
+    if (a == 0) return B[b];
+    return cmul(A[a], B[b]);
+  }
+};
+
+template <typename T, int N, int E, int NB> struct TwoStep {
+  using V = Cx<T>;
+  static constexpr int P = N / E;
+  static_assert(E >= P && E % P == 0, "each thread must own whole second-step DFTs");
+  static constexpr int PAD = 16;                           // LDS padding (complex) per row group
+  static constexpr int LDS_F = E * (P * NB + PAD);         // forward exchange footprint
+  static constexpr int LDS_I = P * (E * NB + PAD);         // inverse exchange footprint
+  static constexpr int LDS = LDS_F > LDS_I ? LDS_F : LDS_I;
+
+  // Forward: v[e] = x[p + P e] on entry; on exit v[t * P + k2] = X[(p + P t) + E k2].
+  static __device__ __forceinline__ void forward(V* v, V* lds, int p, int b, const ThreadTwiddles<T, N, E>& tw) {
+    RegDFT<E, +1, V>::run(v);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw.get(k));
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[k * (P * NB + PAD) + p * NB + b] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) v[t * P + pp] = lds[(p + P * t) * (P * NB + PAD) + pp * NB + b];
+#pragma unroll
+    for (int t = 0; t < E / P; ++t) RegDFT<P, +1, V>::run(&v[t * P]);
+  }
+
+  // Inverse (unnormalised): v[t * P + k2] = X[(p + P t) + E k2] on entry;
+  // on exit v[n2] = x[p + P n2].
+  static __device__ __forceinline__ void inverse(V* v, V* lds, int p, int b, const ThreadTwiddles<T, N, E>& tw) {
+#pragma unroll
+    for (int t = 0; t < E / P; ++t) RegDFT<P, -1, V>::run(&v[t * P]);
+    // twiddle W_N^(-n1 (p + P t)) = conj(W_N^(n1 p)) * W_E^(-n1 t)
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int n1 = 1; n1 < P; ++n1) v[t * P + n1] = cmul(v[t * P + n1], cconj(tw.get(n1)));
+    apply_const_tw<1>(v);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) lds[n1 * (E * NB + PAD) + (p + P * t) * NB + b] = v[t * P + n1];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = lds[p * (E * NB + PAD) + k * NB + b];
+    RegDFT<E, -1, V>::run(v);
+  }
+
+  // multiply slot (t, n1) by W_E^(-n1 t) for t >= 1 (compile-time)
+  template <int TT> static __device__ __forceinline__ void apply_const_tw(V* v) {
+    if constexpr (TT < E / P) {
+      apply_const_tw_n1<TT, 1>(v);
+      apply_const_tw<TT + 1>(v);
+    }
+  }
+  template <int TT, int N1> static __device__ __forceinline__ void apply_const_tw_n1(V* v) {
+    if constexpr (N1 < P) {
+      v[TT * P + N1] = cmul_w<-1, N1 * TT, E>(v[TT * P + N1]);
+      apply_const_tw_n1<TT, N1 + 1>(v);
+    }
+  }
+
+  // Spectral index held in forward-output slot (t, k2) of thread p.
+  static __device__ __forceinline__ int slot_index(int p, int t, int k2) { return (p + P * t) + E * k2; }
+};
+
+}  // namespace dt

@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
   const int o = blockIdx.y;
   const bool o_neg = 2 * o > p.outer_len;
   const int of = o_neg ? p.outer_len - o : o;
-  const FusedGroup& G = fs.g[blockIdx.z];
+  const FusedItem& IT = fs.items[blockIdx.z];
+  const FusedGroup& G = fs.g[IT.group];
   const V* tw = (const V*)p.tw;
   auto addr = [b](int i) { return i * NB + b; };
 
@@ -147,7 +148,7 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
   };
   // v *= kernel spectrum of table t at this block's (kx, outer, line) slots
   auto times_table = [&](const TabRef& t, const V* v, V* res, bool accumulate) {
-    const T* tab = (const T*)t.ptr + (int64_t)of * fs.tab_outer_stride + kxs;
+    const T* tab = (const T*)t.ptr + (int64_t)of * fs.tab_outer_stride + (int64_t)blockIdx.x * fs.tab_tile_stride + b;
     const bool flip_o = t.odd_outer && o_neg;
 #pragma unroll
     for (int s = 0; s < E / RL; ++s)
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
         const int l = Fw::template in_index<S - 1>(q, s, r);
         const bool l_neg = 2 * l > N;
         const int lf = l_neg ? N - l : l;
-        T tv = active ? tab[(int64_t)lf * fs.tab_line_stride] : T(0);
+        T tv = tab[(int64_t)lf * fs.tab_line_stride];
         if (flip_o != (t.odd_line && l_neg)) tv = -tv;
         const V prod = mul_mi_pow(cscale(v[s * RL + r], tv), t.phase);
         res[s * RL + r] = accumulate ? cadd(res[s * RL + r], prod) : prod;
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
   if (G.mode == 0) {
     V spec[E];
     load_fwd(G.in_ch[0], spec);
-    for (int c = 0; c < G.n_out; ++c) {
+    for (int c = IT.c0; c < IT.c1; ++c) {
       V v[E];
       times_table(fs.tabs[G.tab[c]], spec, v, false);
       inv_store(v, G.out_ch[c]);
@@ -309,17 +310,56 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <typename T> struct ColShape;
-template <> struct ColShape<float> {
-  static constexpr int nb(int N) { return N <= 512 ? 16 : (N == 1024 ? 8 : 4); }
-  static constexpr int nt(int N) { return N * nb(N) / 8 < 256 ? N * nb(N) / 8 : 256; }
-};
-template <> struct ColShape<double> {
-  static constexpr int nb(int N) { return N <= 512 ? 8 : (N == 1024 ? 4 : 2); }
-  static constexpr int nt(int N) { return N * nb(N) / 8 < 256 ? N * nb(N) / 8 : 256; }
+// Column tile shapes: NB consecutive kx bins per block (NB * sizeof(complex)
+// >= 128 bytes per row segment where the LDS budget allows), NT threads,
+// E = N * NB / NT elements per thread.  Separate shapes for the plain and the
+// fused column passes.
+#ifndef DT_C2C_NB32
+#define DT_C2C_NB32 16
+#endif
+#ifndef DT_C2C_NT32
+#define DT_C2C_NT32 512
+#endif
+#ifndef DT_FUSED_NB32
+#define DT_FUSED_NB32 16
+#endif
+#ifndef DT_FUSED_NT32
+#define DT_FUSED_NT32 512
+#endif
+#ifndef DT_C2C_NB64
+#define DT_C2C_NB64 8
+#endif
+#ifndef DT_C2C_NT64
+#define DT_C2C_NT64 512
+#endif
+#ifndef DT_FUSED_NB64
+#define DT_FUSED_NB64 8
+#endif
+#ifndef DT_FUSED_NT64
+#define DT_FUSED_NT64 512
+#endif
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+template <typename T, bool FUSED> struct ColShape {
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr int NBP = F64 ? (FUSED ? DT_FUSED_NB64 : DT_C2C_NB64) : (FUSED ? DT_FUSED_NB32 : DT_C2C_NB32);
+  static constexpr int NTP = F64 ? (FUSED ? DT_FUSED_NT64 : DT_C2C_NT64) : (FUSED ? DT_FUSED_NT32 : DT_C2C_NT32);
+  static constexpr int nb(int N) { return cmin(NBP, 65536 / (N * (int)sizeof(Cx<T>))); }
+  static constexpr int nt(int N) { return cmin(NTP, N * nb(N) / 8); }
 };
 
-int col_tile_width(int N, bool fp64) { return fp64 ? ColShape<double>::nb(N) : ColShape<float>::nb(N); }
+int col2_tile_width(int N, bool fp64, bool fused);
+template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
+                                           int outer, int chans, hipStream_t st);
+template <typename T> bool launch_col2_fused(const void* in, void* out, const ColParams& p, const FusedSpec& fs,
+                                             int N, int tiles, int outer, hipStream_t st);
+
+int col_tile_width(int N, bool fp64, bool fused) {
+  const int nb2 = col2_tile_width(N, fp64, fused);
+  if (nb2 > 0) return nb2;
+  if (fp64) return fused ? ColShape<double, true>::nb(N) : ColShape<double, false>::nb(N);
+  return fused ? ColShape<float, true>::nb(N) : ColShape<float, false>::nb(N);
+}
 
 // Row passes transform M_x/2 complex points, column passes M points; M >= 64.
 #define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(256) X(512) X(1024)
@@ -343,11 +383,12 @@ template <typename T> bool launch_row_r2c(const T* in, void* out, const RowParam
 
 template <typename T> bool launch_col_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
                                           int outer, int chans, hipStream_t st) {
+  if (launch_col2_c2c<T>(in, out, p, N, dir, tiles, outer, chans, st)) return true;
   const dim3 grid(tiles, outer, chans);
   switch (N) {
 #define CASE(NN)                                                                                         \
   case NN: {                                                                                             \
-    constexpr int NB = ColShape<T>::nb(NN), NT = ColShape<T>::nt(NN);                                    \
+    constexpr int NB = ColShape<T, false>::nb(NN), NT = ColShape<T, false>::nt(NN);                      \
     if (dir > 0)                                                                                         \
       hipLaunchKernelGGL((k_col_c2c<T, NN, NB, NT, 1>), grid, dim3(NT), 0, st, (const Cx<T>*)in, (Cx<T>*)out, p); \
     else                                                                                                 \
@@ -362,11 +403,12 @@ template <typename T> bool launch_col_c2c(const void* in, void* out, const ColPa
 
 template <typename T> bool launch_col_fused(const void* in, void* out, const ColParams& p, const FusedSpec& fs,
                                             int N, int tiles, int outer, hipStream_t st) {
-  const dim3 grid(tiles, outer, fs.n_groups);
+  if (launch_col2_fused<T>(in, out, p, fs, N, tiles, outer, st)) return true;
+  const dim3 grid(tiles, outer, fs.n_items);
   switch (N) {
 #define CASE(NN)                                                                                         \
   case NN: {                                                                                             \
-    constexpr int NB = ColShape<T>::nb(NN), NT = ColShape<T>::nt(NN);                                    \
+    constexpr int NB = ColShape<T, true>::nb(NN), NT = ColShape<T, true>::nt(NN);                        \
     hipLaunchKernelGGL((k_col_fused<T, NN, NB, NT>), grid, dim3(NT), 0, st, (const Cx<T>*)in, (Cx<T>*)out, p, fs); \
     return true;                                                                                         \
   }

@@ -1,0 +1,383 @@
+// Column passes on the two-step register FFT engine (see fft_twostep.hpp):
+// the strided C2C pass and the fused forward / kernel-spectrum product /
+// inverse pass of the last axis (Sec. 3, Table 1 steps 3-5).  Used for the
+// transform lengths whose register footprint fits; the Stockham kernels in
+// k_fft.hip cover the rest.
+#include "dt_launch.hpp"
+#include "fft_twostep.hpp"
+
+namespace dt {
+
+// Factorisation N = E * P per length and precision (0 = not provided).
+template <typename T, bool FUSED> constexpr int twostep_E(int N) {
+#ifdef DT_NO_TWOSTEP
+  return 0;
+#endif
+  if (sizeof(T) == 4) {
+    if (FUSED) return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : 0;
+    return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : N == 1024 ? 32 : 0;
+  }
+  // float64: a fused pass keeps two copies of the column in registers
+  if (FUSED) return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : 0;
+  return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : 0;
+}
+#ifndef DT_FUSED2_NB32
+#define DT_FUSED2_NB32 16
+#endif
+template <typename T, bool FUSED = false> constexpr int twostep_NB() {
+  return sizeof(T) == 4 ? (FUSED ? DT_FUSED2_NB32 : 16) : 8;
+}
+
+template <typename T, int N, int E, int NB, int DIR, bool HALF>
+__global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out,
+                                                          ColParams p) {
+  using V = Cx<T>;
+  using TS = TwoStep<T, N, E, NB>;
+  constexpr int P = TS::P;
+  __shared__ V lds[TS::LDS];
+  const int tid = threadIdx.x;
+  const int b = tid % NB, pt = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const int kxs = active ? kx : 0;
+  ThreadTwiddles<T, N, E> tw;
+  tw.load((const V*)p.tw, pt);
+  const V* src = in + blockIdx.z * p.in_ch + blockIdx.y * p.in_outer + kxs;
+  V* dst = out + blockIdx.z * p.out_ch + blockIdx.y * p.out_outer + kxs;
+  V v[E];
+  if constexpr (DIR > 0) {
+    // natural input rows pt + P e (pruned), outputs in slot order
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = pt + P * e;
+      if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
+      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
+    }
+    TS::forward(v, lds, pt, b, tw);
+    if (!active) return;
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) {
+        const int k = TS::slot_index(pt, t, k2);
+        if (k < p.n_out) dst[(int64_t)k * p.out_line] = v[t * P + k2];
+      }
+  } else {
+    // inputs in slot order, natural output rows pt + P n2 (pruned)
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) {
+        const int k = TS::slot_index(pt, t, k2);
+        v[t * P + k2] = (active && k < p.n_in) ? src[(int64_t)k * p.in_line] : mk<V>(T(0), T(0));
+      }
+    TS::inverse(v, lds, pt, b, tw);
+    if (!active) return;
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      if (HALF && n2 >= E / 2) continue;
+      const int n = pt + P * n2;
+      if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
+    }
+  }
+}
+
+template <typename T, int N, int E, int NB, bool HALF>
+__global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out,
+                                                            ColParams p, FusedSpec fs) {
+  using V = Cx<T>;
+  using TS = TwoStep<T, N, E, NB>;
+  constexpr int P = TS::P;
+  __shared__ V lds[TS::LDS];
+  const int tid = threadIdx.x;
+  const int b = tid % NB, pt = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const int kxs = active ? kx : 0;
+  const int o = blockIdx.y;
+  const bool o_neg = 2 * o > p.outer_len;
+  const int of = o_neg ? p.outer_len - o : o;
+  const FusedItem& IT = fs.items[blockIdx.z];
+  const FusedGroup& G = fs.g[IT.group];
+  ThreadTwiddles<T, N, E> tw;
+  tw.load((const V*)p.tw, pt);
+
+  auto load_fwd = [&](int ch, V* v) {
+    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = pt + P * e;
+      if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
+      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
+    }
+    TS::forward(v, lds, pt, b, tw);
+  };
+  // kernel-spectrum values of table tab at this thread's slots (sign folded in)
+  auto load_tab = [&](int tab, T* tv) {
+    const TabRef& t = fs.tabs[tab];
+    const T* base = (const T*)t.ptr + (int64_t)of * fs.tab_outer_stride + (int64_t)blockIdx.x * fs.tab_tile_stride + b;
+    const bool flip_o = t.odd_outer && o_neg;
+#pragma unroll
+    for (int tt = 0; tt < E / P; ++tt)
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) {
+        const int l = TS::slot_index(pt, tt, k2);
+        const bool l_neg = 2 * l > N;
+        const int lf = l_neg ? N - l : l;
+        const T val = base[(int64_t)lf * fs.tab_line_stride];
+        tv[tt * P + k2] = (flip_o != (t.odd_line && l_neg)) ? -val : val;
+      }
+  };
+  auto times = [&](const T* tv, int phase, const V* v, V* res, bool accumulate) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const V prod = mul_mi_pow(cscale(v[e], tv[e]), phase);
+      res[e] = accumulate ? cadd(res[e], prod) : prod;
+    }
+  };
+  auto inv_store = [&](V* v, int ch) {
+    TS::inverse(v, lds, pt, b, tw);
+    if (!active) return;
+    V* dst = out + (int64_t)ch * p.out_ch + (int64_t)o * p.out_outer + kx;
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      if (HALF && n2 >= E / 2) continue;
+      const int n = pt + P * n2;
+      if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
+    }
+  };
+
+  if (G.mode == 0) {
+    T tv[E];
+    load_tab(G.tab[IT.c0], tv);       // issued before the forward transform
+    V spec[E];
+    load_fwd(G.in_ch[0], spec);
+    for (int c = IT.c0; c < IT.c1; ++c) {
+      V v[E];
+      times(tv, fs.tabs[G.tab[c]].phase, spec, v, false);
+      if (c + 1 < IT.c1) load_tab(G.tab[c + 1], tv);   // prefetch the next channel's table
+      inv_store(v, G.out_ch[c]);
+    }
+  } else {
+    V acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = mk<V>(T(0), T(0));
+    for (int i = 0; i < G.n_in; ++i) {
+      T tv[E];
+      load_tab(G.tab[i], tv);
+      V v[E];
+      load_fwd(G.in_ch[i], v);
+      times(tv, fs.tabs[G.tab[i]].phase, v, acc, true);
+    }
+    inv_store(acc, G.out_ch[0]);
+  }
+}
+
+// 3D variant of the fused pass with the kernel tables staged in LDS.  The
+// tables are stored tile-major, so the slice a block needs (all folded kz of
+// one kx tile at one |ky|) is a contiguous run that is copied with 16-byte
+// loads.  With MIRROR the block owns the column pair (ky, M_y - ky), which
+// share the slice: every folded table entry then serves all four spectral
+// points (+-ky, +-kz) from one read.
+constexpr int kTabChunk = 4;
+#ifndef DT_FUSED_MIRROR
+#define DT_FUSED_MIRROR 1
+#endif
+
+template <typename T, int N, int E, int NB, bool HALF, bool MIRROR>
+__global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>* __restrict__ in,
+                                                                   Cx<T>* __restrict__ out, ColParams p,
+                                                                   FusedSpec fs) {
+  using V = Cx<T>;
+  using TS = TwoStep<T, N, E, NB>;
+  constexpr int P = TS::P;
+  constexpr int H = N / 2 + 1;                     // folded rows along the transform axis
+  constexpr int SLICE = H * NB;                    // table elements per channel slice
+  constexpr int SLICE16 = SLICE * (int)sizeof(T) / 16;
+  static_assert((SLICE * sizeof(T)) % 16 == 0, "slice must be a whole number of 16-byte words");
+  __shared__ V lds[TS::LDS];
+  __shared__ __align__(16) T tab_lds[kTabChunk * SLICE];
+  const int tid = threadIdx.x;
+  constexpr int NT = P * NB;
+  const int b = tid % NB, pt = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const int kxs = active ? kx : 0;
+  int of, n_cols;
+  if (MIRROR) {
+    of = blockIdx.y;
+    n_cols = (of == 0 || 2 * of == p.outer_len) ? 1 : 2;
+  } else {
+    of = 2 * (int)blockIdx.y > p.outer_len ? p.outer_len - (int)blockIdx.y : (int)blockIdx.y;
+    n_cols = 1;
+  }
+  const FusedItem& IT = fs.items[blockIdx.z];
+  const FusedGroup& G = fs.g[IT.group];
+  ThreadTwiddles<T, N, E> tw;
+  tw.load((const V*)p.tw, pt);
+
+  // copy the contiguous table slices of tabs[0..nt) into LDS with 16-byte loads
+  auto stage = [&](const int* tabs, int nt) {
+    __syncthreads();
+    for (int i = tid; i < nt * SLICE16; i += NT) {
+      const int c = i / SLICE16, j = i - c * SLICE16;
+      const uint4* src = (const uint4*)((const T*)fs.tabs[tabs[c]].ptr + (int64_t)of * fs.tab_outer_stride +
+                                        (int64_t)blockIdx.x * fs.tab_tile_stride);
+      ((uint4*)tab_lds)[i] = src[j];
+    }
+    __syncthreads();
+  };
+  auto load_fwd = [&](int ch, int o, V* v) {
+    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = pt + P * e;
+      if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
+      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
+    }
+    TS::forward(v, lds, pt, b, tw);
+  };
+  auto times = [&](int slot, int tab, bool o_neg, const V* v, V* res, bool accumulate) {
+    const TabRef& t = fs.tabs[tab];
+    const bool flip_o = t.odd_outer && o_neg;
+    const T* tl = tab_lds + slot * SLICE + b;
+#pragma unroll
+    for (int tt = 0; tt < E / P; ++tt)
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) {
+        const int l = TS::slot_index(pt, tt, k2);
+        const bool l_neg = 2 * l > N;
+        const int lf = l_neg ? N - l : l;
+        T val = tl[lf * NB];
+        if (flip_o != (t.odd_line && l_neg)) val = -val;
+        const V prod = mul_mi_pow(cscale(v[tt * P + k2], val), t.phase);
+        res[tt * P + k2] = accumulate ? cadd(res[tt * P + k2], prod) : prod;
+      }
+  };
+  auto inv_store = [&](V* v, int ch, int o) {
+    TS::inverse(v, lds, pt, b, tw);
+    if (!active) return;
+    V* dst = out + (int64_t)ch * p.out_ch + (int64_t)o * p.out_outer + kx;
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      if (HALF && n2 >= E / 2) continue;
+      const int n = pt + P * n2;
+      if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
+    }
+  };
+  auto column = [&](int col) { return MIRROR ? (col == 0 ? of : p.outer_len - of) : (int)blockIdx.y; };
+
+  if (G.mode == 0) {
+    for (int c0 = IT.c0; c0 < IT.c1; c0 += kTabChunk) {
+      const int nc = IT.c1 - c0 < kTabChunk ? IT.c1 - c0 : kTabChunk;
+      stage(&G.tab[c0], nc);
+      for (int col = 0; col < n_cols; ++col) {
+        const int o = column(col);
+        const bool o_neg = 2 * o > p.outer_len;
+        V spec[E];
+        load_fwd(G.in_ch[0], o, spec);
+        for (int c = 0; c < nc; ++c) {
+          V v[E];
+          times(c, G.tab[c0 + c], o_neg, spec, v, false);
+          inv_store(v, G.out_ch[c0 + c], o);
+        }
+      }
+    }
+  } else {
+    stage(G.tab, G.n_in);
+    for (int col = 0; col < n_cols; ++col) {
+      const int o = column(col);
+      const bool o_neg = 2 * o > p.outer_len;
+      V acc[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] = mk<V>(T(0), T(0));
+      for (int i = 0; i < G.n_in; ++i) {
+        V v[E];
+        load_fwd(G.in_ch[i], o, v);
+        times(i, G.tab[i], o_neg, v, acc, true);
+      }
+      inv_store(acc, G.out_ch[0], o);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (return false when the length has no two-step factorisation)
+// ---------------------------------------------------------------------------
+int col2_tile_width(int N, bool fp64, bool fused) {
+  const int E = fp64 ? (fused ? twostep_E<double, true>(N) : twostep_E<double, false>(N))
+                     : (fused ? twostep_E<float, true>(N) : twostep_E<float, false>(N));
+  if (E == 0) return 0;
+  if (fused) return fp64 ? twostep_NB<double, true>() : twostep_NB<float, true>();
+  return fp64 ? twostep_NB<double>() : twostep_NB<float>();
+}
+
+#define DT_FOR_EACH_COL2_N(X) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
+                                           int outer, int chans, hipStream_t st) {
+  const dim3 grid(tiles, outer, chans);
+  const bool half = dir > 0 ? (2 * p.n_in == N) : (2 * p.n_out == N);
+  switch (N) {
+#define CASE(NN)                                                                                          \
+  case NN: {                                                                                              \
+    constexpr int E = twostep_E<T, false>(NN);                                                            \
+    if constexpr (E == 0) {                                                                               \
+      return false;                                                                                       \
+    } else {                                                                                              \
+      constexpr int NB = twostep_NB<T>();                                                                 \
+      constexpr int NT = (NN / E) * NB;                                                                   \
+      const Cx<T>* i_ = (const Cx<T>*)in;                                                                 \
+      Cx<T>* o_ = (Cx<T>*)out;                                                                            \
+      if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, true>), grid, dim3(NT), 0, st, i_, o_, p);   \
+      else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, false>), grid, dim3(NT), 0, st, i_, o_, p);     \
+      else if (half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, true>), grid, dim3(NT), 0, st, i_, o_, p);        \
+      else hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, false>), grid, dim3(NT), 0, st, i_, o_, p);                 \
+      return true;                                                                                        \
+    }                                                                                                     \
+  }
+    DT_FOR_EACH_COL2_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template <typename T> bool launch_col2_fused(const void* in, void* out, const ColParams& p, const FusedSpec& fs,
+                                             int N, int tiles, int outer, hipStream_t st) {
+  const dim3 grid(tiles, outer, fs.n_items);
+  const bool half = 2 * p.n_in == N && 2 * p.n_out == N;
+  switch (N) {
+#define CASE(NN)                                                                                          \
+  case NN: {                                                                                              \
+    constexpr int E = twostep_E<T, true>(NN);                                                             \
+    if constexpr (E == 0) {                                                                               \
+      return false;                                                                                       \
+    } else {                                                                                              \
+      constexpr int NB = twostep_NB<T, true>();                                                                 \
+      constexpr int NT = (NN / E) * NB;                                                                   \
+      const Cx<T>* i_ = (const Cx<T>*)in;                                                                 \
+      Cx<T>* o_ = (Cx<T>*)out;                                                                            \
+      if (p.outer_len > 1) {                                                                              \
+        constexpr bool MIR = DT_FUSED_MIRROR != 0;                                                          \
+        const dim3 gm(tiles, MIR ? p.outer_len / 2 + 1 : p.outer_len, fs.n_items);                          \
+        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, E, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
+        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, E, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
+      } else if (half) hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, true>), grid, dim3(NT), 0, st, i_, o_, p, fs); \
+      else hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, false>), grid, dim3(NT), 0, st, i_, o_, p, fs);            \
+      return true;                                                                                        \
+    }                                                                                                     \
+  }
+    DT_FOR_EACH_COL2_N(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+template bool launch_col2_c2c<float>(const void*, void*, const ColParams&, int, int, int, int, int, hipStream_t);
+template bool launch_col2_c2c<double>(const void*, void*, const ColParams&, int, int, int, int, int, hipStream_t);
+template bool launch_col2_fused<float>(const void*, void*, const ColParams&, const FusedSpec&, int, int, int,
+                                       hipStream_t);
+template bool launch_col2_fused<double>(const void*, void*, const ColParams&, const FusedSpec&, int, int, int,
+                                        hipStream_t);
+
+}  // namespace dt

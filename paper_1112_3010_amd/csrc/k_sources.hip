@@ -333,15 +333,22 @@ __global__ void __launch_bounds__(256) k_tab_axis(TabGeom tg, int axis, int odd,
   out[i] = acc;
 }
 
+// Store in the tile-major layout read by the fused pass: element (x, y, z)
+// of the folded range goes to ((outer * tiles + x / nb) * H_line + line) * nb + x % nb
+// with (line, outer) = (z, y) in 3D and (y, -) in 2D.
 template <typename T>
 __global__ void __launch_bounds__(256) k_tab_store(TabGeom tg, const double* __restrict__ in, double scale,
-                                                   T* __restrict__ out, int64_t pitch) {
+                                                   T* __restrict__ out, int nb, int tiles) {
   const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int64_t x = i % tg.H[0];
-  const int64_t row = i / tg.H[0];
-  out[row * pitch + x] = (T)(in[i] * scale);
+  const int64_t y = (i / tg.H[0]) % tg.H[1];
+  const int64_t z = i / ((int64_t)tg.H[0] * tg.H[1]);
+  const int64_t line = tg.ndim == 3 ? z : y;
+  const int64_t outer = tg.ndim == 3 ? y : 0;
+  const int64_t H_line = tg.ndim == 3 ? tg.H[2] : tg.H[1];
+  out[((outer * tiles + x / nb) * H_line + line) * nb + x % nb] = (T)(in[i] * scale);
 }
 
 int launch_tab_sample(const TabKernel& kd, const TabGeom& tg, double* out, double* partials, hipStream_t st) {
@@ -357,13 +364,13 @@ void launch_tab_axis(const TabGeom& tg, int axis, int odd, const void* trig, con
   hipLaunchKernelGGL(k_tab_axis, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tg, axis, odd,
                      (const double2*)trig, in, out);
 }
-template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out,
-                                            int64_t pitch, hipStream_t st) {
+template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out, int nb,
+                                            int tiles, hipStream_t st) {
   const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
   hipLaunchKernelGGL(k_tab_store<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tg, in, scale, out,
-                     pitch);
+                     nb, tiles);
 }
-template void launch_tab_store<float>(const TabGeom&, const double*, double, float*, int64_t, hipStream_t);
-template void launch_tab_store<double>(const TabGeom&, const double*, double, double*, int64_t, hipStream_t);
+template void launch_tab_store<float>(const TabGeom&, const double*, double, float*, int, int, hipStream_t);
+template void launch_tab_store<double>(const TabGeom&, const double*, double, double*, int, int, hipStream_t);
 
 }  // namespace dt

@@ -15,7 +15,7 @@
 using namespace dt;
 
 namespace dt {
-int col_tile_width(int N, bool fp64);
+int col_tile_width(int N, bool fp64, bool fused);
 }
 
 namespace {
@@ -63,7 +63,8 @@ struct dt_plan_s {
   bool fp64 = false;
   size_t w = 4;          // bytes per real
   int Mh = 0, MhP = 0;   // half spectrum length and pitch along x
-  int NB = 16;           // column tile width
+  int NB = 16;           // column tile width (the half-spectrum pitch is a multiple of it)
+  int NBf = 16;          // tile width of the fused pass (kernel tables are laid out for it)
   std::vector<Table> tabs;
   int t_f = -1, t_u[3] = {-1, -1, -1}, t_h[6] = {-1, -1, -1, -1, -1, -1}, t_sign[3] = {-1, -1, -1}, t_rf = -1;
   int e_sign_tab = 0;
@@ -272,9 +273,12 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   p->fp64 = precision == DT_FP64;
   p->w = p->fp64 ? 8 : 4;
   p->Mh = (int)(p->M[0] / 2 + 1);
-  p->NB = col_tile_width((int)p->M[1], p->fp64);
-  for (int a = 2; a < ndim; ++a) p->NB = std::max(p->NB, col_tile_width((int)p->M[a], p->fp64));
+  // the half-spectrum pitch is a multiple of every column tile width
+  p->NB = 1;
+  for (int a = 1; a < ndim; ++a)
+    for (int fused = 0; fused < 2; ++fused) p->NB = std::max(p->NB, col_tile_width((int)p->M[a], p->fp64, fused));
   p->MhP = (p->Mh + p->NB - 1) / p->NB * p->NB;
+  p->NBf = col_tile_width((int)p->M[ndim - 1], p->fp64, true);
 
   // kernel tables
   const int D = ndim;
@@ -462,7 +466,7 @@ template <typename T> dt_status build_tables(dt_plan p, hipStream_t st) {
       std::swap(cur, nxt);
     }
     const double scale = std::ldexp(1.0, -t.e) / p->npad();
-    launch_tab_store<T>(tg, cur, scale, (T*)(p->ws + p->off_tabs + t.off), p->MhP, st);
+    launch_tab_store<T>(tg, cur, scale, (T*)(p->ws + p->off_tabs + t.off), p->NBf, p->MhP / p->NBf, st);
   }
   if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
   return hip_status(hipGetLastError());
@@ -517,8 +521,8 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t My = p->M[1];
   const int MhP = p->MhP;
-  auto tiles_for = [&](int64_t len) {
-    const int nb = col_tile_width((int)len, p->fp64);
+  auto tiles_for = [&](int64_t len, bool fused) {
+    const int nb = col_tile_width((int)len, p->fp64, fused);
     return (p->Mh + nb - 1) / nb;
   };
   RowParams rp{};
@@ -538,7 +542,7 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     cp.inner = p->Mh; cp.n_in = (int)ny; cp.n_out = (int)ny; cp.outer_len = 1;
     cp.tw = p->ws + p->off_tw[1]; cp.tw_stride = 1;
     PassTimer t(p, st, "col_fused");
-    if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My), 1, st)) return DT_E_UNSUPPORTED;
+    if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My, true), 1, st)) return DT_E_UNSUPPORTED;
   } else {
     const int64_t Mz = p->M[2];
     ColParams c2{};
@@ -548,7 +552,7 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     c2.tw = p->ws + p->off_tw[1]; c2.tw_stride = 1;
     {
       PassTimer t(p, st, "col_fwd_y");
-      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My), (int)nz, n_in, st))
+      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My, false), (int)nz, n_in, st))
         return DT_E_UNSUPPORTED;
     }
     ColParams c3{};
@@ -558,7 +562,7 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     c3.tw = p->ws + p->off_tw[2]; c3.tw_stride = 1;
     {
       PassTimer t(p, st, "col_fused");
-      if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz), (int)My, st))
+      if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz, true), (int)My, st))
         return DT_E_UNSUPPORTED;
     }
     ColParams c4{};
@@ -568,11 +572,30 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     c4.tw = p->ws + p->off_tw[1]; c4.tw_stride = 1;
     {
       PassTimer t(p, st, "col_inv_y");
-      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My), (int)nz, n_out, st))
+      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My, false), (int)nz, n_out, st))
         return DT_E_UNSUPPORTED;
     }
   }
   return DT_OK;
+}
+
+#ifndef DT_FUSED_SLICE
+#define DT_FUSED_SLICE 0   // output channels per block column of the fused pass (0 = all)
+#endif
+// Work items of the fused pass: mode-0 groups are split into slices of
+// DT_FUSED_SLICE outputs (each block recomputes the forward transform of its
+// column, which keeps its register footprint that of a single transform).
+void fill_items(FusedSpec& fs, int slice) {
+  fs.n_items = 0;
+  for (int g = 0; g < fs.n_groups; ++g) {
+    const FusedGroup& G = fs.g[g];
+    if (G.mode == 1 || slice <= 0) {
+      fs.items[fs.n_items++] = {g, 0, G.mode == 1 ? 1 : G.n_out};
+      continue;
+    }
+    for (int c = 0; c < G.n_out; c += slice)
+      fs.items[fs.n_items++] = {g, c, std::min(G.n_out, c + slice)};
+  }
 }
 
 void fill_tabrefs(dt_plan p, FusedSpec& fs) {
@@ -584,14 +607,11 @@ void fill_tabrefs(dt_plan p, FusedSpec& fs) {
     r.odd_line = p->tabs[t].par[line_axis];
     r.odd_outer = p->ndim == 3 ? p->tabs[t].par[1] : 0;
   }
-  const int64_t H1 = p->M[1] / 2 + 1;
-  if (p->ndim == 3) {
-    fs.tab_line_stride = H1 * p->MhP;
-    fs.tab_outer_stride = p->MhP;
-  } else {
-    fs.tab_line_stride = p->MhP;
-    fs.tab_outer_stride = 0;
-  }
+  const int64_t H_line = p->M[p->ndim - 1] / 2 + 1;
+  const int64_t tiles = p->MhP / p->NBf;
+  fs.tab_line_stride = p->NBf;
+  fs.tab_tile_stride = H_line * p->NBf;
+  fs.tab_outer_stride = p->ndim == 3 ? tiles * H_line * p->NBf : 0;
 }
 
 template <typename T>
@@ -712,6 +732,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
     ep.scale_mu = std::ldexp(1.0, e_s + p->e_sign_tab);
   }
   fs.n_groups = gi;
+  fill_items(fs, DT_FUSED_SLICE);
 
   dt_status s = run_passes<T>(p, n_in, fs, n_out, st);
   if (s != DT_OK) return s;
@@ -790,6 +811,7 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
   }
   Gr.out_ch[D] = D;
   Gr.tab[D] = p->t_rf;
+  fill_items(fs, DT_FUSED_SLICE);
   dt_status s = run_passes<T>(p, 1, fs, D + 1, st);
   if (s != DT_OK) return s;
   GatherParams gp{};
