@@ -427,11 +427,22 @@ template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p
   if (threads > 1024) return false;
   const int64_t blocks = (e.n_rows + rpb - 1) / rpb;
   const size_t shmem = (size_t)rpb * e.C * (N + 1) * sizeof(Cx<T>);
-  if (shmem > 65536) return false;
+  // Beyond 64 KiB (long float64 rows with many channels) the kernel needs the
+  // larger per-workgroup LDS of gfx950, granted per kernel.
+  int dev = 0, lds_max = 65536;
+  if (shmem > 65536) {
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return false;
+    if (shmem > (size_t)lds_max) return false;
+  }
   if (blocks <= 0) return true;
   switch (N) {
 #define CASE(NN)                                                                                         \
   case NN:                                                                                               \
+    if (shmem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_c2r_epi<T, NN>),      \
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) \
+      return false;                                                                                      \
     hipLaunchKernelGGL((k_row_c2r_epi<T, NN>), dim3((unsigned)blocks), dim3(threads), shmem, st,         \
                        (const Cx<T>*)in, p, e);                                                          \
     return true;

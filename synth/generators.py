@@ -229,10 +229,11 @@ def jittered_sphere_points(k: int, radius: float, jitter: float, seed: int,
 
 
 def ellipsoid_target(n: int, seed: int, n_samples: int = 200_000,
-                     axes_range=(0.2, 0.35), centre=(0.5, 0.5, 0.5)) -> np.ndarray:
+                     axes_range=(0.2, 0.35), centre=(0.5, 0.5, 0.5), cells=None) -> np.ndarray:
     """Unsigned distance on the n^3 cell-centred grid of [0,1]^3 to a random
     ellipsoid (axes U[axes_range], random rotation), approximated by the
-    nearest of ``n_samples`` surface samples.  Returns float32 [z][y][x]."""
+    nearest of ``n_samples`` surface samples.  Returns float32 [z][y][x], or
+    the values at the given flat node indices (x fastest) when ``cells`` is set."""
     from scipy.spatial import cKDTree
     rng = _rng(seed)
     axes = rng.uniform(axes_range[0], axes_range[1], size=3)
@@ -244,6 +245,11 @@ def ellipsoid_target(n: int, seed: int, n_samples: int = 200_000,
     u /= np.linalg.norm(u, axis=1, keepdims=True)
     surf = np.asarray(centre) + (u * axes) @ q.T
     tree = cKDTree(surf)
+    if cells is not None:
+        cells = np.asarray(cells, dtype=np.int64)
+        ijk = np.stack([cells % n, (cells // n) % n, cells // (n * n)], axis=1)
+        dist, _ = tree.query((ijk + 0.5) / n, k=1, workers=-1)
+        return dist.astype(np.float32)
     c = (np.arange(n) + 0.5) / n
     zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
     X = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)

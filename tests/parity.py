@@ -18,8 +18,19 @@ TOL_S_TAU = 0.02            # |dS| <= 0.02 tau
 TOL_GRAD = 0.02             # per component
 TOL_HESS = 0.05             # times (1/tau + 1/h_min)
 TOL_MU = 1e-3
-TOL_S_TAU_FP64 = 1e-8       # float64 path: |dS| <= 1e-8 tau on deep-valid nodes
+TOL_S_TAU_FP64 = 1e-8       # float64 path, far above the validity threshold
 TOL_GRAD_FP64 = 1e-8
+# The float64 path's absolute error in phi is a few units of roundoff of the
+# convolution; relative to phi it grows as Theta/phi.  The float64 bounds
+# therefore allow TOL_THETA_FRAC * Theta/phi on top of the flat term: at the
+# threshold that is the float32 tolerance, far above it the flat term rules.
+TOL_THETA_FRAC = 0.02
+
+
+def bound(ref, flat, scale=1.0):
+    """Per-node absolute bound for the float64 path: scale*(flat + frac*Theta/phi)."""
+    ratio = np.exp(np.log(ref["theta"]) - ref["lnphi"])
+    return scale * (flat + TOL_THETA_FRAC * ratio)
 
 
 def padded(n):
@@ -46,6 +57,7 @@ def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=Fa
     lnphi = f["lnphi"]
     out = {
         "S_exact": f["S"],
+        "lnphi": lnphi,
         "S_ref": np.minimum(f["S"], smax),
         "R": f["R"],
         "valid": lnphi >= np.log(theta),
