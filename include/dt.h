@@ -196,6 +196,92 @@ dt_status dt_plan_set_timing(dt_plan plan, int enable);
 dt_status dt_plan_timings(dt_plan plan, dt_pass_timing* out, int max_entries, int* n_entries);
 dt_status dt_plan_reset_timings(dt_plan plan);
 
+/* ------------------------------------------------------------------------
+ * Batched 2D distance fields (many independent instances per call)
+ *
+ * Each instance is its own 2D problem (dims, spacing, origin, tau) with its
+ * own sources; S and grad S are those of eqs. STilde and SxSyconv per
+ * instance, exactly as dt_gradient would give them except for the padding:
+ * every axis is padded to M = 2 s with s the smallest 2^a 3^b 5^c 7^d >= n,
+ * which still gives the linear convolution (Table 1 with M >= 2n - 1).  The
+ * validity threshold uses each instance's own N_pad, ||f||_1 and ||g||_2.
+ * One call launches each pass once for all instances (the blocks of a pass
+ * are a list of (instance, rows or kx bins) items) so that small instances
+ * share the chip; the launch sequence can be captured once into a HIP graph
+ * and replayed.
+ *
+ * Sources: Y packs every instance's points (float32, x then y), instance i
+ *   owning rows [K_offsets[i], K_offsets[i+1]) (K_offsets: host array of
+ *   n_inst + 1 nondecreasing values, K_offsets[0] = 0).  An instance with no
+ *   sources gets S = +inf and zero gradient.  Out-of-grid or non-finite
+ *   sources are skipped and set the sticky error (dt_batch_last_error).
+ * Outputs: S packs the instances' [ny][nx] fields back to back, instance i
+ *   at node_offset(i) = sum_{j<i} nx_j ny_j; grad packs [2][ny][nx] per
+ *   instance at 2 node_offset(i).  Both have the plan's working type.
+ * Memory: the caller provides the workspace (dt_batch_workspace_size) and
+ *   all inputs and outputs; the library allocates no device memory.  With
+ *   graph replay enabled, one non-blocking stream (default priority) and
+ *   the graph itself are created on the first call and kept by the plan.
+ * ------------------------------------------------------------------------ */
+typedef struct dt_batch_plan_s* dt_batch_plan;
+
+typedef struct {
+  int64_t dims[2];     /* nx, ny (2 .. 1024) */
+  double spacing[2];   /* hx, hy > 0 */
+  double origin[2];
+  double tau;          /* > 0, physical units */
+} dt_instance_desc;
+
+typedef struct {
+  int64_t padded[2];     /* M_x, M_y */
+  int64_t node_offset;   /* offset of the instance in the packed S */
+  int64_t total_nodes;   /* length of the packed S */
+  int precision;
+  double kernel_l1;      /* ||f||_1 over the instance's padded grid */
+} dt_batch_instance_info_t;
+
+/* Launch shape of the batched passes: column tile width (kx bins per block)
+ * and threads per block of the column pass and of the two row passes. */
+typedef struct {
+  int col_nb;
+  int col_threads;   /* 64 .. 1024 */
+  int row_threads;   /* 64 .. 512 */
+} dt_batch_tiles;
+
+/* precision: DT_FP32_SCALED or DT_FP64; out_mask: DT_OUT_S and/or
+ * DT_OUT_GRAD; c_theta <= 0 selects 1024.  DT_E_UNSUPPORTED for n > 1024. */
+dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const dt_instance_desc* inst, int precision,
+                               unsigned out_mask, double c_theta);
+dt_status dt_batch_workspace_size(dt_batch_plan plan, size_t* bytes);
+/* Attaches the workspace (>= the size above, 256-byte aligned), builds the
+ * kernel spectra of every distinct geometry and the default tiles;
+ * synchronises the stream. */
+dt_status dt_batch_set_workspace(dt_batch_plan plan, void* dev_ptr, size_t bytes, void* stream);
+dt_status dt_batch_instance_info(dt_batch_plan plan, int i, dt_batch_instance_info_t* info);
+/* Tiles: DT_E_UNSUPPORTED (previous tiles kept) when a pass would exceed
+ * 32 elements per thread or the device's LDS per block. */
+dt_status dt_batch_set_tiles(dt_batch_plan plan, const dt_batch_tiles* tiles);
+dt_status dt_batch_get_tiles(dt_batch_plan plan, dt_batch_tiles* tiles);
+/* enable != 0: calls capture their launch sequence into a HIP graph the
+ * first time and replay it while Y, S, grad and K_offsets are unchanged. */
+dt_status dt_batch_set_graph(dt_batch_plan plan, int enable);
+/* S and/or grad (device, packed as above) as the plan's out_mask requests.
+ * When K_offsets differ from the previous call they are copied to the
+ * workspace first (a synchronous host-to-device copy). */
+dt_status dt_forward_batched(dt_batch_plan plan, const float* Y, const int64_t* K_offsets, void* S, void* grad,
+                             void* stream);
+/* Times every feasible tile choice (reps calls each, eager, on `stream`),
+ * keeps the fastest and returns it in *best (may be NULL).  Overwrites S
+ * and grad.  Synchronises the stream. */
+dt_status dt_batch_autotune(dt_batch_plan plan, const float* Y, const int64_t* K_offsets, void* S, void* grad,
+                            int reps, void* stream, dt_batch_tiles* best);
+/* Synchronises the plan's stream; returns and clears the sticky error. */
+dt_status dt_batch_last_error(dt_batch_plan plan);
+/* Validity scalars (theta, s_max, g_l2) of instance i from the last call;
+ * synchronises the plan's stream. */
+dt_status dt_batch_stats(dt_batch_plan plan, int i, dt_call_stats* stats);
+dt_status dt_destroy_batch_plan(dt_batch_plan plan);
+
 const char* dt_status_str(dt_status status);
 
 #ifdef __cplusplus

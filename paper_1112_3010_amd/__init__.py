@@ -10,5 +10,6 @@ library libdt.so (C ABI in include/dt.h); this package is its binding.
 
 from ._lib import DtError, load as load_library  # noqa: F401
 from .field import Plan, DistanceField, distance_field  # noqa: F401
+from .batch import BatchPlan  # noqa: F401
 
-__all__ = ["Plan", "DistanceField", "distance_field", "DtError", "load_library"]
+__all__ = ["Plan", "BatchPlan", "DistanceField", "distance_field", "DtError", "load_library"]

@@ -23,6 +23,9 @@ EXPORTED = (
     "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_info", "dt_destroy_plan",
     "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
     "dt_last_error", "dt_last_stats", "dt_plan_set_timing", "dt_plan_timings", "dt_plan_reset_timings",
+    "dt_create_batch_plan", "dt_batch_workspace_size", "dt_batch_set_workspace", "dt_batch_instance_info",
+    "dt_batch_set_tiles", "dt_batch_get_tiles", "dt_batch_set_graph", "dt_forward_batched", "dt_batch_autotune",
+    "dt_batch_last_error", "dt_batch_stats", "dt_destroy_batch_plan",
     "dt_status_str",
 )
 
@@ -82,6 +85,29 @@ class DtPassTiming(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class DtInstanceDesc(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int64 * 2),
+        ("spacing", ctypes.c_double * 2),
+        ("origin", ctypes.c_double * 2),
+        ("tau", ctypes.c_double),
+    ]
+
+
+class DtBatchInstanceInfo(ctypes.Structure):
+    _fields_ = [
+        ("padded", ctypes.c_int64 * 2),
+        ("node_offset", ctypes.c_int64),
+        ("total_nodes", ctypes.c_int64),
+        ("precision", ctypes.c_int),
+        ("kernel_l1", ctypes.c_double),
+    ]
+
+
+class DtBatchTiles(ctypes.Structure):
+    _fields_ = [("col_nb", ctypes.c_int), ("col_threads", ctypes.c_int), ("row_threads", ctypes.c_int)]
+
+
 class DtError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -118,6 +144,20 @@ def load():
     lib.dt_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.dt_plan_timings.argtypes = [vp, ctypes.POINTER(DtPassTiming), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dt_plan_reset_timings.argtypes = [vp]
+    lib.dt_create_batch_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(DtInstanceDesc),
+                                         ctypes.c_int, ctypes.c_uint, dbl]
+    lib.dt_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dt_batch_set_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.dt_batch_instance_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(DtBatchInstanceInfo)]
+    lib.dt_batch_set_tiles.argtypes = [vp, ctypes.POINTER(DtBatchTiles)]
+    lib.dt_batch_get_tiles.argtypes = [vp, ctypes.POINTER(DtBatchTiles)]
+    lib.dt_batch_set_graph.argtypes = [vp, ctypes.c_int]
+    lib.dt_forward_batched.argtypes = [vp, vp, ctypes.POINTER(i64), vp, vp, vp]
+    lib.dt_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(i64), vp, vp, ctypes.c_int, vp,
+                                      ctypes.POINTER(DtBatchTiles)]
+    lib.dt_batch_last_error.argtypes = [vp]
+    lib.dt_batch_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(DtCallStats)]
+    lib.dt_destroy_batch_plan.argtypes = [vp]
     lib.dt_status_str.argtypes = [st]
     lib.dt_status_str.restype = ctypes.c_char_p
     for name in EXPORTED:

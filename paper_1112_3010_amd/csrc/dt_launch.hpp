@@ -2,6 +2,8 @@
 // family).  All launches are asynchronous on the given stream.
 #pragma once
 
+#include <vector>
+
 #include "dt_internal.hpp"
 
 namespace dt {
@@ -28,6 +30,9 @@ struct TabGeom {
   int H[3];       // folded lengths M/2 + 1 (1 for an absent axis)
   double h[3];
 };
+
+// Host: exp(-2 pi i m / M) for m < M as interleaved (re, im) float64.
+void make_twiddles(int M, std::vector<double>& out);
 
 template <typename T> void launch_fill_zero(T* p, int64_t n, hipStream_t st);
 template <typename T> void launch_splat_points(const float* Y, int64_t K, const GridGeom& g, T* cnt, T cval,

@@ -1,0 +1,133 @@
+// Runtime mixed-radix FFT in LDS for the batched path (gfx950).
+//
+// Batched instances have padded lengths that are 7-smooth (2^a 3^b 5^c 7^d)
+// rather than powers of two, and their lengths differ inside one launch, so
+// the radix schedule is a runtime list (radices 8, 4, 2, 7, 5, 3).  A block
+// holds L independent lines of length N in LDS; element i of line l sits at
+// lds[i * istride + l * lstride].  Each stage is a self-sorting (Stockham,
+// decimation in time) pass: butterfly j (k = j mod Ns, Ns = product of the
+// earlier radices) reads x[j + r N/R], multiplies input r by W_(Ns R)^(k r),
+// does a size-R DFT and writes X[(j / Ns) Ns R + k + r Ns].  All butterflies
+// of a stage are read into registers before any result is written back, so
+// one LDS buffer suffices (two barriers per stage).
+#pragma once
+
+#include "fft_engine.hpp"
+#include "fft_twostep.hpp"
+
+namespace dt {
+
+constexpr int kMixedMaxStages = 12;
+
+struct MixedPlan {
+  int n_st;
+  int radix[kMixedMaxStages];
+};
+
+// Size-3/5/7 DFTs: pair inputs j and R-j, X_k = x0 + sum_j a_j cos(2 pi j k/R)
+// - i DIR sum_j b_j sin(2 pi j k/R) with a_j = x_j + x_(R-j), b_j = x_j - x_(R-j);
+// X_(R-k) takes the opposite sign of the sine part.
+template <int R, int DIR, typename V> __device__ __forceinline__ void dft_odd(V* x) {
+  using T = decltype(V::x);
+  constexpr int H = (R - 1) / 2;
+  V a[H], b[H];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    a[j - 1] = cadd(x[j], x[R - j]);
+    b[j - 1] = csub(x[j], x[R - j]);
+  }
+  V x0 = x[0];
+  V s0 = x0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) s0 = cadd(s0, a[j]);
+  V out[R];
+  out[0] = s0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    V A = x0, B = mk<V>(T(0), T(0));
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const T c = (T)ct_cos2pi((long)j * k, R);
+      const T s = (T)ct_sin2pi((long)j * k, R);
+      A = mk<V>(A.x + c * a[j - 1].x, A.y + c * a[j - 1].y);
+      B = mk<V>(B.x + s * b[j - 1].x, B.y + s * b[j - 1].y);
+    }
+    // -i * DIR * B = DIR * (B.y, -B.x)
+    const V mb = DIR > 0 ? mk<V>(B.y, -B.x) : mk<V>(-B.y, B.x);
+    out[k] = cadd(A, mb);
+    out[R - k] = csub(A, mb);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = out[r];
+}
+
+template <int R, int DIR, typename V> __device__ __forceinline__ void dft_small(V* x) {
+  if constexpr (R == 2 || R == 4 || R == 8) Bfly<R, DIR, V>::run(x);
+  else dft_odd<R, DIR, V>(x);
+}
+
+// One Stockham stage of radix R over all L lines.  ECAP bounds the elements a
+// thread holds: the caller guarantees N * L <= ECAP * nthr.
+template <typename T, int DIR, int R, int ECAP, bool LINE_FAST>
+__device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istride, int lstride, int Ns,
+                                            const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
+  using V = Cx<T>;
+  constexpr int BM = (ECAP + R - 1) / R;
+  const int nbf = N / R;
+  const int total = nbf * L;
+  const int tstep = (N / (Ns * R)) * twstride;   // twiddle index step per unit of k * r
+  V v[BM][R];
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    const int u = tid + b * nthr;
+    if (u < total) {
+      const int l = LINE_FAST ? u % L : u / nbf;
+      const int j = LINE_FAST ? u / L : u % nbf;
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = lds[(j + r * nbf) * istride + l * lstride];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], twiddle<DIR>(tw, k * r * tstep));
+      }
+      dft_small<R, DIR>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    const int u = tid + b * nthr;
+    if (u < total) {
+      const int l = LINE_FAST ? u % L : u / nbf;
+      const int j = LINE_FAST ? u / L : u % nbf;
+      const int k = j % Ns;
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(base + r * Ns) * istride + l * lstride] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of L lines held in LDS (natural order in and out).  The
+// caller must have synchronised after filling LDS; on return the results are
+// visible to the whole block.  tw holds exp(-2 pi i m / (N * twstride)).
+template <typename T, int DIR, int ECAP, bool LINE_FAST>
+__device__ void mixed_fft(Cx<T>* lds, int N, int L, int istride, int lstride, const MixedPlan& mp,
+                          const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
+  int Ns = 1;
+  for (int s = 0; s < mp.n_st; ++s) {
+    const int R = mp.radix[s];
+    switch (R) {
+      case 8: mixed_stage<T, DIR, 8, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      case 4: mixed_stage<T, DIR, 4, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      case 2: mixed_stage<T, DIR, 2, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      case 7: mixed_stage<T, DIR, 7, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      case 5: mixed_stage<T, DIR, 5, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      default: mixed_stage<T, DIR, 3, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace dt

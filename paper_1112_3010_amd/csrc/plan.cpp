@@ -145,8 +145,10 @@ struct PassTimer {
   }
 };
 
+}  // namespace
+
 // Twiddles exp(-2 pi i m / M) in float64 with octant reduction of the angle.
-void make_twiddles(int M, std::vector<double>& out) {
+void dt::make_twiddles(int M, std::vector<double>& out) {
   out.resize(2 * (size_t)M);
   for (int m = 0; m < M; ++m) {
     // angle = 2 pi m / M; reduce to [0, pi/4] by symmetry for accuracy
@@ -174,6 +176,8 @@ void make_twiddles(int M, std::vector<double>& out) {
     out[2 * (size_t)m + 1] = -s;
   }
 }
+
+namespace {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 

@@ -40,15 +40,33 @@ def padded(n):
     return m
 
 
+def smooth7_at_least(n):
+    """Smallest 2^a 3^b 5^c 7^d >= n."""
+    m = max(int(n), 1)
+    while True:
+        r = m
+        for p in (2, 3, 5, 7):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return m
+        m += 1
+
+
+def batch_padded(n):
+    """Padding rule of the batched path: M = 2 s, s the smallest 7-smooth >= n."""
+    return 2 * smooth7_at_least(n)
+
+
 def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=False, cells=None,
-              c_theta=oracle.C_THETA):
+              c_theta=oracle.C_THETA, padded_dims=None):
     """Oracle fields at all nodes (or at the given flat node indices)."""
     D = len(dims)
     idx, valid = oracle.snap(pts, origin, spacing, dims)
     Yh = oracle.node_coords(idx[valid], origin, spacing)
     _, mult = oracle.cell_multiplicities(idx[valid], dims)
     g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
-    Mp = tuple(padded(n) for n in dims)
+    Mp = tuple(padded(n) for n in dims) if padded_dims is None else tuple(padded_dims)
     l1 = oracle.kernel_l1(Mp, spacing, tau)
     theta = oracle.theta(precision, Mp, l1, g_l2, c_theta)
     smax = oracle.s_max(tau, theta)

@@ -1,0 +1,168 @@
+"""GPU parity of the batched 2D path (many instances per call): every
+instance against the oracle with the batched padding rule, graph replay and
+tile choices against the eager default (bitwise), and the 96-instance
+workload on sampled nodes."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1112_3010_amd as dtm
+    dtm.load_library()
+    return dtm
+
+
+SMALL_DIMS = [(97, 130), (128, 128), (37, 200), (250, 64), (500, 300), (12, 9), (64, 64)]
+SMALL_K = [50, 200, 1, 0, 1500, 5, 40]
+
+
+def _small_points():
+    pts = []
+    for i, (dims, K) in enumerate(zip(SMALL_DIMS, SMALL_K)):
+        y = synth.generators.uniform_points(2, K, seed=900 + i) if K else np.zeros((0, 2), np.float32)
+        pts.append(y)
+    return pts
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _cells(dims, pts, n_uniform, n_near, seed):
+    nx, ny = dims
+    rng = np.random.default_rng(seed)
+    a = rng.choice(nx * ny, min(n_uniform, nx * ny), replace=False)
+    if len(pts) == 0:
+        return np.unique(a)
+    idx = np.floor(pts.astype(np.float64) * np.array([nx, ny])).astype(np.int64)
+    pick = idx[rng.integers(0, len(idx), n_near)] + rng.integers(-4, 5, size=(n_near, 2))
+    pick = np.clip(pick, 0, [nx - 1, ny - 1])
+    return np.unique(np.concatenate([a, pick[:, 0] + nx * pick[:, 1]]))
+
+
+def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats):
+    nx, ny = dims
+    h = (1.0 / nx, 1.0 / ny)
+    if len(pts) == 0:
+        assert np.all(np.isinf(S)) and np.all(S > 0), tag
+        assert np.all(G == 0), tag
+        return
+    Mp = (parity.batch_padded(nx), parity.batch_padded(ny))
+    ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, prec, grad=True, cells=cells, padded_dims=Mp)
+    assert stats["theta"] == pytest.approx(ref["theta"], rel=1e-9), tag
+    S = S.ravel()[cells] if cells is not None else S.ravel()
+    g = G.reshape(2, -1)[:, cells] if cells is not None else G.reshape(2, -1)
+    dS = np.abs(S - ref["S_ref"])
+    deep = ref["deep"]
+    dG = np.abs(g - ref["grad"].T)[:, deep]
+    msg = f"[{tag} {prec}] max|dS|/tau={dS.max() / tau:.3e} max|dgrad|={dG.max() if dG.size else 0:.3e}"
+    assert dS.max() <= parity.TOL_S_TAU * tau, msg
+    if dG.size:
+        assert dG.max() <= parity.TOL_GRAD, msg
+    if prec == "fp64":
+        assert np.all(dS[deep] <= parity.bound(ref, parity.TOL_S_TAU_FP64, tau)[deep]), msg
+        assert np.all(dG <= parity.bound(ref, parity.TOL_GRAD_FP64)[deep]), msg
+    inval = ~ref["valid"] & (ref["S_exact"] > ref["s_max"] + 0.05 * tau)
+    assert np.all(g[:, inval] == 0), msg
+    return msg
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_small_against_oracle(dt, prec):
+    pts = _small_points()
+    taus = [2.0 / d[0] for d in SMALL_DIMS]
+    plan = dt.BatchPlan(SMALL_DIMS, taus, precision=prec, graph=False)
+    for i, (nx, ny) in enumerate(SMALL_DIMS):
+        assert plan.padded(i) == (parity.batch_padded(nx), parity.batch_padded(ny))
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    S, G = plan.forward(Y.cuda(), offs)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    for i, (dims, tau) in enumerate(zip(SMALL_DIMS, taus)):
+        s, g = plan.views(S, G)[i]
+        cells = None if dims[0] * dims[1] <= 40000 else _cells(dims, pts[i], 2000, 2000, 950 + i)
+        msg = _check_instance(f"inst {i} {dims} K={len(pts[i])}", prec, dims, tau, pts[i], _np(s), _np(g), cells,
+                              plan.stats(i))
+        if msg:
+            print("\n" + msg, flush=True)
+
+
+def test_batch_graph_replay_and_tiles_bitwise(dt):
+    pts = _small_points()
+    taus = [2.0 / d[0] for d in SMALL_DIMS]
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    Y = Y.cuda()
+    plan = dt.BatchPlan(SMALL_DIMS, taus, precision="fp32", graph=False)
+    S0, G0 = plan.forward(Y, offs)
+    torch.cuda.synchronize()
+    # tile choices change only which block handles which rows / kx bins
+    for t in [(1, 256, 128), (4, 512, 512), (16, 512, 256), (2, 1024, 64)]:
+        plan.set_tiles(*t)
+        S1, G1 = plan.forward(Y, offs)
+        torch.cuda.synchronize()
+        assert torch.equal(S1, S0) and torch.equal(G1, G0), t
+    # graph replays, with eager work and synchronisation between them
+    plan.set_graph(True)
+    S2, G2 = plan.empty_outputs()
+    for rep in range(4):
+        plan.forward_into(Y, offs, S2, G2)
+        junk = (S0 * 2.0).sum()
+        torch.cuda.synchronize()
+        assert torch.equal(S2, S0) and torch.equal(G2, G0), rep
+        S2.fill_(-1.0)
+        G2.fill_(-1.0)
+        del junk
+    # a new output buffer makes a new graph
+    S3, G3 = plan.forward(Y, offs)
+    torch.cuda.synchronize()
+    assert torch.equal(S3, S0) and torch.equal(G3, G0)
+    assert plan.last_error() == 0
+
+
+def test_batch_out_of_grid_source(dt):
+    dims = [(64, 48), (40, 40)]
+    pts = [synth.generators.uniform_points(2, 30, seed=960), synth.generators.uniform_points(2, 20, seed=961)]
+    bad = np.concatenate([pts[1], np.array([[1.5, 0.5]], np.float32)])
+    plan = dt.BatchPlan(dims, [2.0 / 64, 2.0 / 40], precision="fp64", graph=False)
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(pts[0]), torch.from_numpy(bad)])
+    S, G = plan.forward(Y.cuda(), offs)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 2
+    assert plan.last_error() == 0
+    for i in range(2):
+        s, g = plan.views(S, G)[i]
+        _check_instance(f"inst {i}", "fp64", dims[i], 2.0 / dims[i][0], pts[i], _np(s), _np(g), None, plan.stats(i))
+
+
+def test_batch_96_instances(dt):
+    inst = synth.workload("c4_batch_2d").extra["instances"]
+    dims = [(n, n) for n, _ in inst]
+    taus = [2.0 / n for n, _ in inst]
+    plan = dt.BatchPlan(dims, taus, precision="fp32", graph=True)
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(y) for _, y in inst])
+    Y = Y.cuda()
+    S, G = plan.forward(Y, offs)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    tiles = plan.autotune(Y, offs, reps=1, cache=False)
+    S1, G1 = plan.forward(Y, offs)
+    torch.cuda.synchronize()
+    assert torch.equal(S1, S) and torch.equal(G1, G), tiles
+    worst = 0.0
+    for i, ((n, y), tau) in enumerate(zip(inst, taus)):
+        s, g = plan.views(S, G)[i]
+        cells = _cells((n, n), y, 24, 24, 970 + i)
+        _check_instance(f"c4 inst {i} n={n} K={len(y)}", "fp32", (n, n), tau, y, _np(s), _np(g), cells,
+                        plan.stats(i))
+    print(f"\n[batch 96] tuned tiles {tiles}; all instances within tolerance", flush=True)
