@@ -166,9 +166,11 @@ template <typename T, int N, int E> struct ThreadTwiddles {
   }
 };
 
-template <typename T, int N, int E, int NB> struct TwoStep {
+template <typename T, int N, int E_, int NB> struct TwoStep {
   using V = Cx<T>;
+  static constexpr int E = E_;
   static constexpr int P = N / E;
+  using Tw = ThreadTwiddles<T, N, E>;
   static_assert(E >= P && E % P == 0, "each thread must own whole second-step DFTs");
   static constexpr int PAD = 16;                           // LDS padding (complex) per row group
   static constexpr int LDS_F = E * (P * NB + PAD);         // forward exchange footprint
@@ -214,6 +216,66 @@ template <typename T, int N, int E, int NB> struct TwoStep {
     RegDFT<E, -1, V>::run(v);
   }
 
+  // Same transforms with the LDS exchange done in two rounds (real parts,
+  // then imaginary parts) through a real buffer of LDS elements: half the
+  // LDS footprint for two more barriers.
+  static __device__ __forceinline__ void exchange_f(V* v, T* ldsr, int p, int b) {
+    constexpr int RS = P * NB + PAD;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) ldsr[k * RS + p * NB + b] = v[k].x;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) v[t * P + pp].x = ldsr[(p + P * t) * RS + pp * NB + b];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) ldsr[k * RS + p * NB + b] = v[k].y;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp) v[t * P + pp].y = ldsr[(p + P * t) * RS + pp * NB + b];
+  }
+  static __device__ __forceinline__ void forward_split(V* v, T* ldsr, int p, int b,
+                                                       const ThreadTwiddles<T, N, E>& tw) {
+    RegDFT<E, +1, V>::run(v);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw.get(k));
+    exchange_f(v, ldsr, p, b);
+#pragma unroll
+    for (int t = 0; t < E / P; ++t) RegDFT<P, +1, V>::run(&v[t * P]);
+  }
+  static __device__ __forceinline__ void inverse_split(V* v, T* ldsr, int p, int b,
+                                                       const ThreadTwiddles<T, N, E>& tw) {
+    constexpr int RS = E * NB + PAD;
+#pragma unroll
+    for (int t = 0; t < E / P; ++t) RegDFT<P, -1, V>::run(&v[t * P]);
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int n1 = 1; n1 < P; ++n1) v[t * P + n1] = cmul(v[t * P + n1], cconj(tw.get(n1)));
+    apply_const_tw<1>(v);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) ldsr[n1 * RS + (p + P * t) * NB + b] = v[t * P + n1].x;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k].x = ldsr[p * RS + k * NB + b];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < E / P; ++t)
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) ldsr[n1 * RS + (p + P * t) * NB + b] = v[t * P + n1].y;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k].y = ldsr[p * RS + k * NB + b];
+    RegDFT<E, -1, V>::run(v);
+  }
+
   // multiply slot (t, n1) by W_E^(-n1 t) for t >= 1 (compile-time)
   template <int TT> static __device__ __forceinline__ void apply_const_tw(V* v) {
     if constexpr (TT < E / P) {
@@ -230,6 +292,113 @@ template <typename T, int N, int E, int NB> struct TwoStep {
 
   // Spectral index held in forward-output slot (t, k2) of thread p.
   static __device__ __forceinline__ int slot_index(int p, int t, int k2) { return (p + P * t) + E * k2; }
+  static __device__ __forceinline__ int slot(int p, int i) { return slot_index(p, i / P, i % P); }
+};
+
+// ---------------------------------------------------------------------------
+// Pair-split four-step FFT for N = E * P with P = 2E (32, 128, 512, 2048).
+//
+// Thread p < P of a column holds x[p + P e] (e < E).  Step 1: size-E DFT in
+// registers and the thread twiddles W_N^(p k1).  One LDS exchange gives
+// thread q = 2 k1 + h the values of k1 at p = 2m + h (m < E); a size-E DFT
+// over m is half of the size-P DFT over p, and the two halves are joined by
+// one radix-2 step between the lane pair (q, q ^ 1) through cross-lane
+// shuffles:  X[k1 + E j + (N/2) h] = Z_0[j] + (-1)^h W_2E^j Z_1[j].
+// With E = N/P = sqrt(N/2) elements per thread instead of the two-step
+// engine's E >= sqrt(N), the per-thread register footprint halves at
+// N = 512.  The inverse runs the adjoint steps in reverse order and ends
+// with x[p + P e] in registers, so forward outputs are inverse inputs.
+// The exchange is done in two rounds (real, then imaginary parts) through a
+// real LDS buffer of LDS elements.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int pair_E(int N) {
+  return N == 32 ? 4 : N == 128 ? 8 : N == 512 ? 16 : N == 2048 ? 32 : 0;
+}
+
+template <typename T, int N, int NB> struct PairFFT {
+  using V = Cx<T>;
+  static constexpr int E = pair_E(N);
+  static constexpr int P = 2 * E;
+  static_assert(E > 0 && E * P == N, "pair split needs N = 2 E^2");
+  static_assert(NB <= 32 && (NB & (NB - 1)) == 0, "lane pairs (q, q ^ 1) must share a wavefront");
+  static constexpr int PAD = 32;
+  static constexpr int RS = P * NB + PAD;    // reals per k1 row of the exchange buffer
+  static constexpr int LDS = E * RS;         // reals
+  using Tw = ThreadTwiddles<T, N, E>;
+
+  template <int DIR, int J> static __device__ __forceinline__ void pair_twiddle(V* v, bool h) {
+    if constexpr (J < E) {
+      const V w = cmul_w<DIR, J, 2 * E>(v[J]);
+      v[J].x = h ? w.x : v[J].x;    // component-wise: a select of whole structs goes through memory
+      v[J].y = h ? w.y : v[J].y;
+      pair_twiddle<DIR, J + 1>(v, h);
+    }
+  }
+  static __device__ __forceinline__ float lane_xor(float x) { return __shfl_xor(x, NB); }
+  static __device__ __forceinline__ double lane_xor(double x) {
+    const int hi = __shfl_xor(__double2hiint(x), NB);
+    const int lo = __shfl_xor(__double2loint(x), NB);
+    return __hiloint2double(hi, lo);
+  }
+  // v[j] <- Z0 + (-1)^h Z1 where this lane holds Z_h and its partner Z_(1-h)
+  static __device__ __forceinline__ void pair_join(V* v, bool h) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const T ox = lane_xor(v[j].x);
+      const T oy = lane_xor(v[j].y);
+      const T rx = h ? ox - v[j].x : v[j].x + ox;
+      const T ry = h ? oy - v[j].y : v[j].y + oy;
+      v[j].x = rx;
+      v[j].y = ry;
+    }
+  }
+  // (k1, p) -> (p >> 1, 2 m + (p & 1)) for the forward direction; reversed for the inverse
+  template <bool FWD> static __device__ __forceinline__ void exchange(V* v, T* ldsr, int p, int b) {
+    const int rq = (p >> 1) * RS + (p & 1) * NB + b;   // read base of the forward direction
+    const int wp = p * NB + b;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (FWD) ldsr[k * RS + wp] = v[k].x;
+      else ldsr[rq + 2 * k * NB] = v[k].x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k].x = FWD ? ldsr[rq + 2 * k * NB] : ldsr[k * RS + wp];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (FWD) ldsr[k * RS + wp] = v[k].y;
+      else ldsr[rq + 2 * k * NB] = v[k].y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k].y = FWD ? ldsr[rq + 2 * k * NB] : ldsr[k * RS + wp];
+  }
+
+  // Forward: v[e] = x[p + P e] on entry; on exit v[j] = X[slot(p, j)].
+  static __device__ __forceinline__ void forward_split(V* v, T* ldsr, int p, int b, const Tw& tw) {
+    RegDFT<E, +1, V>::run(v);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw.get(k));
+    exchange<true>(v, ldsr, p, b);
+    RegDFT<E, +1, V>::run(v);
+    const bool h = (p & 1) != 0;
+    pair_twiddle<+1, 0>(v, h);
+    pair_join(v, h);
+  }
+  // Inverse (unnormalised): v[j] = X[slot(p, j)] on entry; on exit v[e] = x[p + P e].
+  static __device__ __forceinline__ void inverse_split(V* v, T* ldsr, int p, int b, const Tw& tw) {
+    const bool h = (p & 1) != 0;
+    pair_join(v, h);
+    pair_twiddle<-1, 0>(v, h);
+    RegDFT<E, -1, V>::run(v);
+    exchange<false>(v, ldsr, p, b);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], cconj(tw.get(k)));
+    RegDFT<E, -1, V>::run(v);
+  }
+  static __device__ __forceinline__ int slot(int p, int j) { return (p >> 1) + E * j + (N / 2) * (p & 1); }
 };
 
 }  // namespace dt

@@ -178,24 +178,43 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 // one kx tile at one |ky|) is a contiguous run that is copied with 16-byte
 // loads.  With MIRROR the block owns the column pair (ky, M_y - ky), which
 // share the slice: every folded table entry then serves all four spectral
-// points (+-ky, +-kz) from one read.
-constexpr int kTabChunk = 4;
+// points (+-ky, +-kz) from one read.  The transform engine ENG (TwoStep or
+// PairFFT) exchanges real and imaginary parts in two rounds through a real
+// LDS buffer, and the tables are staged kTabChunk channels at a time, which
+// keeps the block's LDS small enough for two blocks per CU.
+#ifndef DT_TAB_CHUNK
+#define DT_TAB_CHUNK 4
+#endif
+constexpr int kTabChunk = DT_TAB_CHUNK;
 #ifndef DT_FUSED_MIRROR
 #define DT_FUSED_MIRROR 1
 #endif
+#ifndef DT_FUSED_MINWAVES
+#define DT_FUSED_MINWAVES 1
+#endif
+#ifndef DT_FUSED_PAIR
+#define DT_FUSED_PAIR 1
+#endif
 
-template <typename T, int N, int E, int NB, bool HALF, bool MIRROR>
-__global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>* __restrict__ in,
-                                                                   Cx<T>* __restrict__ out, ColParams p,
-                                                                   FusedSpec fs) {
+// The pair-split engine serves the float32 3D fused pass where N = 2 E^2
+// (in float64 its two columns of E complex doubles exceed the register file
+// and the Stockham or two-step kernels are faster).
+template <typename T> constexpr bool fused_pair(int N) {
+  return DT_FUSED_PAIR != 0 && sizeof(T) == 4 && pair_E(N) > 0 && N >= 128 && N <= 512;
+}
+
+template <typename T, int N, class ENG, int NB, bool HALF, bool MIRROR>
+__global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_staged(const Cx<T>* __restrict__ in,
+                                                                                     Cx<T>* __restrict__ out,
+                                                                                     ColParams p, FusedSpec fs) {
   using V = Cx<T>;
-  using TS = TwoStep<T, N, E, NB>;
-  constexpr int P = TS::P;
+  constexpr int E = ENG::E;
+  constexpr int P = ENG::P;
   constexpr int H = N / 2 + 1;                     // folded rows along the transform axis
   constexpr int SLICE = H * NB;                    // table elements per channel slice
   constexpr int SLICE16 = SLICE * (int)sizeof(T) / 16;
   static_assert((SLICE * sizeof(T)) % 16 == 0, "slice must be a whole number of 16-byte words");
-  __shared__ V lds[TS::LDS];
+  __shared__ __align__(16) T xch[ENG::LDS];
   __shared__ __align__(16) T tab_lds[kTabChunk * SLICE];
   const int tid = threadIdx.x;
   constexpr int NT = P * NB;
@@ -213,7 +232,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>*
   }
   const FusedItem& IT = fs.items[blockIdx.z];
   const FusedGroup& G = fs.g[IT.group];
-  ThreadTwiddles<T, N, E> tw;
+  typename ENG::Tw tw;
   tw.load((const V*)p.tw, pt);
 
   // copy the contiguous table slices of tabs[0..nt) into LDS with 16-byte loads
@@ -235,27 +254,25 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>*
       if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
       else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
     }
-    TS::forward(v, lds, pt, b, tw);
+    ENG::forward_split(v, xch, pt, b, tw);
   };
   auto times = [&](int slot, int tab, bool o_neg, const V* v, V* res, bool accumulate) {
     const TabRef& t = fs.tabs[tab];
     const bool flip_o = t.odd_outer && o_neg;
     const T* tl = tab_lds + slot * SLICE + b;
 #pragma unroll
-    for (int tt = 0; tt < E / P; ++tt)
-#pragma unroll
-      for (int k2 = 0; k2 < P; ++k2) {
-        const int l = TS::slot_index(pt, tt, k2);
-        const bool l_neg = 2 * l > N;
-        const int lf = l_neg ? N - l : l;
-        T val = tl[lf * NB];
-        if (flip_o != (t.odd_line && l_neg)) val = -val;
-        const V prod = mul_mi_pow(cscale(v[tt * P + k2], val), t.phase);
-        res[tt * P + k2] = accumulate ? cadd(res[tt * P + k2], prod) : prod;
-      }
+    for (int i = 0; i < E; ++i) {
+      const int l = ENG::slot(pt, i);
+      const bool l_neg = 2 * l > N;
+      const int lf = l_neg ? N - l : l;
+      T val = tl[lf * NB];
+      if (flip_o != (t.odd_line && l_neg)) val = -val;
+      const V prod = mul_mi_pow(cscale(v[i], val), t.phase);
+      res[i] = accumulate ? cadd(res[i], prod) : prod;
+    }
   };
   auto inv_store = [&](V* v, int ch, int o) {
-    TS::inverse(v, lds, pt, b, tw);
+    ENG::inverse_split(v, xch, pt, b, tw);
     if (!active) return;
     V* dst = out + (int64_t)ch * p.out_ch + (int64_t)o * p.out_outer + kx;
 #pragma unroll
@@ -268,23 +285,42 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>*
   auto column = [&](int col) { return MIRROR ? (col == 0 ? of : p.outer_len - of) : (int)blockIdx.y; };
 
   if (G.mode == 0) {
-    for (int c0 = IT.c0; c0 < IT.c1; c0 += kTabChunk) {
-      const int nc = IT.c1 - c0 < kTabChunk ? IT.c1 - c0 : kTabChunk;
-      stage(&G.tab[c0], nc);
+    if (IT.c1 - IT.c0 <= kTabChunk) {
+      // every table of the item fits: stage once for both columns
+      stage(&G.tab[IT.c0], IT.c1 - IT.c0);
       for (int col = 0; col < n_cols; ++col) {
         const int o = column(col);
         const bool o_neg = 2 * o > p.outer_len;
         V spec[E];
         load_fwd(G.in_ch[0], o, spec);
-        for (int c = 0; c < nc; ++c) {
+        for (int c = IT.c0; c < IT.c1; ++c) {
           V v[E];
-          times(c, G.tab[c0 + c], o_neg, spec, v, false);
-          inv_store(v, G.out_ch[c0 + c], o);
+          times(c - IT.c0, G.tab[c], o_neg, spec, v, false);
+          inv_store(v, G.out_ch[c], o);
+        }
+      }
+    } else {
+      // one forward transform per column; the table chunks are restaged per
+      // column (the second time from L2)
+      for (int col = 0; col < n_cols; ++col) {
+        const int o = column(col);
+        const bool o_neg = 2 * o > p.outer_len;
+        V spec[E];
+        load_fwd(G.in_ch[0], o, spec);
+        for (int c0 = IT.c0; c0 < IT.c1; c0 += kTabChunk) {
+          const int nc = IT.c1 - c0 < kTabChunk ? IT.c1 - c0 : kTabChunk;
+          stage(&G.tab[c0], nc);
+          for (int c = 0; c < nc; ++c) {
+            V v[E];
+            times(c, G.tab[c0 + c], o_neg, spec, v, false);
+            inv_store(v, G.out_ch[c0 + c], o);
+          }
         }
       }
     }
   } else {
-    stage(G.tab, G.n_in);
+    const bool once = G.n_in <= kTabChunk;
+    if (once) stage(G.tab, G.n_in);
     for (int col = 0; col < n_cols; ++col) {
       const int o = column(col);
       const bool o_neg = 2 * o > p.outer_len;
@@ -294,7 +330,8 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>*
       for (int i = 0; i < G.n_in; ++i) {
         V v[E];
         load_fwd(G.in_ch[i], o, v);
-        times(i, G.tab[i], o_neg, v, acc, true);
+        if (!once) stage(&G.tab[i], 1);
+        times(once ? i : 0, G.tab[i], o_neg, v, acc, true);
       }
       inv_store(acc, G.out_ch[0], o);
     }
@@ -305,8 +342,9 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused_staged(const Cx<T>*
 // Launchers (return false when the length has no two-step factorisation)
 // ---------------------------------------------------------------------------
 int col2_tile_width(int N, bool fp64, bool fused) {
-  const int E = fp64 ? (fused ? twostep_E<double, true>(N) : twostep_E<double, false>(N))
-                     : (fused ? twostep_E<float, true>(N) : twostep_E<float, false>(N));
+  int E = fp64 ? (fused ? twostep_E<double, true>(N) : twostep_E<double, false>(N))
+               : (fused ? twostep_E<float, true>(N) : twostep_E<float, false>(N));
+  if (fused && (fp64 ? fused_pair<double>(N) : fused_pair<float>(N))) E = pair_E(N);
   if (E == 0) return 0;
   if (fused) return fp64 ? twostep_NB<double, true>() : twostep_NB<float, true>();
   return fp64 ? twostep_NB<double>() : twostep_NB<float>();
@@ -346,25 +384,39 @@ template <typename T> bool launch_col2_fused(const void* in, void* out, const Co
                                              int N, int tiles, int outer, hipStream_t st) {
   const dim3 grid(tiles, outer, fs.n_items);
   const bool half = 2 * p.n_in == N && 2 * p.n_out == N;
+  const Cx<T>* i_ = (const Cx<T>*)in;
+  Cx<T>* o_ = (Cx<T>*)out;
+  constexpr bool MIR = DT_FUSED_MIRROR != 0;
+  const dim3 gm(tiles, MIR ? p.outer_len / 2 + 1 : p.outer_len, fs.n_items);
   switch (N) {
 #define CASE(NN)                                                                                          \
   case NN: {                                                                                              \
     constexpr int E = twostep_E<T, true>(NN);                                                             \
-    if constexpr (E == 0) {                                                                               \
-      return false;                                                                                       \
-    } else {                                                                                              \
-      constexpr int NB = twostep_NB<T, true>();                                                                 \
+    constexpr int NB = twostep_NB<T, true>();                                                             \
+    if (p.outer_len > 1) {                                                                                \
+      if constexpr (fused_pair<T>(NN)) {                                                                     \
+        using ENG = PairFFT<T, NN, NB>;                                                                   \
+        constexpr int NT = ENG::P * NB;                                                                   \
+        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
+        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
+        return true;                                                                                      \
+      } else if constexpr (E > 0) {                                                                       \
+        using ENG = TwoStep<T, NN, E, NB>;                                                                \
+        constexpr int NT = ENG::P * NB;                                                                   \
+        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
+        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
+        return true;                                                                                      \
+      } else {                                                                                            \
+        return false;                                                                                     \
+      }                                                                                                   \
+    }                                                                                                     \
+    if constexpr (E > 0) {                                                                                \
       constexpr int NT = (NN / E) * NB;                                                                   \
-      const Cx<T>* i_ = (const Cx<T>*)in;                                                                 \
-      Cx<T>* o_ = (Cx<T>*)out;                                                                            \
-      if (p.outer_len > 1) {                                                                              \
-        constexpr bool MIR = DT_FUSED_MIRROR != 0;                                                          \
-        const dim3 gm(tiles, MIR ? p.outer_len / 2 + 1 : p.outer_len, fs.n_items);                          \
-        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, E, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
-        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, E, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
-      } else if (half) hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, true>), grid, dim3(NT), 0, st, i_, o_, p, fs); \
-      else hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, false>), grid, dim3(NT), 0, st, i_, o_, p, fs);            \
+      if (half) hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, true>), grid, dim3(NT), 0, st, i_, o_, p, fs); \
+      else hipLaunchKernelGGL((k_col2_fused<T, NN, E, NB, false>), grid, dim3(NT), 0, st, i_, o_, p, fs);     \
       return true;                                                                                        \
+    } else {                                                                                              \
+      return false;                                                                                       \
     }                                                                                                     \
   }
     DT_FOR_EACH_COL2_N(CASE)
