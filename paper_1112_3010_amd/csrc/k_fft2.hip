@@ -22,7 +22,7 @@ template <typename T, bool FUSED> constexpr int twostep_E(int N) {
   return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : 0;
 }
 #ifndef DT_FUSED2_NB32
-#define DT_FUSED2_NB32 16
+#define DT_FUSED2_NB32 8
 #endif
 template <typename T, bool FUSED = false> constexpr int twostep_NB() {
   return sizeof(T) == 4 ? (FUSED ? DT_FUSED2_NB32 : 16) : 8;
@@ -186,6 +186,8 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 #define DT_TAB_CHUNK 4
 #endif
 constexpr int kTabChunk = DT_TAB_CHUNK;
+// s_waitcnt immediate with vmcnt = 0 and expcnt, lgkmcnt at their maxima (no wait on those)
+constexpr int kWaitVmcnt0 = 0x0F70;
 #ifndef DT_FUSED_MIRROR
 #define DT_FUSED_MIRROR 1
 #endif
@@ -234,16 +236,42 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
   const FusedGroup& G = fs.g[IT.group];
   typename ENG::Tw tw;
   tw.load((const V*)p.tw, pt);
+  // complete the twiddle loads now: a wait at their first use would also
+  // wait for the asynchronous table copy issued below
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 
-  // copy the contiguous table slices of tabs[0..nt) into LDS with 16-byte loads
+  // Copy the contiguous table slices of tabs[0..nt) into LDS.  Each wave
+  // moves 1 KiB runs with direct global-to-LDS loads, which do not pass
+  // through registers and complete asynchronously: the copy overlaps the
+  // column loads that follow.  It is complete for the whole block once every
+  // wave has waited for its loads and passed a barrier: load_fwd waits for
+  // all loads before its first exchange barrier, stage_wait does both.
   auto stage = [&](const int* tabs, int nt) {
-    __syncthreads();
-    for (int i = tid; i < nt * SLICE16; i += NT) {
-      const int c = i / SLICE16, j = i - c * SLICE16;
-      const uint4* src = (const uint4*)((const T*)fs.tabs[tabs[c]].ptr + (int64_t)of * fs.tab_outer_stride +
-                                        (int64_t)blockIdx.x * fs.tab_tile_stride);
-      ((uint4*)tab_lds)[i] = src[j];
+    // slice addresses first: a wait for these loads would also wait for copies already issued
+    const uint4* src[kTabChunk];
+#pragma unroll
+    for (int c = 0; c < kTabChunk; ++c)
+      src[c] = c < nt ? (const uint4*)((const T*)fs.tabs[tabs[c]].ptr + (int64_t)of * fs.tab_outer_stride +
+                                       (int64_t)blockIdx.x * fs.tab_tile_stride)
+                      : nullptr;
+    __syncthreads();                                  // earlier readers of tab_lds are done
+    constexpr int RUNS = (SLICE16 + 63) / 64;         // 64-lane runs per slice
+    constexpr int NW = NT / 64;
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < kTabChunk; ++c) {
+      if (c >= nt) break;
+      for (int r = w; r < RUNS; r += NW) {
+        const int idx = r * 64 + lane;
+        if (idx < SLICE16)
+          __builtin_amdgcn_global_load_lds(
+              (__attribute__((address_space(1))) void*)(src[c] + idx),
+              (__attribute__((address_space(3))) void*)((uint4*)tab_lds + c * SLICE16 + r * 64), 16, 0, 0);
+      }
     }
+  };
+  auto stage_wait = [&]() {
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
   };
   auto load_fwd = [&](int ch, int o, V* v) {
@@ -254,7 +282,8 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
       if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
       else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
     }
-    ENG::forward_split(v, xch, pt, b, tw);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the column and any table copy issued before it
+    ENG::forward_split(v, xch, pt, b, tw);      // starts with a barrier
   };
   auto times = [&](int slot, int tab, bool o_neg, const V* v, V* res, bool accumulate) {
     const TabRef& t = fs.tabs[tab];
@@ -310,6 +339,7 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
         for (int c0 = IT.c0; c0 < IT.c1; c0 += kTabChunk) {
           const int nc = IT.c1 - c0 < kTabChunk ? IT.c1 - c0 : kTabChunk;
           stage(&G.tab[c0], nc);
+          stage_wait();
           for (int c = 0; c < nc; ++c) {
             V v[E];
             times(c, G.tab[c0 + c], o_neg, spec, v, false);
@@ -330,7 +360,10 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
       for (int i = 0; i < G.n_in; ++i) {
         V v[E];
         load_fwd(G.in_ch[i], o, v);
-        if (!once) stage(&G.tab[i], 1);
+        if (!once) {
+          stage(&G.tab[i], 1);
+          stage_wait();
+        }
         times(once ? i : 0, G.tab[i], o_neg, v, acc, true);
       }
       inv_store(acc, G.out_ch[0], o);
