@@ -154,6 +154,79 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls):
     return res
 
 
+def triangle_centres(V, F):
+    """Incenters of the mesh triangles (float32, K x 3): the sources of the
+    backward workload, given to dt_backward as points."""
+    V = np.asarray(V, dtype=np.float64)
+    v0, v1, v2 = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    a = np.linalg.norm(v1 - v2, axis=1)[:, None]
+    b = np.linalg.norm(v2 - v0, axis=1)[:, None]
+    c = np.linalg.norm(v0 - v1, axis=1)[:, None]
+    return ((a * v0 + b * v1 + c * v2) / (a + b + c)).astype(np.float32)
+
+
+def backward_bytes(dims, Mp, w, K):
+    """Algorithmic HBM bytes per launch of the backward passes (dL/dY and
+    dL/dtau): the forward transform of w = G e^(S/tau), the products with the
+    D gradient kernels and the r f kernel, and the gather at the K sources."""
+    D = len(dims)
+    b = pass_bytes(dims, Mp, w, c_in=1, c_out=D + 1, n_tab=D + 1, out_fields=0)
+    del b["row_c2r_epi"]
+    N = int(np.prod(dims))
+    Mh = Mp[0] // 2 + 1
+    b["prep_w"] = 3 * N * w
+    b["gather"] = K * (D + 1) * Mh * 2 * w + K * D * 4
+    return b
+
+
+def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
+    """Time dt_backward on the 256^3 grid with the mesh's triangle centres as
+    sources and dL/dS = S (the loss S^2 / 2)."""
+    import torch
+    import paper_1112_3010_amd as dt
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "backward"])
+    Yd = torch.from_numpy(Y).cuda()
+    S = plan.distance(Yd)
+    G = S.clone()
+    for _ in range(warmup):
+        plan.backward(Yd, S, G)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.backward(Yd, S, G)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.set_timing(True)
+    plan.timings(reset=True)
+    for _ in range(timing_calls):
+        plan.backward(Yd, S, G)
+    per = plan.timings(reset=True)
+    plan.set_timing(False)
+    w = 8 if prec == "fp64" else 4
+    nbytes = backward_bytes(dims, plan.padded, w, len(Y))
+    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
+    total = sum(nbytes.values())
+    N = int(np.prod(dims))
+    res = {"value": round(N / (ms * 1e-3), 1), "unit": "grid pts/s", "ms_per_call": round(ms, 4),
+           "sources": len(Y),
+           "roofline": {"bound": "hbm", "achieved": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": dom, "bytes_per_launch": nbytes[dom]},
+           "path": {"model_bytes": total, "achieved_gbs": round(total / (ms * 1e-3) / 1e9, 1),
+                    "frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "pass_ms": {k: round(v, 4) for k, v in avg.items()},
+                    "pass_gbs": {k: round(nbytes[k] / (avg[k] * 1e-3) / 1e9, 1) for k in avg if k in nbytes}}}
+    del plan
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(V, F, dims, tau, n_cells, seed=0):
     """The oracle (FP64 direct sums, S and grad S) on a bounded random sample
     of nodes of the same workload, one core."""
@@ -286,10 +359,15 @@ def main():
     log(f"workload: 256^3, {len(F)} triangles, tau = h")
     r32 = run_gpu("fp32", V, F, dims, tau, args.steps, args.warmup, args.timing_calls)
     log("fp32:", json.dumps(r32))
-    r64 = None
+    Yc = triangle_centres(V, F)
+    b32 = run_backward("fp32", Yc, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
+    log("fp32 backward:", json.dumps(b32))
+    r64 = b64 = None
     if not args.no_fp64:
         r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
         log("fp64:", json.dumps(r64))
+        b64 = run_backward("fp64", Yc, dims, tau, max(5, args.steps // 4), args.warmup, args.timing_calls)
+        log("fp64 backward:", json.dumps(b64))
     khash = kernel_hash()
 
     def roof(r, prec):
@@ -319,12 +397,14 @@ def main():
                  "pass_gbs": r32["pass_gbs"], "s_max_over_tau": round(r32["s_max_over_tau"], 3),
                  "plan_setup_s": round(r32["plan_setup_s"], 3)},
     }
+    line["backward"] = b32
     if r64 is not None:
         line["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
                         "dtype": "f64", "roofline": roof(r64, "fp64"),
                         "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
                                  "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
-                                 "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3)}}
+                                 "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3)},
+                        "backward": b64}
     if not args.no_cpu:
         cb = cpu_baseline(V, F, dims, tau, args.cpu_cells)
         cb["value"] = round(cb["value"], 2)

@@ -293,6 +293,7 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
   // Spectral index held in forward-output slot (t, k2) of thread p.
   static __device__ __forceinline__ int slot_index(int p, int t, int k2) { return (p + P * t) + E * k2; }
   static __device__ __forceinline__ int slot(int p, int i) { return slot_index(p, i / P, i % P); }
+  static constexpr bool LINEAR_FOLD = false;
 };
 
 // ---------------------------------------------------------------------------
@@ -399,6 +400,13 @@ template <typename T, int N, int NB> struct PairFFT {
     RegDFT<E, -1, V>::run(v);
   }
   static __device__ __forceinline__ int slot(int p, int j) { return (p >> 1) + E * j + (N / 2) * (p & 1); }
+  // Folded index |k| of slot j is linear in j: lanes with h = 0 hold k < N/2,
+  // lanes with h = 1 hold k >= N/2 (negative frequencies; k = N/2 is the
+  // Nyquist index, where every odd kernel spectrum vanishes).
+  static constexpr bool LINEAR_FOLD = true;
+  static __device__ __forceinline__ int fold_base(int p) { return (p & 1) ? N / 2 - (p >> 1) : (p >> 1); }
+  static __device__ __forceinline__ int fold_step(int p) { return (p & 1) ? -E : E; }
+  static __device__ __forceinline__ bool fold_neg(int p) { return (p & 1) != 0; }
 };
 
 }  // namespace dt

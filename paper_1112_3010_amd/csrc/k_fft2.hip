@@ -285,19 +285,44 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the column and any table copy issued before it
     ENG::forward_split(v, xch, pt, b, tw);      // starts with a barrier
   };
+  // res[i] (+)= v[i] * kernel spectrum at slot i: the folded table entry with
+  // the signs of the odd axes and the factor (-i)^phase
   auto times = [&](int slot, int tab, bool o_neg, const V* v, V* res, bool accumulate) {
     const TabRef& t = fs.tabs[tab];
     const bool flip_o = t.odd_outer && o_neg;
-    const T* tl = tab_lds + slot * SLICE + b;
+    if constexpr (ENG::LINEAR_FOLD) {
+      // one sign per lane and a linear walk through the table column
+      const bool flip = flip_o != (t.odd_line && ENG::fold_neg(pt));
+      const T* tl = tab_lds + slot * SLICE + b + ENG::fold_base(pt) * NB;
+      const int step = ENG::fold_step(pt) * NB;
+      T val[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int l = ENG::slot(pt, i);
-      const bool l_neg = 2 * l > N;
-      const int lf = l_neg ? N - l : l;
-      T val = tl[lf * NB];
-      if (flip_o != (t.odd_line && l_neg)) val = -val;
-      const V prod = mul_mi_pow(cscale(v[i], val), t.phase);
-      res[i] = accumulate ? cadd(res[i], prod) : prod;
+      for (int i = 0; i < E; ++i) val[i] = flip ? -tl[i * step] : tl[i * step];
+      auto apply = [&](auto rot) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const V prod = rot(cscale(v[i], val[i]));
+          res[i] = accumulate ? cadd(res[i], prod) : prod;
+        }
+      };
+      switch (t.phase & 3) {   // uniform: one branch per call, not per element
+        case 0: apply([](V a) { return a; }); break;
+        case 1: apply([](V a) { return mul_mi(a); }); break;
+        case 2: apply([](V a) { return mk<V>(-a.x, -a.y); }); break;
+        default: apply([](V a) { return mul_pi(a); }); break;
+      }
+    } else {
+      const T* tl = tab_lds + slot * SLICE + b;
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = ENG::slot(pt, i);
+        const bool l_neg = 2 * l > N;
+        const int lf = l_neg ? N - l : l;
+        T val = tl[lf * NB];
+        if (flip_o != (t.odd_line && l_neg)) val = -val;
+        const V prod = mul_mi_pow(cscale(v[i], val), t.phase);
+        res[i] = accumulate ? cadd(res[i], prod) : prod;
+      }
     }
   };
   auto inv_store = [&](V* v, int ch, int o) {
