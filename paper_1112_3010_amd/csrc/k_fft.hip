@@ -18,6 +18,7 @@
 
 #include "dt_launch.hpp"
 #include "fft_engine.hpp"
+#include "epilogue.hpp"
 
 namespace dt {
 
@@ -200,51 +201,6 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 // ---------------------------------------------------------------------------
 // Row pass: half spectrum -> real, fused with the epilogue
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void hess_pair(int ndim, int h, int& i, int& j) {
-  if (ndim == 2) {
-    const int a[3] = {0, 0, 1}, c[3] = {0, 1, 1};
-    i = a[h]; j = c[h];
-  } else {
-    const int a[6] = {0, 0, 0, 1, 1, 2}, c[6] = {0, 1, 2, 1, 2, 2};
-    i = a[h]; j = c[h];
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void epilogue_cell(const EpiParams& e, const T* vals, int64_t node) {
-  const T theta = (T)e.theta[0];
-  const T smax = (T)e.theta[1];
-  const T tau = (T)e.tau;
-  T label = T(1);
-  if (e.ch_mu >= 0) {
-    const T mu = vals[e.ch_mu] * (T)e.scale_mu;
-    label = mu >= T(0.5) ? T(1) : T(-1);
-    if (e.label) e.label[node] = (int8_t)(mu >= T(0.5) ? 1 : -1);
-    if (e.mu) ((T*)e.mu)[node] = mu;
-  }
-  if (e.ch_phi < 0) return;
-  const T cphi = vals[e.ch_phi];
-  const T phi = cphi * (T)e.scale_phi;
-  const bool valid = phi >= theta;
-  const T sgn = (e.signed_out && e.ch_mu >= 0) ? label : T(1);
-  if (e.S) ((T*)e.S)[node] = sgn * (valid ? -tau * log(phi) : smax);
-  if (e.ch_u[0] < 0) return;
-  T g[3] = {T(0), T(0), T(0)};
-  const T inv = valid ? T(1) / cphi : T(0);
-  for (int a = 0; a < e.ndim; ++a) g[a] = valid ? vals[e.ch_u[a]] * inv * (T)e.scale_u[a] : T(0);
-  if (e.grad)
-    for (int a = 0; a < e.ndim; ++a) ((T*)e.grad)[a * e.plane + node] = sgn * g[a];
-  if (e.hess && e.ch_h[0] >= 0) {
-    const int nh = e.ndim == 2 ? 3 : 6;
-    for (int h = 0; h < nh; ++h) {
-      int i, j;
-      hess_pair(e.ndim, h, i, j);
-      const T hv = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
-      ((T*)e.hess)[h * e.plane + node] = hv;
-    }
-  }
-}
-
 template <typename T, int N>
 __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
