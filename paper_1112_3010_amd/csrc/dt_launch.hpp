@@ -35,17 +35,18 @@ struct TabGeom {
 void make_twiddles(int M, std::vector<double>& out);
 
 template <typename T> void launch_fill_zero(T* p, int64_t n, hipStream_t st);
+// Splats: inv_cval = 1 / cval (a power of two); msq (nullable) accumulates
+// the sum of squared multiplicities of the count image.
 template <typename T> void launch_splat_points(const float* Y, int64_t K, const GridGeom& g, T* cnt, T cval,
-                                               uint32_t* err, hipStream_t st);
+                                               double inv_cval, double* msq, uint32_t* err, hipStream_t st);
 template <typename T> void launch_splat_polygon(const float* P, int64_t K, const GridGeom& g, T* cnt, T cval,
-                                                T* g1, T* g2, double w1, double w2, uint32_t* err, hipStream_t st);
+                                                double inv_cval, double* msq, T* g1, T* g2, double w1, double w2,
+                                                uint32_t* err, hipStream_t st);
 template <typename T> void launch_splat_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
-                                             const GridGeom& g, T* cnt, T cval, T* gp0, T* gp1, T* gp2,
-                                             double w0, double w1, double w2, uint32_t* err, hipStream_t st);
-template <typename T> int launch_grid_msq(const T* cnt, int64_t n, double inv_cval, double* partials,
-                                          hipStream_t st);
-void launch_finalize_theta(const double* partials, int n_partials, double coef, double tau, double* scal,
-                           hipStream_t st);
+                                             const GridGeom& g, T* cnt, T cval, double inv_cval, double* msq, T* gp0,
+                                             T* gp1, T* gp2, double w0, double w1, double w2, uint32_t* err,
+                                             hipStream_t st);
+void launch_finalize_theta_msq(double* msq, double coef, double tau, double* scal, hipStream_t st);
 
 int launch_tab_sample(const TabKernel& kd, const TabGeom& tg, double* out, double* partials, hipStream_t st);
 void launch_tab_axis(const TabGeom& tg, int axis, int odd, const void* trig, const double* in, double* out,

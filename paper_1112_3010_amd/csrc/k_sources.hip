@@ -55,41 +55,73 @@ __device__ __forceinline__ bool snap_node(const GridGeom& g, const double* y, in
   return true;
 }
 
+// Sum of squared multiplicities, accumulated while splatting: adding one
+// source to a node that already holds m of them raises sum m^2 by 2m + 1.
+// Every lane of the wave takes part (lanes without a source add 0), then one
+// atomic per wave.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const int hi = __shfl_xor(__double2hiint(v), off);
+    const int lo = __shfl_xor(__double2loint(v), off);
+    v += __hiloint2double(hi, lo);
+  }
+  return v;
+}
+__device__ __forceinline__ void msq_add(double inc, double* msq) {
+  if (!msq) return;
+  const double s = wave_sum(inc);
+  if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(msq, s);
+}
+// Add one (scaled) source to the count image; returns the increment of sum m^2.
+template <typename T> __device__ __forceinline__ double count_add(T* cnt, int64_t lin, T cval, double inv_cval) {
+  const T old = atomicAdd(&cnt[lin], cval);
+  return 2.0 * ((double)old * inv_cval) + 1.0;
+}
+
 // Point sources: count image only.
 template <typename T>
 __global__ void __launch_bounds__(256) k_splat_points(const float* __restrict__ Y, int64_t K, GridGeom g,
-                                                      T* __restrict__ cnt, T cval, uint32_t* err) {
+                                                      T* __restrict__ cnt, T cval, double inv_cval, double* msq,
+                                                      uint32_t* err) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  double y[3];
-  for (int d = 0; d < g.ndim; ++d) y[d] = (double)Y[k * g.ndim + d];
-  int idx[3];
-  int64_t lin;
-  if (!snap_node(g, y, lin, idx, err)) return;
-  atomicAdd(&cnt[lin], cval);
+  double inc = 0.0;
+  if (k < K) {
+    double y[3];
+    for (int d = 0; d < g.ndim; ++d) y[d] = (double)Y[k * g.ndim + d];
+    int idx[3];
+    int64_t lin;
+    if (snap_node(g, y, lin, idx, err)) inc = count_add(cnt, lin, cval, inv_cval);
+  }
+  msq_add(inc, msq);
 }
 
 // Closed polygon: optional count image, tangent images g1 (Z^1) and g2 (Z^2)
 // with Z_k = Yhat_{k+1} - Yhat_k on the snapped points (wrapping at K).
 template <typename T>
 __global__ void __launch_bounds__(256) k_splat_polygon(const float* __restrict__ P, int64_t K, GridGeom g,
-                                                       T* __restrict__ cnt, T cval, T* __restrict__ g1,
-                                                       T* __restrict__ g2, double w1, double w2, uint32_t* err) {
+                                                       T* __restrict__ cnt, T cval, double inv_cval, double* msq,
+                                                       T* __restrict__ g1, T* __restrict__ g2, double w1, double w2,
+                                                       uint32_t* err) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int64_t kn = (k + 1 == K) ? 0 : k + 1;
-  double y[2] = {(double)P[2 * k], (double)P[2 * k + 1]};
-  double yn[2] = {(double)P[2 * kn], (double)P[2 * kn + 1]};
-  int idx[3], idn[3];
-  int64_t lin, linn;
-  if (!snap_node(g, y, lin, idx, err)) return;
-  if (cnt) atomicAdd(&cnt[lin], cval);
-  if (!g1) return;
-  if (!snap_node(g, yn, linn, idn, nullptr)) return;  // the next point reports its own error
-  const double zx = (double)(idn[0] - idx[0]) * g.h[0];
-  const double zy = (double)(idn[1] - idx[1]) * g.h[1];
-  atomicAdd(&g1[lin], (T)(zx * w1));
-  atomicAdd(&g2[lin], (T)(zy * w2));
+  double inc = 0.0;
+  if (k < K) {
+    const int64_t kn = (k + 1 == K) ? 0 : k + 1;
+    double y[2] = {(double)P[2 * k], (double)P[2 * k + 1]};
+    double yn[2] = {(double)P[2 * kn], (double)P[2 * kn + 1]};
+    int idx[3], idn[3];
+    int64_t lin, linn;
+    if (snap_node(g, y, lin, idx, err)) {
+      if (cnt) inc = count_add(cnt, lin, cval, inv_cval);
+      // the next point reports its own error
+      if (g1 && snap_node(g, yn, linn, idn, nullptr)) {
+        const double zx = (double)(idn[0] - idx[0]) * g.h[0];
+        const double zy = (double)(idn[1] - idx[1]) * g.h[1];
+        atomicAdd(&g1[lin], (T)(zx * w1));
+        atomicAdd(&g2[lin], (T)(zy * w2));
+      }
+    }
+  }
+  msq_add(inc, msq);
 }
 
 // Incenter and area vector of one triangle.  The incenter order of
@@ -125,124 +157,94 @@ __device__ __forceinline__ void triangle_sources(const double* v0, const double*
 template <typename T>
 __global__ void __launch_bounds__(256) k_splat_mesh(const float* __restrict__ V, int64_t nv,
                                                     const int32_t* __restrict__ F, int64_t nf, GridGeom g,
-                                                    T* __restrict__ cnt, T cval, T* __restrict__ gp0,
-                                                    T* __restrict__ gp1, T* __restrict__ gp2, double w0,
-                                                    double w1, double w2, uint32_t* err) {
+                                                    T* __restrict__ cnt, T cval, double inv_cval, double* msq,
+                                                    T* __restrict__ gp0, T* __restrict__ gp1, T* __restrict__ gp2,
+                                                    double w0, double w1, double w2, uint32_t* err) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  double v[3][3];
-  for (int c = 0; c < 3; ++c) {
-    const int32_t vi = F[3 * f + c];
-    if (vi < 0 || (int64_t)vi >= nv) {
-      atomicOr(err, kErrRange);
-      return;
+  double inc = 0.0;
+  if (f < nf) {
+    double v[3][3];
+    bool ok = true;
+    for (int c = 0; c < 3 && ok; ++c) {
+      const int32_t vi = F[3 * f + c];
+      if (vi < 0 || (int64_t)vi >= nv) {
+        atomicOr(err, kErrRange);
+        ok = false;
+      } else {
+        for (int d = 0; d < 3; ++d) v[c][d] = (double)V[3 * (int64_t)vi + d];
+      }
     }
-    for (int d = 0; d < 3; ++d) v[c][d] = (double)V[3 * (int64_t)vi + d];
+    double incr[3], area[3];
+    int idx[3];
+    int64_t lin;
+    if (ok) {
+      triangle_sources(v[0], v[1], v[2], incr, area);
+      if (snap_node(g, incr, lin, idx, err)) {
+        if (cnt) inc = count_add(cnt, lin, cval, inv_cval);
+        if (gp0) {
+          atomicAdd(&gp0[lin], (T)(area[0] * w0));
+          atomicAdd(&gp1[lin], (T)(area[1] * w1));
+          atomicAdd(&gp2[lin], (T)(area[2] * w2));
+        }
+      }
+    }
   }
-  double inc[3], area[3];
-  triangle_sources(v[0], v[1], v[2], inc, area);
-  int idx[3];
-  int64_t lin;
-  if (!snap_node(g, inc, lin, idx, err)) return;
-  if (cnt) atomicAdd(&cnt[lin], cval);
-  if (gp0) {
-    atomicAdd(&gp0[lin], (T)(area[0] * w0));
-    atomicAdd(&gp1[lin], (T)(area[1] * w1));
-    atomicAdd(&gp2[lin], (T)(area[2] * w2));
-  }
+  msq_add(inc, msq);
 }
 
 template <typename T> void launch_splat_points(const float* Y, int64_t K, const GridGeom& g, T* cnt, T cval,
-                                               uint32_t* err, hipStream_t st) {
+                                               double inv_cval, double* msq, uint32_t* err, hipStream_t st) {
   if (K <= 0) return;
   hipLaunchKernelGGL(k_splat_points<T>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, Y, K, g, cnt, cval,
-                     err);
+                     inv_cval, msq, err);
 }
 template <typename T> void launch_splat_polygon(const float* P, int64_t K, const GridGeom& g, T* cnt, T cval,
-                                                T* g1, T* g2, double w1, double w2, uint32_t* err, hipStream_t st) {
+                                                double inv_cval, double* msq, T* g1, T* g2, double w1, double w2,
+                                                uint32_t* err, hipStream_t st) {
   if (K <= 0) return;
   hipLaunchKernelGGL(k_splat_polygon<T>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, P, K, g, cnt,
-                     cval, g1, g2, w1, w2, err);
+                     cval, inv_cval, msq, g1, g2, w1, w2, err);
 }
 template <typename T> void launch_splat_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
-                                             const GridGeom& g, T* cnt, T cval, T* gp0, T* gp1, T* gp2,
-                                             double w0, double w1, double w2, uint32_t* err, hipStream_t st) {
+                                             const GridGeom& g, T* cnt, T cval, double inv_cval, double* msq, T* gp0,
+                                             T* gp1, T* gp2, double w0, double w1, double w2, uint32_t* err,
+                                             hipStream_t st) {
   if (nf <= 0) return;
   hipLaunchKernelGGL(k_splat_mesh<T>, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, V, nv, F, nf, g,
-                     cnt, cval, gp0, gp1, gp2, w0, w1, w2, err);
+                     cnt, cval, inv_cval, msq, gp0, gp1, gp2, w0, w1, w2, err);
 }
 #define DT_INST_SPLAT(T)                                                                                   \
-  template void launch_splat_points<T>(const float*, int64_t, const GridGeom&, T*, T, uint32_t*,          \
-                                       hipStream_t);                                                      \
-  template void launch_splat_polygon<T>(const float*, int64_t, const GridGeom&, T*, T, T*, T*, double,    \
-                                        double, uint32_t*, hipStream_t);                                  \
+  template void launch_splat_points<T>(const float*, int64_t, const GridGeom&, T*, T, double, double*,    \
+                                       uint32_t*, hipStream_t);                                           \
+  template void launch_splat_polygon<T>(const float*, int64_t, const GridGeom&, T*, T, double, double*,   \
+                                        T*, T*, double, double, uint32_t*, hipStream_t);                  \
   template void launch_splat_mesh<T>(const float*, int64_t, const int32_t*, int64_t, const GridGeom&, T*, \
-                                     T, T*, T*, T*, double, double, double, uint32_t*, hipStream_t);
+                                     T, double, double*, T*, T*, T*, double, double, double, uint32_t*,    \
+                                     hipStream_t);
 DT_INST_SPLAT(float)
 DT_INST_SPLAT(double)
 
 // ---------------------------------------------------------------------------
 // Validity scalars: Theta = c * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
 // ---------------------------------------------------------------------------
-// Sum of squared multiplicities over a count image (values m * inv_scale^-1).
-template <typename T>
-__global__ void __launch_bounds__(256) k_grid_msq(const T* __restrict__ cnt, int64_t n, double inv_cval,
-                                                  double* __restrict__ partials) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double m = (double)cnt[i] * inv_cval;
-    acc += m * m;
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+// Validity scalars from the sum of squared multiplicities accumulated by the
+// splat (msq[0]), which is cleared for the next call.
+__global__ void k_finalize_theta_msq(double* __restrict__ msq, double coef, double tau, double* __restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  const double gl2 = sqrt(msq[0]);
+  msq[0] = 0.0;
+  const double theta = coef * gl2;
+  scal[0] = theta;
+  scal[1] = -tau * log(theta);
+  scal[2] = gl2;
+  int e;
+  frexp(theta, &e);
+  scal[3] = ldexp(1.0, e - 1);
+}
+void launch_finalize_theta_msq(double* msq, double coef, double tau, double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_theta_msq, dim3(1), dim3(64), 0, st, msq, coef, tau, scal);
 }
 
-template <typename T> int launch_grid_msq(const T* cnt, int64_t n, double inv_cval, double* partials,
-                                          hipStream_t st) {
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_grid_msq<T>, dim3(blocks), dim3(256), 0, st, cnt, n, inv_cval, partials);
-  return blocks;
-}
-template int launch_grid_msq<float>(const float*, int64_t, double, double*, hipStream_t);
-template int launch_grid_msq<double>(const double*, int64_t, double, double*, hipStream_t);
-
-// scal[0] = Theta, scal[1] = S_max, scal[2] = ||g||_2, scal[3] = 2^floor(log2 Theta)
-__global__ void __launch_bounds__(256) k_finalize_theta(const double* __restrict__ partials, int n_partials,
-                                                        double coef, double tau, double* __restrict__ scal) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n_partials; i += blockDim.x) acc += partials[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double gl2 = sqrt(red[0]);
-    const double theta = coef * gl2;
-    scal[0] = theta;
-    scal[1] = -tau * log(theta);
-    scal[2] = gl2;
-    int e;
-    frexp(theta, &e);              // theta = f * 2^e with f in [0.5, 1)
-    scal[3] = ldexp(1.0, e - 1);   // largest power of two <= theta
-  }
-}
-
-void launch_finalize_theta(const double* partials, int n_partials, double coef, double tau, double* scal,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_theta, dim3(1), dim3(256), 0, st, partials, n_partials, coef, tau, scal);
-}
 
 // ---------------------------------------------------------------------------
 // Plan-time kernel spectra

@@ -104,6 +104,7 @@ struct dt_plan_s {
   double npad() const { return (double)M[0] * (double)M[1] * (double)M[2]; }
   double unit() const { return fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24); }
   double* scal() const { return (double*)(ws + off_scal); }
+  double* msq() const { return scal() + 16; }   // splat accumulator of sum m^2 (cleared by the finalize)
   uint32_t* err() const { return (uint32_t*)(ws + off_err); }
   double* partA() const { return (double*)(ws + off_partA); }
   double* partB() const { return (double*)(ws + off_partB); }
@@ -676,22 +677,25 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
   if (rq.sign)
     for (int a = 0; a < D; ++a) sg[a] = img + (int64_t)(sign_in0 + a) * N;
   PassTimer* splat_t = new PassTimer(p, st, "splat");
-  if (rq.dist && Y) launch_splat_points<T>(Y, K, g, cnt, cval, p->err(), st);
-  if (D == 2 && shape && (rq.sign || (rq.dist && !Y)))
-    launch_splat_polygon<T>(shape->points, shape->n_points, g, (rq.dist && !Y) ? cnt : nullptr, cval,
-                            rq.sign ? sg[0] : nullptr, rq.sign ? sg[1] : nullptr, ws_scale, ws_scale, p->err(), st);
-  if (D == 3 && shape && (rq.sign || (rq.dist && !Y)))
+  const double inv_cval = std::ldexp(1.0, e_g);
+  double* msq = p->msq();
+  if (rq.dist && Y) launch_splat_points<T>(Y, K, g, cnt, cval, inv_cval, msq, p->err(), st);
+  const bool shape_counts = rq.dist && !Y;
+  if (D == 2 && shape && (rq.sign || shape_counts))
+    launch_splat_polygon<T>(shape->points, shape->n_points, g, shape_counts ? cnt : nullptr, cval, inv_cval,
+                            shape_counts ? msq : nullptr, rq.sign ? sg[0] : nullptr, rq.sign ? sg[1] : nullptr,
+                            ws_scale, ws_scale, p->err(), st);
+  if (D == 3 && shape && (rq.sign || shape_counts))
     launch_splat_mesh<T>(shape->vertices, shape->n_vertices, shape->faces, shape->n_faces, g,
-                         (rq.dist && !Y) ? cnt : nullptr, cval, sg[0], sg[1], sg[2], ws_scale, ws_scale, ws_scale,
-                         p->err(), st);
+                         shape_counts ? cnt : nullptr, cval, inv_cval, shape_counts ? msq : nullptr, sg[0], sg[1],
+                         sg[2], ws_scale, ws_scale, ws_scale, p->err(), st);
   delete splat_t;
 
-  // validity scalars
+  // validity scalars (the splat accumulated the sum of squared multiplicities)
   if (rq.dist) {
     PassTimer t(p, st, "validity");
-    const int nb = launch_grid_msq<T>(cnt, N, std::ldexp(1.0, e_g), p->partA(), st);
     const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
-    launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+    launch_finalize_theta_msq(msq, coef, p->tau, p->scal(), st);
   }
 
   // fused groups and epilogue channel map
@@ -786,13 +790,12 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
   }
   {
     PassTimer t(p, st, "splat");
-    launch_splat_points<T>(Y, K, g, img, cval, p->err(), st);
+    launch_splat_points<T>(Y, K, g, img, cval, std::ldexp(1.0, e_g), p->msq(), p->err(), st);
   }
   {
     PassTimer t(p, st, "validity");
-    const int nb = launch_grid_msq<T>(img, N, std::ldexp(1.0, e_g), p->partA(), st);
     const double coef = p->c_theta * p->unit() * std::log2(p->npad()) * p->kernel_l1 / std::sqrt(p->npad());
-    launch_finalize_theta(p->partA(), nb, coef, p->tau, p->scal(), st);
+    launch_finalize_theta_msq(p->msq(), coef, p->tau, p->scal(), st);
   }
   // w = G exp(S/tau) on valid nodes (overwrites the count image)
   int ngs;
