@@ -198,11 +198,12 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 #define DT_FUSED_PAIR 1
 #endif
 
-// The pair-split engine serves the float32 3D fused pass where N = 2 E^2
-// (in float64 its two columns of E complex doubles exceed the register file
-// and the Stockham or two-step kernels are faster).
+// The pair-split engine serves the 3D fused pass where N = 2 E^2.
+#ifndef DT_FUSED_PAIR64
+#define DT_FUSED_PAIR64 1
+#endif
 template <typename T> constexpr bool fused_pair(int N) {
-  return DT_FUSED_PAIR != 0 && sizeof(T) == 4 && pair_E(N) > 0 && N >= 128 && N <= 512;
+  return DT_FUSED_PAIR != 0 && (sizeof(T) == 4 || DT_FUSED_PAIR64 != 0) && pair_E(N) > 0 && N >= 128 && N <= 512;
 }
 
 template <typename T, int N, class ENG, int NB, bool HALF, bool MIRROR>
