@@ -161,7 +161,7 @@ dt_batch_tiles default_tiles(dt_batch_plan p) {
   dt_batch_tiles t{1, 512, 256};
   const size_t lds_cap = std::min<size_t>((size_t)p->lds_max, 131072);
   for (int nb : {16, 8, 4, 2, 1})
-    if (my * nb <= 32 * 512 && (size_t)(my * nb) * 2 * p->wsz() <= lds_cap) {
+    if (my * nb <= 32 * 512 && (size_t)(2 * my * nb) * 2 * p->wsz() <= lds_cap) {
       t.col_nb = nb;
       break;
     }
@@ -193,7 +193,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       const int c = (int)std::min<int64_t>(nb, sx + 1 - kx);
       lists[P_COL].push_back({i, kx, c, 0});
       need[P_COL] = std::max<int64_t>(need[P_COL], (int64_t)I.My * c);
-      lds[P_COL] = std::max<size_t>(lds[P_COL], (size_t)I.My * c * 2 * w);
+      lds[P_COL] = std::max<size_t>(lds[P_COL], (size_t)2 * I.My * c * 2 * w);   // spectrum + work column
     }
     // epilogue: C lines per row
     r = std::min<int>(rows_per_block(sx, p->C, nt_row, w), I.ny);

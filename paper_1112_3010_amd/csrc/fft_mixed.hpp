@@ -66,24 +66,42 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft_small(
   else dft_odd<R, DIR, V>(x);
 }
 
+// Division by a block-uniform divisor d in [1, 4096] through a multiply-high:
+// q = floor(u * (floor((2^32 - 1) / d) + 1) / 2^32) equals u / d for every
+// u < 2^16 (checked exhaustively), which covers every index of a stage.
+struct FastDiv {
+  uint32_t d, m;
+  __device__ __forceinline__ explicit FastDiv(uint32_t d_) : d(d_), m(d_ > 1 ? 0xFFFFFFFFu / d_ + 1u : 0u) {}
+  __device__ __forceinline__ uint32_t div(uint32_t u) const { return d > 1 ? __umulhi(u, m) : u; }
+};
+
 // One Stockham stage of radix R over all L lines.  ECAP bounds the elements a
-// thread holds: the caller guarantees N * L <= ECAP * nthr.
+// thread holds: the caller guarantees N * L <= ECAP * nthr (< 2^16).
 template <typename T, int DIR, int R, int ECAP, bool LINE_FAST>
 __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istride, int lstride, int Ns,
-                                            const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
+                                            const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr,
+                                            const FastDiv& fL) {
   using V = Cx<T>;
   constexpr int BM = (ECAP + R - 1) / R;
   const int nbf = N / R;
   const int total = nbf * L;
   const int tstep = (N / (Ns * R)) * twstride;   // twiddle index step per unit of k * r
+  const FastDiv fNs((uint32_t)Ns), fnbf((uint32_t)nbf);
   V v[BM][R];
 #pragma unroll
   for (int b = 0; b < BM; ++b) {
     const int u = tid + b * nthr;
     if (u < total) {
-      const int l = LINE_FAST ? u % L : u / nbf;
-      const int j = LINE_FAST ? u / L : u % nbf;
-      const int k = j % Ns;
+      int l, j;
+      if (LINE_FAST) {
+        j = (int)fL.div((uint32_t)u);
+        l = u - j * L;
+      } else {
+        l = (int)fnbf.div((uint32_t)u);
+        j = u - l * nbf;
+      }
+      const int g = (int)fNs.div((uint32_t)j);
+      const int k = j - g * Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = lds[(j + r * nbf) * istride + l * lstride];
       if (Ns > 1) {
@@ -98,10 +116,17 @@ __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istrid
   for (int b = 0; b < BM; ++b) {
     const int u = tid + b * nthr;
     if (u < total) {
-      const int l = LINE_FAST ? u % L : u / nbf;
-      const int j = LINE_FAST ? u / L : u % nbf;
-      const int k = j % Ns;
-      const int base = (j / Ns) * Ns * R + k;
+      int l, j;
+      if (LINE_FAST) {
+        j = (int)fL.div((uint32_t)u);
+        l = u - j * L;
+      } else {
+        l = (int)fnbf.div((uint32_t)u);
+        j = u - l * nbf;
+      }
+      const int g = (int)fNs.div((uint32_t)j);
+      const int k = j - g * Ns;
+      const int base = g * Ns * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[(base + r * Ns) * istride + l * lstride] = v[b][r];
     }
@@ -115,16 +140,17 @@ __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istrid
 template <typename T, int DIR, int ECAP, bool LINE_FAST>
 __device__ void mixed_fft(Cx<T>* lds, int N, int L, int istride, int lstride, const MixedPlan& mp,
                           const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
+  const FastDiv fL((uint32_t)L);
   int Ns = 1;
   for (int s = 0; s < mp.n_st; ++s) {
     const int R = mp.radix[s];
     switch (R) {
-      case 8: mixed_stage<T, DIR, 8, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
-      case 4: mixed_stage<T, DIR, 4, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
-      case 2: mixed_stage<T, DIR, 2, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
-      case 7: mixed_stage<T, DIR, 7, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
-      case 5: mixed_stage<T, DIR, 5, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
-      default: mixed_stage<T, DIR, 3, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr); break;
+      case 8: mixed_stage<T, DIR, 8, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+      case 4: mixed_stage<T, DIR, 4, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+      case 2: mixed_stage<T, DIR, 2, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+      case 7: mixed_stage<T, DIR, 7, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+      case 5: mixed_stage<T, DIR, 5, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+      default: mixed_stage<T, DIR, 3, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
     }
     Ns *= R;
   }

@@ -118,20 +118,21 @@ __global__ void __launch_bounds__(512) k_batch_row_r2c(BatchArgs a) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const T* img = (const T*)a.in + I->img_off + (int64_t)bb.first * nx;
   const V* tw = (const V*)a.tw + I->twx_off;
+  const FastDiv fN((uint32_t)N), fH((uint32_t)(N + 1));
   for (int t = tid; t < L * N; t += nthr) {
-    const int l = t / N, m = t - l * N;
+    const int l = (int)fN.div((uint32_t)t), m = t - l * N;
     const T* src = img + (int64_t)l * nx;
     const T x0 = 2 * m < nx ? src[2 * m] : T(0);
     const T x1 = 2 * m + 1 < nx ? src[2 * m + 1] : T(0);
     lds[l * LP + m] = mk<V>(x0, x1);
   }
   __syncthreads();
-  const MixedPlan px = I->px;
+  const MixedPlan& px = I->px;   // read per stage from the descriptor (no private copy)
   mixed_fft<T, 1, ECAP, false>(lds, N, L, 1, LP, px, tw, 2, tid, nthr);
   V* out = (V*)a.out + I->spec_off + (int64_t)bb.first * pitch;
   const int H = N + 1;
   for (int t = tid; t < L * H; t += nthr) {
-    const int l = t / H, k = t - l * H;
+    const int l = (int)fH.div((uint32_t)t), k = t - l * H;
     const V zk = lds[l * LP + (k == N ? 0 : k)];
     const V zc = cconj(lds[l * LP + (k == 0 ? 0 : N - k)]);
     const V ev = cscale(cadd(zk, zc), T(0.5));
@@ -153,46 +154,39 @@ __global__ void __launch_bounds__(ECAP == 8 ? 1024 : 512) k_batch_col_fused(Batc
   const int N = I->My, L = bb.count, ny = I->ny, pitch = I->pitch;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int NL = N * L;
+  const FastDiv fL((uint32_t)L);
+  // two LDS buffers: the forward spectrum (kept) and the inverse work column
+  V* spec = lds;
+  V* work = lds + NL;
   const V* in = (const V*)a.in + I->spec_off + bb.first;
   for (int t = tid; t < NL; t += nthr) {
-    const int i = t / L, l = t - i * L;
-    lds[t] = i < ny ? in[(int64_t)i * pitch + l] : mk<V>(T(0), T(0));
+    const int i = (int)fL.div((uint32_t)t), l = t - i * L;
+    spec[t] = i < ny ? in[(int64_t)i * pitch + l] : mk<V>(T(0), T(0));
   }
   __syncthreads();
-  const MixedPlan py = I->py;
+  const MixedPlan& py = I->py;
   const V* tw = (const V*)a.tw + I->twy_off;
-  mixed_fft<T, 1, ECAP, true>(lds, N, L, L, 1, py, tw, 1, tid, nthr);
-  V G[ECAP];
-#pragma unroll
-  for (int q = 0; q < ECAP; ++q) {
-    const int e = tid + q * nthr;
-    G[q] = e < NL ? lds[e] : mk<V>(T(0), T(0));
-  }
-  __syncthreads();
+  mixed_fft<T, 1, ECAP, true>(spec, N, L, L, 1, py, tw, 1, tid, nthr);
   const T* tab = (const T*)a.tab + I->tab_off + bb.first;
   V* out = (V*)a.out + I->fused_off + bb.first;
   const int64_t ch_out = (int64_t)ny * pitch;
   for (int c = 0; c < a.C; ++c) {
     const T* tc = tab + c * I->tab_stride;
     const bool odd_y = c == 2;   // u_y is odd in y; u_x and u_y carry the factor -i
-#pragma unroll
-    for (int q = 0; q < ECAP; ++q) {
-      const int e = tid + q * nthr;
-      if (e < NL) {
-        const int i = e / L, l = e - i * L;
-        const bool hi = 2 * i > N;
-        T tv = tc[(int64_t)(hi ? N - i : i) * pitch + l];
-        if (odd_y && hi) tv = -tv;
-        const V z = cscale(G[q], tv);
-        lds[e] = c == 0 ? z : mul_mi(z);
-      }
+    for (int e = tid; e < NL; e += nthr) {
+      const int i = (int)fL.div((uint32_t)e), l = e - i * L;
+      const bool hi = 2 * i > N;
+      T tv = tc[(int64_t)(hi ? N - i : i) * pitch + l];
+      if (odd_y && hi) tv = -tv;
+      const V z = cscale(spec[e], tv);
+      work[e] = c == 0 ? z : mul_mi(z);
     }
     __syncthreads();
-    mixed_fft<T, -1, ECAP, true>(lds, N, L, L, 1, py, tw, 1, tid, nthr);
+    mixed_fft<T, -1, ECAP, true>(work, N, L, L, 1, py, tw, 1, tid, nthr);
     V* oc = out + c * ch_out;
     for (int t = tid; t < ny * L; t += nthr) {
-      const int i = t / L, l = t - i * L;
-      oc[(int64_t)i * pitch + l] = lds[t];
+      const int i = (int)fL.div((uint32_t)t), l = t - i * L;
+      oc[(int64_t)i * pitch + l] = work[t];
     }
     __syncthreads();
   }
@@ -226,7 +220,7 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
     lds[line * LP + k] = mk<V>(ev.x - od.y, ev.y + od.x);   // ev + i od
   }
   __syncthreads();
-  const MixedPlan px = I->px;
+  const MixedPlan& px = I->px;   // read per stage from the descriptor (no private copy)
   mixed_fft<T, -1, ECAP, false>(lds, N, L * C, 1, LP, px, tw, 2, tid, nthr);
   const int64_t Ki = a.koff[ii + 1] - a.koff[ii];
   const int eg = ceil_log2_count(Ki);
