@@ -154,14 +154,13 @@ int ecap_for(int64_t elems, int nthr) {
 }
 
 // Default tiles: 512 threads per column block and the widest power-of-two
-// tile whose longest column set fits 32 elements per thread and 128 KiB of LDS.
+// tile whose longest column set fits 32 elements per thread and the LDS.
 dt_batch_tiles default_tiles(dt_batch_plan p) {
   int64_t my = 0;
   for (const auto& I : p->inst) my = std::max<int64_t>(my, I.My);
   dt_batch_tiles t{1, 512, 256};
-  const size_t lds_cap = std::min<size_t>((size_t)p->lds_max, 131072);
   for (int nb : {16, 8, 4, 2, 1})
-    if (my * nb <= 32 * 512 && (size_t)(2 * my * nb) * 2 * p->wsz() <= lds_cap) {
+    if (my * nb <= 32 * 512 && (size_t)(2 * my * nb + my) * 2 * p->wsz() <= (size_t)p->lds_max) {
       t.col_nb = nb;
       break;
     }
@@ -186,14 +185,15 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       const int c = std::min(r, I.ny - y);
       lists[P_R2C].push_back({i, y, c, 0});
       need[P_R2C] = std::max<int64_t>(need[P_R2C], sx * c);
-      lds[P_R2C] = std::max<size_t>(lds[P_R2C], (size_t)c * (sx + 1) * 2 * w);
+      lds[P_R2C] = std::max<size_t>(lds[P_R2C], (size_t)(c * (sx + 1) + 2 * sx) * 2 * w);   // lines + twiddles
     }
     // column pass: nb consecutive kx bins
     for (int kx = 0; kx <= sx; kx += nb) {
       const int c = (int)std::min<int64_t>(nb, sx + 1 - kx);
       lists[P_COL].push_back({i, kx, c, 0});
       need[P_COL] = std::max<int64_t>(need[P_COL], (int64_t)I.My * c);
-      lds[P_COL] = std::max<size_t>(lds[P_COL], (size_t)2 * I.My * c * 2 * w);   // spectrum + work column
+      // spectrum + work column + the twiddle table
+      lds[P_COL] = std::max<size_t>(lds[P_COL], (size_t)(2 * I.My * c + I.My) * 2 * w);
     }
     // epilogue: C lines per row
     r = std::min<int>(rows_per_block(sx, p->C, nt_row, w), I.ny);
@@ -201,7 +201,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       const int c = std::min(r, I.ny - y);
       lists[P_EPI].push_back({i, y, c, 0});
       need[P_EPI] = std::max<int64_t>(need[P_EPI], sx * c * p->C);
-      lds[P_EPI] = std::max<size_t>(lds[P_EPI], (size_t)c * p->C * (sx + 1) * 2 * w);
+      lds[P_EPI] = std::max<size_t>(lds[P_EPI], (size_t)(c * p->C * (sx + 1) + 2 * sx) * 2 * w);
     }
   }
   const int nthr[3] = {nt_row, nt_col, nt_row};

@@ -117,7 +117,9 @@ __global__ void __launch_bounds__(512) k_batch_row_r2c(BatchArgs a) {
   const int N = I->sx, L = bb.count, LP = N + 1, nx = I->nx, pitch = I->pitch;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const T* img = (const T*)a.in + I->img_off + (int64_t)bb.first * nx;
-  const V* tw = (const V*)a.tw + I->twx_off;
+  const V* twg = (const V*)a.tw + I->twx_off;
+  V* tw = lds + L * LP;      // exp(-2 pi i m / M_x), m < M_x, staged for every stage
+  for (int t = tid; t < 2 * N; t += nthr) tw[t] = twg[t];
   const FastDiv fN((uint32_t)N), fH((uint32_t)(N + 1));
   for (int t = tid; t < L * N; t += nthr) {
     const int l = (int)fN.div((uint32_t)t), m = t - l * N;
@@ -158,14 +160,17 @@ __global__ void __launch_bounds__(ECAP == 8 ? 1024 : 512) k_batch_col_fused(Batc
   // two LDS buffers: the forward spectrum (kept) and the inverse work column
   V* spec = lds;
   V* work = lds + NL;
+  V* twl = lds + 2 * NL;     // the instance's twiddles exp(-2 pi i m / M_y), read by every stage
   const V* in = (const V*)a.in + I->spec_off + bb.first;
   for (int t = tid; t < NL; t += nthr) {
     const int i = (int)fL.div((uint32_t)t), l = t - i * L;
     spec[t] = i < ny ? in[(int64_t)i * pitch + l] : mk<V>(T(0), T(0));
   }
+  const V* twg = (const V*)a.tw + I->twy_off;
+  for (int t = tid; t < N; t += nthr) twl[t] = twg[t];
   __syncthreads();
   const MixedPlan& py = I->py;
-  const V* tw = (const V*)a.tw + I->twy_off;
+  const V* tw = twl;
   mixed_fft<T, 1, ECAP, true>(spec, N, L, L, 1, py, tw, 1, tid, nthr);
   const T* tab = (const T*)a.tab + I->tab_off + bb.first;
   V* out = (V*)a.out + I->fused_off + bb.first;
@@ -207,11 +212,15 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
   const int nx = I->nx, ny = I->ny, pitch = I->pitch;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const V* in = (const V*)a.in + I->fused_off + (int64_t)bb.first * pitch;
-  const V* tw = (const V*)a.tw + I->twx_off;
+  const V* twg = (const V*)a.tw + I->twx_off;
+  V* tw = lds + L * C * LP;  // exp(-2 pi i m / M_x), m < M_x, staged for every stage
+  for (int t = tid; t < 2 * N; t += nthr) tw[t] = twg[t];
+  __syncthreads();
   const int64_t ch_in = (int64_t)ny * pitch;
+  const FastDiv fN((uint32_t)N), fC((uint32_t)C), fX((uint32_t)nx);
   for (int t = tid; t < L * C * N; t += nthr) {
-    const int line = t / N, k = t - line * N;
-    const int l = line / C, c = line - l * C;
+    const int line = (int)fN.div((uint32_t)t), k = t - line * N;
+    const int l = (int)fC.div((uint32_t)line), c = line - l * C;
     const V* src = in + c * ch_in + (int64_t)l * pitch;
     const V xk = src[k];
     const V xc = cconj(src[N - k]);
@@ -235,7 +244,7 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
   T* G = (T*)a.grad;
   const int64_t plane = (int64_t)nx * ny;
   for (int t = tid; t < L * nx; t += nthr) {
-    const int l = t / nx, x = t - l * nx;
+    const int l = (int)fX.div((uint32_t)t), x = t - l * nx;
     const int64_t node = (int64_t)(bb.first + l) * nx + x;
     const T cphi = ldr[(int64_t)(l * C) * 2 * LP + x];
     const T phi = cphi * scale_phi;
