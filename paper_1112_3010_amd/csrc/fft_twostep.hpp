@@ -335,10 +335,17 @@ template <typename T, int N, int NB> struct PairFFT {
       pair_twiddle<DIR, J + 1>(v, h);
     }
   }
-  static __device__ __forceinline__ float lane_xor(float x) { return __shfl_xor(x, NB); }
+  // value of lane ^ NB.  For NB = 8 the partner sits in the other half of the
+  // same 16-lane row: a DPP row rotate by 8 (a plain VALU move); otherwise a
+  // cross-lane permute.
+  static __device__ __forceinline__ int lane_xor_i(int x) {
+    if constexpr (NB == 8) return __builtin_amdgcn_update_dpp(0, x, 0x128 /* row_ror:8 */, 0xF, 0xF, false);
+    else return __shfl_xor(x, NB);
+  }
+  static __device__ __forceinline__ float lane_xor(float x) { return __int_as_float(lane_xor_i(__float_as_int(x))); }
   static __device__ __forceinline__ double lane_xor(double x) {
-    const int hi = __shfl_xor(__double2hiint(x), NB);
-    const int lo = __shfl_xor(__double2loint(x), NB);
+    const int hi = lane_xor_i(__double2hiint(x));
+    const int lo = lane_xor_i(__double2loint(x));
     return __hiloint2double(hi, lo);
   }
   // v[j] <- Z0 + (-1)^h Z1 where this lane holds Z_h and its partner Z_(1-h)

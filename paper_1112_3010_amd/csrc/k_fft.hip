@@ -22,6 +22,11 @@
 
 namespace dt {
 
+// LDS position of element i of a row line: XOR-swizzling the low five bits
+// with bits 3..7 spreads the strided Stockham accesses over the 64 banks
+// (a bijection on [0, N) for power-of-two N).
+__device__ __forceinline__ int row_swz(int i) { return i ^ ((i >> 3) & 31); }
+
 // ---------------------------------------------------------------------------
 // Row pass: real -> half spectrum
 // ---------------------------------------------------------------------------
@@ -52,7 +57,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
       const T c = (active && m + 1 < p.nx) ? src[m + 1] : T(0);
       v[s * R0 + r] = mk<V>(a, c);
     }
-  auto addr = [b](int i) { return b * LP + i; };
+  auto addr = [b](int i) { return b * LP + row_swz(i); };
   F::run(v, lds, q, tw, 2, addr);
   __syncthreads();
   F::store_last(lds, v, q, addr);
@@ -60,8 +65,8 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
   if (!active) return;
   V* dst = out + line * (int64_t)p.pitch;
   for (int k = q; k <= N; k += Q) {
-    const V zk = lds[b * LP + (k & (N - 1))];
-    const V zc = cconj(lds[b * LP + ((N - k) & (N - 1))]);
+    const V zk = lds[addr(k & (N - 1))];
+    const V zc = cconj(lds[addr((N - k) & (N - 1))]);
     const V ev = cscale(cadd(zk, zc), T(0.5));
     const V od = cscale(mul_mi(csub(zk, zc)), T(0.5));
     dst[k] = cadd(ev, cmul(tw[k], od));
@@ -239,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
       }
       v[s * R0 + r] = z;
     }
-  auto addr = [b](int i) { return b * LP + i; };
+  auto addr = [b](int i) { return b * LP + row_swz(i); };
   B::run(v, lds, q, tw, 2, addr);
   __syncthreads();
   T* ldr = reinterpret_cast<T*>(lds);

@@ -296,13 +296,11 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
       const bool flip = flip_o != (t.odd_line && ENG::fold_neg(pt));
       const T* tl = tab_lds + slot * SLICE + b + ENG::fold_base(pt) * NB;
       const int step = ENG::fold_step(pt) * NB;
-      T val[E];
-#pragma unroll
-      for (int i = 0; i < E; ++i) val[i] = flip ? -tl[i * step] : tl[i * step];
+      const T sgn = flip ? T(-1) : T(1);
       auto apply = [&](auto rot) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-          const V prod = rot(cscale(v[i], val[i]));
+          const V prod = rot(cscale(v[i], sgn * tl[i * step]));
           res[i] = accumulate ? cadd(res[i], prod) : prod;
         }
       };
