@@ -325,7 +325,17 @@ template <typename T, int N, int NB> struct PairFFT {
   static constexpr int PAD = 32;
   static constexpr int RS = P * NB + PAD;    // reals per k1 row of the exchange buffer
   static constexpr int LDS = E * RS;         // reals
-  using Tw = ThreadTwiddles<T, N, E>;
+  // all E - 1 thread twiddles W_N^(p k), k = 1 .. E-1, formed once per block
+  struct Tw {
+    V w[E];
+    __device__ __forceinline__ void load(const V* tw, int p) {
+      ThreadTwiddles<T, N, E> ab;
+      ab.load(tw, p);
+#pragma unroll
+      for (int k = 0; k < E; ++k) w[k] = ab.get(k);
+    }
+    __device__ __forceinline__ V get(int k) const { return w[k]; }
+  };
 
   template <int DIR, int J> static __device__ __forceinline__ void pair_twiddle(V* v, bool h) {
     if constexpr (J < E) {
@@ -348,16 +358,17 @@ template <typename T, int N, int NB> struct PairFFT {
     const int lo = lane_xor_i(__double2loint(x));
     return __hiloint2double(hi, lo);
   }
-  // v[j] <- Z0 + (-1)^h Z1 where this lane holds Z_h and its partner Z_(1-h)
+  // v[j] <- Z0 + (-1)^h Z1 where this lane holds Z_h and its partner Z_(1-h):
+  // lane 0 adds the partner's value, lane 1 subtracts its own from it, i.e.
+  // v <- sgn v + partner with sgn = (-1)^h (one FMA per component, no select)
   static __device__ __forceinline__ void pair_join(V* v, bool h) {
+    const T sgn = h ? T(-1) : T(1);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const T ox = lane_xor(v[j].x);
       const T oy = lane_xor(v[j].y);
-      const T rx = h ? ox - v[j].x : v[j].x + ox;
-      const T ry = h ? oy - v[j].y : v[j].y + oy;
-      v[j].x = rx;
-      v[j].y = ry;
+      v[j].x = fma(sgn, v[j].x, ox);
+      v[j].y = fma(sgn, v[j].y, oy);
     }
   }
   // (k1, p) -> (p >> 1, 2 m + (p & 1)) for the forward direction; reversed for the inverse
