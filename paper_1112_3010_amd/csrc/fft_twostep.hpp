@@ -316,15 +316,20 @@ __host__ __device__ constexpr int pair_E(int N) {
   return N == 32 ? 4 : N == 128 ? 8 : N == 512 ? 16 : N == 2048 ? 32 : 0;
 }
 
-template <typename T, int N, int NB> struct PairFFT {
+#ifndef DT_PAIR_SPLIT
+#define DT_PAIR_SPLIT 0
+#endif
+template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT> struct PairFFT {
   using V = Cx<T>;
   static constexpr int E = pair_E(N);
   static constexpr int P = 2 * E;
   static_assert(E > 0 && E * P == N, "pair split needs N = 2 E^2");
   static_assert(NB <= 32 && (NB & (NB - 1)) == 0, "lane pairs (q, q ^ 1) must share a wavefront");
-  static constexpr int PAD = 32;
-  static constexpr int RS = P * NB + PAD;    // reals per k1 row of the exchange buffer
-  static constexpr int LDS = E * RS;         // reals
+  // row stride of the exchange buffer (elements of the exchanged type): the
+  // padding puts the two rows that a half-wave reads on disjoint banks
+  static constexpr int PAD = SPLIT ? 32 : 16;
+  static constexpr int RS = P * NB + PAD;
+  static constexpr int LDS = E * RS * (SPLIT ? 1 : 2);   // reals
   // all E - 1 thread twiddles W_N^(p k), k = 1 .. E-1, formed once per block
   struct Tw {
     V w[E];
@@ -375,6 +380,20 @@ template <typename T, int N, int NB> struct PairFFT {
   template <bool FWD> static __device__ __forceinline__ void exchange(V* v, T* ldsr, int p, int b) {
     const int rq = (p >> 1) * RS + (p & 1) * NB + b;   // read base of the forward direction
     const int wp = p * NB + b;
+    if constexpr (SPLIT == 0) {
+      // whole complex values in one round (needs LDS complex elements)
+      V* lds = reinterpret_cast<V*>(ldsr);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        if (FWD) lds[k * RS + wp] = v[k];
+        else lds[rq + 2 * k * NB] = v[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = FWD ? lds[rq + 2 * k * NB] : lds[k * RS + wp];
+      return;
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < E; ++k) {
