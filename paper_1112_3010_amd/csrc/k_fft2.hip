@@ -82,6 +82,57 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
   }
 }
 
+// The same strided pass on the pair-split engine (N = 2 E^2, 8-column tiles).
+template <typename T, int N, int NB, int DIR, bool HALF>
+__global__ void __launch_bounds__(2 * pair_E(N) * NB) k_col2_c2c_pair(const Cx<T>* __restrict__ in,
+                                                                     Cx<T>* __restrict__ out, ColParams p) {
+  using V = Cx<T>;
+  using ENG = PairFFT<T, N, NB>;
+  constexpr int E = ENG::E, P = ENG::P;
+  __shared__ __align__(16) T xch[ENG::LDS];
+  const int tid = threadIdx.x;
+  const int b = tid % NB, pt = tid / NB;
+  const int kx = blockIdx.x * NB + b;
+  const bool active = kx < p.inner;
+  const int kxs = active ? kx : 0;
+  typename ENG::Tw tw;
+  tw.load((const V*)p.tw, pt);
+  const V* src = in + blockIdx.z * p.in_ch + blockIdx.y * p.in_outer + kxs;
+  V* dst = out + blockIdx.z * p.out_ch + blockIdx.y * p.out_outer + kxs;
+  V v[E];
+  if constexpr (DIR > 0) {
+    // natural input rows pt + P e (pruned), outputs in slot order
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = pt + P * e;
+      if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
+      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
+    }
+    ENG::forward_split(v, xch, pt, b, tw);
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = ENG::slot(pt, j);
+      if (k < p.n_out) dst[(int64_t)k * p.out_line] = v[j];
+    }
+  } else {
+    // inputs in slot order, natural output rows pt + P n2 (pruned)
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int k = ENG::slot(pt, j);
+      v[j] = (active && k < p.n_in) ? src[(int64_t)k * p.in_line] : mk<V>(T(0), T(0));
+    }
+    ENG::inverse_split(v, xch, pt, b, tw);
+    if (!active) return;
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      if (HALF && n2 >= E / 2) continue;
+      const int n = pt + P * n2;
+      if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
+    }
+  }
+}
+
 template <typename T, int N, int E, int NB, bool HALF>
 __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __restrict__ in, Cx<T>* __restrict__ out,
                                                             ColParams p, FusedSpec fs) {
@@ -178,10 +229,11 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 // one kx tile at one |ky|) is a contiguous run that is copied with 16-byte
 // loads.  With MIRROR the block owns the column pair (ky, M_y - ky), which
 // share the slice: every folded table entry then serves all four spectral
-// points (+-ky, +-kz) from one read.  The transform engine ENG (TwoStep or
-// PairFFT) exchanges real and imaginary parts in two rounds through a real
-// LDS buffer, and the tables are staged kTabChunk channels at a time, which
-// keeps the block's LDS small enough for two blocks per CU.
+// points (+-ky, +-kz) from one read.  The transform engine ENG is PairFFT
+// (one complex LDS exchange) or TwoStep (real and imaginary parts exchanged in
+// two rounds through a real LDS buffer); the tables are staged kTabChunk
+// channels at a time, which keeps the block's LDS small enough for two blocks
+// per CU.
 #ifndef DT_TAB_CHUNK
 #define DT_TAB_CHUNK 4
 #endif
@@ -202,6 +254,15 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 #ifndef DT_FUSED_PAIR64
 #define DT_FUSED_PAIR64 1
 #endif
+// The float64 strided C2C passes use the pair-split engine at these lengths
+// (in float32 the two-step kernel with 16-column tiles streams faster).
+#ifndef DT_C2C_PAIR
+#define DT_C2C_PAIR 1
+#endif
+constexpr int kPairNB = 8;
+template <typename T> constexpr bool c2c_pair(int N) {
+  return DT_C2C_PAIR != 0 && sizeof(T) == 8 && (N == 128 || N == 512);
+}
 template <typename T> constexpr bool fused_pair(int N) {
   return DT_FUSED_PAIR != 0 && (sizeof(T) == 4 || DT_FUSED_PAIR64 != 0) && pair_E(N) > 0 && N >= 128 && N <= 512;
 }
@@ -402,6 +463,7 @@ int col2_tile_width(int N, bool fp64, bool fused) {
   int E = fp64 ? (fused ? twostep_E<double, true>(N) : twostep_E<double, false>(N))
                : (fused ? twostep_E<float, true>(N) : twostep_E<float, false>(N));
   if (fused && (fp64 ? fused_pair<double>(N) : fused_pair<float>(N))) E = pair_E(N);
+  if (!fused && (fp64 ? c2c_pair<double>(N) : c2c_pair<float>(N))) return kPairNB;
   if (E == 0) return 0;
   if (fused) return fp64 ? twostep_NB<double, true>() : twostep_NB<float, true>();
   return fp64 ? twostep_NB<double>() : twostep_NB<float>();
@@ -413,6 +475,24 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
                                            int outer, int chans, hipStream_t st) {
   const dim3 grid(tiles, outer, chans);
   const bool half = dir > 0 ? (2 * p.n_in == N) : (2 * p.n_out == N);
+  if (c2c_pair<T>(N)) {
+    const Cx<T>* i_ = (const Cx<T>*)in;
+    Cx<T>* o_ = (Cx<T>*)out;
+    switch (N) {
+#define CASEP(NN)                                                                                         \
+  case NN: {                                                                                              \
+    constexpr int NT = 2 * pair_E(NN) * kPairNB;                                                          \
+    if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, true>), grid, dim3(NT), 0, st, i_, o_, p);  \
+    else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, false>), grid, dim3(NT), 0, st, i_, o_, p);    \
+    else if (half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, true>), grid, dim3(NT), 0, st, i_, o_, p);       \
+    else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, false>), grid, dim3(NT), 0, st, i_, o_, p);                \
+    return true;                                                                                          \
+  }
+      CASEP(128) CASEP(512)
+#undef CASEP
+      default: break;
+    }
+  }
   switch (N) {
 #define CASE(NN)                                                                                          \
   case NN: {                                                                                              \
