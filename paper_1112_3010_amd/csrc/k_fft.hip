@@ -379,10 +379,13 @@ template <typename T> bool launch_col_fused(const void* in, void* out, const Col
   }
 }
 
+#ifndef DT_EPI_THREADS
+#define DT_EPI_THREADS 128
+#endif
 template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p, const EpiParams& e, int N,
                                               hipStream_t st) {
   const int Q = N / 8;
-  int rpb = 256 / (e.C * Q);
+  int rpb = DT_EPI_THREADS / (e.C * Q);
   if (rpb < 1) rpb = 1;
   const int threads = rpb * e.C * Q;
   if (threads > 1024) return false;
