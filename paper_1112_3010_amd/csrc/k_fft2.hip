@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
   };
-  auto load_fwd = [&](int ch, int o, V* v) {
+  auto issue_load = [&](int ch, int o, V* v) {
     const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -344,6 +344,9 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
       if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
       else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
     }
+  };
+  auto load_fwd = [&](int ch, int o, V* v) {
+    issue_load(ch, o, v);
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the column and any table copy issued before it
     ENG::forward_split(v, xch, pt, b, tw);      // starts with a barrier
   };
@@ -400,17 +403,27 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
 
   if (G.mode == 0) {
     if (IT.c1 - IT.c0 <= kTabChunk) {
-      // every table of the item fits: stage once for both columns
+      // every table of the item fits: stage once for both columns.  The
+      // second column's input is loaded before the first column's stores, so
+      // waiting for it does not wait for those stores (the vector memory
+      // counter covers loads and stores in issue order).
       stage(&G.tab[IT.c0], IT.c1 - IT.c0);
+      V spec[E];
+      load_fwd(G.in_ch[0], column(0), spec);
       for (int col = 0; col < n_cols; ++col) {
         const int o = column(col);
         const bool o_neg = 2 * o > p.outer_len;
-        V spec[E];
-        load_fwd(G.in_ch[0], o, spec);
+        V nxt[E];
+        if (col + 1 < n_cols) issue_load(G.in_ch[0], column(col + 1), nxt);
         for (int c = IT.c0; c < IT.c1; ++c) {
           V v[E];
           times(c - IT.c0, G.tab[c], o_neg, spec, v, false);
           inv_store(v, G.out_ch[c], o);
+        }
+        if (col + 1 < n_cols) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) spec[e] = nxt[e];
+          ENG::forward_split(spec, xch, pt, b, tw);
         }
       }
     } else {
