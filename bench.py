@@ -95,7 +95,13 @@ def kernel_hash():
     return h.hexdigest()
 
 
-def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls):
+def sample_cells(dims, n_cells, seed=0):
+    """Random node sample shared by the CPU baseline and the accuracy report."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(int(np.prod(dims)), n_cells, replace=False))
+
+
+def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
     import torch
     import paper_1112_3010_amd as dt
     t0 = time.time()
@@ -149,6 +155,10 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls):
         "s_max_over_tau": stats["s_max"] / tau,
         "padded": list(Mp),
     }
+    if cells is not None:
+        idx = torch.from_numpy(cells).cuda()
+        res["sample_S"] = out["S"].reshape(-1)[idx].double().cpu().numpy()
+        res["sample_grad"] = out["grad"].reshape(len(dims), -1)[:, idx].double().cpu().numpy().T
     del plan
     torch.cuda.empty_cache()
     return res
@@ -227,9 +237,11 @@ def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
     return res
 
 
-def cpu_baseline(V, F, dims, tau, n_cells, seed=0):
+def cpu_baseline(V, F, dims, tau, cells, gpu_results=()):
     """The oracle (FP64 direct sums, S and grad S) on a bounded random sample
-    of nodes of the same workload, one core."""
+    of nodes of the same workload, one core.  Its fields also give the GPU
+    results' errors on that sample: |S - min(S_exact, S_max)| on every sampled
+    node, the gradient on nodes with phi >= 2 Theta."""
     import oracle
     from threadpoolctl import threadpool_limits
     inc, _ = oracle.mesh_sources(V, F)
@@ -237,16 +249,32 @@ def cpu_baseline(V, F, dims, tau, n_cells, seed=0):
     o = (0.0,) * len(dims)
     idx, valid = oracle.sign.snap_f64(inc, o, h, dims)
     Yh = oracle.node_coords(idx[valid], o, h)
-    rng = np.random.default_rng(seed)
-    cells = rng.choice(int(np.prod(dims)), n_cells, replace=False)
     X = oracle.grid_nodes(dims, o, h, cells)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        oracle.fields(X, Yh, tau, grad=True)
+        f = oracle.fields(X, Yh, tau, grad=True)
         dt_s = time.perf_counter() - t0
-    return {"value": n_cells / dt_s, "unit": "grid pts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cells} random nodes of the 256^3 grid, all {int(valid.sum())} sources each, "
-                      f"S and grad S in float64 ({dt_s:.1f} s)"}
+    out = {"value": len(cells) / dt_s, "unit": "grid pts/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(cells)} random nodes of the 256^3 grid, all {int(valid.sum())} sources each, "
+                     f"S and grad S in float64 ({dt_s:.1f} s)"}
+    _, mult = oracle.cell_multiplicities(idx[valid], dims)
+    g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
+    Mp = tuple(max(64, 1 << int(np.ceil(np.log2(2 * n)))) for n in dims)
+    l1 = oracle.kernel_l1(Mp, h, tau)
+    acc = {}
+    for prec, r in gpu_results:
+        if r is None or "sample_S" not in r:
+            continue
+        th = oracle.theta(prec, Mp, l1, g_l2)
+        s_ref = np.minimum(f["S"], oracle.s_max(tau, th))
+        deep = f["lnphi"] >= np.log(2.0 * th)
+        eS = np.abs(r["sample_S"] - s_ref)
+        eG = np.abs(r["sample_grad"] - f["grad"])[deep]
+        acc[prec] = {"max_abs_S_over_tau": float(eS.max() / tau),
+                     "max_abs_S_over_tau_deep": float(eS[deep].max() / tau) if deep.any() else None,
+                     "max_abs_grad_deep": float(eG.max()) if eG.size else None,
+                     "deep_nodes": int(deep.sum()), "s_max_over_tau": oracle.s_max(tau, th) / tau}
+    return out, acc
 
 
 def batch_bytes(dims, w, C):
@@ -357,15 +385,16 @@ def main():
     tau = 1.0 / n
     V, F = synth.harmonic_star_mesh(seed=3)
     log(f"workload: 256^3, {len(F)} triangles, tau = h")
-    r32 = run_gpu("fp32", V, F, dims, tau, args.steps, args.warmup, args.timing_calls)
-    log("fp32:", json.dumps(r32))
+    cells = sample_cells(dims, args.cpu_cells)
+    r32 = run_gpu("fp32", V, F, dims, tau, args.steps, args.warmup, args.timing_calls, cells)
+    log("fp32:", json.dumps({k: v for k, v in r32.items() if not k.startswith("sample_")}))
     Yc = triangle_centres(V, F)
     b32 = run_backward("fp32", Yc, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
     log("fp32 backward:", json.dumps(b32))
     r64 = b64 = None
     if not args.no_fp64:
-        r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
-        log("fp64:", json.dumps(r64))
+        r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls, cells)
+        log("fp64:", json.dumps({k: v for k, v in r64.items() if not k.startswith("sample_")}))
         b64 = run_backward("fp64", Yc, dims, tau, max(5, args.steps // 4), args.warmup, args.timing_calls)
         log("fp64 backward:", json.dumps(b64))
     khash = kernel_hash()
@@ -406,9 +435,10 @@ def main():
                                  "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3)},
                         "backward": b64}
     if not args.no_cpu:
-        cb = cpu_baseline(V, F, dims, tau, args.cpu_cells)
+        cb, acc = cpu_baseline(V, F, dims, tau, cells, [("fp32", r32), ("fp64", r64)])
         cb["value"] = round(cb["value"], 2)
         line["cpu_baseline"] = cb
+        line["accuracy_vs_oracle"] = dict(acc, sample=f"the cpu_baseline's {len(cells)} nodes")
     print(json.dumps(line), flush=True)
 
 
