@@ -16,6 +16,8 @@
 //                and the winding number / degree label of Sec. 4.
 #include <math.h>
 
+#include <algorithm>
+
 #include "dt_launch.hpp"
 #include "fft_engine.hpp"
 #include "epilogue.hpp"
@@ -206,6 +208,9 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 // ---------------------------------------------------------------------------
 // Row pass: half spectrum -> real, fused with the epilogue
 // ---------------------------------------------------------------------------
+#ifndef DT_EPI_DMA
+#define DT_EPI_DMA 1
+#endif
 template <typename T, int N>
 __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
@@ -227,8 +232,61 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
   const int64_t row = (int64_t)blockIdx.x * RPB + rl;
   const bool active = row < e.n_rows;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
-  const V* src = in + (int64_t)c * e.ch_stride + (active ? row : 0) * (int64_t)p.pitch;
   V v[E];
+#if DT_EPI_DMA
+  // Copy the block's half-spectrum lines into LDS with direct global-to-LDS
+  // loads (16-byte words, one contiguous run per line, no registers), then
+  // read each bin k and its mirror N - k from there.  A line of N + 1 bins
+  // is rounded up to whole words; the row pitch (>= N + 2 complex values)
+  // keeps the rounded read inside the row.
+  constexpr int W16 = ((N + 1) * (int)sizeof(V) + 15) / 16;   // words per line
+  constexpr int LW = W16 * 16 / (int)sizeof(V);               // complex values per staged line
+  V twk[E];
+#pragma unroll
+  for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) twk[s * R0 + r] = tw[B::template in_index<0>(q, s, r)];
+  {
+    // Only whole waves copy: a wave's copy writes 64 consecutive words, one
+    // per hardware lane, and a partial last wave lacks some of those lanes.
+    // The launch has at least one whole wave.
+    const int words = lines * W16;
+    const int lane = tid & 63, w = tid >> 6, nfw = blockDim.x >> 6;
+    for (int r = w; w < nfw && r * 64 < words; r += nfw) {
+      const int u = r * 64 + lane;
+      const int line = u / W16, wd = u - line * W16;
+      const int64_t row_u = (int64_t)blockIdx.x * RPB + line / C;
+      if (u < words && row_u < e.n_rows) {
+        const uint4* g = reinterpret_cast<const uint4*>(in + (int64_t)(line % C) * e.ch_stride +
+                                                        row_u * (int64_t)p.pitch) + wd;
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)g,
+                                         (__attribute__((address_space(3))) void*)((uint4*)smem_raw + r * 64), 16,
+                                         0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+  }
+  const V* raw = lds + b * LW;
+#pragma unroll
+  for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int k = B::template in_index<0>(q, s, r);
+      V z = mk<V>(T(0), T(0));
+      if (active) {
+        const V xk = raw[k];
+        const V xc = cconj(raw[N - k]);
+        const V ev = cadd(xk, xc);
+        const V od = cmul(csub(xk, xc), cconj(twk[s * R0 + r]));
+        z = mk<V>(ev.x - od.y, ev.y + od.x);  // ev + i * od
+      }
+      v[s * R0 + r] = z;
+    }
+  // the staged lines alias the exchange buffer: B::run passes a barrier
+  // before its first LDS store
+#else
+  const V* src = in + (int64_t)c * e.ch_stride + (active ? row : 0) * (int64_t)p.pitch;
 #pragma unroll
   for (int s = 0; s < E / R0; ++s)
 #pragma unroll
@@ -244,6 +302,7 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
       }
       v[s * R0 + r] = z;
     }
+#endif
   auto addr = [b](int i) { return b * LP + row_swz(i); };
   B::run(v, lds, q, tw, 2, addr);
   __syncthreads();
@@ -388,9 +447,14 @@ template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p
   int rpb = DT_EPI_THREADS / (e.C * Q);
   if (rpb < 1) rpb = 1;
   const int threads = rpb * e.C * Q;
-  if (threads > 1024) return false;
+  if (threads > 1024 || (DT_EPI_DMA && threads < 64)) return false;
   const int64_t blocks = (e.n_rows + rpb - 1) / rpb;
-  const size_t shmem = (size_t)rpb * e.C * (N + 1) * sizeof(Cx<T>);
+  // exchange lines of N + 1 values; the staged input lines are rounded up to
+  // whole 16-byte words (and need that much row pitch)
+  const size_t stage_line = ((size_t)(N + 1) * sizeof(Cx<T>) + 15) / 16 * 16;
+  if (DT_EPI_DMA && (size_t)p.pitch * sizeof(Cx<T>) < stage_line) return false;
+  const size_t shmem = std::max((size_t)rpb * e.C * (N + 1) * sizeof(Cx<T>),
+                                DT_EPI_DMA ? (size_t)rpb * e.C * stage_line : (size_t)0);
   // Beyond 64 KiB (long float64 rows with many channels) the kernel needs the
   // larger per-workgroup LDS of gfx950, granted per kernel.
   int dev = 0, lds_max = 65536;

@@ -238,8 +238,6 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 #define DT_TAB_CHUNK 4
 #endif
 constexpr int kTabChunk = DT_TAB_CHUNK;
-// s_waitcnt immediate with vmcnt = 0 and expcnt, lgkmcnt at their maxima (no wait on those)
-constexpr int kWaitVmcnt0 = 0x0F70;
 #ifndef DT_FUSED_MIRROR
 #define DT_FUSED_MIRROR 1
 #endif
