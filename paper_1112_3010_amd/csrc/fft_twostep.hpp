@@ -354,7 +354,7 @@ template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT> struct PairFFT {
   // same 16-lane row: a DPP row rotate by 8 (a plain VALU move); otherwise a
   // cross-lane permute.
   static __device__ __forceinline__ int lane_xor_i(int x) {
-    if constexpr (NB == 8) return __builtin_amdgcn_update_dpp(0, x, 0x128 /* row_ror:8 */, 0xF, 0xF, false);
+    if constexpr (NB == 8) return __builtin_amdgcn_mov_dpp(x, 0x128 /* row_ror:8 */, 0xF, 0xF, false);
     else return __shfl_xor(x, NB);
   }
   static __device__ __forceinline__ float lane_xor(float x) { return __int_as_float(lane_xor_i(__float_as_int(x))); }
