@@ -354,7 +354,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--timing-calls", type=int, default=10)
-    ap.add_argument("--cpu-cells", type=int, default=4096)
+    ap.add_argument("--cpu-cells", type=int, default=12288)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", choices=["mesh256", "batch"], default="mesh256",
