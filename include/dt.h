@@ -240,8 +240,10 @@ typedef struct {
   double kernel_l1;      /* ||f||_1 over the instance's padded grid */
 } dt_batch_instance_info_t;
 
-/* Launch shape of the batched passes: column tile width (kx bins per block)
- * and threads per block of the column pass and of the two row passes. */
+/* Launch shape of the batched passes: column tile width (kx bins per block
+ * for the instances with the longest columns; an instance with shorter
+ * columns takes proportionally more bins, up to 64) and threads per block of
+ * the column pass and of the two row passes. */
 typedef struct {
   int col_nb;
   int col_threads;   /* 64 .. 1024 */

@@ -176,6 +176,8 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
   size_t lds[3] = {0, 0, 0};
   const int nt_row = p->tiles.row_threads, nt_col = p->tiles.col_threads, nb = p->tiles.col_nb;
   if (nt_row < 64 || nt_row > 512 || nt_col < 64 || nt_col > 1024 || nb < 1 || nb > 64) return DT_E_ARG;
+  int64_t my_max = 0;
+  for (const auto& I : p->inst) my_max = std::max<int64_t>(my_max, I.My);
   for (int i = 0; i < p->n; ++i) {
     const BatchInst& I = p->inst[i];
     const int64_t sx = I.sx;
@@ -187,9 +189,13 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       need[P_R2C] = std::max<int64_t>(need[P_R2C], sx * c);
       lds[P_R2C] = std::max<size_t>(lds[P_R2C], (size_t)(c * (sx + 1) + 2 * sx) * 2 * w);   // lines + twiddles
     }
-    // column pass: nb consecutive kx bins
-    for (int kx = 0; kx <= sx; kx += nb) {
-      const int c = (int)std::min<int64_t>(nb, sx + 1 - kx);
+    // column pass: the tile width applies to the longest columns; shorter
+    // columns take proportionally more bins (the same elements per block,
+    // at most 64 bins), so small instances still fill the block's threads
+    // and read longer row segments
+    const int nbi = (int)std::min<int64_t>(64, std::max<int64_t>(nb, nb * my_max / I.My));
+    for (int kx = 0; kx <= sx; kx += nbi) {
+      const int c = (int)std::min<int64_t>(nbi, sx + 1 - kx);
       lists[P_COL].push_back({i, kx, c, 0});
       need[P_COL] = std::max<int64_t>(need[P_COL], (int64_t)I.My * c);
       // spectrum + work column + the twiddle table
