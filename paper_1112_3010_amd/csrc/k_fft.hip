@@ -32,6 +32,9 @@ __device__ __forceinline__ int row_swz(int i) { return i ^ ((i >> 3) & 31); }
 // ---------------------------------------------------------------------------
 // Row pass: real -> half spectrum
 // ---------------------------------------------------------------------------
+#ifndef DT_R2C_DMA
+#define DT_R2C_DMA 1
+#endif
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>* __restrict__ out, RowParams p) {
   using V = Cx<T>;
@@ -41,26 +44,56 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
   constexpr int LP = N + 1;
   constexpr int R0 = fft_radix(N, 0);
   using F = Stockham<T, N, E, +1>;
-  __shared__ V lds[LPB * LP];
+  __shared__ __align__(16) V lds[LPB * LP];
   const int tid = threadIdx.x;
   const int q = tid % Q, b = tid / Q;
   const int64_t line = (int64_t)blockIdx.x * LPB + b;
   const bool active = line < p.n_lines;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
-  const T* src = in + (active ? line : 0) * (int64_t)p.nx;
   V v[E];
-#pragma unroll
-  for (int s = 0; s < E / R0; ++s)
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int i = F::template in_index<0>(q, s, r);
-      const int m = 2 * i;
-      const T a = (active && m < p.nx) ? src[m] : T(0);
-      const T c = (active && m + 1 < p.nx) ? src[m + 1] : T(0);
-      v[s * R0 + r] = mk<V>(a, c);
+  if (DT_R2C_DMA && (p.nx * (int)sizeof(T)) % 16 == 0) {
+    // The block's rows are one contiguous run of LPB * nx reals: copy it
+    // into LDS with direct global-to-LDS loads (16-byte words), then take
+    // each thread's sample pairs from there.  The rows (nx <= 2N reals)
+    // fit the exchange buffer, which B::run writes only after a barrier.
+    const int wpl = p.nx * (int)sizeof(T) / 16;   // words per row
+    const int64_t line0 = (int64_t)blockIdx.x * LPB;
+    const int64_t rows = p.n_lines - line0 < LPB ? p.n_lines - line0 : LPB;
+    const int words = (int)rows * wpl;
+    const uint4* g = reinterpret_cast<const uint4*>(in + line0 * (int64_t)p.nx);
+    const int lane = tid & 63, w = tid >> 6, nfw = blockDim.x >> 6;   // whole waves only
+    for (int r = w; w < nfw && r * 64 < words; r += nfw) {
+      const int u = r * 64 + lane;
+      if (u < words)
+        __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(g + u),
+                                         (__attribute__((address_space(3))) void*)((uint4*)lds + r * 64), 16, 0, 0);
     }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    const T* raw = reinterpret_cast<const T*>(lds) + b * p.nx;
+#pragma unroll
+    for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int m = 2 * F::template in_index<0>(q, s, r);
+        const T a = (active && m < p.nx) ? raw[m] : T(0);
+        const T c = (active && m + 1 < p.nx) ? raw[m + 1] : T(0);
+        v[s * R0 + r] = mk<V>(a, c);
+      }
+  } else {
+    const T* src = in + (active ? line : 0) * (int64_t)p.nx;
+#pragma unroll
+    for (int s = 0; s < E / R0; ++s)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int m = 2 * F::template in_index<0>(q, s, r);
+        const T a = (active && m < p.nx) ? src[m] : T(0);
+        const T c = (active && m + 1 < p.nx) ? src[m + 1] : T(0);
+        v[s * R0 + r] = mk<V>(a, c);
+      }
+  }
   auto addr = [b](int i) { return b * LP + row_swz(i); };
-  F::run(v, lds, q, tw, 2, addr);
+  F::run(v, lds, q, tw, 2, addr);   // its first LDS store follows a barrier
   __syncthreads();
   F::store_last(lds, v, q, addr);
   __syncthreads();
