@@ -26,6 +26,9 @@ What it computes, each by its plain definition in float64 with NumPy:
   convolution) in float64 with ``numpy.fft``, for context timing and as an
   independent check of the grid conventions.
 * ``metrics``    — the percentage error of Sec. 6.1 (eq. percentError).
+* ``curvature``  — Gaussian, mean and principal curvatures from the gradient
+  and Hessian (the derived quantities named at the end of Sec. 5): of the
+  graph surface (x, y, S) in 2D, of the level surfaces of S in 3D.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against values that do
 not come from the oracle itself (closed forms, the paper's bounds and printed
@@ -49,3 +52,4 @@ from .validity import kernel_l1, theta, s_max, UNIT_ROUNDOFF, C_THETA  # noqa: F
 from .adjoint import loss_gradients  # noqa: F401
 from .metrics import percent_error  # noqa: F401
 from .table1 import table1_distance  # noqa: F401
+from .curvature import curvature, graph_curvature, level_set_curvature, G_MIN  # noqa: F401
