@@ -151,6 +151,7 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
         "pass_gbs": {k: round(nbytes[k] / (avg[k] * 1e-3) / 1e9, 1) for k in avg if k in nbytes},
         "dom_bytes": nbytes[dom],
         "model_bytes": total_model,
+        "pass_bytes": nbytes,
         "path_gbs": total_model / (ms * 1e-3) / 1e9,
         "s_max_over_tau": stats["s_max"] / tau,
         "padded": list(Mp),
@@ -233,6 +234,55 @@ def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
                     "pass_ms": {k: round(v, 4) for k, v in avg.items()},
                     "pass_gbs": {k: round(nbytes[k] / (avg[k] * 1e-3) / 1e9, 1) for k in avg if k in nbytes}}}
     del plan
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_curvature(prec, Y, dims, tau, steps, warmup, timing_calls):
+    """Time dt_forward with S and the curvature outputs (mean, Gaussian, k1,
+    k2) on the 256^3 grid: the gradient and Hessian channels (1 + D + D(D+1)/2
+    output channels through the fused pass) and the curvature epilogue."""
+    import torch
+    import paper_1112_3010_amd as dt
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "curv"])
+    Yd = torch.from_numpy(Y).cuda()
+    out = {"S": plan._empty(), "curv": plan._empty(4)}
+    for _ in range(warmup):
+        plan.forward_into(out, Yd)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.forward_into(out, Yd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.set_timing(True)
+    plan.timings(reset=True)
+    for _ in range(timing_calls):
+        plan.forward_into(out, Yd)
+    per = plan.timings(reset=True)
+    plan.set_timing(False)
+    D = len(dims)
+    C = 1 + D + D * (D + 1) // 2
+    w = 8 if prec == "fp64" else 4
+    nbytes = pass_bytes(dims, plan.padded, w, c_in=1, c_out=C, n_tab=C, out_fields=5)
+    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
+    total = sum(nbytes.values())
+    N = int(np.prod(dims))
+    res = {"value": round(N / (ms * 1e-3), 1), "unit": "grid pts/s", "ms_per_call": round(ms, 4),
+           "outputs": "S + mean, Gaussian, k1, k2 (10 channels)",
+           "roofline": {"bound": "hbm", "achieved": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": dom, "bytes_per_launch": nbytes[dom]},
+           "path": {"model_bytes": total, "achieved_gbs": round(total / (ms * 1e-3) / 1e9, 1),
+                    "frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "pass_ms": {k: round(v, 4) for k, v in avg.items()}}}
+    del plan, out
     torch.cuda.empty_cache()
     return res
 
@@ -391,6 +441,8 @@ def main():
     Yc = triangle_centres(V, F)
     b32 = run_backward("fp32", Yc, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
     log("fp32 backward:", json.dumps(b32))
+    c32 = run_curvature("fp32", Yc, dims, tau, max(5, args.steps // 5), args.warmup, args.timing_calls)
+    log("fp32 curvature:", json.dumps(c32))
     r64 = b64 = None
     if not args.no_fp64:
         r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls, cells)
@@ -398,6 +450,17 @@ def main():
         b64 = run_backward("fp64", Yc, dims, tau, max(5, args.steps // 4), args.warmup, args.timing_calls)
         log("fp64 backward:", json.dumps(b64))
     khash = kernel_hash()
+
+    def counter_frac(r, prec):
+        """Whole-path HBM bytes from the rocprofv3 counters of the passes that
+        have them (the rest at their algorithmic bytes), over the call's time."""
+        got = {k: counters_for(khash, prec, k) for k in r["pass_bytes"]}
+        if got.get(r["dominant"]) is None:
+            return None
+        total = sum(v if v is not None else r["pass_bytes"][k] for k, v in got.items())
+        gbs = total / (r["ms_per_step"] * 1e-3) / 1e9
+        return {"bytes": int(total), "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "passes_with_counters": sorted(k for k, v in got.items() if v is not None)}
 
     def roof(r, prec):
         traffic = counters_for(khash, prec, r["dominant"])
@@ -424,15 +487,17 @@ def main():
         "path": {"model_bytes": r32["model_bytes"], "achieved_gbs": round(r32["path_gbs"], 1),
                  "frac": round(r32["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r32["pass_ms"],
                  "pass_gbs": r32["pass_gbs"], "s_max_over_tau": round(r32["s_max_over_tau"], 3),
-                 "plan_setup_s": round(r32["plan_setup_s"], 3)},
+                 "plan_setup_s": round(r32["plan_setup_s"], 3), "counters": counter_frac(r32, "fp32")},
     }
     line["backward"] = b32
+    line["curvature"] = c32
     if r64 is not None:
         line["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
                         "dtype": "f64", "roofline": roof(r64, "fp64"),
                         "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
                                  "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
-                                 "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3)},
+                                 "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3),
+                                 "counters": counter_frac(r64, "fp64")},
                         "backward": b64}
     if not args.no_cpu:
         cb, acc = cpu_baseline(V, F, dims, tau, cells, [("fp32", r32), ("fp64", r64)])

@@ -80,7 +80,8 @@ enum {
   DT_OUT_GRAD = 2,       /* gradient of S (kernels (X_i/r) f)             */
   DT_OUT_HESS = 4,       /* Hessian of S (kernels H_ij)                    */
   DT_OUT_SIGN = 8,       /* winding number / topological degree kernels   */
-  DT_OUT_BACKWARD = 16   /* adjoint: gradient kernels and r f for d/dtau  */
+  DT_OUT_BACKWARD = 16,  /* adjoint: gradient kernels and r f for d/dtau  */
+  DT_OUT_CURV = 32       /* curvatures: the gradient and Hessian kernels   */
 };
 
 /* Closed boundary for the sign (and, optionally, the sources). */
@@ -102,7 +103,17 @@ enum { DT_SHAPE_POLYGON = 1, DT_SHAPE_MESH = 2 };
 /* Output buffers for dt_forward (device pointers; NULL = not wanted).
  * S: N values; grad: ndim x N (channel first); hess: ndim(ndim+1)/2 x N in
  * the order xx, xy, [xz,] yy, [yz,] zz; label: N int8 (+1 inside, -1
- * outside); mu: N values.  N = prod dims.  Value type = plan type. */
+ * outside); mu: N values.  N = prod dims.  Value type = plan type.
+ * curv (needs DT_OUT_CURV or DT_OUT_HESS): 4 x N, channel first: mean,
+ * Gaussian and the two principal curvatures k1 >= k2 (the derived quantities
+ * named at the end of Sec. 5), computed per node from grad S and the Hessian
+ * of the unsigned S.  2D: of the graph surface (x, y, S), upward normal:
+ * W = 1 + |grad S|^2, Gaussian = det(H) / W^2, mean = ((1 + S_y^2) S_xx
+ * - 2 S_x S_y S_xy + (1 + S_x^2) S_yy) / (2 W^1.5).  3D: of the level surface
+ * of S through the node, normal grad S / |grad S|: mean = (|g|^2 tr H
+ * - g^T H g) / (2 |g|^3), Gaussian = g^T adj(H) g / |g|^4, and 0 for all four
+ * where |grad S| < 1e-3.  k1,2 = mean +/- sqrt(max(mean^2 - Gaussian, 0)).
+ * Nodes outside the valid band (zero derivatives) get 0. */
 typedef struct {
   void* S;
   void* grad;
@@ -110,6 +121,7 @@ typedef struct {
   int8_t* label;
   void* mu;
   int signed_outputs;    /* nonzero: S and grad are multiplied by the label */
+  void* curv;
 } dt_outputs;
 
 typedef struct {

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("DT_LIB_PATH") or os.path.join(HERE, "libdt.so")
 
 DT_OK, DT_E_ARG, DT_E_RANGE, DT_E_PRECISION, DT_E_WORKSPACE, DT_E_HIP, DT_E_UNSUPPORTED = range(7)
 DT_FP32_SCALED, DT_FP64, DT_AUTO = 0, 1, 2
-DT_OUT_S, DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_SIGN, DT_OUT_BACKWARD = 1, 2, 4, 8, 16
+DT_OUT_S, DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_SIGN, DT_OUT_BACKWARD, DT_OUT_CURV = 1, 2, 4, 8, 16, 32
 DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
 
 EXPORTED = (
@@ -50,6 +50,7 @@ class DtOutputs(ctypes.Structure):
         ("label", ctypes.c_void_p),
         ("mu", ctypes.c_void_p),
         ("signed_outputs", ctypes.c_int),
+        ("curv", ctypes.c_void_p),
     ]
 
 

@@ -102,6 +102,7 @@ struct EpiParams {
   int8_t* label;
   void* mu;
   int signed_out;
+  void* curv;               // 4 x N: mean, Gaussian, k1, k2 (NULL = not wanted)
 };
 
 }  // namespace dt

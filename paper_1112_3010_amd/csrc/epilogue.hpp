@@ -1,7 +1,7 @@
 // Per-node epilogue of the final row pass (Table 1 step 6 and Sec. 5):
 // undo the power-of-two scales, validity test against Theta, S = -tau log phi,
-// gradient u / phi, Hessian h / phi + S_i S_j / tau, winding number or degree
-// and the sign label.
+// gradient u / phi, Hessian h / phi + S_i S_j / tau, curvatures, winding
+// number or degree and the sign label.
 #pragma once
 
 #include "dt_internal.hpp"
@@ -26,7 +26,51 @@ __device__ __forceinline__ void hess_pair(int ndim, int h, int& i, int& j) {
   }
 }
 
-template <typename T>
+// Curvatures from grad S (g) and the Hessian (h, library channel order), the
+// derived quantities named at the end of Sec. 5.  c = mean, Gaussian, k1, k2
+// with k1,2 = mean +/- sqrt(max(mean^2 - Gaussian, 0)).
+template <typename T> __device__ __forceinline__ void principal(T mean, T gauss, T* c) {
+  const T s = sqrt(fmax(mean * mean - gauss, T(0)));
+  c[0] = mean;
+  c[1] = gauss;
+  c[2] = mean + s;
+  c[3] = mean - s;
+}
+// 2D: the graph surface (x, y, S) with the upward normal; h = xx, xy, yy.
+template <typename T> __device__ __forceinline__ void curvature_graph(const T* g, const T* h, T* c) {
+  const T gx2 = g[0] * g[0], gy2 = g[1] * g[1];
+  const T W = T(1) + gx2 + gy2;
+  const T gauss = (h[0] * h[2] - h[1] * h[1]) / (W * W);
+  const T mean = ((T(1) + gy2) * h[0] - T(2) * g[0] * g[1] * h[1] + (T(1) + gx2) * h[2]) / (T(2) * W * sqrt(W));
+  principal(mean, gauss, c);
+}
+// |grad S| below which the 3D level surface is not defined by the derivatives
+constexpr double kCurvGradMin = 1e-3;
+// 3D: the level surface of S through the node, normal g / |g|;
+// h = xx, xy, xz, yy, yz, zz.  Mean (|g|^2 tr h - g^T h g) / (2 |g|^3),
+// Gaussian g^T adj(h) g / |g|^4.
+template <typename T> __device__ __forceinline__ void curvature_level_set(const T* g, const T* h, T* c) {
+  const T a = h[0], b = h[1], cc = h[2], d = h[3], e = h[4], f = h[5];
+  const T q = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  if (!(q >= T(kCurvGradMin * kCurvGradMin))) {
+    c[0] = c[1] = c[2] = c[3] = T(0);
+    return;
+  }
+  const T gHg = g[0] * g[0] * a + g[1] * g[1] * d + g[2] * g[2] * f +
+                T(2) * (g[0] * g[1] * b + g[0] * g[2] * cc + g[1] * g[2] * e);
+  // adjugate of the symmetric Hessian
+  const T A00 = d * f - e * e, A01 = cc * e - b * f, A02 = b * e - cc * d;
+  const T A11 = a * f - cc * cc, A12 = b * cc - a * e, A22 = a * d - b * b;
+  const T gAg = g[0] * g[0] * A00 + g[1] * g[1] * A11 + g[2] * g[2] * A22 +
+                T(2) * (g[0] * g[1] * A01 + g[0] * g[2] * A02 + g[1] * g[2] * A12);
+  const T mean = (q * (a + d + f) - gHg) / (T(2) * q * sqrt(q));
+  const T gauss = gAg / (q * q);
+  principal(mean, gauss, c);
+}
+
+// CURV: the instantiation that also writes curvatures (kept apart so that the
+// other outputs' final pass keeps its register budget).
+template <typename T, bool CURV = false>
 __device__ __forceinline__ void epilogue_cell(const EpiParams& e, const T* vals, int64_t node) {
   const T theta = (T)e.theta[0];
   const T smax = (T)e.theta[1];
@@ -50,14 +94,32 @@ __device__ __forceinline__ void epilogue_cell(const EpiParams& e, const T* vals,
   for (int a = 0; a < e.ndim; ++a) g[a] = valid ? vals[e.ch_u[a]] * inv * (T)e.scale_u[a] : T(0);
   if (e.grad)
     for (int a = 0; a < e.ndim; ++a) ((T*)e.grad)[a * e.plane + node] = sgn * g[a];
-  if (e.hess && e.ch_h[0] >= 0) {
+  if constexpr (!CURV) {
+    if (e.hess && e.ch_h[0] >= 0) {
+      const int nh = e.ndim == 2 ? 3 : 6;
+      for (int h = 0; h < nh; ++h) {
+        int i, j;
+        hess_pair(e.ndim, h, i, j);
+        const T hv = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
+        ((T*)e.hess)[h * e.plane + node] = hv;
+      }
+    }
+  } else {
     const int nh = e.ndim == 2 ? 3 : 6;
-    for (int h = 0; h < nh; ++h) {
+    T hv[6];
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+      if (h >= nh) break;
       int i, j;
       hess_pair(e.ndim, h, i, j);
-      const T hv = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
-      ((T*)e.hess)[h * e.plane + node] = hv;
+      hv[h] = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
+      if (e.hess) ((T*)e.hess)[h * e.plane + node] = hv[h];
     }
+    T c[4];
+    if (e.ndim == 2) curvature_graph(g, hv, c);
+    else curvature_level_set(g, hv, c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ((T*)e.curv)[k * e.plane + node] = c[k];
   }
 }
 

@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 #ifndef DT_EPI_DMA
 #define DT_EPI_DMA 1
 #endif
-template <typename T, int N>
+template <typename T, int N, bool CURV>
 __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
   constexpr int E = 8;
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
     if (row2 >= e.n_rows) continue;
     T vals[kMaxChan];
     for (int cc = 0; cc < C; ++cc) vals[cc] = ldr[(int64_t)(r2 * C + cc) * 2 * LP + x];
-    epilogue_cell<T>(e, vals, row2 * nx + x);
+    epilogue_cell<T, CURV>(e, vals, row2 * nx + x);
   }
 }
 
@@ -471,6 +471,17 @@ template <typename T> bool launch_col_fused(const void* in, void* out, const Col
   }
 }
 
+template <typename T, int N, bool CURV>
+static bool launch_epi_kernel(const void* in, const RowParams& p, const EpiParams& e, int64_t blocks, int threads,
+                              size_t shmem, hipStream_t st) {
+  if (shmem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_c2r_epi<T, N, CURV>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+    return false;
+  hipLaunchKernelGGL((k_row_c2r_epi<T, N, CURV>), dim3((unsigned)blocks), dim3(threads), shmem, st,
+                     (const Cx<T>*)in, p, e);
+  return true;
+}
+
 #ifndef DT_EPI_THREADS
 #define DT_EPI_THREADS 128
 #endif
@@ -501,12 +512,8 @@ template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p
   switch (N) {
 #define CASE(NN)                                                                                         \
   case NN:                                                                                               \
-    if (shmem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_row_c2r_epi<T, NN>),      \
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess) \
-      return false;                                                                                      \
-    hipLaunchKernelGGL((k_row_c2r_epi<T, NN>), dim3((unsigned)blocks), dim3(threads), shmem, st,         \
-                       (const Cx<T>*)in, p, e);                                                          \
-    return true;
+    return e.curv ? launch_epi_kernel<T, NN, true>(in, p, e, blocks, threads, shmem, st)                 \
+                  : launch_epi_kernel<T, NN, false>(in, p, e, blocks, threads, shmem, st);
     DT_FOR_EACH_N(CASE)
 #undef CASE
     default: return false;

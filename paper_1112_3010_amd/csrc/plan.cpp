@@ -234,7 +234,7 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   if (!dims || !spacing || !origin) return DT_E_ARG;
   if (!finite_pos(tau)) return DT_E_ARG;
   if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO) return DT_E_ARG;
-  const unsigned known = DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_SIGN | DT_OUT_BACKWARD;
+  const unsigned known = DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_SIGN | DT_OUT_BACKWARD | DT_OUT_CURV;
   if (out_mask == 0 || (out_mask & ~known)) return DT_E_ARG;
   if (!(c_theta <= 0) && !finite_pos(c_theta)) return DT_E_ARG;
   for (int a = 0; a < ndim; ++a) {
@@ -287,12 +287,14 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
 
   // kernel tables
   const int D = ndim;
-  const bool dist = out_mask & (DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS);
-  const bool grad = out_mask & (DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_BACKWARD);
+  // curvatures need the gradient and Hessian kernels
+  const bool hessfam = out_mask & (DT_OUT_HESS | DT_OUT_CURV);
+  const bool dist = (out_mask & (DT_OUT_S | DT_OUT_GRAD)) || hessfam;
+  const bool grad = (out_mask & (DT_OUT_GRAD | DT_OUT_BACKWARD)) || hessfam;
   if (dist) p->t_f = add_table(p, KER_F, 0, 0, 1.0);
   if (grad)
     for (int a = 0; a < D; ++a) p->t_u[a] = add_table(p, KER_U, a, 0, 1.0);
-  if (out_mask & DT_OUT_HESS) {
+  if (hessfam) {
     int hcount = 0;
     for (int i = 0; i < D; ++i)
       for (int j = i; j < D; ++j) p->t_h[hcount++] = add_table(p, KER_H, i, j, 1.0);
@@ -310,8 +312,8 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   // channel counts
   const int nh = D == 2 ? 3 : 6;
   const int in_fwd = (dist ? 1 : 0) + ((out_mask & DT_OUT_SIGN) ? D : 0);
-  const int out_fwd = (dist ? 1 : 0) + ((out_mask & (DT_OUT_GRAD | DT_OUT_HESS)) ? D : 0) +
-                      ((out_mask & DT_OUT_HESS) ? nh : 0) + ((out_mask & DT_OUT_SIGN) ? 1 : 0);
+  const int out_fwd = (dist ? 1 : 0) + (((out_mask & DT_OUT_GRAD) || hessfam) ? D : 0) + (hessfam ? nh : 0) +
+                      ((out_mask & DT_OUT_SIGN) ? 1 : 0);
   p->in_max = std::max(in_fwd, (out_mask & DT_OUT_BACKWARD) ? 1 : 0);
   p->out_max = std::max(out_fwd, (out_mask & DT_OUT_BACKWARD) ? D + 1 : 0);
   p->in_max = std::max(p->in_max, 1);  // the backward's count image needs one channel
@@ -624,7 +626,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
                       hipStream_t st) {
   const int D = p->ndim;
   Request rq;
-  rq.hess = out->hess != nullptr;
+  rq.hess = out->hess != nullptr || out->curv != nullptr;
   rq.grad = out->grad != nullptr || rq.hess;
   rq.dist = out->S != nullptr || rq.grad;
   rq.sign = out->label != nullptr || out->mu != nullptr;
@@ -767,6 +769,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
   ep.label = out->label;
   ep.mu = out->mu;
   ep.signed_out = out->signed_outputs;
+  ep.curv = out->curv;
   {
     PassTimer t(p, st, "row_c2r_epi");
     if (!launch_row_c2r_epi<T>(p->R1p(), rp, ep, (int)(p->M[0] / 2), st)) return DT_E_UNSUPPORTED;

@@ -15,7 +15,7 @@ from . import _lib as L
 
 PRECISIONS = {"fp32": L.DT_FP32_SCALED, "fp32_scaled": L.DT_FP32_SCALED, "fp64": L.DT_FP64, "auto": L.DT_AUTO}
 OUTPUT_BITS = {"S": L.DT_OUT_S, "grad": L.DT_OUT_GRAD, "hess": L.DT_OUT_HESS, "sign": L.DT_OUT_SIGN,
-               "backward": L.DT_OUT_BACKWARD}
+               "backward": L.DT_OUT_BACKWARD, "curv": L.DT_OUT_CURV}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -30,7 +30,8 @@ class Plan:
     """A prepared grid: padded sizes, kernel spectra, workspace.
 
     dims, spacing, origin are given x first.  ``outputs`` is an iterable of
-    "S", "grad", "hess", "sign", "backward" (kernel families to prepare).
+    "S", "grad", "hess", "sign", "backward", "curv" (kernel families to
+    prepare; "curv" prepares the gradient and Hessian kernels).
     """
 
     def __init__(self, dims, spacing=None, origin=None, tau=None, precision="fp32", outputs=("S", "grad"),
@@ -132,8 +133,9 @@ class Plan:
 
     # -- entry points --------------------------------------------------------
     def forward(self, Y=None, *, polygon=None, vertices=None, faces=None, S=True, grad=False, hess=False,
-                label=False, mu=False, signed=False):
-        """Run one pipeline for any subset of outputs; returns a dict."""
+                label=False, mu=False, signed=False, curv=False):
+        """Run one pipeline for any subset of outputs; returns a dict.
+        ``curv``: a (4, *grid) tensor of mean, Gaussian, k1, k2."""
         Yc = self._points(Y)
         sh, keep = self._shape(polygon, vertices, faces)
         out = {}
@@ -147,12 +149,15 @@ class Plan:
             out["label"] = self._empty(dtype=torch.int8)
         if mu:
             out["mu"] = self._empty()
+        if curv:
+            out["curv"] = self._empty(4)
         o = L.DtOutputs()
         o.S = out["S"].data_ptr() if S else None
         o.grad = out["grad"].data_ptr() if grad else None
         o.hess = out["hess"].data_ptr() if hess else None
         o.label = out["label"].data_ptr() if label else None
         o.mu = out["mu"].data_ptr() if mu else None
+        o.curv = out["curv"].data_ptr() if curv else None
         o.signed_outputs = 1 if signed else 0
         K = 0 if Yc is None else Yc.shape[0]
         L.check(L.load().dt_forward(self._h, _ptr(Yc), K, ctypes.byref(sh) if sh is not None else None,
@@ -162,11 +167,11 @@ class Plan:
 
     def forward_into(self, out, Y=None, *, polygon=None, vertices=None, faces=None, signed=False):
         """Like forward() but writes into preallocated tensors in ``out``
-        (keys among S, grad, hess, label, mu)."""
+        (keys among S, grad, hess, label, mu, curv)."""
         Yc = self._points(Y)
         sh, keep = self._shape(polygon, vertices, faces)
         o = L.DtOutputs()
-        for key in ("S", "grad", "hess", "label", "mu"):
+        for key in ("S", "grad", "hess", "label", "mu", "curv"):
             t = out.get(key)
             setattr(o, key, None if t is None else t.data_ptr())
         o.signed_outputs = 1 if signed else 0

@@ -1,0 +1,90 @@
+"""GPU parity of the curvature outputs (mean, Gaussian, k1, k2) against the
+oracle's curvatures of its own gradient and Hessian.
+
+Compared on nodes where the field is well conditioned: phi >= 10 Theta
+(the float32 error of phi there is a fifth of its error at the parity
+band's edge), and in 3D |grad S| >= 0.5 (the level-set formulas divide by
+|grad S|^3).  Tolerances (float32): 1e-3 (1/tau + 1/h) for the mean
+curvature, its square for the Gaussian curvature, and for k1,2 the mean
+tolerance plus the square root of the discriminant's tolerance
+2 |mean| tol_mean + tol_gauss (the square root amplifies errors near
+umbilic points, where the discriminant vanishes).  Float64: the same forms
+on the float64 Hessian bound.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL_CURV = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1112_3010_amd as dtm
+    dtm.load_library()
+    return dtm
+
+
+def _check(res, ref, tau, h, prec, tag, D):
+    C = res["curv"].detach().cpu().numpy().astype(np.float64).reshape(4, -1)
+    c = oracle.curvature(ref["grad"], ref["hess"])
+    ok = ref["lnphi"] >= np.log(10 * ref["theta"])
+    if D == 3:
+        ok &= np.einsum("ni,ni->n", ref["grad"], ref["grad"]) >= 0.25
+    assert ok.sum() > 50
+    scale = 1.0 / tau + 1.0 / min(h)
+    if prec == "fp32":
+        tm = np.full(ok.sum(), TOL_CURV * scale)
+        tg = np.full(ok.sum(), TOL_CURV * scale ** 2)
+    else:
+        b = parity.bound(ref, 1e-7, 1.0)[ok]
+        tm, tg = b * scale, b * scale ** 2
+    tk = tm + np.sqrt(2 * np.abs(c["mean"][ok]) * tm + tg)
+    errs = {}
+    for i, (k, t) in enumerate((("mean", tm), ("gauss", tg), ("k1", tk), ("k2", tk))):
+        d = np.abs(C[i][ok] - c[k][ok])
+        errs[k] = float((d / t).max())
+        assert np.all(d <= t), f"{tag} {k}: worst {d.max():.3e} vs tol {t[np.argmax(d)]:.3e}"
+    print(f"\n[curv {tag}] worst error / tolerance: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    # clearly outside the valid band every curvature is 0
+    inval = ref["lnphi"] < np.log(0.5 * ref["theta"])
+    if inval.any():
+        assert np.all(C[:, inval] == 0)
+
+
+@pytest.mark.parametrize("dims,K,tau_h,prec", [((90, 70), 40, 2.0, "fp32"), ((90, 70), 40, 2.0, "fp64"),
+                                               ((200, 130), 300, 3.0, "fp32"),
+                                               ((34, 30, 28), 40, 2.0, "fp32"), ((34, 30, 28), 40, 2.0, "fp64")])
+def test_curvature(dt, dims, K, tau_h, prec):
+    D = len(dims)
+    pts = synth.generators.uniform_points(D, K, seed=401 + D + K)
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "curv"])
+    Y = torch.from_numpy(pts).cuda()
+    res = plan.forward(Y, S=True, curv=True)
+    both = plan.forward(Y, S=False, grad=True, hess=True, curv=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    # the curvature outputs do not depend on which other outputs are written
+    assert torch.equal(res["curv"], both["curv"])
+    ref = parity.reference(dims, h, (0.0,) * D, tau, pts, prec, grad=True, hess=True)
+    _check(res, ref, tau, h, prec, f"{dims} {prec}", D)
+
+
+def test_curvature_needs_hessian_kernels(dt):
+    """A plan without the curvature (or Hessian) kernels rejects a curvature request."""
+    plan = dt.Plan((64, 48), None, None, 2.0 / 64, precision="fp32", outputs=["S", "grad"])
+    Y = torch.from_numpy(synth.generators.uniform_points(2, 10, seed=3)).cuda()
+    with pytest.raises(RuntimeError):
+        plan.forward(Y, S=True, curv=True)
