@@ -53,6 +53,18 @@ def random_grid_points(dims, k: int, seed: int, distinct: bool = False,
     return pts.astype(np.float32)
 
 
+def grid_node_subset(n_axis: int, lo: float, h: float, k: int, seed: int) -> np.ndarray:
+    """K distinct nodes, drawn without replacement, of the square grid with
+    nodes lo + i h (i < n_axis per axis); float32 coordinates (x, y), exact
+    for power-of-two h and lo.  The point sets of the 2D accuracy experiments
+    (Sec. 6.1): Example 1 uses n_axis = 129, lo = -0.125, h = 1/512, k = 5000;
+    Example 2 n_axis = 257, h = 1/1024, k = 10000."""
+    rng = _rng(seed)
+    flat = rng.choice(n_axis * n_axis, size=k, replace=False)
+    iy, ix = np.divmod(flat, n_axis)
+    return np.stack([lo + ix * h, lo + iy * h], axis=1).astype(np.float32)
+
+
 def uniform_points(d: int, k: int, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     """K points uniform in [lo, hi)^d (float32)."""
     rng = _rng(seed)
