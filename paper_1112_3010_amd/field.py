@@ -181,6 +181,12 @@ class Plan:
         del keep
         return out
 
+    def distance_into(self, S, Y):
+        """dt_distance into a preallocated tensor S (plan dtype, grid shape)."""
+        Yc = self._points(Y)
+        L.check(L.load().dt_distance(self._h, _ptr(Yc), Yc.shape[0], _ptr(S), _stream(self.device)), "dt_distance")
+        return S
+
     def distance(self, Y):
         Yc = self._points(Y)
         S = self._empty()
