@@ -178,7 +178,12 @@ dt_status dt_hessian(dt_plan plan, const float* Y, int64_t K, void* hess, void* 
 dt_status dt_sign(dt_plan plan, const dt_shape* shape, int8_t* label, void* mu_or_null, void* stream);
 /* Any subset of outputs in one pipeline.  Sources: Y (K points) if Y is
  * non-NULL, else the shape's points (polygon) or triangle incenters (mesh).
- * The sign needs a shape. */
+ * The sign needs a shape.
+ * dt_distance, dt_gradient, dt_hessian, dt_sign, dt_forward and dt_backward
+ * only enqueue kernels on the given stream: no device allocation, no host
+ * synchronisation and no memset nodes, so a caller may capture them into a
+ * HIP graph (with plan timing off) and replay it with new contents of the
+ * captured buffers (same K, same pointers). */
 dt_status dt_forward(dt_plan plan, const float* Y, int64_t K, const dt_shape* shape_or_null,
                      const dt_outputs* out, void* stream);
 /* Adjoint of dt_distance (needs DT_OUT_BACKWARD).  S: the forward's output

@@ -227,6 +227,14 @@ class Plan:
                                      _stream(self.device)), "dt_backward")
         return dY, dtau
 
+    def backward_into(self, dY, dtau, Y, S, dL_dS):
+        """dt_backward into preallocated dY (K x ndim float32) and dtau (a
+        float64 scalar tensor, or None); S and dL_dS of the plan's dtype."""
+        Yc = self._points(Y)
+        L.check(L.load().dt_backward(self._h, _ptr(Yc), Yc.shape[0], _ptr(S), _ptr(dL_dS), _ptr(dY), _ptr(dtau),
+                                     _stream(self.device)), "dt_backward")
+        return dY, dtau
+
     def set_timing(self, enable=True):
         L.check(L.load().dt_plan_set_timing(self._h, 1 if enable else 0), "dt_plan_set_timing")
 
