@@ -16,6 +16,8 @@
 // kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_engine.hpp"
 
 namespace dt {
@@ -146,6 +148,7 @@ template <int R, int DIR, typename V> struct RegDFT {
 // k = a + 8 b, W^(p k) = W^(p a) W^(8 p b).
 template <typename T, int N, int E> struct ThreadTwiddles {
   using V = Cx<T>;
+  static constexpr bool NEEDS_BARRIER = false;
   static constexpr int NB8 = E / 8;
   V A[8];
   V B[NB8 > 0 ? NB8 : 1];
@@ -319,7 +322,7 @@ __host__ __device__ constexpr int pair_E(int N) {
 #ifndef DT_PAIR_SPLIT
 #define DT_PAIR_SPLIT 0
 #endif
-template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT> struct PairFFT {
+template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT, bool TWL = false> struct PairFFT {
   using V = Cx<T>;
   static constexpr int E = pair_E(N);
   static constexpr int P = 2 * E;
@@ -331,7 +334,8 @@ template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT> struct PairFFT {
   static constexpr int RS = P * NB + PAD;
   static constexpr int LDS = E * RS * (SPLIT ? 1 : 2);   // reals
   // all E - 1 thread twiddles W_N^(p k), k = 1 .. E-1, formed once per block
-  struct Tw {
+  struct TwReg {
+    static constexpr bool NEEDS_BARRIER = false;
     V w[E];
     __device__ __forceinline__ void load(const V* tw, int p) {
       ThreadTwiddles<T, N, E> ab;
@@ -341,6 +345,23 @@ template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT> struct PairFFT {
     }
     __device__ __forceinline__ V get(int k) const { return w[k]; }
   };
+  // The same twiddles in an LDS table (row p, odd row stride), read at each
+  // use: frees 2E registers per thread.  The block fills the table together,
+  // so a barrier must pass before the first get.
+  struct TwLds {
+    static constexpr bool NEEDS_BARRIER = true;
+    const V* row;
+    __device__ __forceinline__ void load(const V* tw, int p) {
+      __shared__ V tab[P * (E + 1)];
+      for (int i = threadIdx.x; i < P * E; i += blockDim.x) {
+        const int r = i / E, k = i % E;
+        tab[r * (E + 1) + k] = tw[(r * k) % N];
+      }
+      row = tab + p * (E + 1);
+    }
+    __device__ __forceinline__ V get(int k) const { return row[k]; }
+  };
+  using Tw = typename std::conditional<TWL, TwLds, TwReg>::type;
 
   template <int DIR, int J> static __device__ __forceinline__ void pair_twiddle(V* v, bool h) {
     if constexpr (J < E) {

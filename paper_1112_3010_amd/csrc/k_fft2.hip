@@ -232,18 +232,45 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 // points (+-ky, +-kz) from one read.  The transform engine ENG is PairFFT
 // (one complex LDS exchange) or TwoStep (real and imaginary parts exchanged in
 // two rounds through a real LDS buffer); the tables are staged kTabChunk
-// channels at a time, which keeps the block's LDS small enough for two blocks
-// per CU.
+// channels at a time.  Per precision: float32 stages all four slices at once
+// with one complex exchange and register twiddles (68 KB of LDS, two blocks
+// per CU).  float64 stages one slice at a time, exchanges in two rounds and
+// keeps the twiddles in LDS: 60 KB of LDS and at most 256 registers, so two
+// blocks share a CU instead of one.
 #ifndef DT_TAB_CHUNK
 #define DT_TAB_CHUNK 4
 #endif
-constexpr int kTabChunk = DT_TAB_CHUNK;
+#ifndef DT_TAB_CHUNK64
+#define DT_TAB_CHUNK64 1
+#endif
+#ifndef DT_FUSED_SPLIT
+#define DT_FUSED_SPLIT DT_PAIR_SPLIT
+#endif
+#ifndef DT_FUSED_SPLIT64
+#define DT_FUSED_SPLIT64 1
+#endif
+#ifndef DT_FUSED_TWL
+#define DT_FUSED_TWL 0
+#endif
+#ifndef DT_FUSED_TWL64
+#define DT_FUSED_TWL64 1
+#endif
 #ifndef DT_FUSED_MIRROR
 #define DT_FUSED_MIRROR 1
 #endif
 #ifndef DT_FUSED_MINWAVES
 #define DT_FUSED_MINWAVES 1
 #endif
+#ifndef DT_FUSED_MINWAVES64
+#define DT_FUSED_MINWAVES64 2
+#endif
+template <typename T> constexpr int tab_chunk() { return sizeof(T) == 8 ? DT_TAB_CHUNK64 : DT_TAB_CHUNK; }
+template <typename T> constexpr int fused_split() { return sizeof(T) == 8 ? DT_FUSED_SPLIT64 : DT_FUSED_SPLIT; }
+template <typename T> constexpr bool fused_twl() { return (sizeof(T) == 8 ? DT_FUSED_TWL64 : DT_FUSED_TWL) != 0; }
+// the float64 hint applies to the 512-point pair engine (the 256^3 grids)
+template <typename T, int N> constexpr int fused_minwaves() {
+  return sizeof(T) == 8 ? (N == 512 ? DT_FUSED_MINWAVES64 : 1) : DT_FUSED_MINWAVES;
+}
 #ifndef DT_FUSED_PAIR
 #define DT_FUSED_PAIR 1
 #endif
@@ -266,12 +293,13 @@ template <typename T> constexpr bool fused_pair(int N) {
 }
 
 template <typename T, int N, class ENG, int NB, bool HALF, bool MIRROR>
-__global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_staged(const Cx<T>* __restrict__ in,
+__global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_fused_staged(const Cx<T>* __restrict__ in,
                                                                                      Cx<T>* __restrict__ out,
                                                                                      ColParams p, FusedSpec fs) {
   using V = Cx<T>;
   constexpr int E = ENG::E;
   constexpr int P = ENG::P;
+  constexpr int kTabChunk = tab_chunk<T>();
   constexpr int H = N / 2 + 1;                     // folded rows along the transform axis
   constexpr int SLICE = H * NB;                    // table elements per channel slice
   constexpr int SLICE16 = SLICE * (int)sizeof(T) / 16;
@@ -299,6 +327,7 @@ __global__ void __launch_bounds__(ENG::P * NB, DT_FUSED_MINWAVES) k_col2_fused_s
   // complete the twiddle loads now: a wait at their first use would also
   // wait for the asynchronous table copy issued below
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  if constexpr (ENG::Tw::NEEDS_BARRIER) __syncthreads();
 
   // Copy the contiguous table slices of tabs[0..nt) into LDS.  Each wave
   // moves 1 KiB runs with direct global-to-LDS loads, which do not pass
@@ -543,7 +572,7 @@ template <typename T> bool launch_col2_fused(const void* in, void* out, const Co
     constexpr int NB = twostep_NB<T, true>();                                                             \
     if (p.outer_len > 1) {                                                                                \
       if constexpr (fused_pair<T>(NN)) {                                                                     \
-        using ENG = PairFFT<T, NN, NB>;                                                                   \
+        using ENG = PairFFT<T, NN, NB, fused_split<T>(), fused_twl<T>()>;                                 \
         constexpr int NT = ENG::P * NB;                                                                   \
         if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
         else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
