@@ -466,6 +466,7 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=12288)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-curv", action="store_true", help="skip the 256^3 curvature timing")
     ap.add_argument("--workload", choices=["mesh256", "batch", "protocol"], default="mesh256",
                     help="mesh256: the 256^3 mesh headline (default); batch: 96 mixed-size 2D instances; "
                          "protocol: Example 1 of Sec. 6.1 against Table 2")
@@ -505,8 +506,10 @@ def main():
     Yc = triangle_centres(V, F)
     b32 = run_backward("fp32", Yc, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls)
     log("fp32 backward:", json.dumps(b32))
-    c32 = run_curvature("fp32", Yc, dims, tau, max(5, args.steps // 5), args.warmup, args.timing_calls)
-    log("fp32 curvature:", json.dumps(c32))
+    c32 = None
+    if not args.no_curv:
+        c32 = run_curvature("fp32", Yc, dims, tau, max(5, args.steps // 5), args.warmup, args.timing_calls)
+        log("fp32 curvature:", json.dumps(c32))
     r64 = b64 = None
     if not args.no_fp64:
         r64 = run_gpu("fp64", V, F, dims, tau, max(5, args.steps // 2), args.warmup, args.timing_calls, cells)
@@ -554,7 +557,8 @@ def main():
                  "plan_setup_s": round(r32["plan_setup_s"], 3), "counters": counter_frac(r32, "fp32")},
     }
     line["backward"] = b32
-    line["curvature"] = c32
+    if c32 is not None:
+        line["curvature"] = c32
     if r64 is not None:
         line["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
                         "dtype": "f64", "roofline": roof(r64, "fp64"),
