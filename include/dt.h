@@ -247,6 +247,18 @@ typedef struct {
   double spacing[2];   /* hx, hy > 0 */
   double origin[2];
   double tau;          /* > 0, physical units */
+  /* 0: linear-convolution padding M_a = 2 s_a, s_a the smallest 7-smooth
+   * number >= n_a.  > 0: reduced padding for calls with at most k_max sources
+   * in this instance.  The kernels are truncated to the box |d_a| <= c_a
+   * cells, c_a = ceil(d_cut / h_a) with d_cut = tau (ln(c_theta k_max)
+   * - ln Theta_low), Theta_low the validity threshold for one source on the
+   * full padding (a lower bound of every call's Theta).  The padded length
+   * is M_a = 2 s'_a, s'_a the smallest 7-smooth number >= (n_a + c_a) / 2,
+   * and at most the full one.  The sources a truncated kernel drops add at most
+   * k_max e^(-d_cut/tau) <= Theta / c_theta to phi, so results change only
+   * below the validity threshold.  A call with more sources in the instance
+   * returns DT_E_ARG. */
+  int64_t k_max;
 } dt_instance_desc;
 
 typedef struct {

@@ -92,6 +92,7 @@ class DtInstanceDesc(ctypes.Structure):
         ("spacing", ctypes.c_double * 2),
         ("origin", ctypes.c_double * 2),
         ("tau", ctypes.c_double),
+        ("k_max", ctypes.c_int64),
     ]
 
 

@@ -28,12 +28,15 @@ class BatchPlan:
     """Plan for ``len(dims)`` independent 2D instances.
 
     dims: sequence of (nx, ny); spacing/origin: per-instance pairs (default
-    1/n and 0); taus: per-instance tau (physical units).
+    1/n and 0); taus: per-instance tau (physical units).  k_max (an int or
+    one per instance; None or 0 = full padding): the most sources a call
+    will give an instance, which enables the reduced padding with truncated
+    kernels (results change only below the validity threshold).
     """
 
     def __init__(self, dims: Sequence, taus: Sequence[float], spacing: Optional[Sequence] = None,
                  origin: Optional[Sequence] = None, precision="fp32", outputs=("S", "grad"), c_theta=0.0,
-                 graph=True, device="cuda"):
+                 graph=True, device="cuda", k_max=None):
         lib = L.load()
         n = len(dims)
         if n < 1 or len(taus) != n:
@@ -47,6 +50,8 @@ class BatchPlan:
             desc[i].spacing[0], desc[i].spacing[1] = float(h[0]), float(h[1])
             desc[i].origin[0], desc[i].origin[1] = float(o[0]), float(o[1])
             desc[i].tau = float(taus[i])
+            if k_max is not None:
+                desc[i].k_max = int(k_max[i] if isinstance(k_max, (list, tuple)) else k_max)
         mask = 0
         for o in outputs:
             mask |= OUTPUT_BITS[o]

@@ -82,6 +82,7 @@ struct dt_batch_plan_s {
   std::vector<int> geo_of;
   struct Geo {
     int64_t Mx, My, pitch;
+    int cut[2];                 // truncation box in cells (0: none)
     double hx, hy, tau;
     int64_t tab_off;
     double l1;
@@ -255,6 +256,7 @@ template <typename T> dt_status build_batch_tables(dt_batch_plan p, hipStream_t 
     tg.M[0] = (int)g.Mx; tg.M[1] = (int)g.My; tg.M[2] = 1;
     tg.H[0] = (int)(g.Mx / 2 + 1); tg.H[1] = (int)(g.My / 2 + 1); tg.H[2] = 1;
     tg.h[0] = g.hx; tg.h[1] = g.hy; tg.h[2] = 1.0;
+    tg.cut[0] = g.cut[0]; tg.cut[1] = g.cut[1]; tg.cut[2] = 0;
     for (int c = 0; c < p->C; ++c) {
       TabKernel kd{};
       kd.kind = c == 0 ? KER_F : KER_U;
@@ -348,6 +350,8 @@ dt_status prepare_call(dt_batch_plan p, const float* Y, const int64_t* K_offsets
   if (K_offsets[0] != 0) return DT_E_ARG;
   for (int i = 0; i < p->n; ++i)
     if (K_offsets[i + 1] < K_offsets[i]) return DT_E_ARG;
+  for (int i = 0; i < p->n; ++i)   // reduced padding holds for at most k_max sources
+    if (p->desc[i].k_max > 0 && K_offsets[i + 1] - K_offsets[i] > p->desc[i].k_max) return DT_E_ARG;
   K_total = K_offsets[p->n];
   if (K_total > 0 && !Y) return DT_E_ARG;
   if (K_total >= ((int64_t)1 << 31) * 256) return DT_E_UNSUPPORTED;
@@ -386,6 +390,7 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
   for (int i = 0; i < n_inst; ++i) {
     const dt_instance_desc& q = d[i];
     if (!finite_pos_b(q.tau)) return DT_E_ARG;
+    if (q.k_max < 0) return DT_E_ARG;
     for (int a = 0; a < 2; ++a) {
       if (q.dims[a] < 2) return DT_E_ARG;
       if (!finite_pos_b(q.spacing[a]) || !std::isfinite(q.origin[a])) return DT_E_ARG;
@@ -402,7 +407,7 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
   p->desc.assign(d, d + n_inst);
   p->inst.resize(n_inst);
   p->geo_of.resize(n_inst);
-  std::map<std::tuple<int64_t, int64_t, double, double, double>, int> geo_index;
+  std::map<std::tuple<int64_t, int64_t, double, double, double, int, int>, int> geo_index;
   int64_t img = 0, spec = 0, outo = 0, tab = 0, scratch = 0, cols = 0, rows = 0;
   for (int i = 0; i < n_inst; ++i) {
     const dt_instance_desc& q = d[i];
@@ -410,8 +415,27 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     std::memset(&I, 0, sizeof(I));
     I.nx = (int)q.dims[0];
     I.ny = (int)q.dims[1];
-    const int64_t sx = smooth7_at_least(q.dims[0]);
-    const int64_t My = 2 * smooth7_at_least(q.dims[1]);
+    int64_t sx = smooth7_at_least(q.dims[0]);
+    int64_t My = 2 * smooth7_at_least(q.dims[1]);
+    int cut[2] = {0, 0};
+    if (q.k_max > 0) {
+      // Reduced padding: the validity threshold of one source on the full
+      // padding bounds every call's Theta from below (||g||_2 >= 1,
+      // ||f||_1 >= f(0) = 1, log2(N)/sqrt(N) falls with N); the truncation
+      // distance then keeps the dropped sources below Theta / c_theta.
+      const double np_full = (double)(2 * sx) * (double)My;
+      const double theta_low = p->c_theta * (p->fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24)) *
+                               std::log2(np_full) / std::sqrt(np_full);
+      const double d_cut = q.tau * (std::log(p->c_theta * (double)q.k_max) - std::log(theta_low));
+      for (int a = 0; a < 2; ++a) {
+        const double c = std::ceil(d_cut / q.spacing[a]);
+        cut[a] = c < 1e9 ? (int)c : 1000000000;
+      }
+      const int64_t sx_r = smooth7_at_least((q.dims[0] + cut[0] + 1) / 2);
+      const int64_t my_r = 2 * smooth7_at_least((q.dims[1] + cut[1] + 1) / 2);
+      if (sx_r < sx) sx = sx_r; else cut[0] = 0;    // no gain on this axis: full padding, no truncation
+      if (my_r < My) My = my_r; else cut[1] = 0;
+    }
     I.sx = (int)sx;
     I.My = (int)My;
     I.pitch = (int)((sx + 1 + 15) / 16 * 16);
@@ -435,11 +459,12 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     }
     I.twx_off = p->tw_off[2 * sx];
     I.twy_off = p->tw_off[My];
-    const auto key = std::make_tuple(2 * sx, My, q.spacing[0], q.spacing[1], q.tau);
+    const auto key = std::make_tuple(2 * sx, My, q.spacing[0], q.spacing[1], q.tau, cut[0], cut[1]);
     auto it = geo_index.find(key);
     if (it == geo_index.end()) {
       dt_batch_plan_s::Geo g{};
       g.Mx = 2 * sx; g.My = My; g.pitch = I.pitch;
+      g.cut[0] = cut[0]; g.cut[1] = cut[1];
       g.hx = q.spacing[0]; g.hy = q.spacing[1]; g.tau = q.tau;
       g.tab_off = tab;
       tab += (int64_t)p->C * (My / 2 + 1) * I.pitch;

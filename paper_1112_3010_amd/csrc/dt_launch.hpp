@@ -29,6 +29,7 @@ struct TabGeom {
   int M[3];       // padded lengths (1 for an absent axis)
   int H[3];       // folded lengths M/2 + 1 (1 for an absent axis)
   double h[3];
+  int cut[3];     // > 0: the kernel is 0 where some |d_a| > cut[a] cells (truncation box)
 };
 
 // Host: exp(-2 pi i m / M) for m < M as interleaved (re, im) float64.

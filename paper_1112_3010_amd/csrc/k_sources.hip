@@ -290,6 +290,7 @@ __global__ void __launch_bounds__(256) k_tab_sample(TabKernel kd, TabGeom tg, do
     double w = 1.0, D[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < tg.ndim; ++a) {
       if (2 * d[a] == tg.M[a]) nyq = true;
+      if (tg.cut[a] > 0 && d[a] > tg.cut[a]) nyq = true;   // outside the truncation box: 0 as well
       if (d[a] > 0) w *= 2.0;
       D[a] = (double)d[a] * tg.h[a];
     }

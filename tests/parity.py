@@ -58,6 +58,32 @@ def batch_padded(n):
     return 2 * smooth7_at_least(n)
 
 
+def batch_padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA):
+    """Reduced padding rule of the batched path for calls with at most k_max
+    sources: the validity threshold of one source on the full padding bounds
+    every call's Theta from below; d_cut = tau (ln(c_theta k_max) - ln
+    Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = 2 s, s the smallest
+    7-smooth >= (n_a + c_a) / 2, unless that is not below the full padding
+    (then full padding and no truncation on that axis).  Returns
+    ((M_x, M_y), (c_x, c_y)) with c = 0 on a fully padded axis."""
+    full = [batch_padded(n) for n in dims]
+    np_full = float(full[0]) * float(full[1])
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    theta_low = c_theta * u * np.log2(np_full) / np.sqrt(np_full)
+    d_cut = tau * (np.log(c_theta * float(k_max)) - np.log(theta_low))
+    Ms, cuts = [], []
+    for n, h, Mf in zip(dims, spacing, full):
+        c = int(np.ceil(d_cut / h))
+        Mr = 2 * smooth7_at_least((n + c + 1) // 2)
+        if Mr < Mf:
+            Ms.append(Mr)
+            cuts.append(c)
+        else:
+            Ms.append(Mf)
+            cuts.append(0)
+    return tuple(Ms), tuple(cuts)
+
+
 def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=False, cells=None,
               c_theta=oracle.C_THETA, padded_dims=None):
     """Oracle fields at all nodes (or at the given flat node indices)."""

@@ -103,3 +103,37 @@ def test_batch_call_checks_without_workspace(lib):
     assert lib.dt_batch_get_tiles(h, ctypes.byref(t2)) == 0 and t2.col_nb == 8
     assert lib.dt_batch_set_graph(h, 1) == 0
     assert lib.dt_destroy_batch_plan(h) == 0
+
+
+def test_batch_reduced_padding_rule(lib):
+    """k_max > 0: the plan's padded sizes follow the reduced rule, leave room
+    for the truncation box (M >= n + c) and never exceed the full padding."""
+    from paper_1112_3010_amd import _lib
+    dims = [(1024, 1024), (700, 130), (128, 128), (64, 1000), (20, 20)]
+    kmax = [20000, 500, 100, 3000, 5]
+    for prec, pname in ((0, "fp32"), (1, "fp64")):
+        d = _desc(dims)
+        for i, k in enumerate(kmax):
+            d[i].k_max = k
+        st, h = _create(lib, dims, prec=prec, desc=d)
+        assert st == 0
+        reduced_any = False
+        for i, (nx, ny) in enumerate(dims):
+            info = _lib.DtBatchInstanceInfo()
+            assert lib.dt_batch_instance_info(h, i, ctypes.byref(info)) == 0
+            Ms, cuts = parity.batch_padded_reduced((nx, ny), (1.0 / nx, 1.0 / ny), 2.0 / nx, kmax[i], pname)
+            assert (info.padded[0], info.padded[1]) == Ms, (pname, i)
+            for n, M, c in zip((nx, ny), Ms, cuts):
+                assert M <= parity.batch_padded(n)
+                if c:
+                    assert M >= n + c
+                    reduced_any = True
+        assert reduced_any
+        # the 1024^2 instance shrinks from 2048 per axis
+        info = _lib.DtBatchInstanceInfo()
+        assert lib.dt_batch_instance_info(h, 0, ctypes.byref(info)) == 0
+        assert info.padded[0] < 2048 and info.padded[1] < 2048
+        assert lib.dt_destroy_batch_plan(h) == 0
+    d = _desc([(64, 64)])
+    d[0].k_max = -1
+    assert _create(lib, [(64, 64)], desc=d)[0] == 1

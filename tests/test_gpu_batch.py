@@ -51,14 +51,15 @@ def _cells(dims, pts, n_uniform, n_near, seed):
     return np.unique(np.concatenate([a, pick[:, 0] + nx * pick[:, 1]]))
 
 
-def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats):
+def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats, Mp=None):
     nx, ny = dims
     h = (1.0 / nx, 1.0 / ny)
     if len(pts) == 0:
         assert np.all(np.isinf(S)) and np.all(S > 0), tag
         assert np.all(G == 0), tag
         return
-    Mp = (parity.batch_padded(nx), parity.batch_padded(ny))
+    if Mp is None:
+        Mp = (parity.batch_padded(nx), parity.batch_padded(ny))
     ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, prec, grad=True, cells=cells, padded_dims=Mp)
     assert stats["theta"] == pytest.approx(ref["theta"], rel=1e-9), tag
     S = S.ravel()[cells] if cells is not None else S.ravel()
@@ -166,3 +167,37 @@ def test_batch_96_instances(dt):
         _check_instance(f"c4 inst {i} n={n} K={len(y)}", "fp32", (n, n), tau, y, _np(s), _np(g), cells,
                         plan.stats(i))
     print(f"\n[batch 96] tuned tiles {tiles}; all instances within tolerance", flush=True)
+
+
+RED_DIMS = [(300, 300), (200, 260), (128, 96), (90, 400)]
+RED_K = [500, 100, 40, 200]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_reduced_padding_against_oracle(dt, prec):
+    """k_max = K per instance: smaller padded grids and kernels truncated to
+    the box the padding leaves wrap-free; every node against the exact
+    (untruncated) oracle with the reduced grid's threshold."""
+    pts = [synth.generators.uniform_points(2, K, seed=950 + i) for i, K in enumerate(RED_K)]
+    taus = [2.0 / d[0] for d in RED_DIMS]
+    plan = dt.BatchPlan(RED_DIMS, taus, precision=prec, graph=False, k_max=RED_K)
+    Mps, truncated = [], 0
+    for i, dims in enumerate(RED_DIMS):
+        Mp, cut = parity.batch_padded_reduced(dims, (1.0 / dims[0], 1.0 / dims[1]), taus[i], RED_K[i], prec)
+        assert plan.padded(i) == Mp
+        truncated += any(cut)
+        Mps.append(Mp)
+    assert truncated >= 3, "the case must exercise truncation"
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    S, G = plan.forward(Y.cuda(), offs)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    for i, ((Si, Gi), dims) in enumerate(zip(plan.views(S, G), RED_DIMS)):
+        msg = _check_instance(f"reduced {i} {dims} M={Mps[i]}", prec, dims, taus[i], pts[i], _np(Si), _np(Gi), None,
+                              plan.stats(i), Mp=Mps[i])
+        print("\n" + msg)
+    # more sources than k_max in an instance is refused
+    more = [synth.generators.uniform_points(2, K + (1 if i == 1 else 0), seed=950 + i) for i, K in enumerate(RED_K)]
+    Y2, offs2 = dt.BatchPlan.pack([torch.from_numpy(p) for p in more])
+    with pytest.raises(RuntimeError):
+        plan.forward(Y2.cuda(), offs2)
