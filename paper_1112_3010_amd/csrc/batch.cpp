@@ -431,9 +431,10 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
         const double c = std::ceil(d_cut / q.spacing[a]);
         cut[a] = c < 1e9 ? (int)c : 1000000000;
       }
-      const int64_t sx_r = smooth7_at_least((q.dims[0] + cut[0] + 1) / 2);
-      const int64_t my_r = 2 * smooth7_at_least((q.dims[1] + cut[1] + 1) / 2);
-      if (sx_r < sx) sx = sx_r; else cut[0] = 0;    // no gain on this axis: full padding, no truncation
+      // an axis whose box reaches n cells cannot gain: full padding, no truncation
+      const int64_t sx_r = cut[0] < q.dims[0] ? smooth7_at_least((q.dims[0] + cut[0] + 1) / 2) : sx;
+      const int64_t my_r = cut[1] < q.dims[1] ? 2 * smooth7_at_least((q.dims[1] + cut[1] + 1) / 2) : My;
+      if (sx_r < sx) sx = sx_r; else cut[0] = 0;
       if (my_r < My) My = my_r; else cut[1] = 0;
     }
     I.sx = (int)sx;
