@@ -42,8 +42,11 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
   const int kxs = active ? kx : 0;
   ThreadTwiddles<T, N, E> tw;
   tw.load((const V*)p.tw, pt);
-  const V* src = in + blockIdx.z * p.in_ch + blockIdx.y * p.in_outer + kxs;
-  V* dst = out + blockIdx.z * p.out_ch + blockIdx.y * p.out_outer + kxs;
+  const int64_t kin = p.in_grp ? (int64_t)(kxs >> 3) * p.in_grp + (kxs & 7) : kxs;
+  const int64_t kout = p.out_grp ? (int64_t)(kxs >> 3) * p.out_grp + (kxs & 7) : kxs;
+  const int64_t in_line = p.in_line, out_line = p.out_line;
+  const V* src = in + blockIdx.z * p.in_ch + (int64_t)blockIdx.y * p.in_outer + kin;
+  V* dst = out + blockIdx.z * p.out_ch + (int64_t)blockIdx.y * p.out_outer + kout;
   V v[E];
   if constexpr (DIR > 0) {
     // natural input rows pt + P e (pruned), outputs in slot order
@@ -51,7 +54,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
     for (int e = 0; e < E; ++e) {
       const int n = pt + P * e;
       if (HALF && e >= E / 2) v[e] = mk<V>(T(0), T(0));
-      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
+      else v[e] = (active && n < p.n_in) ? src[(int64_t)n * in_line] : mk<V>(T(0), T(0));
     }
     TS::forward(v, lds, pt, b, tw);
     if (!active) return;
@@ -60,7 +63,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
 #pragma unroll
       for (int k2 = 0; k2 < P; ++k2) {
         const int k = TS::slot_index(pt, t, k2);
-        if (k < p.n_out) dst[(int64_t)k * p.out_line] = v[t * P + k2];
+        if (k < p.n_out) dst[(int64_t)k * out_line] = v[t * P + k2];
       }
   } else {
     // inputs in slot order, natural output rows pt + P n2 (pruned)
@@ -69,7 +72,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
 #pragma unroll
       for (int k2 = 0; k2 < P; ++k2) {
         const int k = TS::slot_index(pt, t, k2);
-        v[t * P + k2] = (active && k < p.n_in) ? src[(int64_t)k * p.in_line] : mk<V>(T(0), T(0));
+        v[t * P + k2] = (active && k < p.n_in) ? src[(int64_t)k * in_line] : mk<V>(T(0), T(0));
       }
     TS::inverse(v, lds, pt, b, tw);
     if (!active) return;
@@ -77,7 +80,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
     for (int n2 = 0; n2 < E; ++n2) {
       if (HALF && n2 >= E / 2) continue;
       const int n = pt + P * n2;
-      if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
+      if (n < p.n_out) dst[(int64_t)n * out_line] = v[n2];
     }
   }
 }
@@ -363,8 +366,9 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
   };
+  const int64_t kin = p.in_grp ? (int64_t)(kxs >> 3) * p.in_grp + (kxs & 7) : kxs;
   auto issue_load = [&](int ch, int o, V* v) {
-    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
+    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kin;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = pt + P * e;
@@ -513,7 +517,7 @@ int col2_tile_width(int N, bool fp64, bool fused) {
 
 template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
                                            int outer, int chans, hipStream_t st) {
-  const dim3 grid(tiles, outer, chans);
+  const dim3 grid1(tiles, outer, chans);
   const bool half = dir > 0 ? (2 * p.n_in == N) : (2 * p.n_out == N);
   if (c2c_pair<T>(N)) {
     const Cx<T>* i_ = (const Cx<T>*)in;
@@ -522,10 +526,10 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
 #define CASEP(NN)                                                                                         \
   case NN: {                                                                                              \
     constexpr int NT = 2 * pair_E(NN) * kPairNB;                                                          \
-    if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, true>), grid, dim3(NT), 0, st, i_, o_, p);  \
-    else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, false>), grid, dim3(NT), 0, st, i_, o_, p);    \
-    else if (half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, true>), grid, dim3(NT), 0, st, i_, o_, p);       \
-    else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, false>), grid, dim3(NT), 0, st, i_, o_, p);                \
+    if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, true>), grid1, dim3(NT), 0, st, i_, o_, p);  \
+    else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, false>), grid1, dim3(NT), 0, st, i_, o_, p);    \
+    else if (half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, true>), grid1, dim3(NT), 0, st, i_, o_, p);       \
+    else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
     return true;                                                                                          \
   }
       CASEP(128) CASEP(512)
@@ -544,10 +548,10 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
       constexpr int NT = (NN / E) * NB;                                                                   \
       const Cx<T>* i_ = (const Cx<T>*)in;                                                                 \
       Cx<T>* o_ = (Cx<T>*)out;                                                                            \
-      if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, true>), grid, dim3(NT), 0, st, i_, o_, p);   \
-      else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, false>), grid, dim3(NT), 0, st, i_, o_, p);     \
-      else if (half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, true>), grid, dim3(NT), 0, st, i_, o_, p);        \
-      else hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, false>), grid, dim3(NT), 0, st, i_, o_, p);                 \
+      if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, true>), grid1, dim3(NT), 0, st, i_, o_, p);  \
+      else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, 1, false>), grid1, dim3(NT), 0, st, i_, o_, p);    \
+      else if (half) hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, true>), grid1, dim3(NT), 0, st, i_, o_, p);       \
+      else hipLaunchKernelGGL((k_col2_c2c<T, NN, E, NB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
       return true;                                                                                        \
     }                                                                                                     \
   }

@@ -522,6 +522,9 @@ struct Layout3 {
   int64_t lineD, zD, chD;   // after the inverse y pass [c][z][y][kx]
 };
 
+#ifndef DT_TILE_MAJOR
+#define DT_TILE_MAJOR 0
+#endif
 template <typename T>
 dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStream_t st) {
   const int D = p->ndim;
@@ -552,9 +555,21 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My, true), 1, st)) return DT_E_UNSUPPORTED;
   } else {
     const int64_t Mz = p->M[2];
+    // Tile-major intermediate between the forward y pass and the fused pass
+    // ([ch][8-bin group][ky][z][8 bins]) when the fused pass reads 8-bin
+    // tiles of float32 bins (64 bytes): each of its columns is then one
+    // contiguous run instead of halves of 128-byte lines.  Both kernels must
+    // be the two-step C2C (16-bin tiles) and the staged fused pass.
+    const bool tile_major = DT_TILE_MAJOR && !p->fp64 && col_tile_width((int)My, false, false) == 16 &&
+                            col_tile_width((int)Mz, false, true) == 8 && My > 1;
     ColParams c2{};
     c2.in_line = MhP; c2.in_outer = ny * MhP; c2.in_ch = nz * ny * MhP;
     c2.out_line = MhP; c2.out_outer = My * MhP; c2.out_ch = nz * My * MhP;
+    if (tile_major) {
+      c2.out_line = nz * 8;          // ky
+      c2.out_outer = 8;              // z
+      c2.out_grp = My * nz * 8;
+    }
     c2.inner = p->Mh; c2.n_in = (int)ny; c2.n_out = (int)My; c2.outer_len = (int)nz;
     c2.tw = p->ws + p->off_tw[1]; c2.tw_stride = 1;
     {
@@ -564,6 +579,11 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     }
     ColParams c3{};
     c3.in_line = My * MhP; c3.in_outer = MhP; c3.in_ch = nz * My * MhP;
+    if (tile_major) {
+      c3.in_line = 8;                // z
+      c3.in_outer = nz * 8;          // ky
+      c3.in_grp = My * nz * 8;
+    }
     c3.out_line = My * MhP; c3.out_outer = MhP; c3.out_ch = nz * My * MhP;
     c3.inner = p->Mh; c3.n_in = (int)nz; c3.n_out = (int)nz; c3.outer_len = (int)My;
     c3.tw = p->ws + p->off_tw[2]; c3.tw_stride = 1;
