@@ -242,3 +242,28 @@ def test_adjoint_128(dt, prec, tol):
           f"valid={ref['valid'].mean():.3f} nonzero G={int((Gs != 0).sum())}", flush=True)
     assert e_y <= tol[0]
     assert e_t <= tol[1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grid_512_sampled(dt, prec):
+    """The largest power-of-two 3D grid below the 1024 limit: 512^3 (padded
+    1024^3: 1024-point y passes and the Stockham fallback of the fused pass),
+    2000 uniform sources, S and grad S on sampled nodes (uniform and near
+    the sources) against the oracle."""
+    dims = (512, 512, 512)
+    h = (1.0 / 512,) * 3
+    tau = 1.5 * h[0]
+    pts = synth.generators.uniform_points(3, 2000, seed=77)
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "grad"])
+    assert plan.padded == (1024, 1024, 1024)
+    S, g = plan.gradient(torch.from_numpy(pts).cuda())
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    idx, _ = oracle.snap(pts, (0.0,) * 3, h, dims)
+    cells = _sample_cells(dims, idx, 1500, 1500, 4, seed=512)
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, pts, prec, grad=True, cells=cells)
+    Sc = _np(S).ravel()[cells]
+    gc = _np(g).reshape(3, -1)[:, cells]
+    del S, g, plan
+    torch.cuda.empty_cache()
+    _check_fields("grid 512^3", prec, tau, h, Sc, gc, None, ref)
