@@ -90,3 +90,43 @@ def test_workspace_and_call_checks(lib):
     assert lib.dt_sign(h, None, None, None, None) == 1
     assert lib.dt_status_str(2) == b"a source was outside the grid or non-finite"
     assert lib.dt_destroy_plan(h) == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every public struct of include/dt.h has the same size and field
+    offsets in C (compiled here with gcc against the header) as in the
+    ctypes mirrors of the Python binding."""
+    import shutil
+    import subprocess
+    from paper_1112_3010_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {
+        "dt_shape": _lib.DtShape, "dt_outputs": _lib.DtOutputs, "dt_plan_info_t": _lib.DtPlanInfo,
+        "dt_call_stats": _lib.DtCallStats, "dt_pass_timing": _lib.DtPassTiming,
+        "dt_instance_desc": _lib.DtInstanceDesc, "dt_batch_instance_info_t": _lib.DtBatchInstanceInfo,
+        "dt_batch_tiles": _lib.DtBatchTiles,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dt.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, *_ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            cname, key, val = ln.split()
+            got[(cname, key)] = int(val)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, *_ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
