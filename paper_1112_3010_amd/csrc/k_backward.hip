@@ -84,9 +84,14 @@ __global__ void __launch_bounds__(256) k_gather(GatherParams p) {
     double accs[4] = {0.0, 0.0, 0.0, 0.0};
     if (ok) {
       const int64_t row = idx[1] + (p.g.ndim == 3 ? (int64_t)p.g.n[1] * idx[2] : 0);
+      // twiddle index (kk x) mod M, advanced by (64 x) mod M per step
+      // (x < n <= 1024, M <= 2048: the products fit 32 bits)
+      const int step = (64 * idx[0]) % p.Mx;
+      int m = (lane * idx[0]) % p.Mx;
       for (int kk = lane; kk <= half; kk += 64) {
-        const int m = (int)(((int64_t)kk * idx[0]) % p.Mx);
         const V w = cconj(tw[m]);  // exp(+2 pi i kk x / M)
+        m += step;
+        if (m >= p.Mx) m -= p.Mx;
         const double wt = (kk == 0 || kk == half) ? 1.0 : 2.0;
         for (int c = 0; c < nch; ++c) {
           const V X = ((const V*)p.spec)[(int64_t)c * p.ch_stride + row * p.pitch + kk];
