@@ -66,7 +66,14 @@ bool mixed_plan_for(int64_t N, MixedPlan& mp) {
   for (int p : {7, 5, 3})
     while (r % p == 0)
       if (!push(p)) return false;
-  return r == 1;
+  if (r != 1) return false;
+  int64_t ns = 1;
+  for (int s = 0; s < mp.n_st; ++s) {
+    mp.m_ns[s] = fastdiv_magic((uint32_t)ns);
+    mp.m_nbf[s] = fastdiv_magic((uint32_t)(N / mp.radix[s]));
+    ns *= mp.radix[s];
+  }
+  return true;
 }
 
 }  // namespace dt
@@ -186,7 +193,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
     int r = std::min<int>(rows_per_block(sx, 1, nt_row, w), I.ny);
     for (int y = 0; y < I.ny; y += r) {
       const int c = std::min(r, I.ny - y);
-      lists[P_R2C].push_back({i, y, c, 0});
+      lists[P_R2C].push_back({i, y, c, (int)fastdiv_magic((uint32_t)c)});
       need[P_R2C] = std::max<int64_t>(need[P_R2C], sx * c);
       lds[P_R2C] = std::max<size_t>(lds[P_R2C], (size_t)(c * (sx + 1) + 2 * sx) * 2 * w);   // lines + twiddles
     }
@@ -197,7 +204,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
     const int nbi = (int)std::min<int64_t>(64, std::max<int64_t>(nb, nb * my_max / I.My));
     for (int kx = 0; kx <= sx; kx += nbi) {
       const int c = (int)std::min<int64_t>(nbi, sx + 1 - kx);
-      lists[P_COL].push_back({i, kx, c, 0});
+      lists[P_COL].push_back({i, kx, c, (int)fastdiv_magic((uint32_t)c)});
       need[P_COL] = std::max<int64_t>(need[P_COL], (int64_t)I.My * c);
       // spectrum + work column + the twiddle table
       lds[P_COL] = std::max<size_t>(lds[P_COL], (size_t)(2 * I.My * c + I.My) * 2 * w);
@@ -206,7 +213,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
     r = std::min<int>(rows_per_block(sx, p->C, nt_row, w), I.ny);
     for (int y = 0; y < I.ny; y += r) {
       const int c = std::min(r, I.ny - y);
-      lists[P_EPI].push_back({i, y, c, 0});
+      lists[P_EPI].push_back({i, y, c, (int)fastdiv_magic((uint32_t)(c * p->C))});
       need[P_EPI] = std::max<int64_t>(need[P_EPI], sx * c * p->C);
       lds[P_EPI] = std::max<size_t>(lds[P_EPI], (size_t)(c * p->C * (sx + 1) + 2 * sx) * 2 * w);
     }
@@ -444,6 +451,9 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     I.hx = q.spacing[0]; I.hy = q.spacing[1];
     I.tau = q.tau;
     if (!mixed_plan_for(sx, I.px) || !mixed_plan_for(My, I.py)) { delete p; return DT_E_UNSUPPORTED; }
+    I.m_sx = fastdiv_magic((uint32_t)sx);
+    I.m_sx1 = fastdiv_magic((uint32_t)(sx + 1));
+    I.m_nx = fastdiv_magic((uint32_t)I.nx);
     I.img_off = img;
     img += (int64_t)I.nx * I.ny;
     I.spec_off = spec;

@@ -30,12 +30,14 @@ struct BatchInst {
   int64_t twy_off;      // complex elements: exp(-2 pi i m / M_y), m < M_y
   MixedPlan px;         // radix schedule of length sx
   MixedPlan py;         // radix schedule of length M_y
+  uint32_t m_sx, m_sx1, m_nx;   // fastdiv_magic of sx, sx + 1 and nx
 };
 
 // One block of a batched pass: rows [first, first + count) of an instance
 // (row passes) or kx bins [first, first + count) (column pass).
 struct BatchBlock {
-  int inst, first, count, pad;
+  int inst, first, count;
+  int magic;   // fastdiv_magic of the block's line count (count, or count * C in the final row pass)
 };
 
 struct BatchArgs {

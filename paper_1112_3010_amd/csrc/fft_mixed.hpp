@@ -19,9 +19,15 @@ namespace dt {
 
 constexpr int kMixedMaxStages = 12;
 
+// Multiply-high constant of FastDiv for divisor d (0 for d <= 1); computed on
+// the host where the divisor is known at plan time.
+__host__ __device__ constexpr uint32_t fastdiv_magic(uint32_t d) { return d > 1 ? 0xFFFFFFFFu / d + 1u : 0u; }
+
 struct MixedPlan {
   int n_st;
   int radix[kMixedMaxStages];
+  uint32_t m_ns[kMixedMaxStages];    // fastdiv_magic(N_s): product of the earlier radices
+  uint32_t m_nbf[kMixedMaxStages];   // fastdiv_magic(N / R_s): butterflies per line
 };
 
 // Size-3/5/7 DFTs: pair inputs j and R-j, X_k = x0 + sum_j a_j cos(2 pi j k/R)
@@ -71,7 +77,9 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft_small(
 // u < 2^16 (checked exhaustively), which covers every index of a stage.
 struct FastDiv {
   uint32_t d, m;
-  __device__ __forceinline__ explicit FastDiv(uint32_t d_) : d(d_), m(d_ > 1 ? 0xFFFFFFFFu / d_ + 1u : 0u) {}
+  __device__ __forceinline__ explicit FastDiv(uint32_t d_) : d(d_), m(fastdiv_magic(d_)) {}
+  // with the constant precomputed (no division on the device)
+  __device__ __forceinline__ FastDiv(uint32_t d_, uint32_t m_) : d(d_), m(m_) {}
   __device__ __forceinline__ uint32_t div(uint32_t u) const { return d > 1 ? __umulhi(u, m) : u; }
 };
 
@@ -80,13 +88,12 @@ struct FastDiv {
 template <typename T, int DIR, int R, int ECAP, bool LINE_FAST>
 __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istride, int lstride, int Ns,
                                             const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr,
-                                            const FastDiv& fL) {
+                                            const FastDiv& fL, const FastDiv& fNs, const FastDiv& fnbf) {
   using V = Cx<T>;
   constexpr int BM = (ECAP + R - 1) / R;
-  const int nbf = N / R;
+  const int nbf = (int)fnbf.d;
   const int total = nbf * L;
   const int tstep = (N / (Ns * R)) * twstride;   // twiddle index step per unit of k * r
-  const FastDiv fNs((uint32_t)Ns), fnbf((uint32_t)nbf);
   V v[BM][R];
 #pragma unroll
   for (int b = 0; b < BM; ++b) {
@@ -137,20 +144,28 @@ __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istrid
 // Full transform of L lines held in LDS (natural order in and out).  The
 // caller must have synchronised after filling LDS; on return the results are
 // visible to the whole block.  tw holds exp(-2 pi i m / (N * twstride)).
+// fL: the line count L with its precomputed constant; every divisor of the
+// stages comes with its constant from the plan, so no integer division runs
+// on the device.
 template <typename T, int DIR, int ECAP, bool LINE_FAST>
-__device__ void mixed_fft(Cx<T>* lds, int N, int L, int istride, int lstride, const MixedPlan& mp,
+__device__ void mixed_fft(Cx<T>* lds, int N, const FastDiv& fL, int istride, int lstride, const MixedPlan& mp,
                           const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
-  const FastDiv fL((uint32_t)L);
+  const int L = (int)fL.d;
   int Ns = 1;
   for (int s = 0; s < mp.n_st; ++s) {
     const int R = mp.radix[s];
+    const FastDiv fNs((uint32_t)Ns, mp.m_ns[s]), fnbf((uint32_t)(N / R), mp.m_nbf[s]);
     switch (R) {
-      case 8: mixed_stage<T, DIR, 8, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
-      case 4: mixed_stage<T, DIR, 4, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
-      case 2: mixed_stage<T, DIR, 2, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
-      case 7: mixed_stage<T, DIR, 7, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
-      case 5: mixed_stage<T, DIR, 5, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
-      default: mixed_stage<T, DIR, 3, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL); break;
+#define DT_MIXED_STAGE(RR)                                                                                     \
+      mixed_stage<T, DIR, RR, ECAP, LINE_FAST>(lds, N, L, istride, lstride, Ns, tw, twstride, tid, nthr, fL, fNs, \
+                                               fnbf)
+      case 8: DT_MIXED_STAGE(8); break;
+      case 4: DT_MIXED_STAGE(4); break;
+      case 2: DT_MIXED_STAGE(2); break;
+      case 7: DT_MIXED_STAGE(7); break;
+      case 5: DT_MIXED_STAGE(5); break;
+      default: DT_MIXED_STAGE(3); break;
+#undef DT_MIXED_STAGE
     }
     Ns *= R;
   }

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(512) k_batch_row_r2c(BatchArgs a) {
   const V* twg = (const V*)a.tw + I->twx_off;
   V* tw = lds + L * LP;      // exp(-2 pi i m / M_x), m < M_x, staged for every stage
   for (int t = tid; t < 2 * N; t += nthr) tw[t] = twg[t];
-  const FastDiv fN((uint32_t)N), fH((uint32_t)(N + 1));
+  const FastDiv fN((uint32_t)N, I->m_sx), fH((uint32_t)(N + 1), I->m_sx1);
   for (int t = tid; t < L * N; t += nthr) {
     const int l = (int)fN.div((uint32_t)t), m = t - l * N;
     const T* src = img + (int64_t)l * nx;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(512) k_batch_row_r2c(BatchArgs a) {
   }
   __syncthreads();
   const MixedPlan& px = I->px;   // read per stage from the descriptor (no private copy)
-  mixed_fft<T, 1, ECAP, false>(lds, N, L, 1, LP, px, tw, 2, tid, nthr);
+  mixed_fft<T, 1, ECAP, false>(lds, N, FastDiv((uint32_t)L, (uint32_t)bb.magic), 1, LP, px, tw, 2, tid, nthr);
   V* out = (V*)a.out + I->spec_off + (int64_t)bb.first * pitch;
   const int H = N + 1;
   for (int t = tid; t < L * H; t += nthr) {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(ECAP == 8 ? 1024 : 512) k_batch_col_fused(Batc
   const int N = I->My, L = bb.count, ny = I->ny, pitch = I->pitch;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int NL = N * L;
-  const FastDiv fL((uint32_t)L);
+  const FastDiv fL((uint32_t)L, (uint32_t)bb.magic);
   // two LDS buffers: the forward spectrum (kept) and the inverse work column
   V* spec = lds;
   V* work = lds + NL;
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(ECAP == 8 ? 1024 : 512) k_batch_col_fused(Batc
   __syncthreads();
   const MixedPlan& py = I->py;
   const V* tw = twl;
-  mixed_fft<T, 1, ECAP, true>(spec, N, L, L, 1, py, tw, 1, tid, nthr);
+  mixed_fft<T, 1, ECAP, true>(spec, N, fL, L, 1, py, tw, 1, tid, nthr);
   const T* tab = (const T*)a.tab + I->tab_off + bb.first;
   V* out = (V*)a.out + I->fused_off + bb.first;
   const int64_t ch_out = (int64_t)ny * pitch;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(ECAP == 8 ? 1024 : 512) k_batch_col_fused(Batc
       work[e] = c == 0 ? z : mul_mi(z);
     }
     __syncthreads();
-    mixed_fft<T, -1, ECAP, true>(work, N, L, L, 1, py, tw, 1, tid, nthr);
+    mixed_fft<T, -1, ECAP, true>(work, N, fL, L, 1, py, tw, 1, tid, nthr);
     V* oc = out + c * ch_out;
     for (int t = tid; t < ny * L; t += nthr) {
       const int i = (int)fL.div((uint32_t)t), l = t - i * L;
@@ -217,7 +217,8 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
   for (int t = tid; t < 2 * N; t += nthr) tw[t] = twg[t];
   __syncthreads();
   const int64_t ch_in = (int64_t)ny * pitch;
-  const FastDiv fN((uint32_t)N), fC((uint32_t)C), fX((uint32_t)nx);
+  const FastDiv fN((uint32_t)N, I->m_sx), fC((uint32_t)C, C == kBatchChan ? fastdiv_magic(kBatchChan) : 0u),
+      fX((uint32_t)nx, I->m_nx);
   for (int t = tid; t < L * C * N; t += nthr) {
     const int line = (int)fN.div((uint32_t)t), k = t - line * N;
     const int l = (int)fC.div((uint32_t)line), c = line - l * C;
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
   }
   __syncthreads();
   const MixedPlan& px = I->px;   // read per stage from the descriptor (no private copy)
-  mixed_fft<T, -1, ECAP, false>(lds, N, L * C, 1, LP, px, tw, 2, tid, nthr);
+  mixed_fft<T, -1, ECAP, false>(lds, N, FastDiv((uint32_t)(L * C), (uint32_t)bb.magic), 1, LP, px, tw, 2, tid, nthr);
   const int64_t Ki = a.koff[ii + 1] - a.koff[ii];
   const int eg = ceil_log2_count(Ki);
   const T scale_phi = (T)ldexp(1.0, eg + I->e_f);
