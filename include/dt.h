@@ -33,11 +33,19 @@
  * Precision. DT_FP32_SCALED works in float32 with power-of-two scaling of
  *         the source image and kernel spectra (exact, so only the range is
  *         affected); DT_FP64 works in float64.  Output fields have the
- *         plan's working type (float or double).
+ *         plan's working type (float or double).  DT_FP64X2 carries the
+ *         whole convolution in double-double arithmetic (pairs of float64,
+ *         about 106 significand bits; u = 2^-104), the GPU counterpart of
+ *         the multiple-precision FFT that Sec. 3.2 resorts to when float64
+ *         fails far from the sources: S_max grows from about 25-30 tau to
+ *         about 60 tau.  It is built for 2D plans with out_mask == DT_OUT_S
+ *         (dt_distance / dt_forward with S only; float64 output; other
+ *         requests return DT_E_UNSUPPORTED); DT_AUTO considers it for such
+ *         plans after float32 and float64.
  * Validity. An FFT convolution in finite precision has an absolute error
  *         floor; nodes where phi falls below the threshold
  *           Theta = c_theta * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
- *         (u = 2^-24 or 2^-53, N_pad = prod M_d, ||f||_1 = sum of the padded
+ *         (u = 2^-24, 2^-53 or 2^-104, N_pad = prod M_d, ||f||_1 = sum of the padded
  *         kernel, ||g||_2 = sqrt(sum of squared multiplicities)) report
  *         S = S_max = -tau log Theta and zero derivatives.  The paper notes
  *         the effect (Sec. 3.2) but gives no rule; this threshold is the
@@ -72,7 +80,7 @@ typedef enum {
   DT_E_UNSUPPORTED = 6   /* valid request this build does not implement */
 } dt_status;
 
-typedef enum { DT_FP32_SCALED = 0, DT_FP64 = 1, DT_AUTO = 2 } dt_precision;
+typedef enum { DT_FP32_SCALED = 0, DT_FP64 = 1, DT_AUTO = 2, DT_FP64X2 = 3 } dt_precision;
 
 /* Kernel families a plan prepares (bit mask for dt_create_plan). */
 enum {
@@ -131,7 +139,7 @@ typedef struct {
   double spacing[3];
   double origin[3];
   double tau;
-  int precision;         /* DT_FP32_SCALED or DT_FP64 after DT_AUTO resolves */
+  int precision;         /* DT_FP32_SCALED, DT_FP64 or DT_FP64X2 after DT_AUTO resolves */
   unsigned out_mask;
   double c_theta;
   double kernel_l1;      /* ||f||_1 over the padded grid (after set_workspace) */
@@ -152,7 +160,8 @@ typedef struct {
  * out_mask selects the kernel families to prepare.  trunc_dist and k_hint
  * only matter for DT_AUTO: the plan uses float32 if a node at distance
  * trunc_dist from an isolated source stays valid for k_hint distinct
- * sources, else float64 if that holds in float64, else DT_E_PRECISION.
+ * sources, else float64 if that holds in float64, else (2D plans of S
+ * alone) double-double if it holds there, else DT_E_PRECISION.
  * c_theta <= 0 selects the default safety factor 1024. Host only. */
 dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
                          const double* origin, double tau, int precision, unsigned out_mask,

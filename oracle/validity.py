@@ -23,7 +23,9 @@ import math
 
 import numpy as np
 
-UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+# "fp64x2": double-double (pairs of float64, 106 significand bits); its
+# compound operations are accurate to a few units of 2^-106, taken as 2^-104.
+UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53, "fp64x2": 2.0 ** -104}
 
 #: Safety factor between the noise estimate and the validity threshold.
 C_THETA = 1024.0

@@ -32,6 +32,14 @@ FLAGS = [
 ]
 
 
+# Per-file additions.  The double-double kernels rely on every product and
+# sum being rounded as written (error-free transformations); the global
+# -ffp-contract=fast lets the backend fuse a product into a later add even
+# where the product's rounding error is taken separately, so that file turns
+# contraction off (its explicit fma calls remain).
+FILE_FLAGS = {"k_dd.hip": ["-ffp-contract=off"]}
+
+
 def _hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -44,7 +52,7 @@ def sources():
 
 
 def _compile(src, obj, verbose):
-    cmd = [_hipcc(), *FLAGS, "-c", src, "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,311 @@
+// Extended-precision (double-double) pipeline for 2D distance fields.
+//
+// The same zero-padded FFT convolution as the float32/float64 paths
+// (Sec. 3, Table 1: splat the indicator, transform, multiply by the kernel
+// spectrum, transform back, S = -tau log phi of eq. STilde), carried in
+// double-double so that the FFT's absolute error floor drops from about
+// 2^-53 to 2^-104 of the largest term.  Sec. 3.2 observes that the float64
+// convolution fails far from the sources for small tau and resorts to
+// multiple-precision arithmetic; this pipeline plays that role on the GPU.
+//
+// Layout in the plan's workspace (x fastest, M = padded lengths):
+//   twx, twy  M/2 complex double-double twiddles exp(-2 pi i k / M)
+//   tab       My x Mx real double-double spectrum of f, scaled by 1/(Mx My)
+//   cnt       ny x nx float64 multiplicities (the indicator g)
+//   G         My x Mx complex double-double work grid
+// The transforms are radix-2 in LDS, one row or column per block:
+// decimation in time (bit-reversed in, natural out) forward and decimation
+// in frequency (natural in, bit-reversed out) inverse, so no permutation
+// pass is needed between them.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dd.hpp"
+#include "dt_dd.hpp"
+
+namespace dt {
+namespace {
+
+using ddm::dd;
+using ddm::ddc;
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int brev(int x, int logM) { return (int)(__builtin_bitreverse32((uint32_t)x) >> (32 - logM)); }
+
+__device__ __forceinline__ ddc zero_c() { return {{0.0, 0.0}, {0.0, 0.0}}; }
+
+// In-place radix-2 decimation in time over bit-reversed input; natural
+// order out.  tw[k] = exp(-2 pi i k / M); INV conjugates it.
+template <bool INV>
+__device__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+  for (int s = 1; s <= logM; ++s) {
+    const int half = 1 << (s - 1);
+    const int ts = M >> s;
+    for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
+      const int j = b & (half - 1);
+      const int i0 = ((b >> (s - 1)) << s) + j;
+      const int i1 = i0 + half;
+      ddc w = tw[j * ts];
+      if (INV) w.im = ddm::neg(w.im);
+      const ddc u = buf[i0];
+      const ddc v = ddm::cmul(buf[i1], w);
+      buf[i0] = ddm::cadd(u, v);
+      buf[i1] = ddm::csub(u, v);
+    }
+    __syncthreads();
+  }
+}
+
+// In-place radix-2 decimation in frequency over natural-order input;
+// bit-reversed order out.
+template <bool INV>
+__device__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+  for (int s = logM; s >= 1; --s) {
+    const int half = 1 << (s - 1);
+    const int ts = M >> s;
+    for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
+      const int j = b & (half - 1);
+      const int i0 = ((b >> (s - 1)) << s) + j;
+      const int i1 = i0 + half;
+      ddc w = tw[j * ts];
+      if (INV) w.im = ddm::neg(w.im);
+      const ddc u = buf[i0];
+      const ddc v = buf[i1];
+      buf[i0] = ddm::cadd(u, v);
+      buf[i1] = ddm::cmul(ddm::csub(u, v), w);
+    }
+    __syncthreads();
+  }
+}
+
+// exp(-2 pi i k / M) for 0 <= k < M/2, M a power of two >= 8: the angle is
+// reduced to an octant so that the series sees |a| <= pi/4.
+__global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M / 2) return;
+  int j, oct;
+  if (8 * k <= M) {
+    j = k;
+    oct = 0;
+  } else if (4 * k <= M) {
+    j = M / 4 - k;
+    oct = 1;
+  } else if (8 * k <= 3 * M) {
+    j = k - M / 4;
+    oct = 2;
+  } else {
+    j = M / 2 - k;
+    oct = 3;
+  }
+  const dd a = ddm::mul_d({ddm::kTwoPiHi, ddm::kTwoPiLo}, (double)j / (double)M);
+  dd s, c;
+  ddm::sincos_reduced(a, s, c);
+  dd cs, sn;
+  switch (oct) {
+    case 0: cs = c; sn = s; break;
+    case 1: cs = s; sn = c; break;
+    case 2: cs = ddm::neg(s); sn = c; break;
+    default: cs = ddm::neg(c); sn = s; break;
+  }
+  tw[k] = {cs, ddm::neg(sn)};
+}
+
+// f = exp(-r / tau) at every displacement of the padded grid (minimum
+// image; the Nyquist lines are set to 0 as in the other precisions).  The
+// displacement h d is an exact double-double product.
+__global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)g.Mx * g.My) return;
+  const int x = (int)(i % g.Mx), y = (int)(i / g.Mx);
+  ddc v = zero_c();
+  if (x != g.Mx / 2 && y != g.My / 2) {
+    const int dx = x < g.Mx / 2 ? x : x - g.Mx;
+    const int dy = y < g.My / 2 ? y : y - g.My;
+    const dd px = ddm::two_prod(g.hx, (double)dx), py = ddm::two_prod(g.hy, (double)dy);
+    const dd r = ddm::sqrt(ddm::add(ddm::mul(px, px), ddm::mul(py, py)));
+    v.re = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
+  }
+  G[i] = v;
+}
+
+// Forward transform of rows.  REAL_IN: row y of the ny x nx multiplicities,
+// zero-padded to Mx; else row y of G in place.
+template <bool REAL_IN>
+__global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restrict__ cnt, ddc* __restrict__ G,
+                                                         const ddc* __restrict__ tw, DDGeom g) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int y = blockIdx.x;
+  const int M = g.Mx;
+  for (int x = threadIdx.x; x < M; x += blockDim.x) {
+    ddc v;
+    if (REAL_IN) {
+      v = zero_c();
+      if (x < g.nx) v.re.hi = cnt[(int64_t)y * g.nx + x];
+    } else {
+      v = G[(int64_t)y * M + x];
+    }
+    buf[brev(x, g.logMx)] = v;
+  }
+  __syncthreads();
+  fft_dit<false>(buf, M, g.logMx, tw);
+  for (int x = threadIdx.x; x < M; x += blockDim.x) G[(int64_t)y * M + x] = buf[x];
+}
+
+// Column kx: forward transform of rows [0, ny_in) (zero above), then either
+// (TABLE) store the scaled real part as the kernel spectrum, or multiply by
+// the spectrum, transform back and store rows [0, ny_out).
+template <bool TABLE>
+__global__ __launch_bounds__(kThreads) void k_dd_col(ddc* __restrict__ G, dd* __restrict__ tab,
+                                                     const ddc* __restrict__ tw, DDGeom g, int ny_in, int ny_out) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int kx = blockIdx.x;
+  const int M = g.My;
+  for (int y = threadIdx.x; y < M; y += blockDim.x)
+    buf[brev(y, g.logMy)] = y < ny_in ? G[(int64_t)y * g.Mx + kx] : zero_c();
+  __syncthreads();
+  fft_dit<false>(buf, M, g.logMy, tw);
+  if (TABLE) {
+    const int e = -(g.logMx + g.logMy);
+    for (int ky = threadIdx.x; ky < M; ky += blockDim.x) tab[(int64_t)ky * g.Mx + kx] = ddm::scale2(buf[ky].re, e);
+    return;
+  }
+  for (int ky = threadIdx.x; ky < M; ky += blockDim.x)
+    buf[ky] = ddm::cmul_real(buf[ky], tab[(int64_t)ky * g.Mx + kx]);
+  __syncthreads();
+  fft_dif<true>(buf, M, g.logMy, tw);
+  for (int y = threadIdx.x; y < ny_out; y += blockDim.x) G[(int64_t)y * g.Mx + kx] = buf[brev(y, g.logMy)];
+}
+
+// Inverse transform of row y and the epilogue: phi = Re, S = -tau log phi
+// where phi >= Theta, else S_max (scal[0] = Theta, scal[1] = S_max).
+__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ G, const ddc* __restrict__ tw,
+                                                             double* __restrict__ S, const double* __restrict__ scal,
+                                                             DDGeom g) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int y = blockIdx.x;
+  const int M = g.Mx;
+  for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = G[(int64_t)y * M + x];
+  __syncthreads();
+  fft_dif<true>(buf, M, g.logMx, tw);
+  const double theta = scal[0], smax = scal[1];
+  for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
+    const dd phi = buf[brev(x, g.logMx)].re;
+    // log(hi + lo) = log(hi) + lo / hi to float64 accuracy
+    const double s = (phi.hi > 0.0 && phi.hi >= theta) ? -g.tau * (log(phi.hi) + phi.lo / phi.hi) : smax;
+    S[(int64_t)y * g.nx + x] = s;
+  }
+}
+
+// Node assignment idx = floor((y - o) / h) in float64; multiplicities by
+// atomic adds (integers, exact in float64).  Bit 1: outside the grid,
+// bit 2: non-finite.
+__global__ void k_dd_splat(const float* __restrict__ Y, int64_t K, double* __restrict__ cnt,
+                           uint32_t* __restrict__ err, DDGeom g) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double y0 = Y[2 * k], y1 = Y[2 * k + 1];
+  if (!__builtin_isfinite(y0) || !__builtin_isfinite(y1)) {
+    atomicOr(err, 2u);
+    return;
+  }
+  const double fx = __builtin_floor((y0 - g.ox) / g.hx), fy = __builtin_floor((y1 - g.oy) / g.hy);
+  if (!(fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny)) {
+    atomicOr(err, 1u);
+    return;
+  }
+  atomicAdd(&cnt[(int64_t)fy * g.nx + (int64_t)fx], 1.0);
+}
+
+// ||g||_2 = sqrt(sum m^2) (exact: integer sums below 2^53) and the validity
+// threshold Theta = c u log2(N_pad) ||f||_1 ||g||_2 / sqrt(N_pad), S_max.
+__global__ __launch_bounds__(1024) void k_dd_finalize(const double* __restrict__ cnt, double* __restrict__ scal,
+                                                      DDGeom g, double c_theta, double unit, double l1) {
+  __shared__ double part[1024];
+  const int64_t n = (int64_t)g.nx * g.ny;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += cnt[i] * cnt[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double npad = (double)g.Mx * (double)g.My;
+    const double gl2 = __builtin_sqrt(part[0]);
+    const double theta = c_theta * unit * (double)(g.logMx + g.logMy) * l1 * gl2 / __builtin_sqrt(npad);
+    scal[0] = theta;
+    scal[1] = -g.tau * log(theta);
+    scal[2] = gl2;
+  }
+}
+
+// Kernels whose dynamic LDS exceeds the default 64 KiB limit must opt in.
+template <typename F>
+hipError_t allow_lds(F kern, size_t lds) {
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t dd_build_tables(void* twx, void* twy, void* tab, void* G, const DDGeom& g, hipStream_t st) {
+  k_dd_twiddles<<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((ddc*)twx, g.Mx);
+  k_dd_twiddles<<<(g.My / 2 + 255) / 256, 256, 0, st>>>((ddc*)twy, g.My);
+  const int64_t total = (int64_t)g.Mx * g.My;
+  k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g);
+  const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc);
+  hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
+  if (e != hipSuccess) return e;
+  k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
+  e = allow_lds(k_dd_col<true>, ly);
+  if (e != hipSuccess) return e;
+  k_dd_col<true><<<g.Mx, kThreads, ly, st>>>((ddc*)G, (dd*)tab, (const ddc*)twy, g, g.My, 0);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, uint32_t* err, const DDGeom& g, hipStream_t st) {
+  k_dd_splat<<<(unsigned)((K + 255) / 256), 256, 0, st>>>(Y, K, cnt, err, g);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_finalize(const double* cnt, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
+                              hipStream_t st) {
+  k_dd_finalize<<<1, 1024, 0, st>>>(cnt, scal, g, c_theta, unit, l1);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
+  const size_t lds = (size_t)g.Mx * sizeof(ddc);
+  const hipError_t e = allow_lds(k_dd_row_fwd<true>, lds);
+  if (e != hipSuccess) return e;
+  k_dd_row_fwd<true><<<g.ny, kThreads, lds, st>>>(cnt, (ddc*)G, (const ddc*)twx, g);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_col_fused(void* G, const void* tab, const void* twy, const DDGeom& g, hipStream_t st) {
+  const size_t lds = (size_t)g.My * sizeof(ddc);
+  const hipError_t e = allow_lds(k_dd_col<false>, lds);
+  if (e != hipSuccess) return e;
+  k_dd_col<false><<<g.Mx, kThreads, lds, st>>>((ddc*)G, (dd*)tab, (const ddc*)twy, g, g.ny, g.ny);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_row_inv_epi(const void* G, const void* twx, double* S, const double* scal, const DDGeom& g,
+                                 hipStream_t st) {
+  const size_t lds = (size_t)g.Mx * sizeof(ddc);
+  const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
+  if (e != hipSuccess) return e;
+  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)G, (const ddc*)twx, S, scal, g);
+  return hipGetLastError();
+}
+
+}  // namespace dt

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "dt.h"
+#include "dt_dd.hpp"
 #include "dt_launch.hpp"
 
 using namespace dt;
@@ -75,6 +76,10 @@ struct dt_plan_s {
   hipStream_t stream = nullptr;
   double kernel_l1 = 0;
   bool ready = false;
+  // double-double plans (2D, S only) use their own workspace regions
+  bool dd = false;
+  DDGeom ddg{};
+  size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0;
   // optional per-pass timing
   bool timing = false;
   struct Pending { std::string name; hipEvent_t a, b; };
@@ -102,7 +107,7 @@ struct dt_plan_s {
   int64_t nodes() const { return n[0] * n[1] * n[2]; }
   int64_t rows() const { return n[1] * n[2]; }
   double npad() const { return (double)M[0] * (double)M[1] * (double)M[2]; }
-  double unit() const { return fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24); }
+  double unit() const { return dd ? std::ldexp(1.0, -104) : fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24); }
   double* scal() const { return (double*)(ws + off_scal); }
   double* msq() const { return scal() + 16; }   // splat accumulator of sum m^2 (cleared by the finalize)
   uint32_t* err() const { return (uint32_t*)(ws + off_err); }
@@ -218,6 +223,44 @@ double host_kernel_l1(const int64_t* M, const double* h, int ndim, double tau) {
 
 dt_status hip_status(hipError_t e) { return e == hipSuccess ? DT_OK : DT_E_HIP; }
 
+int log2_exact(int64_t m) {
+  int e = 0;
+  while ((int64_t(1) << e) < m) ++e;
+  return e;
+}
+
+// Workspace of a double-double plan: scalars and error word (same offsets
+// as the other precisions, so the stats calls are shared), twiddles, the
+// real spectrum, the multiplicities and the complex work grid.
+void setup_dd(dt_plan p) {
+  p->dd = true;
+  p->fp64 = true;  // outputs are float64
+  p->w = 8;
+  DDGeom& g = p->ddg;
+  g.nx = (int)p->n[0];
+  g.ny = (int)p->n[1];
+  g.Mx = (int)p->M[0];
+  g.My = (int)p->M[1];
+  g.logMx = log2_exact(p->M[0]);
+  g.logMy = log2_exact(p->M[1]);
+  g.hx = p->h[0];
+  g.hy = p->h[1];
+  g.ox = p->o[0];
+  g.oy = p->o[1];
+  g.tau = p->tau;
+  const size_t npad = (size_t)g.Mx * g.My;
+  size_t off = 0;
+  p->off_scal = off; off = align_up(off + 64 * sizeof(double));
+  p->off_err = off; off = align_up(off + sizeof(uint32_t));
+  p->off_R1 = off;  // end of the region cleared at attach
+  p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * kDDComplexBytes);
+  p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * kDDComplexBytes);
+  p->off_dd_tab = off; off = align_up(off + npad * kDDRealBytes);
+  p->off_dd_cnt = off; off = align_up(off + (size_t)g.nx * g.ny * sizeof(double));
+  p->off_dd_G = off; off = align_up(off + npad * kDDComplexBytes);
+  p->ws_bytes = off;
+}
+
 template <typename T> size_t complex_bytes() { return 2 * sizeof(T); }
 
 }  // namespace
@@ -233,7 +276,8 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   if (ndim != 2 && ndim != 3) return DT_E_ARG;
   if (!dims || !spacing || !origin) return DT_E_ARG;
   if (!finite_pos(tau)) return DT_E_ARG;
-  if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO) return DT_E_ARG;
+  if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO && precision != DT_FP64X2)
+    return DT_E_ARG;
   const unsigned known = DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_SIGN | DT_OUT_BACKWARD | DT_OUT_CURV;
   if (out_mask == 0 || (out_mask & ~known)) return DT_E_ARG;
   if (!(c_theta <= 0) && !finite_pos(c_theta)) return DT_E_ARG;
@@ -263,10 +307,14 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    for (int cand = 0; cand < 2 && chosen < 0; ++cand) {
-      const double u = cand == 0 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+    // double-double is a candidate only where it is built: 2D plans of S alone
+    const int n_cand = (ndim == 2 && out_mask == DT_OUT_S) ? 3 : 2;
+    const int cands[3] = {DT_FP32_SCALED, DT_FP64, DT_FP64X2};
+    const int ubits[3] = {24, 53, 104};
+    for (int c = 0; c < n_cand && chosen < 0; ++c) {
+      const double u = std::ldexp(1.0, -ubits[c]);
       const double theta = p->c_theta * u * std::log2(np) * l1 * std::sqrt((double)k_hint) / std::sqrt(np);
-      if (trunc_dist <= -tau * std::log(theta)) chosen = cand == 0 ? DT_FP32_SCALED : DT_FP64;
+      if (trunc_dist <= -tau * std::log(theta)) chosen = cands[c];
     }
     if (chosen < 0) {
       delete p;
@@ -275,6 +323,15 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
     precision = chosen;
   }
   p->prec = precision;
+  if (precision == DT_FP64X2) {
+    if (ndim != 2 || out_mask != DT_OUT_S) {
+      delete p;
+      return DT_E_UNSUPPORTED;
+    }
+    setup_dd(p);
+    *out = p;
+    return DT_OK;
+  }
   p->fp64 = precision == DT_FP64;
   p->w = p->fp64 ? 8 : 4;
   p->Mh = (int)(p->M[0] / 2 + 1);
@@ -490,6 +547,15 @@ extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t byte
   p->ready = false;
   // clear the scalars, the error word and the pitch padding of the table region
   launch_fill_zero<double>((double*)p->ws, (int64_t)(p->off_R1 / sizeof(double)), st);
+  if (p->dd) {
+    hipError_t e = dd_build_tables(p->ws + p->off_dd_twx, p->ws + p->off_dd_twy, p->ws + p->off_dd_tab,
+                                   p->ws + p->off_dd_G, p->ddg, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return DT_E_HIP;
+    p->kernel_l1 = host_kernel_l1(p->M, p->h, 2, p->tau);
+    p->ready = true;
+    return DT_OK;
+  }
   const dt_status s = p->fp64 ? build_tables<double>(p, st) : build_tables<float>(p, st);
   if (s != DT_OK) return s;
   p->ready = true;
@@ -870,12 +936,48 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
 
 }  // namespace
 
+// The double-double pipeline: S only, from explicit sources.
+static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
+                         hipStream_t st) {
+  if (out->grad || out->hess || out->label || out->mu || out->curv || out->signed_outputs || shape)
+    return DT_E_UNSUPPORTED;
+  if (!out->S || !Y || K < 1) return DT_E_ARG;
+  if (!p->ready) return DT_E_WORKSPACE;
+  const DDGeom& g = p->ddg;
+  double* cnt = (double*)(p->ws + p->off_dd_cnt);
+  char* G = p->ws + p->off_dd_G;
+  hipError_t e;
+  {
+    PassTimer t(p, st, "splat");
+    launch_fill_zero<double>(cnt, (int64_t)g.nx * g.ny, st);
+    e = dd_launch_splat(Y, K, cnt, p->err(), g, st);
+    if (e == hipSuccess) e = dd_launch_finalize(cnt, p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, "dd_row_fwd");
+    e = dd_launch_row_fwd(cnt, G, p->ws + p->off_dd_twx, g, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, "dd_col_fused");
+    e = dd_launch_col_fused(G, p->ws + p->off_dd_tab, p->ws + p->off_dd_twy, g, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, "dd_row_inv_epi");
+    e = dd_launch_row_inv_epi(G, p->ws + p->off_dd_twx, (double*)out->S, p->scal(), g, st);
+  }
+  return hip_status(e);
+}
+
 extern "C" dt_status dt_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
                                 void* stream) {
   if (!p || !out) return DT_E_ARG;
   if (!Y && K != 0) return DT_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;
+  if (p->dd) return run_forward_dd(p, Y, K, shape, out, st);
   return p->fp64 ? run_forward<double>(p, Y, K, shape, out, st) : run_forward<float>(p, Y, K, shape, out, st);
 }
 
@@ -913,6 +1015,7 @@ extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const voi
                                  float* dL_dY, double* dL_dtau, void* stream) {
   if (!p || !Y || K < 1 || !S || !dL_dS || !dL_dY) return DT_E_ARG;
   if (!(p->mask & DT_OUT_BACKWARD)) return DT_E_ARG;
+  if (p->dd) return DT_E_UNSUPPORTED;
   if (!p->ready) return DT_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;

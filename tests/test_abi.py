@@ -130,3 +130,36 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, *_ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_fp64x2_plans(lib):
+    from paper_1112_3010_amd import _lib
+    st, h = _plan(lib, prec=3, mask=1)
+    assert st == 0
+    info = _lib.DtPlanInfo()
+    assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    assert info.precision == 3 and info.unit_roundoff == 2.0 ** -104
+    size = ctypes.c_size_t()
+    assert lib.dt_plan_workspace_size(h, ctypes.byref(size)) == 0
+    assert size.value >= 128 * 128 * (32 + 16)          # complex grid + real spectrum
+    dummy = ctypes.c_void_p(4096)
+    assert lib.dt_distance(h, dummy, 10, dummy, None) == 4          # no workspace yet
+    assert lib.dt_gradient(h, dummy, 10, None, dummy, None) == 6    # S only
+    assert lib.dt_backward(h, dummy, 10, dummy, dummy, dummy, None, None) == 1
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, prec=3, mask=3)[0] == 6                        # gradient not built
+    assert _plan(lib, ndim=3, dims=(32, 32, 32), prec=3, mask=1)[0] == 6
+
+
+def test_auto_picks_fp64x2_for_2d_distance(lib):
+    from paper_1112_3010_amd import _lib
+    dims = (128, 128)
+    tau = 2.0 / 128
+    st, h = _plan(lib, dims=dims, tau=tau, prec=2, mask=1, trunc=45 * tau, khint=1000)
+    assert st == 0
+    info = _lib.DtPlanInfo()
+    assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    assert info.precision == 3
+    lib.dt_destroy_plan(h)
+    # with the gradient requested there is no extended-precision candidate
+    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=3, trunc=45 * tau, khint=1000)[0] == 3
