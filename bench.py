@@ -84,11 +84,18 @@ def counters_for(kernel_file_hash, precision, pass_name):
     return None
 
 
-def kernel_hash():
-    """Hash of every kernel and host source of the library."""
+# sources of the double-double pipeline only (no float32/float64 launch uses them)
+DD_SOURCES = ("dd.hpp", "dt_dd.hpp", "k_dd.hip")
+
+
+def kernel_hash(include_dd=False):
+    """Hash of the kernel and host sources of the library (without the
+    double-double pipeline's own files unless include_dd)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1112_3010_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f in DD_SOURCES and not include_dd:
+            continue
         if f.endswith((".hip", ".hpp", ".cpp")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + b"\0" + fh.read())
@@ -460,6 +467,112 @@ def run_batch(steps, warmup):
     print(json.dumps(line), flush=True)
 
 
+# float64 VALU operations of the double-double primitives (each add, mul or
+# fma one operation): the accurate add is two TwoSums (6 each), two
+# Fast2Sums (3 each) and two adds; the product is TwoProd (mul + fma), two
+# cross products, two adds and a Fast2Sum.
+DD_ADD_OPS, DD_MUL_OPS = 20, 9
+# one float64 VALU operation per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
+# (78.6 TFLOP/s with an FMA counted as two)
+F64_OPS_PEAK_T = 256 * 64 * 2.4e9 / 1e12
+
+
+def dd_col_ops(Mx, My):
+    """Operations of the fused double-double column pass: per column a
+    forward and an inverse radix-2 transform of My points (My/2 log2 My
+    butterflies, each a complex multiply of 4 products and 2 adds plus a
+    complex add and subtract) and My real-by-complex products."""
+    bfly = (4 * DD_MUL_OPS + 2 * DD_ADD_OPS) + 4 * DD_ADD_OPS
+    logM = int(round(np.log2(My)))
+    return Mx * (2 * (My // 2) * logM * bfly + My * 2 * DD_MUL_OPS)
+
+
+def run_dd(steps, warmup, no_cpu, cpu_cells):
+    """The double-double path on the 1024^2 polygon workload (K = 8000,
+    tau = 0.5 h: the smallest tau of that workload, where float64 loses the
+    most of the grid), S only, timed beside the float64 path on the same
+    input.  ALU-bound: the roofline counts float64 operations."""
+    import torch
+    import paper_1112_3010_amd as dt
+    import synth
+    w = synth.workload("c2_2d_1024_polygon")
+    dims = w.dims
+    h = tuple(1.0 / n for n in dims)
+    tau = w.taus[0]
+    Yd = torch.from_numpy(w.points).cuda()
+    res = {}
+    for prec in ("fp64x2", "fp64"):
+        plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S"])
+        S = plan._empty()
+        for _ in range(warmup):
+            plan.distance_into(S, Yd)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.distance_into(S, Yd)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        plan.set_timing(True)
+        plan.timings(reset=True)
+        for _ in range(5):
+            plan.distance_into(S, Yd)
+        per = plan.timings(reset=True)
+        plan.set_timing(False)
+        st = plan.last_stats()
+        res[prec] = {"ms": ms, "pass_ms": {k: round(v[1] / v[0], 4) for k, v in per.items() if v[0] > 0},
+                     "s_max_over_tau": st["s_max"] / tau, "S": S.cpu().numpy().astype(np.float64).ravel(),
+                     "padded": plan.padded, "theta": st["theta"]}
+        log(f"{prec}: {ms:.3f} ms, S_max/tau {st['s_max'] / tau:.2f}, passes {res[prec]['pass_ms']}")
+        del plan
+    r = res["fp64x2"]
+    Mx, My = r["padded"]
+    col_ms = r["pass_ms"]["dd_col_fused"]
+    ops = dd_col_ops(Mx, My)
+    achieved = ops / (col_ms * 1e-3) / 1e12
+    nodes = dims[0] * dims[1]
+    line = {"metric": "grid pts/s for S at 1024^2 in double-double (extended valid band)",
+            "value": round(nodes / (r["ms"] * 1e-3), 1), "unit": "grid pts/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64x2", "data": "synthetic",
+            "config": {"workload": "polygon_2d_1024_K8000_tau0.5h_S", "padded": [Mx, My]},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(F64_OPS_PEAK_T, 2),
+                         "unit": "T f64-ops/s", "frac": round(achieved / F64_OPS_PEAK_T, 4), "traffic": None,
+                         "kernel": "dd_col_fused", "ops_per_launch": ops},
+            "pass_ms": r["pass_ms"], "s_max_over_tau": round(r["s_max_over_tau"], 2),
+            "fp64": {"ms_per_step": round(res["fp64"]["ms"], 4), "pass_ms": res["fp64"]["pass_ms"],
+                     "s_max_over_tau": round(res["fp64"]["s_max_over_tau"], 2)}}
+    if not no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        rng = np.random.default_rng(2024)
+        cells = np.sort(rng.choice(nodes, cpu_cells, replace=False))
+        o = (0.0, 0.0)
+        idx, valid = oracle.snap(w.points, o, h, dims)
+        Yh = oracle.node_coords(idx[valid], o, h)
+        X = oracle.grid_nodes(dims, o, h, cells)
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            f = oracle.fields(X, Yh, tau)
+            dt_s = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(len(cells) / dt_s, 2), "unit": "grid pts/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{len(cells)} random nodes of the 1024^2 grid, all {int(valid.sum())} "
+                                          f"sources each, S in float64 ({dt_s:.1f} s)"}
+        acc = {}
+        for prec in ("fp64x2", "fp64"):
+            smax = res[prec]["s_max_over_tau"] * tau
+            ref = np.minimum(f["S"], smax)
+            Sg = res[prec]["S"][cells]
+            deep = f["lnphi"] >= np.log(2.0 * res[prec]["theta"])
+            acc[prec] = {"max_dS_over_tau": float(np.abs(Sg - ref).max() / tau),
+                         "resolved_fraction": round(float(deep.mean()), 4)}
+        line["accuracy_vs_oracle"] = acc
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -470,9 +583,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-curv", action="store_true", help="skip the 256^3 curvature timing")
-    ap.add_argument("--workload", choices=["mesh256", "batch", "protocol"], default="mesh256",
+    ap.add_argument("--workload", choices=["mesh256", "batch", "protocol", "dd"], default="mesh256",
                     help="mesh256: the 256^3 mesh headline (default); batch: 96 mixed-size 2D instances; "
-                         "protocol: Example 1 of Sec. 6.1 against Table 2")
+                         "protocol: Example 1 of Sec. 6.1 against Table 2; dd: 1024^2 polygon S in double-double")
     ap.add_argument("--trials", type=int, default=200, help="trials per tau of --workload protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (3 times) to calibrate HBM traffic counters, then exit")
@@ -496,6 +609,9 @@ def main():
         return
     if args.workload == "protocol":
         run_protocol(args.trials)
+        return
+    if args.workload == "dd":
+        run_dd(args.steps, args.warmup, args.no_cpu, min(args.cpu_cells, 4096))
         return
     import synth
     n = 256

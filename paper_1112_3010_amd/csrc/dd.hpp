@@ -9,8 +9,10 @@
 // argument reduction, Taylor series evaluated by Horner's rule and one
 // Newton step, all in this arithmetic.
 //
-// Files that include this header compile with floating-point contraction
-// off, so every rounding the transformations rely on happens as written.
+// Every rounding the transformations rely on must happen as written: a file
+// that includes this header is compiled with -ffp-contract=off (the pragma
+// below covers the front end only; a global fast-contraction flag still lets
+// the backend fuse a product into a later sum).
 #pragma once
 #include <hip/hip_runtime.h>
 

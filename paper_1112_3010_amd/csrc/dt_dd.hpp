@@ -18,8 +18,11 @@ constexpr size_t kDDComplexBytes = 32, kDDRealBytes = 16;
 // Plan time: twiddles of both axes, then f sampled into G and transformed;
 // tab receives the scaled real spectrum.  G is scratch (My x Mx complex).
 hipError_t dd_build_tables(void* twx, void* twy, void* tab, void* G, const DDGeom& g, hipStream_t st);
-hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, uint32_t* err, const DDGeom& g, hipStream_t st);
-hipError_t dd_launch_finalize(const double* cnt, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
+// Multiplicities into cnt (cleared by the caller) and sum m^2 into *msq
+// (left at 0 by dd_launch_finalize, which consumes it).
+hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
+                           hipStream_t st);
+hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
                               hipStream_t st);
 hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st);
 hipError_t dd_launch_col_fused(void* G, const void* tab, const void* twy, const DDGeom& g, hipStream_t st);

@@ -202,47 +202,45 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
 }
 
 // Node assignment idx = floor((y - o) / h) in float64; multiplicities by
-// atomic adds (integers, exact in float64).  Bit 1: outside the grid,
-// bit 2: non-finite.
-__global__ void k_dd_splat(const float* __restrict__ Y, int64_t K, double* __restrict__ cnt,
-                           uint32_t* __restrict__ err, DDGeom g) {
+// atomic adds (integers, exact in float64).  Each add that raises a count
+// from c to c + 1 raises sum m^2 by 2c + 1; those increments are summed per
+// wave and added to *msq (integer sums below 2^53: exact in any order).
+// Bit 1: outside the grid, bit 2: non-finite.
+__global__ __launch_bounds__(256) void k_dd_splat(const float* __restrict__ Y, int64_t K, double* __restrict__ cnt,
+                                                  double* __restrict__ msq, uint32_t* __restrict__ err, DDGeom g) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const double y0 = Y[2 * k], y1 = Y[2 * k + 1];
-  if (!__builtin_isfinite(y0) || !__builtin_isfinite(y1)) {
-    atomicOr(err, 2u);
-    return;
+  double inc = 0.0;
+  if (k < K) {
+    const double y0 = Y[2 * k], y1 = Y[2 * k + 1];
+    if (!__builtin_isfinite(y0) || !__builtin_isfinite(y1)) {
+      atomicOr(err, 2u);
+    } else {
+      const double fx = __builtin_floor((y0 - g.ox) / g.hx), fy = __builtin_floor((y1 - g.oy) / g.hy);
+      if (!(fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny)) {
+        atomicOr(err, 1u);
+      } else {
+        const double old = atomicAdd(&cnt[(int64_t)fy * g.nx + (int64_t)fx], 1.0);
+        inc = 2.0 * old + 1.0;
+      }
+    }
   }
-  const double fx = __builtin_floor((y0 - g.ox) / g.hx), fy = __builtin_floor((y1 - g.oy) / g.hy);
-  if (!(fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny)) {
-    atomicOr(err, 1u);
-    return;
-  }
-  atomicAdd(&cnt[(int64_t)fy * g.nx + (int64_t)fx], 1.0);
+  for (int off = 32; off > 0; off >>= 1) inc += __shfl_xor(inc, off);
+  if ((threadIdx.x & 63) == 0 && inc != 0.0) atomicAdd(msq, inc);
 }
 
-// ||g||_2 = sqrt(sum m^2) (exact: integer sums below 2^53) and the validity
-// threshold Theta = c u log2(N_pad) ||f||_1 ||g||_2 / sqrt(N_pad), S_max.
-__global__ __launch_bounds__(1024) void k_dd_finalize(const double* __restrict__ cnt, double* __restrict__ scal,
-                                                      DDGeom g, double c_theta, double unit, double l1) {
-  __shared__ double part[1024];
-  const int64_t n = (int64_t)g.nx * g.ny;
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += cnt[i] * cnt[i];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double npad = (double)g.Mx * (double)g.My;
-    const double gl2 = __builtin_sqrt(part[0]);
-    const double theta = c_theta * unit * (double)(g.logMx + g.logMy) * l1 * gl2 / __builtin_sqrt(npad);
-    scal[0] = theta;
-    scal[1] = -g.tau * log(theta);
-    scal[2] = gl2;
-  }
+// ||g||_2 = sqrt(sum m^2) and the validity threshold
+// Theta = c u log2(N_pad) ||f||_1 ||g||_2 / sqrt(N_pad), S_max; clears the
+// accumulator for the next call.
+__global__ void k_dd_finalize(double* __restrict__ msq, double* __restrict__ scal, DDGeom g, double c_theta,
+                              double unit, double l1) {
+  if (threadIdx.x != 0) return;
+  const double npad = (double)g.Mx * (double)g.My;
+  const double gl2 = __builtin_sqrt(*msq);
+  *msq = 0.0;
+  const double theta = c_theta * unit * (double)(g.logMx + g.logMy) * l1 * gl2 / __builtin_sqrt(npad);
+  scal[0] = theta;
+  scal[1] = -g.tau * log(theta);
+  scal[2] = gl2;
 }
 
 // Kernels whose dynamic LDS exceeds the default 64 KiB limit must opt in.
@@ -272,14 +270,15 @@ hipError_t dd_build_tables(void* twx, void* twy, void* tab, void* G, const DDGeo
   return hipGetLastError();
 }
 
-hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, uint32_t* err, const DDGeom& g, hipStream_t st) {
-  k_dd_splat<<<(unsigned)((K + 255) / 256), 256, 0, st>>>(Y, K, cnt, err, g);
+hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
+                           hipStream_t st) {
+  k_dd_splat<<<(unsigned)((K + 255) / 256), 256, 0, st>>>(Y, K, cnt, msq, err, g);
   return hipGetLastError();
 }
 
-hipError_t dd_launch_finalize(const double* cnt, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
+hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
                               hipStream_t st) {
-  k_dd_finalize<<<1, 1024, 0, st>>>(cnt, scal, g, c_theta, unit, l1);
+  k_dd_finalize<<<1, 64, 0, st>>>(msq, scal, g, c_theta, unit, l1);
   return hipGetLastError();
 }
 

@@ -950,8 +950,8 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   {
     PassTimer t(p, st, "splat");
     launch_fill_zero<double>(cnt, (int64_t)g.nx * g.ny, st);
-    e = dd_launch_splat(Y, K, cnt, p->err(), g, st);
-    if (e == hipSuccess) e = dd_launch_finalize(cnt, p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
+    e = dd_launch_splat(Y, K, cnt, p->msq(), p->err(), g, st);
+    if (e == hipSuccess) e = dd_launch_finalize(p->msq(), p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
   {
