@@ -13,7 +13,8 @@
 //   tab       My x Mx real double-double spectrum of f, scaled by 1/(Mx My)
 //   cnt       ny x nx float64 multiplicities (the indicator g)
 //   G         My x Mx complex double-double work grid
-// The transforms are radix-2 in LDS, one row or column per block:
+// The transforms are radix-2 in LDS (stages fused in pairs), one row or
+// column per block:
 // decimation in time (bit-reversed in, natural out) forward and decimation
 // in frequency (natural in, bit-reversed out) inverse, so no permutation
 // pass is needed between them.
@@ -36,45 +37,88 @@ __device__ __forceinline__ int brev(int x, int logM) { return (int)(__builtin_bi
 
 __device__ __forceinline__ ddc zero_c() { return {{0.0, 0.0}, {0.0, 0.0}}; }
 
+__device__ __forceinline__ ddc twiddle(const ddc* __restrict__ tw, int k, bool inv) {
+  ddc w = tw[k];
+  if (inv) w.im = ddm::neg(w.im);
+  return w;
+}
+
 // In-place radix-2 decimation in time over bit-reversed input; natural
-// order out.  tw[k] = exp(-2 pi i k / M); INV conjugates it.
+// order out.  tw[k] = exp(-2 pi i k / M); INV conjugates it.  Stages s and
+// s + 1 are taken together: a thread carries four elements through both in
+// registers (the same butterflies as two radix-2 stages), which halves the
+// LDS round trips and barriers; an odd last stage runs alone.
 template <bool INV>
 __device__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
-  for (int s = 1; s <= logM; ++s) {
+  int s = 1;
+  for (; s + 1 <= logM; s += 2) {
     const int half = 1 << (s - 1);
-    const int ts = M >> s;
+    for (int q = threadIdx.x; q < (M >> 2); q += blockDim.x) {
+      const int j = q & (half - 1);
+      const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
+      const ddc wa = twiddle(tw, j * (M >> s), INV);
+      const ddc wb = twiddle(tw, j * (M >> (s + 1)), INV);
+      const ddc wc = twiddle(tw, (j + half) * (M >> (s + 1)), INV);
+      const ddc a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      const ddc t1 = ddm::cmul(a1, wa), t3 = ddm::cmul(a3, wa);
+      const ddc x0 = ddm::cadd(a0, t1), x1 = ddm::csub(a0, t1);
+      const ddc x2 = ddm::cadd(a2, t3), x3 = ddm::csub(a2, t3);
+      const ddc u2 = ddm::cmul(x2, wb), u3 = ddm::cmul(x3, wc);
+      buf[i0] = ddm::cadd(x0, u2);
+      buf[i0 + 2 * half] = ddm::csub(x0, u2);
+      buf[i0 + half] = ddm::cadd(x1, u3);
+      buf[i0 + 3 * half] = ddm::csub(x1, u3);
+    }
+    __syncthreads();
+  }
+  if (s == logM) {
+    const int half = 1 << (s - 1);
     for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
       const int j = b & (half - 1);
       const int i0 = ((b >> (s - 1)) << s) + j;
-      const int i1 = i0 + half;
-      ddc w = tw[j * ts];
-      if (INV) w.im = ddm::neg(w.im);
+      const ddc v = ddm::cmul(buf[i0 + half], twiddle(tw, j * (M >> s), INV));
       const ddc u = buf[i0];
-      const ddc v = ddm::cmul(buf[i1], w);
       buf[i0] = ddm::cadd(u, v);
-      buf[i1] = ddm::csub(u, v);
+      buf[i0 + half] = ddm::csub(u, v);
     }
     __syncthreads();
   }
 }
 
 // In-place radix-2 decimation in frequency over natural-order input;
-// bit-reversed order out.
+// bit-reversed order out.  An odd top stage runs alone, then stages t and
+// t - 1 are taken together as in fft_dit.
 template <bool INV>
 __device__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
-  for (int s = logM; s >= 1; --s) {
-    const int half = 1 << (s - 1);
-    const int ts = M >> s;
+  int t = logM;
+  if (logM & 1) {
+    const int half = 1 << (t - 1);
     for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
       const int j = b & (half - 1);
-      const int i0 = ((b >> (s - 1)) << s) + j;
-      const int i1 = i0 + half;
-      ddc w = tw[j * ts];
-      if (INV) w.im = ddm::neg(w.im);
-      const ddc u = buf[i0];
-      const ddc v = buf[i1];
+      const int i0 = ((b >> (t - 1)) << t) + j;
+      const ddc u = buf[i0], v = buf[i0 + half];
       buf[i0] = ddm::cadd(u, v);
-      buf[i1] = ddm::cmul(ddm::csub(u, v), w);
+      buf[i0 + half] = ddm::cmul(ddm::csub(u, v), twiddle(tw, j * (M >> t), INV));
+    }
+    __syncthreads();
+    --t;
+  }
+  for (; t >= 2; t -= 2) {
+    const int s = t - 1;              // lower stage of the pair
+    const int half = 1 << (s - 1);
+    for (int q = threadIdx.x; q < (M >> 2); q += blockDim.x) {
+      const int j = q & (half - 1);
+      const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
+      const ddc wb = twiddle(tw, j * (M >> t), INV);
+      const ddc wc = twiddle(tw, (j + half) * (M >> t), INV);
+      const ddc wa = twiddle(tw, j * (M >> s), INV);
+      const ddc a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      const ddc y0 = ddm::cadd(a0, a2), y2 = ddm::cmul(ddm::csub(a0, a2), wb);
+      const ddc y1 = ddm::cadd(a1, a3), y3 = ddm::cmul(ddm::csub(a1, a3), wc);
+      buf[i0] = ddm::cadd(y0, y1);
+      buf[i0 + half] = ddm::cmul(ddm::csub(y0, y1), wa);
+      buf[i0 + 2 * half] = ddm::cadd(y2, y3);
+      buf[i0 + 3 * half] = ddm::cmul(ddm::csub(y2, y3), wa);
     }
     __syncthreads();
   }
