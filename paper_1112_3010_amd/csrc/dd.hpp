@@ -85,6 +85,17 @@ __device__ __forceinline__ dd div_d(dd a, double b) {
   return fast_two_sum(q1, q2);
 }
 
+// a / b: three quotient digits, each from the float64 quotient of the
+// current remainder's leading part.
+__device__ __forceinline__ dd div(dd a, dd b) {
+  const double q1 = a.hi / b.hi;
+  dd r = sub(a, mul_d(b, q1));
+  const double q2 = r.hi / b.hi;
+  r = sub(r, mul_d(b, q2));
+  const double q3 = r.hi / b.hi;
+  return add(fast_two_sum(q1, q2), {q3, 0.0});
+}
+
 // sqrt(a) for a >= 0: the float64 root refined by one Newton step whose
 // residual a - x^2 is formed in double-double.
 __device__ __forceinline__ dd sqrt(dd a) {

@@ -15,18 +15,26 @@ struct DDGeom {
 // Bytes of one complex double-double value and one real one.
 constexpr size_t kDDComplexBytes = 32, kDDRealBytes = 16;
 
-// Plan time: twiddles of both axes, then f sampled into G and transformed;
-// tab receives the scaled real spectrum.  G is scratch (My x Mx complex).
-hipError_t dd_build_tables(void* twx, void* twy, void* tab, void* G, const DDGeom& g, hipStream_t st);
+// Plan time: twiddles of both axes, then for each table t < n_tabs (0: f,
+// 1 + a: the gradient kernel of axis a) the samples into G (scratch,
+// My x Mx complex) and their transform; tabs receives the scaled real
+// (t = 0) or imaginary (t > 0) spectra, My x Mx each.
+hipError_t dd_build_tables(void* twx, void* twy, void* tabs, int n_tabs, void* G, const DDGeom& g, hipStream_t st);
 // Multiplicities into cnt (cleared by the caller) and sum m^2 into *msq
 // (left at 0 by dd_launch_finalize, which consumes it).
 hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
                            hipStream_t st);
 hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
                               hipStream_t st);
+// Forward row transforms of the ny source rows into G.
 hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st);
-hipError_t dd_launch_col_fused(void* G, const void* tab, const void* twy, const DDGeom& g, hipStream_t st);
-hipError_t dd_launch_row_inv_epi(const void* G, const void* twx, double* S, const double* scal, const DDGeom& g,
-                                 hipStream_t st);
+// Columns of G: forward, times each of the C spectra, inverse, into Gout
+// (C x ny x Mx).
+hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
+                               hipStream_t st);
+// Inverse row transforms of the C channels and the epilogue: S (ny x nx)
+// and, for C = 3, grad (2 x ny x nx); either may be null.
+hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, const double* scal,
+                                 const DDGeom& g, hipStream_t st);
 
 }  // namespace dt

@@ -10,9 +10,12 @@
 //
 // Layout in the plan's workspace (x fastest, M = padded lengths):
 //   twx, twy  M/2 complex double-double twiddles exp(-2 pi i k / M)
-//   tab       My x Mx real double-double spectrum of f, scaled by 1/(Mx My)
+//   tabs      C spectra, My x Mx double-double each, scaled by 1/(Mx My): the
+//             real spectrum of f, then the imaginary parts of the gradient
+//             kernels' (C = 3 when the gradient is prepared)
 //   cnt       ny x nx float64 multiplicities (the indicator g)
-//   G         My x Mx complex double-double work grid
+//   G         My x Mx complex double-double work grid (row spectra)
+//   Gc        C x ny x Mx complex double-double (column-pass outputs)
 // The transforms are radix-2 in LDS (stages fused in pairs), one row or
 // column per block:
 // decimation in time (bit-reversed in, natural out) forward and decimation
@@ -156,10 +159,12 @@ __global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
   tw[k] = {cs, ddm::neg(sn)};
 }
 
-// f = exp(-r / tau) at every displacement of the padded grid (minimum
-// image; the Nyquist lines are set to 0 as in the other precisions).  The
-// displacement h d is an exact double-double product.
-__global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g) {
+// Kernel samples at every displacement d of the padded grid (minimum image;
+// the Nyquist lines are set to 0 as in the other precisions): kind 0 is
+// f = exp(-r / tau), kind 1 + a the gradient kernel (h_a d_a / r) f, 0 at
+// r = 0 (eq. SxSyconv).  The displacement h d is an exact double-double
+// product.
+__global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)g.Mx * g.My) return;
   const int x = (int)(i % g.Mx), y = (int)(i / g.Mx);
@@ -169,7 +174,11 @@ __global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g) {
     const int dy = y < g.My / 2 ? y : y - g.My;
     const dd px = ddm::two_prod(g.hx, (double)dx), py = ddm::two_prod(g.hy, (double)dy);
     const dd r = ddm::sqrt(ddm::add(ddm::mul(px, px), ddm::mul(py, py)));
-    v.re = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
+    const dd f = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
+    if (kind == 0)
+      v.re = f;
+    else if (r.hi > 0.0)
+      v.re = ddm::mul(ddm::div(kind == 1 ? px : py, r), f);
   }
   G[i] = v;
 }
@@ -198,50 +207,96 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restric
   for (int x = threadIdx.x; x < M; x += blockDim.x) G[(int64_t)y * M + x] = buf[x];
 }
 
-// Column kx: forward transform of rows [0, ny_in) (zero above), then either
-// (TABLE) store the scaled real part as the kernel spectrum, or multiply by
-// the spectrum, transform back and store rows [0, ny_out).
-template <bool TABLE>
-__global__ __launch_bounds__(kThreads) void k_dd_col(ddc* __restrict__ G, dd* __restrict__ tab,
-                                                     const ddc* __restrict__ tw, DDGeom g, int ny_in, int ny_out) {
+// Table mode (plan time): column kx of the row-transformed samples in G,
+// forward transform, and the real (IMAG = false) or imaginary part of the
+// spectrum, scaled by 1/(Mx My), into tab.
+template <bool IMAG>
+__global__ __launch_bounds__(kThreads) void k_dd_col_table(const ddc* __restrict__ G, dd* __restrict__ tab,
+                                                           const ddc* __restrict__ tw, DDGeom g) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
   const int kx = blockIdx.x;
   const int M = g.My;
-  for (int y = threadIdx.x; y < M; y += blockDim.x)
-    buf[brev(y, g.logMy)] = y < ny_in ? G[(int64_t)y * g.Mx + kx] : zero_c();
+  for (int y = threadIdx.x; y < M; y += blockDim.x) buf[brev(y, g.logMy)] = G[(int64_t)y * g.Mx + kx];
   __syncthreads();
   fft_dit<false>(buf, M, g.logMy, tw);
-  if (TABLE) {
-    const int e = -(g.logMx + g.logMy);
-    for (int ky = threadIdx.x; ky < M; ky += blockDim.x) tab[(int64_t)ky * g.Mx + kx] = ddm::scale2(buf[ky].re, e);
-    return;
-  }
+  const int e = -(g.logMx + g.logMy);
   for (int ky = threadIdx.x; ky < M; ky += blockDim.x)
-    buf[ky] = ddm::cmul_real(buf[ky], tab[(int64_t)ky * g.Mx + kx]);
-  __syncthreads();
-  fft_dif<true>(buf, M, g.logMy, tw);
-  for (int y = threadIdx.x; y < ny_out; y += blockDim.x) G[(int64_t)y * g.Mx + kx] = buf[brev(y, g.logMy)];
+    tab[(int64_t)ky * g.Mx + kx] = ddm::scale2(IMAG ? buf[ky].im : buf[ky].re, e);
 }
 
-// Inverse transform of row y and the epilogue: phi = Re, S = -tau log phi
-// where phi >= Theta, else S_max (scal[0] = Theta, scal[1] = S_max).
-__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ G, const ddc* __restrict__ tw,
-                                                             double* __restrict__ S, const double* __restrict__ scal,
-                                                             DDGeom g) {
+// Column kx, for each channel c < C: forward transform of rows [0, ny) of
+// Gin (zero above), product with spectrum c (channel 0 real: f; channels
+// 1.. imaginary: the odd gradient kernels, i v), inverse transform, rows
+// [0, ny) into channel c of Gout (ny x Mx each).  The forward transform is
+// redone per channel so that one LDS buffer suffices.
+__global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
+                                                           const dd* __restrict__ tabs, const ddc* __restrict__ tw,
+                                                           DDGeom g, int C) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int kx = blockIdx.x;
+  const int M = g.My;
+  const int64_t npad = (int64_t)g.Mx * g.My, plane = (int64_t)g.ny * g.Mx;
+  for (int c = 0; c < C; ++c) {
+    for (int y = threadIdx.x; y < M; y += blockDim.x)
+      buf[brev(y, g.logMy)] = y < g.ny ? Gin[(int64_t)y * g.Mx + kx] : zero_c();
+    __syncthreads();
+    fft_dit<false>(buf, M, g.logMy, tw);
+    const dd* tab = tabs + c * npad;
+    for (int ky = threadIdx.x; ky < M; ky += blockDim.x) {
+      const dd t = tab[(int64_t)ky * g.Mx + kx];
+      const ddc a = buf[ky];
+      // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
+      buf[ky] = c == 0 ? ddm::cmul_real(a, t) : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
+    }
+    __syncthreads();
+    fft_dif<true>(buf, M, g.logMy, tw);
+    for (int y = threadIdx.x; y < g.ny; y += blockDim.x) Gout[c * plane + (int64_t)y * g.Mx + kx] = buf[brev(y, g.logMy)];
+    __syncthreads();
+  }
+}
+
+// Inverse transforms of row y and the epilogue: phi = Re of channel 0,
+// S = -tau log phi where phi >= Theta, else S_max (scal[0] = Theta,
+// scal[1] = S_max); with C = 3 also grad_a S = psi_a / phi (eq. SxSyconv),
+// 0 where phi < Theta.  S or grad may be null.  phi stays in registers
+// (nx <= kMaxPerThread * blockDim.x) while the gradient channels are
+// transformed.
+constexpr int kMaxPerThread = 4;
+
+__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
+                                                             double* __restrict__ S, double* __restrict__ grad,
+                                                             const double* __restrict__ scal, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
   const int y = blockIdx.x;
   const int M = g.Mx;
-  for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = G[(int64_t)y * M + x];
-  __syncthreads();
-  fft_dif<true>(buf, M, g.logMx, tw);
+  const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
   const double theta = scal[0], smax = scal[1];
-  for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
-    const dd phi = buf[brev(x, g.logMx)].re;
-    // log(hi + lo) = log(hi) + lo / hi to float64 accuracy
-    const double s = (phi.hi > 0.0 && phi.hi >= theta) ? -g.tau * (log(phi.hi) + phi.lo / phi.hi) : smax;
-    S[(int64_t)y * g.nx + x] = s;
+  double phi[kMaxPerThread];
+  for (int c = 0; c < C; ++c) {
+    for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
+    __syncthreads();
+    fft_dif<true>(buf, M, g.logMx, tw);
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int x = threadIdx.x + k * blockDim.x;
+      if (x >= g.nx) break;
+      const dd v = buf[brev(x, g.logMx)].re;
+      if (c == 0) {
+        phi[k] = v.hi;
+        if (S) {
+          // log(hi + lo) = log(hi) + lo / hi to float64 accuracy
+          const bool ok0 = v.hi > 0.0 && v.hi >= theta;
+          S[(int64_t)y * g.nx + x] = ok0 ? -g.tau * (log(v.hi) + v.lo / v.hi) : smax;
+        }
+      } else if (grad) {
+        const bool ok = phi[k] > 0.0 && phi[k] >= theta;
+        grad[(c - 1) * nodes + (int64_t)y * g.nx + x] = ok ? v.hi / phi[k] : 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -299,18 +354,24 @@ hipError_t allow_lds(F kern, size_t lds) {
 
 }  // namespace
 
-hipError_t dd_build_tables(void* twx, void* twy, void* tab, void* G, const DDGeom& g, hipStream_t st) {
+hipError_t dd_build_tables(void* twx, void* twy, void* tabs, int n_tabs, void* G, const DDGeom& g, hipStream_t st) {
   k_dd_twiddles<<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((ddc*)twx, g.Mx);
   k_dd_twiddles<<<(g.My / 2 + 255) / 256, 256, 0, st>>>((ddc*)twy, g.My);
   const int64_t total = (int64_t)g.Mx * g.My;
-  k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g);
   const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc);
   hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
+  if (e == hipSuccess) e = allow_lds(k_dd_col_table<false>, ly);
+  if (e == hipSuccess) e = allow_lds(k_dd_col_table<true>, ly);
   if (e != hipSuccess) return e;
-  k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
-  e = allow_lds(k_dd_col<true>, ly);
-  if (e != hipSuccess) return e;
-  k_dd_col<true><<<g.Mx, kThreads, ly, st>>>((ddc*)G, (dd*)tab, (const ddc*)twy, g, g.My, 0);
+  for (int t = 0; t < n_tabs; ++t) {
+    dd* tab = (dd*)tabs + t * total;
+    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t);
+    k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
+    if (t == 0)
+      k_dd_col_table<false><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
+    else
+      k_dd_col_table<true><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
+  }
   return hipGetLastError();
 }
 
@@ -334,20 +395,22 @@ hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const 
   return hipGetLastError();
 }
 
-hipError_t dd_launch_col_fused(void* G, const void* tab, const void* twy, const DDGeom& g, hipStream_t st) {
+hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
+                               hipStream_t st) {
   const size_t lds = (size_t)g.My * sizeof(ddc);
-  const hipError_t e = allow_lds(k_dd_col<false>, lds);
+  const hipError_t e = allow_lds(k_dd_col_fused, lds);
   if (e != hipSuccess) return e;
-  k_dd_col<false><<<g.Mx, kThreads, lds, st>>>((ddc*)G, (dd*)tab, (const ddc*)twy, g, g.ny, g.ny);
+  k_dd_col_fused<<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
   return hipGetLastError();
 }
 
-hipError_t dd_launch_row_inv_epi(const void* G, const void* twx, double* S, const double* scal, const DDGeom& g,
-                                 hipStream_t st) {
+hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, const double* scal,
+                                 const DDGeom& g, hipStream_t st) {
+  if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
   const size_t lds = (size_t)g.Mx * sizeof(ddc);
   const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)G, (const ddc*)twx, S, scal, g);
+  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, scal, g, C);
   return hipGetLastError();
 }
 

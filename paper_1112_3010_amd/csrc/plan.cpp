@@ -79,7 +79,8 @@ struct dt_plan_s {
   // double-double plans (2D, S only) use their own workspace regions
   bool dd = false;
   DDGeom ddg{};
-  size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0;
+  int dd_tabs = 1;       // 1: f; 3: f and the two gradient kernels
+  size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0, off_dd_Gc = 0;
   // optional per-pass timing
   bool timing = false;
   struct Pending { std::string name; hipEvent_t a, b; };
@@ -231,9 +232,11 @@ int log2_exact(int64_t m) {
 
 // Workspace of a double-double plan: scalars and error word (same offsets
 // as the other precisions, so the stats calls are shared), twiddles, the
-// real spectrum, the multiplicities and the complex work grid.
+// spectra, the multiplicities, the complex work grid and the column-pass
+// outputs.
 void setup_dd(dt_plan p) {
   p->dd = true;
+  p->dd_tabs = (p->mask & DT_OUT_GRAD) ? 3 : 1;
   p->fp64 = true;  // outputs are float64
   p->w = 8;
   DDGeom& g = p->ddg;
@@ -255,9 +258,10 @@ void setup_dd(dt_plan p) {
   p->off_R1 = off;  // end of the region cleared at attach
   p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * kDDComplexBytes);
   p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * kDDComplexBytes);
-  p->off_dd_tab = off; off = align_up(off + npad * kDDRealBytes);
+  p->off_dd_tab = off; off = align_up(off + (size_t)p->dd_tabs * npad * kDDRealBytes);
   p->off_dd_cnt = off; off = align_up(off + (size_t)g.nx * g.ny * sizeof(double));
   p->off_dd_G = off; off = align_up(off + npad * kDDComplexBytes);
+  p->off_dd_Gc = off; off = align_up(off + (size_t)p->dd_tabs * g.ny * g.Mx * kDDComplexBytes);
   p->ws_bytes = off;
 }
 
@@ -307,8 +311,8 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    // double-double is a candidate only where it is built: 2D plans of S alone
-    const int n_cand = (ndim == 2 && out_mask == DT_OUT_S) ? 3 : 2;
+    // double-double is a candidate only where it is built: 2D plans of S and grad S
+    const int n_cand = (ndim == 2 && !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD))) ? 3 : 2;
     const int cands[3] = {DT_FP32_SCALED, DT_FP64, DT_FP64X2};
     const int ubits[3] = {24, 53, 104};
     for (int c = 0; c < n_cand && chosen < 0; ++c) {
@@ -324,7 +328,7 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   }
   p->prec = precision;
   if (precision == DT_FP64X2) {
-    if (ndim != 2 || out_mask != DT_OUT_S) {
+    if (ndim != 2 || (out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD))) {
       delete p;
       return DT_E_UNSUPPORTED;
     }
@@ -549,7 +553,7 @@ extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t byte
   launch_fill_zero<double>((double*)p->ws, (int64_t)(p->off_R1 / sizeof(double)), st);
   if (p->dd) {
     hipError_t e = dd_build_tables(p->ws + p->off_dd_twx, p->ws + p->off_dd_twy, p->ws + p->off_dd_tab,
-                                   p->ws + p->off_dd_G, p->ddg, st);
+                                   p->dd_tabs, p->ws + p->off_dd_G, p->ddg, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return DT_E_HIP;
     p->kernel_l1 = host_kernel_l1(p->M, p->h, 2, p->tau);
@@ -936,12 +940,13 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
 
 }  // namespace
 
-// The double-double pipeline: S only, from explicit sources.
+// The double-double pipeline: S and grad S from explicit sources.
 static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
                          hipStream_t st) {
-  if (out->grad || out->hess || out->label || out->mu || out->curv || out->signed_outputs || shape)
-    return DT_E_UNSUPPORTED;
-  if (!out->S || !Y || K < 1) return DT_E_ARG;
+  if (out->hess || out->label || out->mu || out->curv || out->signed_outputs || shape) return DT_E_UNSUPPORTED;
+  if ((!out->S && !out->grad) || !Y || K < 1) return DT_E_ARG;
+  if (out->grad && p->dd_tabs < 3) return DT_E_ARG;   // gradient kernels not prepared
+  const int C = out->grad ? 3 : 1;
   if (!p->ready) return DT_E_WORKSPACE;
   const DDGeom& g = p->ddg;
   double* cnt = (double*)(p->ws + p->off_dd_cnt);
@@ -961,12 +966,13 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   if (e != hipSuccess) return DT_E_HIP;
   {
     PassTimer t(p, st, "dd_col_fused");
-    e = dd_launch_col_fused(G, p->ws + p->off_dd_tab, p->ws + p->off_dd_twy, g, st);
+    e = dd_launch_col_fused(G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, C, p->ws + p->off_dd_twy, g, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
   {
     PassTimer t(p, st, "dd_row_inv_epi");
-    e = dd_launch_row_inv_epi(G, p->ws + p->off_dd_twx, (double*)out->S, p->scal(), g, st);
+    e = dd_launch_row_inv_epi(p->ws + p->off_dd_Gc, C, p->ws + p->off_dd_twx, (double*)out->S, (double*)out->grad,
+                              p->scal(), g, st);
   }
   return hip_status(e);
 }

@@ -144,10 +144,13 @@ def test_fp64x2_plans(lib):
     assert size.value >= 128 * 128 * (32 + 16)          # complex grid + real spectrum
     dummy = ctypes.c_void_p(4096)
     assert lib.dt_distance(h, dummy, 10, dummy, None) == 4          # no workspace yet
-    assert lib.dt_gradient(h, dummy, 10, None, dummy, None) == 6    # S only
+    assert lib.dt_gradient(h, dummy, 10, None, dummy, None) == 1    # no gradient kernels
     assert lib.dt_backward(h, dummy, 10, dummy, dummy, dummy, None, None) == 1
     lib.dt_destroy_plan(h)
-    assert _plan(lib, prec=3, mask=3)[0] == 6                        # gradient not built
+    st, h = _plan(lib, prec=3, mask=3)                               # S and grad S
+    assert st == 0
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, prec=3, mask=5)[0] == 6                        # Hessian not built
     assert _plan(lib, ndim=3, dims=(32, 32, 32), prec=3, mask=1)[0] == 6
 
 
@@ -161,5 +164,5 @@ def test_auto_picks_fp64x2_for_2d_distance(lib):
     assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
     assert info.precision == 3
     lib.dt_destroy_plan(h)
-    # with the gradient requested there is no extended-precision candidate
-    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=3, trunc=45 * tau, khint=1000)[0] == 3
+    # with the Hessian requested there is no extended-precision candidate
+    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=5, trunc=45 * tau, khint=1000)[0] == 3

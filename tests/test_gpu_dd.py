@@ -84,6 +84,41 @@ def test_dd_distance_vs_oracle(dt, dims, K, frac, tau_h, name):
         np.testing.assert_allclose(S[inval], ref["s_max"], rtol=1e-12)
 
 
+TOL_GRAD_DD = 1e-12
+
+
+@pytest.mark.parametrize("dims,K,frac,tau_h", [((100, 77), 5, 0.25, 1.0), ((333, 200), 40, 0.3, 2.0)])
+def test_dd_gradient_vs_oracle(dt, dims, K, frac, tau_h):
+    """grad S = (u * g) / (f * g) (eq. SxSyconv) in double-double, on every
+    node the extended precision resolves; S identical to the S-only plan's."""
+    pts = _clustered(K, frac, seed=900 + K)
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    Y = torch.from_numpy(pts).cuda()
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad"])
+    S, g = plan.gradient(Y)
+    S_only = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S"]).distance(Y)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    assert torch.equal(S, S_only)
+    ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, "fp64x2", grad=True)
+    S = S.cpu().numpy().ravel()
+    g = g.cpu().numpy().reshape(2, -1)
+    deep, valid = ref["deep"], ref["valid"]
+    dG = np.abs(g - ref["grad"].T)
+    theta64 = oracle.theta("fp64", ref["padded"], ref["kernel_l1"], ref["g_l2"])
+    beyond64 = deep & (ref["lnphi"] < np.log(theta64))
+    print(f"\n[dd grad {dims}] max|dgrad| deep={dG[:, deep].max():.3e} beyond fp64={beyond64.sum()} "
+          f"max|dS|/tau={np.abs(S - ref['S_ref']).max() / tau:.3e}")
+    assert np.all(dG[:, deep] <= parity.bound(ref, TOL_GRAD_DD)[deep])
+    assert dG[:, valid].max() <= parity.TOL_GRAD
+    # |grad S| < 1 (Sec. 5.1); far out it tends to 1, so allow the parity bound
+    assert beyond64.sum() > 0
+    assert np.all(np.hypot(*g[:, beyond64]) <= 1.0 + 2 * parity.bound(ref, TOL_GRAD_DD)[beyond64])
+    inval = ~valid & (ref["S_exact"] > ref["s_max"] + 0.05 * tau)
+    assert np.all(g[:, inval] == 0)
+
+
 def test_dd_single_source_is_exact_distance(dt):
     """With one source phi = exp(-r/tau), so S = r throughout the valid band."""
     dims = (128, 96)
@@ -134,6 +169,6 @@ def test_dd_source_outside_grid_sets_sticky_error(dt):
 
 def test_dd_rejects_what_it_does_not_build(dt):
     with pytest.raises(Exception):
-        dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "grad"])
+        dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "hess"])
     with pytest.raises(Exception):
         dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S"])
