@@ -527,6 +527,22 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
                      "padded": plan.padded, "theta": st["theta"]}
         log(f"{prec}: {ms:.3f} ms, S_max/tau {st['s_max'] / tau:.2f}, passes {res[prec]['pass_ms']}")
         del plan
+    # S and grad S in double-double (three channels through the column pass)
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad"])
+    out = {"S": plan._empty(), "grad": plan._empty(2)}
+    for _ in range(warmup):
+        plan.forward_into(out, Yd)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.forward_into(out, Yd)
+    e1.record()
+    torch.cuda.synchronize()
+    grad_ms = e0.elapsed_time(e1) / steps
+    log(f"fp64x2 S + grad: {grad_ms:.3f} ms")
+    del plan
     r = res["fp64x2"]
     Mx, My = r["padded"]
     col_ms = r["pass_ms"]["dd_col_fused"]
@@ -542,6 +558,7 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
                          "unit": "T f64-ops/s", "frac": round(achieved / F64_OPS_PEAK_T, 4), "traffic": None,
                          "kernel": "dd_col_fused", "ops_per_launch": ops},
             "pass_ms": r["pass_ms"], "s_max_over_tau": round(r["s_max_over_tau"], 2),
+            "with_grad_ms_per_step": round(grad_ms, 4),
             "fp64": {"ms_per_step": round(res["fp64"]["ms"], 4), "pass_ms": res["fp64"]["pass_ms"],
                      "s_max_over_tau": round(res["fp64"]["s_max_over_tau"], 2)}}
     if not no_cpu:

@@ -228,8 +228,12 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_table(const ddc* __restrict
 // Column kx, for each channel c < C: forward transform of rows [0, ny) of
 // Gin (zero above), product with spectrum c (channel 0 real: f; channels
 // 1.. imaginary: the odd gradient kernels, i v), inverse transform, rows
-// [0, ny) into channel c of Gout (ny x Mx each).  The forward transform is
-// redone per channel so that one LDS buffer suffices.
+// [0, ny) into channel c of Gout (ny x Mx each).  With several channels
+// (MULTI) each thread keeps its bins of the forward spectrum in registers
+// (My <= kSpecPerThread * blockDim.x), so the forward transform runs once.
+constexpr int kSpecPerThread = 8;
+
+template <bool MULTI>
 __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
                                                            const dd* __restrict__ tabs, const ddc* __restrict__ tw,
                                                            DDGeom g, int C) {
@@ -238,15 +242,26 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
   const int kx = blockIdx.x;
   const int M = g.My;
   const int64_t npad = (int64_t)g.Mx * g.My, plane = (int64_t)g.ny * g.Mx;
+  for (int y = threadIdx.x; y < M; y += blockDim.x)
+    buf[brev(y, g.logMy)] = y < g.ny ? Gin[(int64_t)y * g.Mx + kx] : zero_c();
+  __syncthreads();
+  fft_dit<false>(buf, M, g.logMy, tw);
+  ddc sp[MULTI ? kSpecPerThread : 1];
+  if (MULTI) {
+#pragma unroll
+    for (int k = 0; k < kSpecPerThread; ++k) {
+      const int ky = threadIdx.x + k * blockDim.x;
+      if (ky < M) sp[k] = buf[ky];
+    }
+  }
   for (int c = 0; c < C; ++c) {
-    for (int y = threadIdx.x; y < M; y += blockDim.x)
-      buf[brev(y, g.logMy)] = y < g.ny ? Gin[(int64_t)y * g.Mx + kx] : zero_c();
-    __syncthreads();
-    fft_dit<false>(buf, M, g.logMy, tw);
     const dd* tab = tabs + c * npad;
-    for (int ky = threadIdx.x; ky < M; ky += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < (MULTI ? kSpecPerThread : M / kThreads + 1); ++k) {
+      const int ky = threadIdx.x + k * blockDim.x;
+      if (ky >= M) break;
       const dd t = tab[(int64_t)ky * g.Mx + kx];
-      const ddc a = buf[ky];
+      const ddc a = MULTI ? sp[k] : buf[ky];
       // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
       buf[ky] = c == 0 ? ddm::cmul_real(a, t) : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
     }
@@ -398,9 +413,16 @@ hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const 
 hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
                                hipStream_t st) {
   const size_t lds = (size_t)g.My * sizeof(ddc);
-  const hipError_t e = allow_lds(k_dd_col_fused, lds);
-  if (e != hipSuccess) return e;
-  k_dd_col_fused<<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
+  if (C > 1) {
+    if (g.My > kSpecPerThread * kThreads) return hipErrorInvalidValue;
+    const hipError_t e = allow_lds(k_dd_col_fused<true>, lds);
+    if (e != hipSuccess) return e;
+    k_dd_col_fused<true><<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
+  } else {
+    const hipError_t e = allow_lds(k_dd_col_fused<false>, lds);
+    if (e != hipSuccess) return e;
+    k_dd_col_fused<false><<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
+  }
   return hipGetLastError();
 }
 

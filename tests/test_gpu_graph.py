@@ -42,7 +42,7 @@ def _capture(fn):
     return g
 
 
-@pytest.mark.parametrize("dims,prec", [((40, 36, 33), "fp32"), ((128, 128), "fp64")])
+@pytest.mark.parametrize("dims,prec", [((40, 36, 33), "fp32"), ((128, 128), "fp64"), ((96, 80), "fp64x2")])
 def test_forward_graph_replays(dt, dims, prec):
     D = len(dims)
     h = tuple(1.0 / n for n in dims)
