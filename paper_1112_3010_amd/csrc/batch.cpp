@@ -161,6 +161,27 @@ int ecap_for(int64_t elems, int nthr) {
   return e <= 8 ? 8 : e <= 16 ? 16 : e <= 32 ? 32 : 64;
 }
 
+#ifndef DT_BATCH_XCD_RUNS
+#define DT_BATCH_XCD_RUNS 1
+#endif
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
+
+// The dispatcher deals a launch's blocks to the XCDs round-robin (block b to
+// XCD b mod 8).  Neighbouring column tiles share 128-byte lines of the
+// spectrum and of the kernel tables, so the column list is reordered to give
+// every XCD one contiguous run of tiles: XCD x takes q + (x < rem) tiles
+// starting at x q + min(x, rem), q = n / 8, rem = n mod 8.  A permutation:
+// every tile still runs exactly once.
+template <typename B> std::vector<B> xcd_runs(const std::vector<B>& v) {
+  const int64_t n = (int64_t)v.size(), q = n / kXcds, rem = n % kXcds;
+  std::vector<B> out(v.size());
+  for (int64_t b = 0; b < n; ++b) {
+    const int64_t x = b % kXcds, j = b / kXcds;
+    out[b] = v[x * q + std::min<int64_t>(x, rem) + j];
+  }
+  return out;
+}
+
 // Default tiles: 512 threads per column block and the widest power-of-two
 // tile whose longest column set fits 32 elements per thread and the LDS.
 dt_batch_tiles default_tiles(dt_batch_plan p) {
@@ -218,6 +239,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       lds[P_EPI] = std::max<size_t>(lds[P_EPI], (size_t)(c * p->C * (sx + 1) + 2 * sx) * 2 * w);
     }
   }
+  if (DT_BATCH_XCD_RUNS) lists[P_COL] = xcd_runs(lists[P_COL]);
   const int nthr[3] = {nt_row, nt_col, nt_row};
   for (int k = 0; k < 3; ++k) {
     if ((int64_t)lists[k].size() > p->blk_cap[k]) return DT_E_UNSUPPORTED;
