@@ -178,6 +178,12 @@ dt_status dt_plan_set_workspace(dt_plan plan, void* dev_ptr, size_t bytes, void*
 dt_status dt_plan_info(dt_plan plan, dt_plan_info_t* info);
 dt_status dt_destroy_plan(dt_plan plan);
 
+/* Sources for the compute calls below: Y holds K points (x first, float32,
+ * device memory, K x ndim row-major), K >= 1.  An empty set has no distance
+ * field (phi = 0 on every node), so K < 1 or a NULL Y is refused with
+ * DT_E_ARG on the host before anything is enqueued (dt_forward alone also
+ * accepts Y = NULL with K = 0 when a shape supplies the sources). */
+
 /* Distance S only (needs DT_OUT_S). */
 dt_status dt_distance(dt_plan plan, const float* Y, int64_t K, void* S, void* stream);
 /* S (optional, may be NULL) and grad S (needs DT_OUT_GRAD). */
