@@ -135,3 +135,49 @@ def test_source_outside_grid_sets_sticky_error(dt):
     assert plan.last_error() == 0       # cleared
     ref = parity.reference(dims, (1 / 64, 1 / 48), (0.0, 0.0), 2.0 / 64, pts, "fp64")
     np.testing.assert_allclose(_np(S).ravel(), ref["S_ref"], atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_single_source_closed_form_3d(dt, prec):
+    """One source: phi = exp(-r/tau) exactly, so S = r and grad S = (X - Y)/r
+    on every valid node, with no oracle involved.  The source sits mid-cell so
+    that snapping to the node below it is unambiguous; node coordinates are
+    built here directly, in [z][y][x] order (x fastest)."""
+    dims = (48, 40, 36)
+    h = tuple(1.0 / n for n in dims)
+    tau = 1.0 * h[0]
+    node = (17, 22, 9)
+    Y = np.array([[(node[a] + 0.5) * h[a] for a in range(3)]], dtype=np.float32)
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad"])
+    res = plan.forward(torch.from_numpy(Y).cuda(), S=True, grad=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    st = plan.last_stats()
+    S = _np(res["S"]).ravel()
+    g = _np(res["grad"]).reshape(3, -1)
+    zz, yy, xx = np.meshgrid(*[np.arange(dims[a]) * h[a] for a in (2, 1, 0)], indexing="ij")
+    d = np.stack([xx.ravel() - node[0] * h[0], yy.ravel() - node[1] * h[1], zz.ravel() - node[2] * h[2]])
+    r = np.sqrt((d ** 2).sum(axis=0))
+    s_max, theta = st["s_max"], st["theta"]
+    assert abs(s_max + tau * np.log(theta)) <= 1e-9 * s_max
+    deep = r <= s_max - tau * np.log(2.0)          # phi >= 2 Theta
+    far = r >= s_max + 0.05 * tau                  # phi clearly below Theta
+    assert deep.sum() > 1000 and far.sum() > 1000
+    dS = np.abs(S - r)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        gx = np.where(r > 0, d / r, 0.0)
+    dG = np.abs(g - gx)[:, deep]
+    print(f"\n[single source {prec}] S_max/tau={s_max / tau:.2f} max|S-r|/tau deep={dS[deep].max() / tau:.3e} "
+          f"max|grad-(X-Y)/r| deep={dG.max():.3e}")
+    if prec == "fp32":
+        assert dS[deep].max() <= parity.TOL_S_TAU * tau
+        assert dG.max() <= parity.TOL_GRAD
+    else:
+        # float64: a flat part plus the relative noise floor Theta/phi = Theta e^(r/tau)
+        ratio = theta * np.exp(r[deep] / tau)
+        assert np.all(dS[deep] <= tau * (parity.TOL_S_TAU_FP64 + parity.TOL_THETA_FRAC * ratio))
+        assert np.all(dG <= parity.TOL_GRAD_FP64 + parity.TOL_THETA_FRAC * ratio)
+    # beyond the band the library writes S_max cast to the plan's type
+    smax_t = float(np.float32(s_max)) if prec == "fp32" else s_max
+    assert np.all(S[far] == smax_t)
+    assert np.all(g[:, far] == 0)
