@@ -82,3 +82,43 @@ def test_autograd_matches_oracle_gradient(dt):
     e_t = abs(float(tau_t.grad.cpu()) - dtau_ref) / abs(dtau_ref)
     print(f"\n[autograd] rel dL/dY={e_y:.3e} rel dL/dtau={e_t:.3e}")
     assert e_y <= 2e-7 and e_t <= 1e-10
+
+
+# dL/dY of the float64 path is held to float32 storage rounding (2e-7); the
+# other bounds are about 50 times the errors measured on an MI355X (float32:
+# 1.8e-7 and 2.7e-8; float64 dL/dtau: 4e-15).
+@pytest.mark.parametrize("prec,tol", [("fp32", (1e-5, 1e-6)), ("fp64", (2e-7, 1e-12))])
+def test_single_source_backward_closed_form(dt, prec, tol):
+    """One source: S = r for every tau, so dS/dY = -(X - Y)/r and dS/dtau = 0
+    on every valid node.  With G vanishing well inside the band (no validity
+    question at its edge), dL/dY = -sum G (X - Y)/r and dL/dtau = 0, written
+    here without the oracle.  G is skewed so that dL/dY is far from zero."""
+    dims = (36, 32, 30)
+    h = tuple(1.0 / n for n in dims)
+    tau = 2.0 * h[0]
+    node = (12, 15, 8)
+    Y = torch.tensor([[(node[a] + 0.5) * h[a] for a in range(3)]], dtype=torch.float32).cuda()
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "backward"])
+    S = plan.distance(Y)
+    torch.cuda.synchronize()
+    s_max = plan.last_stats()["s_max"]
+    zz, yy, xx = np.meshgrid(*[np.arange(dims[a]) * h[a] for a in (2, 1, 0)], indexing="ij")
+    d = np.stack([xx.ravel() - node[0] * h[0], yy.ravel() - node[1] * h[1], zz.ravel() - node[2] * h[2]])
+    r = np.sqrt((d ** 2).sum(axis=0))
+    R = 0.6 * s_max
+    G = np.maximum(0.0, 1.0 - r / R) ** 2 * (1.0 + 2.0 * d[0] / R + d[1] / R)
+    assert np.count_nonzero(G) > 500
+    with np.errstate(invalid="ignore", divide="ignore"):
+        unit = np.where(r > 0, d / r, 0.0)
+    dY_ref = -(G * unit).sum(axis=1)
+    Gt = torch.from_numpy(G).to(plan.dtype).cuda().reshape(plan.shape)
+    dY, dtau = plan.backward(Y, S, Gt)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    e_y = _rel(dY.cpu().numpy().ravel(), dY_ref)
+    scale_t = float(np.abs(G).sum() * s_max / tau)
+    e_t = abs(float(dtau.cpu())) / scale_t
+    print(f"\n[single-source backward {prec}] |dL/dY|={np.linalg.norm(dY_ref):.3e} rel err={e_y:.3e} "
+          f"|dL/dtau|/(sum|G| S_max/tau)={e_t:.3e}")
+    assert e_y <= tol[0]
+    assert e_t <= tol[1]
