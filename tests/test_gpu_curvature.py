@@ -88,3 +88,45 @@ def test_curvature_needs_hessian_kernels(dt):
     Y = torch.from_numpy(synth.generators.uniform_points(2, 10, seed=3)).cuda()
     with pytest.raises(RuntimeError):
         plan.forward(Y, S=True, curv=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_single_source_sphere_curvatures(dt, prec):
+    """One source in 3D: every level set of S = r is a sphere, so mean
+    curvature and both principal curvatures are 1/r and the Gaussian one is
+    1/r^2, checked without the oracle on nodes with phi >= 10 Theta and
+    r >= 2h.  The k1, k2 bound widens as in the oracle comparison, since
+    k = H +/- sqrt(H^2 - K) amplifies errors where H^2 = K."""
+    dims = (38, 36, 32)
+    h = tuple(1.0 / n for n in dims)
+    tau = 2.0 * h[0]
+    node = (19, 16, 14)
+    Y = np.array([[(node[a] + 0.5) * h[a] for a in range(3)]], dtype=np.float32)
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "curv"])
+    res = plan.forward(torch.from_numpy(Y).cuda(), S=True, curv=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    s_max = plan.last_stats()["s_max"]
+    C = res["curv"].detach().cpu().numpy().astype(np.float64).reshape(4, -1)
+    zz, yy, xx = np.meshgrid(*[np.arange(dims[a]) * h[a] for a in (2, 1, 0)], indexing="ij")
+    r = np.sqrt((xx.ravel() - node[0] * h[0]) ** 2 + (yy.ravel() - node[1] * h[1]) ** 2
+                + (zz.ravel() - node[2] * h[2]) ** 2)
+    ok = (r <= s_max - tau * np.log(10.0)) & (r >= 2.0 * max(h))
+    assert ok.sum() > 1000
+    inv_r = 1.0 / r[ok]
+    scale = 1.0 / tau + 1.0 / min(h)
+    if prec == "fp32":
+        tm = np.full(ok.sum(), TOL_CURV * scale)
+        tg = np.full(ok.sum(), TOL_CURV * scale ** 2)
+    else:
+        b = 1e-7 + parity.TOL_THETA_FRAC * np.exp((r[ok] - s_max) / tau)   # Theta/phi for one source
+        tm, tg = b * scale, b * scale ** 2
+    tk = tm + np.sqrt(2 * inv_r * tm + tg)
+    errs = {}
+    for i, (k, ref, t) in enumerate((("mean", inv_r, tm), ("gauss", inv_r ** 2, tg), ("k1", inv_r, tk),
+                                     ("k2", inv_r, tk))):
+        d = np.abs(C[i][ok] - ref)
+        errs[k] = float((d / t).max())
+        assert np.all(d <= t), f"{prec} {k}: worst {d.max():.3e} vs tol {t[np.argmax(d)]:.3e}"
+    print(f"\n[sphere curvatures {prec}] nodes={int(ok.sum())} worst error / tolerance: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
