@@ -140,9 +140,10 @@ def test_source_outside_grid_sets_sticky_error(dt):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_single_source_closed_form_3d(dt, prec):
     """One source: phi = exp(-r/tau) exactly, so S = r and grad S = (X - Y)/r
-    on every valid node, with no oracle involved.  The source sits mid-cell so
-    that snapping to the node below it is unambiguous; node coordinates are
-    built here directly, in [z][y][x] order (x fastest)."""
+    on every valid node, with no oracle involved.  Nodes lie at cell centres,
+    (i + 1/2) h, and the source is placed exactly on one, so snapping is
+    unambiguous and exact.  Positions are measured from the first node (only
+    differences X - Y enter), in [z][y][x] order (x fastest)."""
     dims = (48, 40, 36)
     h = tuple(1.0 / n for n in dims)
     tau = 1.0 * h[0]
@@ -218,3 +219,53 @@ def test_single_source_hessian_closed_form_3d(dt, prec):
         # flat part plus the relative noise floor Theta/phi = exp((r - S_max)/tau)
         ratio = np.exp((r[sel] - s_max) / tau)
         assert np.all(dH <= scale * (1e-7 + parity.TOL_THETA_FRAC * ratio))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_single_source_closed_form_2d(dt, prec):
+    """The 2D kernels on one source: S = r, grad S = (X - Y)/r and
+    H = (I - n n^T)/r (components xx, xy, yy), without the oracle; S_max
+    and a zero gradient and Hessian beyond the band."""
+    dims = (130, 100)
+    h = tuple(1.0 / n for n in dims)
+    tau = 1.5 * h[0]
+    node = (47, 61)
+    Y = np.array([[(node[a] + 0.5) * h[a] for a in range(2)]], dtype=np.float32)
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad", "hess"])
+    res = plan.forward(torch.from_numpy(Y).cuda(), S=True, grad=True, hess=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    s_max = plan.last_stats()["s_max"]
+    S = _np(res["S"]).ravel()
+    g = _np(res["grad"]).reshape(2, -1)
+    H = _np(res["hess"]).reshape(3, -1)
+    yy, xx = np.meshgrid(np.arange(dims[1]) * h[1], np.arange(dims[0]) * h[0], indexing="ij")
+    d = np.stack([xx.ravel() - node[0] * h[0], yy.ravel() - node[1] * h[1]])
+    r = np.sqrt((d ** 2).sum(axis=0))
+    deep = r <= s_max - tau * np.log(2.0)
+    far = r >= s_max + 0.05 * tau
+    assert deep.sum() > 300 and far.sum() > 300
+    ratio = np.exp((r - s_max) / tau)              # Theta/phi for one source
+    with np.errstate(invalid="ignore", divide="ignore"):
+        n = np.where(r > 0, d / r, 0.0)
+    sel = deep & (r >= 2.0 * max(h))
+    ns, rs = n[:, sel], r[sel]
+    Href = np.stack([(1.0 - ns[0] * ns[0]) / rs, -ns[0] * ns[1] / rs, (1.0 - ns[1] * ns[1]) / rs])
+    dS = np.abs(S - r)[deep]
+    dG = np.abs(g - n)[:, deep]
+    dH = np.abs(H[:, sel] - Href)
+    scale = 1.0 / tau + 1.0 / min(h)
+    print(f"\n[single source 2d {prec}] S_max/tau={s_max / tau:.2f} max|S-r|/tau={dS.max() / tau:.3e} "
+          f"max|dgrad|={dG.max():.3e} max|dH|/(1/tau+1/h)={dH.max() / scale:.3e}")
+    if prec == "fp32":
+        assert dS.max() <= parity.TOL_S_TAU * tau
+        assert dG.max() <= parity.TOL_GRAD
+        assert dH.max() <= parity.TOL_HESS * scale
+    else:
+        b = parity.TOL_THETA_FRAC * ratio
+        assert np.all(dS <= tau * (parity.TOL_S_TAU_FP64 + b[deep]))
+        assert np.all(dG <= parity.TOL_GRAD_FP64 + b[deep])
+        assert np.all(dH <= scale * (1e-7 + b[sel]))
+    smax_t = float(np.float32(s_max)) if prec == "fp32" else s_max
+    assert np.all(S[far] == smax_t)
+    assert np.all(g[:, far] == 0) and np.all(H[:, far] == 0)
