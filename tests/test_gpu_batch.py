@@ -201,3 +201,46 @@ def test_batch_reduced_padding_against_oracle(dt, prec):
     Y2, offs2 = dt.BatchPlan.pack([torch.from_numpy(p) for p in more])
     with pytest.raises(RuntimeError):
         plan.forward(Y2.cuda(), offs2)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_single_sources_closed_form(dt, prec):
+    """One source per instance on uneven grids (7-smooth padding): S = r and
+    grad S = (X - Y)/r on every deep node, S_max and a zero gradient beyond the
+    band, without the oracle.  Sources lie exactly on nodes (cell centres);
+    positions are measured from the first node, x fastest."""
+    dims = [(97, 130), (250, 64), (37, 200), (128, 128)]
+    nodes = [(40, 71), (201, 30), (18, 150), (64, 10)]
+    taus = [2.0 / max(d) for d in dims]
+    pts = [np.array([[(nd[0] + 0.5) / d[0], (nd[1] + 0.5) / d[1]]], dtype=np.float32) for d, nd in zip(dims, nodes)]
+    plan = dt.BatchPlan(dims, taus, precision=prec, graph=False)
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    S, G = plan.forward(Y.cuda(), offs)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    for i, ((nx, ny), nd, tau) in enumerate(zip(dims, nodes, taus)):
+        s, g = plan.views(S, G)[i]
+        s, g = _np(s).ravel(), _np(g).reshape(2, -1)
+        s_max = plan.stats(i)["s_max"]
+        yy, xx = np.meshgrid(np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
+        d = np.stack([xx.ravel() - nd[0] / nx, yy.ravel() - nd[1] / ny])
+        r = np.sqrt((d ** 2).sum(axis=0))
+        deep = r <= s_max - tau * np.log(2.0)
+        far = r >= s_max + 0.05 * tau
+        assert deep.sum() > 100 and far.sum() > 100
+        with np.errstate(invalid="ignore", divide="ignore"):
+            n = np.where(r > 0, d / r, 0.0)
+        dS = np.abs(s - r)[deep]
+        dG = np.abs(g - n)[:, deep]
+        print(f"\n[batch single source {i} {(nx, ny)} {prec}] S_max/tau={s_max / tau:.2f} "
+              f"max|S-r|/tau={dS.max() / tau:.3e} max|dgrad|={dG.max():.3e}")
+        if prec == "fp32":
+            assert dS.max() <= parity.TOL_S_TAU * tau
+            assert dG.max() <= parity.TOL_GRAD
+        else:
+            b = parity.TOL_THETA_FRAC * np.exp((r[deep] - s_max) / tau)   # Theta/phi for one source
+            assert np.all(dS <= tau * (parity.TOL_S_TAU_FP64 + b))
+            assert np.all(dG <= parity.TOL_GRAD_FP64 + b)
+        smax_t = float(np.float32(s_max)) if prec == "fp32" else s_max
+        assert np.all(s[far] == smax_t)
+        assert np.all(g[:, far] == 0)
