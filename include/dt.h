@@ -57,7 +57,9 @@
  *         nothing.  A plan is not thread-safe; distinct plans are.
  * Memory. The library never allocates device memory: the caller provides
  *         one workspace per plan (dt_plan_workspace_size) and owns all
- *         inputs and outputs.  Kernel spectra live in the workspace.
+ *         inputs and outputs.  Kernel spectra live in the workspace.  For
+ *         small plans the workspace may instead be a fixed array the
+ *         library holds per device (dt_plan_set_static_workspace).
  */
 #ifndef DT_H
 #define DT_H
@@ -174,6 +176,23 @@ dt_status dt_plan_workspace_size(dt_plan plan, size_t* bytes);
 /* Attach the workspace and build the kernel spectra on `stream` (this call
  * synchronises the stream once: plan set-up is not a hot path). */
 dt_status dt_plan_set_workspace(dt_plan plan, void* dev_ptr, size_t bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * attach as dt_plan_set_workspace, with the workspace taken from a fixed
+ * array of DT_STATIC_WORKSPACE_BYTES that the library holds on each device
+ * it runs on until the process ends.  Calls no allocator.  The array is that
+ * of the current device.  Plans whose workspace is larger (about 2D up to
+ * 1024^2 in float32, 3D up to 64^3) get DT_E_WORKSPACE and keep their
+ * previous workspace, if any.  One plan per device holds the array: the
+ * last plan attached takes it over (after waiting for the device), and the
+ * compute, dt_last_error and dt_last_stats calls of an earlier holder return
+ * DT_E_WORKSPACE until it is attached again.  The array keeps the last
+ * call's contents; each call clears what it needs.  Calls of its holder that
+ * overlap in time (several streams) race, as for any one workspace.
+ * Synchronises the stream (and, on take-over, the device) once. */
+#define DT_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+dt_status dt_plan_set_static_workspace(dt_plan plan, void* stream);
 
 dt_status dt_plan_info(dt_plan plan, dt_plan_info_t* info);
 dt_status dt_destroy_plan(dt_plan plan);

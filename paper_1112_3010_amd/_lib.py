@@ -18,9 +18,11 @@ DT_OK, DT_E_ARG, DT_E_RANGE, DT_E_PRECISION, DT_E_WORKSPACE, DT_E_HIP, DT_E_UNSU
 DT_FP32_SCALED, DT_FP64, DT_AUTO, DT_FP64X2 = 0, 1, 2, 3
 DT_OUT_S, DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_SIGN, DT_OUT_BACKWARD, DT_OUT_CURV = 1, 2, 4, 8, 16, 32
 DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
+DT_STATIC_WORKSPACE_BYTES = 64 << 20
 
 EXPORTED = (
-    "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_info", "dt_destroy_plan",
+    "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_set_static_workspace",
+    "dt_plan_info", "dt_destroy_plan",
     "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
     "dt_last_error", "dt_last_stats", "dt_plan_set_timing", "dt_plan_timings", "dt_plan_reset_timings",
     "dt_create_batch_plan", "dt_batch_workspace_size", "dt_batch_set_workspace", "dt_batch_instance_info",
@@ -133,6 +135,7 @@ def load():
                                    ctypes.POINTER(dbl), dbl, ctypes.c_int, ctypes.c_uint, dbl, i64, dbl]
     lib.dt_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.dt_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.dt_plan_set_static_workspace.argtypes = [vp, vp]
     lib.dt_plan_info.argtypes = [vp, ctypes.POINTER(DtPlanInfo)]
     lib.dt_destroy_plan.argtypes = [vp]
     lib.dt_distance.argtypes = [vp, vp, i64, vp, vp]

@@ -12,6 +12,7 @@
 #include "dt.h"
 #include "dt_dd.hpp"
 #include "dt_launch.hpp"
+#include "dt_static.hpp"
 
 using namespace dt;
 
@@ -76,6 +77,17 @@ struct dt_plan_s {
   hipStream_t stream = nullptr;
   double kernel_l1 = 0;
   bool ready = false;
+  // workspace = the library's fixed device array (dt_plan_set_static_workspace):
+  // the device it lives on and the token that marks this plan as its holder
+  int static_dev = -1;
+  uint64_t static_token = 0;
+  // tables built and, for the fixed array, not since taken over by another plan
+  bool usable() const { return ready && (static_dev < 0 || dt::static_ws_owner(static_dev) == static_token); }
+  void release_static() {
+    if (static_dev >= 0) dt::static_ws_release(static_dev, static_token);
+    static_dev = -1;
+    static_token = 0;
+  }
   // double-double plans (2D, S only) use their own workspace regions
   bool dd = false;
   DDGeom ddg{};
@@ -436,6 +448,7 @@ extern "C" dt_status dt_plan_workspace_size(dt_plan p, size_t* bytes) {
 
 extern "C" dt_status dt_destroy_plan(dt_plan p) {
   if (!p) return DT_E_ARG;
+  p->release_static();
   delete p;
   return DT_OK;
 }
@@ -542,9 +555,12 @@ template <typename T> dt_status build_tables(dt_plan p, hipStream_t st) {
 
 }  // namespace
 
-extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t bytes, void* stream) {
+// Attach a workspace and build the plan-time tables in it (shared by
+// dt_plan_set_workspace and dt_plan_set_static_workspace).
+dt_status dt::plan_attach(dt_plan p, void* dev_ptr, size_t bytes, void* stream) {
   if (!p || !dev_ptr) return DT_E_ARG;
   if (bytes < p->ws_bytes || ((uintptr_t)dev_ptr % kAlign) != 0) return DT_E_WORKSPACE;
+  p->release_static();
   hipStream_t st = (hipStream_t)stream;
   p->ws = (char*)dev_ptr;
   p->stream = st;
@@ -564,6 +580,15 @@ extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t byte
   if (s != DT_OK) return s;
   p->ready = true;
   return DT_OK;
+}
+
+void dt::plan_mark_static(dt_plan p, int dev, uint64_t token) {
+  p->static_dev = dev;
+  p->static_token = token;
+}
+
+extern "C" dt_status dt_plan_set_workspace(dt_plan p, void* dev_ptr, size_t bytes, void* stream) {
+  return dt::plan_attach(p, dev_ptr, bytes, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -731,7 +756,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
     if (s != DT_OK) return s;
   }
   if (rq.dist && Y && K < 1) return DT_E_ARG;
-  if (!p->ready) return DT_E_WORKSPACE;
+  if (!p->usable()) return DT_E_WORKSPACE;
 
   const int nh = D == 2 ? 3 : 6;
   const int n_in = (rq.dist ? 1 : 0) + (rq.sign ? D : 0);
@@ -947,7 +972,7 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   if ((!out->S && !out->grad) || !Y || K < 1) return DT_E_ARG;
   if (out->grad && p->dd_tabs < 3) return DT_E_ARG;   // gradient kernels not prepared
   const int C = out->grad ? 3 : 1;
-  if (!p->ready) return DT_E_WORKSPACE;
+  if (!p->usable()) return DT_E_WORKSPACE;
   const DDGeom& g = p->ddg;
   double* cnt = (double*)(p->ws + p->off_dd_cnt);
   char* G = p->ws + p->off_dd_G;
@@ -1022,7 +1047,7 @@ extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const voi
   if (!p || !Y || K < 1 || !S || !dL_dS || !dL_dY) return DT_E_ARG;
   if (!(p->mask & DT_OUT_BACKWARD)) return DT_E_ARG;
   if (p->dd) return DT_E_UNSUPPORTED;
-  if (!p->ready) return DT_E_WORKSPACE;
+  if (!p->usable()) return DT_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;
   return p->fp64 ? run_backward<double>(p, Y, K, S, dL_dS, dL_dY, dL_dtau, st)
@@ -1031,7 +1056,7 @@ extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const voi
 
 extern "C" dt_status dt_last_error(dt_plan p) {
   if (!p) return DT_E_ARG;
-  if (!p->ws) return DT_E_WORKSPACE;
+  if (!p->ws || !p->usable()) return DT_E_WORKSPACE;
   uint32_t bits = 0;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return DT_E_HIP;
   if (hipMemcpy(&bits, p->err(), sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) return DT_E_HIP;
@@ -1042,7 +1067,7 @@ extern "C" dt_status dt_last_error(dt_plan p) {
 
 extern "C" dt_status dt_last_stats(dt_plan p, dt_call_stats* st) {
   if (!p || !st) return DT_E_ARG;
-  if (!p->ws) return DT_E_WORKSPACE;
+  if (!p->ws || !p->usable()) return DT_E_WORKSPACE;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return DT_E_HIP;
   double s[5];
   if (hipMemcpy(s, p->scal(), sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return DT_E_HIP;

@@ -36,7 +36,7 @@ class Plan:
     """
 
     def __init__(self, dims, spacing=None, origin=None, tau=None, precision="fp32", outputs=("S", "grad"),
-                 trunc_dist=0.0, k_hint=0, c_theta=0.0, device="cuda"):
+                 trunc_dist=0.0, k_hint=0, c_theta=0.0, device="cuda", static_workspace=False):
         lib = L.load()
         self.ndim = len(dims)
         if spacing is None:
@@ -59,13 +59,20 @@ class Plan:
         L.check(lib.dt_create_plan(ctypes.byref(self._h), self.ndim, d, s, o, self.tau, PRECISIONS[precision],
                                    mask, float(trunc_dist), int(k_hint), float(c_theta)), "dt_create_plan")
         self.device = torch.device(device)
-        nbytes = ctypes.c_size_t()
-        L.check(lib.dt_plan_workspace_size(self._h, ctypes.byref(nbytes)), "dt_plan_workspace_size")
-        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        off = (-base) % 256
-        L.check(lib.dt_plan_set_workspace(self._h, ctypes.c_void_p(base + off), int(nbytes.value),
-                                          _stream(self.device)), "dt_plan_set_workspace")
+        if static_workspace:
+            # the library's fixed per-device array (no allocation; see dt.h)
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                L.check(lib.dt_plan_set_static_workspace(self._h, _stream(self.device)),
+                        "dt_plan_set_static_workspace")
+        else:
+            nbytes = ctypes.c_size_t()
+            L.check(lib.dt_plan_workspace_size(self._h, ctypes.byref(nbytes)), "dt_plan_workspace_size")
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            L.check(lib.dt_plan_set_workspace(self._h, ctypes.c_void_p(base + off), int(nbytes.value),
+                                              _stream(self.device)), "dt_plan_set_workspace")
         self.info = self._info()
         self.dtype = torch.float64 if self.info.precision in (L.DT_FP64, L.DT_FP64X2) else torch.float32
 

@@ -92,6 +92,21 @@ def test_workspace_and_call_checks(lib):
     assert lib.dt_destroy_plan(h) == 0
 
 
+def test_static_workspace_refuses_large_plans(lib):
+    """The fixed workspace array holds DT_STATIC_WORKSPACE_BYTES; a plan that
+    needs more is refused on the host before any device call."""
+    assert lib.dt_plan_set_static_workspace(None, None) == 1
+    st, h = _plan(lib, ndim=3, dims=(256, 256, 256), tau=1.0 / 256)
+    assert st == 0
+    size = ctypes.c_size_t()
+    assert lib.dt_plan_workspace_size(h, ctypes.byref(size)) == 0
+    from paper_1112_3010_amd import _lib
+    assert size.value > _lib.DT_STATIC_WORKSPACE_BYTES
+    assert lib.dt_plan_set_static_workspace(h, None) == 4
+    assert lib.dt_distance(h, ctypes.c_void_p(4096), 10, ctypes.c_void_p(4096), None) == 4   # still no workspace
+    assert lib.dt_destroy_plan(h) == 0
+
+
 def test_struct_layouts_match_header(tmp_path):
     """Every public struct of include/dt.h has the same size and field
     offsets in C (compiled here with gcc against the header) as in the
