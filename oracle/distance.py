@@ -23,13 +23,26 @@ from __future__ import annotations
 
 import numpy as np
 
-_CHUNK_ELEMS = 1 << 22
+_CHUNK_ELEMS = 1 << 20   # node x source elements per chunk (sized for threads)
 
 
 def _chunks(n_rows, k, per_elem=1):
     step = max(1, _CHUNK_ELEMS // max(1, k * per_elem))
     for s in range(0, n_rows, step):
         yield s, min(n_rows, s + step)
+
+
+def run_chunks(fn, chunks, workers=1):
+    """Apply fn(s, e) to every node chunk, on `workers` threads (NumPy
+    releases the interpreter lock inside its array loops).  Each chunk writes
+    only its own rows, so the result does not depend on the thread count;
+    the return values come back in chunk order."""
+    chunks = list(chunks)
+    if workers <= 1 or len(chunks) <= 1:
+        return [fn(s, e) for s, e in chunks]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(workers, len(chunks))) as ex:
+        return list(ex.map(lambda c: fn(*c), chunks))
 
 
 def nearest_distance(X, Y):
@@ -43,11 +56,12 @@ def nearest_distance(X, Y):
     return out
 
 
-def fields(X, Y, tau, grad=False, hess=False, rmean=False):
+def fields(X, Y, tau, grad=False, hess=False, rmean=False, workers=1):
     """Direct-sum fields at nodes X (N x D) from sources Y (K x D), float64.
 
     Returns a dict with ``R``, ``S``, ``lnphi`` (= log phi) and, on request,
-    ``grad`` (N x D), ``hess`` (N x D x D) and ``rmean`` (N).
+    ``grad`` (N x D), ``hess`` (N x D x D) and ``rmean`` (N).  ``workers``
+    threads share the node chunks (same values for any count).
     """
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
@@ -65,7 +79,8 @@ def fields(X, Y, tau, grad=False, hess=False, rmean=False):
         out["rmean"] = np.empty(N)
     eye = np.eye(D)
     per = D * D if hess else D
-    for s, e in _chunks(N, K, per):
+
+    def chunk(s, e):
         diff = X[s:e, None, :] - Y[None, :, :]               # X - Y_k
         r = np.sqrt(np.einsum("ckd,ckd->ck", diff, diff))
         R = r.min(axis=1)
@@ -92,6 +107,8 @@ def fields(X, Y, tau, grad=False, hess=False, rmean=False):
                 # second term vanishes: they drop out as required.
                 H = np.einsum("ck,ckij->cij", p, term) + g[:, :, None] * g[:, None, :] / tau
                 out["hess"][s:e] = H
+
+    run_chunks(chunk, _chunks(N, K, per), workers)
     return out
 
 

@@ -8,9 +8,14 @@ the plan.
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 import oracle
+
+# threads for the oracle's direct sums (the GPU hosts give one GPU 16 cores)
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 # Tolerances (absolute).  S: on every node against min(S_exact, S_max).
 # Derivatives: on nodes with phi_exact >= 2 Theta ("deep valid").
@@ -85,7 +90,7 @@ def batch_padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_
 
 
 def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=False, cells=None,
-              c_theta=oracle.C_THETA, padded_dims=None):
+              c_theta=oracle.C_THETA, padded_dims=None, rmean=False):
     """Oracle fields at all nodes (or at the given flat node indices)."""
     D = len(dims)
     idx, valid = oracle.snap(pts, origin, spacing, dims)
@@ -97,7 +102,7 @@ def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=Fa
     theta = oracle.theta(precision, Mp, l1, g_l2, c_theta)
     smax = oracle.s_max(tau, theta)
     X = oracle.grid_nodes(dims, origin, spacing, cells)
-    f = oracle.fields(X, Yh, tau, grad=grad, hess=hess)
+    f = oracle.fields(X, Yh, tau, grad=grad, hess=hess, rmean=rmean, workers=WORKERS)
     lnphi = f["lnphi"]
     out = {
         "S_exact": f["S"],
@@ -118,7 +123,17 @@ def reference(dims, spacing, origin, tau, pts, precision, *, grad=False, hess=Fa
         out["grad"] = f["grad"]
     if hess:
         out["hess"] = f["hess"]
+    if rmean:
+        out["rmean"] = f["rmean"]
     return out
+
+
+def adjoint_noise(precision, padded_dims, l1, w_l2, c_theta=oracle.C_THETA):
+    """Absolute rounding floor of the adjoint's FFT correlation at one source,
+    by the same model as the validity threshold with the node weights w =
+    G/phi in place of the source image: c_theta u log2(N_pad) ||f||_1
+    ||w||_2 / sqrt(N_pad) (|u_i| <= f, so ||u_i||_1 <= ||f||_1)."""
+    return oracle.theta(precision, padded_dims, l1, w_l2, c_theta)
 
 
 def hess_components(H, D):

@@ -1,10 +1,14 @@
-"""GPU parity at the full workload sizes (1024^2 polygon, 256^3 mesh,
-128^3 adjoint), in the launch configuration the benchmark times.
+"""GPU parity at the full workload sizes (1024^2 polygon, 256^3 mesh and
+its backward, 128^3 adjoint), in the launch configuration the benchmark
+times.
 
-The oracle's direct sums cannot cover 16.7 M nodes, so each test compares the
-GPU fields on a seeded sample of nodes computed one by one by the oracle:
-half drawn uniformly over the grid, half within a few cells of a source
-(where every field is valid and the derivatives are large).
+The oracle's direct sums cannot cover 16.7 M nodes against 60 000 sources,
+so the 256^3 tests compare the GPU fields on a seeded sample of nodes
+computed one by one by the oracle: part drawn uniformly over the grid, part
+within a few cells of a source (where every field is valid and the
+derivatives are large).  The 128^3 adjoint takes its loss over every node,
+and a 48 x 40 x 256 grid (the 512-point engine of the 256^3 workload's fused
+pass) is compared on every node.
 """
 
 import numpy as np
@@ -171,11 +175,12 @@ def test_mesh_256_bench_configuration(dt, c3, prec):
     assert plan.last_stats()["theta"] == pytest.approx(ref["theta"], rel=1e-9)
 
 
-def test_mesh_256_sign(dt, c3):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mesh_256_sign(dt, c3, prec):
     w, Yh, Pk, idx = c3
     dims = w.dims
     h = (1.0 / dims[0],) * 3
-    plan = dt.Plan(dims, None, None, h[0], precision="fp32", outputs=["S", "sign"])
+    plan = dt.Plan(dims, None, None, h[0], precision=prec, outputs=["S", "sign"])
     Vd, Fd = torch.from_numpy(w.vertices).cuda(), torch.from_numpy(w.faces).cuda()
     res = plan.forward(vertices=Vd, faces=Fd, S=True, label=True, mu=True)
     torch.cuda.synchronize()
@@ -194,54 +199,230 @@ def test_mesh_256_sign(dt, c3):
     dist = oracle.mesh_distance(X, w.vertices, w.faces)
     band = dist < np.sqrt(3) * h[0]
     mism_geo = int(np.sum(lab[~band] != np.where(wex[~band] > 0.5, 1, -1)))
-    print(f"\n[mesh 256^3 sign] n={len(cells)} max|dmu|={dmu:.3e} mismatches vs mu={mism_mu} "
-          f"vs geometry={mism_geo} (band {band.sum()})", flush=True)
+    # S of the same call against the oracle on the sampled nodes
+    ref = parity.reference(dims, h, (0.0,) * 3, h[0], Yh.astype(np.float32), prec, cells=cells)
+    dS = np.abs(_np(res["S"]).ravel()[cells] - ref["S_ref"])
+    lim = parity.bound(ref, parity.TOL_S_TAU_FP64, h[0]) if prec == "fp64" else parity.TOL_S_TAU * h[0]
+    print(f"\n[mesh 256^3 sign {prec}] n={len(cells)} max|dmu|={dmu:.3e} mismatches vs mu={mism_mu} "
+          f"vs geometry={mism_geo} (band {band.sum()}) max|dS|/bound={(dS / lim).max():.3e}", flush=True)
     assert dmu <= parity.TOL_MU
     assert mism_mu == 0
     assert mism_geo == 0
+    assert np.all(dS <= lim)
 
 
 # ---------------------------------------------------------------------------
-# 128^3 adjoint: 4096 points near a sphere, tau = 4h, L = sum over a node
-# sample of (S - T)^2 with T the distance to an ellipsoid
+# 128^3 adjoint: 4096 points near a sphere, tau = 4h, L = sum over every node
+# of (S - T)^2 with T the distance to a random ellipsoid
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,tol", [("fp32", (1e-3, 1e-3)), ("fp64", (2e-7, 1e-10))])
-def test_adjoint_128(dt, prec, tol):
-    w = synth.workload("c5_3d_128_grad", with_target=False)
+# float32 bar of the contract: relative L2 error of dL/dY and relative error
+# of dL/dtau
+TOL_ADJ_FP32 = 1e-3
+# float64: per component, the first-order effect of the forward's per-node
+# error bound (relative error of phi e = TOL_S_TAU_FP64 + TOL_THETA_FRAC
+# theta/phi, the bound the float64 S parity uses) on the node weights
+# G/phi, plus the adjoint correlation's own rounding floor and float32
+# storage of dL/dY
+STORE32 = 2.0 ** -23
+
+
+def _fp64_adjoint_bounds(sens_Y, sens_Y_theta, sens_tau, sens_tau_theta, noise, dY_ref):
+    bY = (parity.TOL_S_TAU_FP64 * sens_Y + parity.TOL_THETA_FRAC * sens_Y_theta)[:, None] \
+        + noise + STORE32 * np.abs(dY_ref)
+    bt = parity.TOL_S_TAU_FP64 * sens_tau + parity.TOL_THETA_FRAC * sens_tau_theta
+    return bY, bt
+
+
+def _c5_tau32(w, Yh, h, Mp, g_l2):
+    """tau for the float32 run: the smallest multiple of h from 8h up whose
+    validity threshold lies at least a factor 2 below phi everywhere on the
+    grid, so that every node is valid and none is on the shell where either
+    side may decide validity differently (checked on the box faces, where
+    the nodes farthest from the sphere lie; the full pass then confirms it
+    on every node).  A factor 10 is out of reach here: phi_min / Theta_32
+    levels off near 10.7 as tau grows past 40h."""
+    n = w.dims[0]
+    face = np.arange(0, n, 4)
+    a, b = np.meshgrid(face, face, indexing="ij")
+    a, b = a.ravel(), b.ravel()
+    lo, hi = np.zeros_like(a), np.full_like(a, n - 1)
+    ijk = np.concatenate([np.stack(c, axis=1) for c in
+                          [(lo, a, b), (hi, a, b), (a, lo, b), (a, hi, b), (a, b, lo), (a, b, hi)]])
+    X = oracle.node_coords(ijk, (0.0,) * 3, h)
+    for m in range(8, 33):
+        tau = m * h[0]
+        th = oracle.theta("fp32", Mp, oracle.kernel_l1(Mp, h, tau), g_l2)
+        if oracle.fields(X, Yh, tau, workers=parity.WORKERS)["lnphi"].min() >= np.log(2 * th):
+            return tau
+    raise AssertionError("no tau up to 32h keeps the whole grid valid in float32")
+
+
+_C5 = {}
+
+
+def _c5_oracle(prec):
+    """Oracle side of the 128^3 differentiation workload with the loss over
+    the whole grid: S and log phi at all 2.1 M nodes and the gradients of
+    L = sum over valid nodes of (min(S, S_max) - T)^2, in one pass over the
+    node-source pairs.  float64 runs at tau = 4h; float32 at the tau where
+    every node is valid in float32 (so no node sits on the validity shell)."""
+    if prec in _C5:
+        return _C5[prec]
+    w = synth.workload("c5_3d_128_grad")
     dims = w.dims
     h = (1.0 / dims[0],) * 3
-    tau = w.taus[0]
-    pts = w.points
-    idx, valid = oracle.snap(pts, (0.0,) * 3, h, dims)
+    idx, valid = oracle.snap(w.points, (0.0,) * 3, h, dims)
     assert valid.all()
-    cells = _sample_cells(dims, idx, 1000, 1000, 8, seed=51)
-    ref = parity.reference(dims, h, (0.0,) * 3, tau, pts, prec, cells=cells)
-    lnphi = ref["lnphi"]
-    keep = np.abs(lnphi - np.log(ref["theta"])) >= np.log(2.0)     # off the validity shell
-    if prec == "fp64":
-        # a node's share of dL/dY carries the relative error of its S, which
-        # for float64 grows as Theta/phi (see tests/parity.py); keep the nodes
-        # where that is below 1e-8 so the bound stays at storage rounding
-        keep &= lnphi >= np.log(ref["theta"]) + np.log(1e6)
-    T = synth.ellipsoid_target(dims[0], seed=5005, cells=cells).astype(np.float64)
-    Gs = np.where(keep, 2.0 * (ref["S_ref"] - T), 0.0)
-    G = np.zeros(int(np.prod(dims)))
-    G[cells] = Gs
+    Yh = oracle.node_coords(idx, (0.0,) * 3, h)
+    _, mult = oracle.cell_multiplicities(idx, dims)
+    g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
+    Mp = tuple(parity.padded(n) for n in dims)
+    tau = w.taus[0] if prec == "fp64" else _c5_tau32(w, Yh, h, Mp, g_l2)
+    l1 = oracle.kernel_l1(Mp, h, tau)
+    theta = oracle.theta(prec, Mp, l1, g_l2)
+    X = oracle.grid_nodes(dims, (0.0,) * 3, h)
+    T = w.target.astype(np.float64).ravel()
+    S, lnphi, per = oracle.l2_loss_gradients(X, Yh, tau, T, [theta], workers=parity.WORKERS)
+    _C5[prec] = dict(w=w, dims=dims, h=h, tau=tau, Yh=Yh, T=T, S=S, lnphi=lnphi, Mp=Mp, l1=l1,
+                     acc=per[0], theta=theta)
+    return _C5[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_adjoint_128_full_grid(dt, prec):
+    """dL/dY and dL/dtau of L = sum over all 128^3 nodes of (S - T)^2 (the
+    differentiation workload as configured), G = 2 (S - T) on every node,
+    against the oracle's direct sums over the valid nodes."""
+    c = _c5_oracle(prec)
+    dims, h, tau = c["dims"], c["h"], c["tau"]
+    theta = c["theta"]
+    acc = c["acc"]
+    smax = oracle.s_max(tau, theta)
+    G = 2.0 * (np.minimum(c["S"], smax) - c["T"])
     plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "backward"])
-    Y = torch.from_numpy(pts).cuda()
+    Y = torch.from_numpy(c["w"].points).cuda()
     S = plan.distance(Y)
     Gt = torch.from_numpy(G).to(plan.dtype).cuda().reshape(plan.shape)
     dY, dtau = plan.backward(Y, S, Gt)
     torch.cuda.synchronize()
     assert plan.last_error() == 0
-    dY_ref, dtau_ref = oracle.loss_gradients(ref["X"], ref["Yhat"], tau, Gs, ref["valid"])
-    e_y = float(np.linalg.norm(dY.cpu().numpy() - dY_ref) / np.linalg.norm(dY_ref))
-    e_t = abs(float(dtau.cpu()) - dtau_ref) / abs(dtau_ref)
-    print(f"\n[adjoint 128^3 {prec}] rel L2 dL/dY={e_y:.3e} rel dL/dtau={e_t:.3e} "
-          f"valid={ref['valid'].mean():.3f} nonzero G={int((Gs != 0).sum())}", flush=True)
-    assert e_y <= tol[0]
-    assert e_t <= tol[1]
+    assert plan.last_stats()["theta"] == pytest.approx(theta, rel=1e-9)
+    dY = dY.cpu().numpy().astype(np.float64)
+    dtau = float(dtau.cpu())
+    dY_ref, dtau_ref = acc["dY"], acc["dtau"]
+    valid = c["lnphi"] >= np.log(theta)
+    shell = np.abs(c["lnphi"] - np.log(theta)) < np.log(2.0)
+    e_y = float(np.linalg.norm(dY - dY_ref) / np.linalg.norm(dY_ref))
+    e_t = abs(dtau - dtau_ref) / abs(dtau_ref)
+    msg = (f"[adjoint 128^3 full grid {prec}] tau={tau / h[0]:g}h valid={valid.mean():.3f} shell={int(shell.sum())} "
+           f"rel L2 dL/dY={e_y:.3e} rel dL/dtau={e_t:.3e}")
+    if prec == "fp32":
+        assert valid.all() and c["lnphi"].min() >= np.log(2 * theta), msg
+        print("\n" + msg, flush=True)
+        assert e_y <= TOL_ADJ_FP32, msg
+        assert e_t <= TOL_ADJ_FP32, msg
+        return
+    w_l2 = float(np.sqrt(np.sum((G[valid] * np.exp(-c["lnphi"][valid])) ** 2)))
+    noise = parity.adjoint_noise("fp64", c["Mp"], c["l1"], w_l2)
+    bY, bt = _fp64_adjoint_bounds(acc["sens_Y"], acc["sens_Y_theta"], acc["sens_tau"], acc["sens_tau_theta"],
+                                  noise, dY_ref)
+    rY = float((np.abs(dY - dY_ref) / bY).max())
+    rt = abs(dtau - dtau_ref) / bt
+    print(f"\n{msg} max|ddY|/bound={rY:.3f} |ddtau|/bound={rt:.3f}", flush=True)
+    assert rY <= 1.0, msg
+    assert rt <= 1.0, msg
+
+
+# ---------------------------------------------------------------------------
+# 256^3 backward with the 60 000 mesh sources (the benchmark's configuration:
+# padded 512^3, pair-split fused pass, 512-wide gather)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,radius", [("fp32", 10), ("fp64", 30)])
+def test_backward_256_bench_configuration(dt, c3, prec, radius):
+    """dt_backward on the benchmark's 256^3 workload.  G is seeded normal on a
+    node sample: uniform over the grid plus nodes within `radius` cells of the
+    sources (out to and past the validity band's edge, about 7 tau in float32
+    and 27 tau in float64), leaving out the shell phi in [Theta/2, 2 Theta]
+    where either side may call a node valid."""
+    w, Yh, Pk, idx = c3
+    dims = w.dims
+    h = (1.0 / dims[0],) * 3
+    tau = h[0]
+    cells = _sample_cells(dims, idx, 800, 2400, radius, seed=61 + radius)
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, Yh.astype(np.float32), prec, cells=cells, rmean=True)
+    lnphi = ref["lnphi"]
+    keep = ref["valid"] & (np.abs(lnphi - np.log(ref["theta"])) >= np.log(2.0))
+    edge = keep & (lnphi < np.log(ref["theta"]) + np.log(100.0))
+    rng = np.random.default_rng(62 + radius)
+    Gs = np.where(keep, rng.standard_normal(len(cells)), 0.0)
+    G = np.zeros(int(np.prod(dims)))
+    G[cells] = Gs
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "backward"])
+    Y = torch.from_numpy(Yh.astype(np.float32)).cuda()
+    S = plan.distance(Y)
+    Gt = torch.from_numpy(G).to(plan.dtype).cuda().reshape(plan.shape)
+    dY, dtau = plan.backward(Y, S, Gt)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    dY = dY.cpu().numpy().astype(np.float64)
+    dtau = float(dtau.cpu())
+    del S, Gt, plan
+    torch.cuda.empty_cache()
+    dY_ref, dtau_ref = oracle.loss_gradients(ref["X"], ref["Yhat"], tau, Gs, ref["valid"], workers=parity.WORKERS)
+    e_y = float(np.linalg.norm(dY - dY_ref) / np.linalg.norm(dY_ref))
+    e_t = abs(dtau - dtau_ref) / abs(dtau_ref)
+    msg = (f"[backward 256^3 {prec}] G on {int(keep.sum())} nodes ({int(edge.sum())} within 100 Theta of the "
+           f"band edge) rel L2 dL/dY={e_y:.3e} rel dL/dtau={e_t:.3e}")
+    assert edge.sum() >= 50, msg
+    if prec == "fp32":
+        print("\n" + msg, flush=True)
+        assert e_y <= TOL_ADJ_FP32, msg
+        assert e_t <= TOL_ADJ_FP32, msg
+        return
+    ratio = np.exp(np.log(ref["theta"]) - lnphi)
+    aG = np.abs(Gs)
+    C = np.stack([aG, aG * ratio], axis=1)
+    sens = oracle.adjoint.source_weight_sums(ref["X"], ref["Yhat"], tau, C, workers=parity.WORKERS)
+    tw = 1.0 + 2.0 * ref["rmean"] / tau
+    w_l2 = float(np.sqrt(np.sum((Gs * np.exp(-lnphi)) ** 2)))
+    noise = parity.adjoint_noise("fp64", ref["padded"], ref["kernel_l1"], w_l2)
+    bY, bt = _fp64_adjoint_bounds(sens[:, 0], sens[:, 1], float(aG @ tw), float((aG * ratio) @ tw), noise, dY_ref)
+    rY = float((np.abs(dY - dY_ref) / bY).max())
+    rt = abs(dtau - dtau_ref) / bt
+    print(f"\n{msg} max|ddY|/bound={rY:.3f} |ddtau|/bound={rt:.3f}", flush=True)
+    assert rY <= 1.0, msg
+    assert rt <= 1.0, msg
+
+
+# ---------------------------------------------------------------------------
+# Every node of a grid whose last axis pads to 512 (the pair-split engine of
+# the fused pass, as at 256^3), in both configurations of that pass: the four
+# S + grad S tables staged once (the benchmark's), and ten channels with
+# the Hessian (tables restaged per chunk)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("outputs", [("S", "grad"), ("S", "grad", "hess")])
+def test_every_node_pair_engine_512(dt, prec, outputs):
+    dims = (48, 40, 256)
+    h = (1.0 / 256,) * 3
+    tau = 1.5 * h[0]
+    rng = np.random.default_rng(4096)
+    pts = (rng.random((200, 3)) * np.asarray(dims) * h[0]).astype(np.float32)
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=list(outputs))
+    assert plan.padded == (128, 128, 512)
+    hess = "hess" in outputs
+    res = plan.forward(torch.from_numpy(pts).cuda(), S=True, grad=True, hess=hess)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, pts, prec, grad=True, hess=hess)
+    assert plan.last_stats()["theta"] == pytest.approx(ref["theta"], rel=1e-9)
+    S = _np(res["S"]).ravel()
+    g = _np(res["grad"]).reshape(3, -1)
+    H = _np(res["hess"]).reshape(6, -1) if hess else None
+    _check_fields(f"every node 48x40x256 {'+'.join(outputs)}", prec, tau, h, S, g, H, ref)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

@@ -70,3 +70,94 @@ def test_theta_scaling():
     assert t32 / t64 == pytest.approx(2.0 ** 29)
     assert oracle.theta("fp32", (64, 64), 20.0, 5.0) == pytest.approx(2 * t32)
     assert oracle.s_max(0.1, np.exp(-7.0)) == pytest.approx(0.7)
+
+
+def _l2_case(d, seed, n_src=10, n_nodes=250, tau=0.06):
+    rng = np.random.default_rng(seed)
+    Y = rng.random((n_src, d))
+    X = rng.random((n_nodes, d))
+    X = X[oracle.nearest_distance(X, Y) > 0.02]
+    T = 0.1 + 0.2 * rng.random(len(X))
+    return X, Y, T, tau
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_l2_loss_gradients_match_finite_differences(d):
+    """dL/dY and dL/dtau of L = sum (min(S, S_max) - T)^2 against central
+    differences of that loss in the continuous source positions and tau,
+    for a threshold that cuts the node set (some nodes are invalid)."""
+    from oracle.adjoint import l2_loss_value
+    X, Y, T, tau = _l2_case(d, 40 + d)
+    lnphi = oracle.fields(X, Y, tau)["lnphi"]
+    theta = float(np.exp(np.quantile(lnphi, 0.3)))
+    # keep nodes clear of the threshold, where the loss has a kink
+    X, T = X[np.abs(lnphi - np.log(theta)) > 0.05], T[np.abs(lnphi - np.log(theta)) > 0.05]
+    S, ln2, per = oracle.l2_loss_gradients(X, Y, tau, T, [theta])
+    assert 0 < per[0]["n_valid"] < len(X)
+    step = 1e-6
+    fd = np.empty_like(Y)
+    for k in range(len(Y)):
+        for j in range(d):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[k, j] += step
+            Ym[k, j] -= step
+            fd[k, j] = (l2_loss_value(X, Yp, tau, T, theta) - l2_loss_value(X, Ym, tau, T, theta)) / (2 * step)
+    np.testing.assert_allclose(per[0]["dY"], fd, rtol=2e-6, atol=1e-7)
+    # tau enters S_max too; hold the threshold's S_max fixed as the library does
+    theta_p = np.exp(np.log(theta) * tau / (tau + step))
+    theta_m = np.exp(np.log(theta) * tau / (tau - step))
+    fdt = (l2_loss_value(X, Y, tau + step, T, theta_p) - l2_loss_value(X, Y, tau - step, T, theta_m)) / (2 * step)
+    assert per[0]["dtau"] == pytest.approx(fdt, rel=1e-5)
+
+
+def test_l2_loss_sensitivities_by_brute_force():
+    """The sensitivity sums written out with plain loops on a tiny case:
+    sum over valid nodes of |G| p_k, of |G| (theta/phi) p_k, and the tau
+    weights (1 + 2 <r>/tau)."""
+    X, Y, T, tau = _l2_case(2, 50, n_src=4, n_nodes=30, tau=0.08)
+    lnphi = oracle.fields(X, Y, tau)["lnphi"]
+    theta = float(np.exp(np.median(lnphi)))
+    S, ln2, per = oracle.l2_loss_gradients(X, Y, tau, T, [theta, theta * 1e-6])
+    for th, acc in zip([theta, theta * 1e-6], per):
+        sY = [0.0] * len(Y)
+        sYt = [0.0] * len(Y)
+        st = stt = 0.0
+        nv = 0
+        for i, x in enumerate(X):
+            r = [float(np.sqrt(((x - y) ** 2).sum())) for y in Y]
+            e = [np.exp(-rk / tau) for rk in r]
+            phi = sum(e)
+            if phi < th:
+                continue
+            nv += 1
+            s = -tau * np.log(phi)
+            g = abs(2 * (min(s, -tau * np.log(th)) - T[i]))
+            rm = sum(ek * rk for ek, rk in zip(e, r)) / phi
+            for k in range(len(Y)):
+                sY[k] += g * e[k] / phi
+                sYt[k] += g * (th / phi) * e[k] / phi
+            st += g * (1 + 2 * rm / tau)
+            stt += g * (th / phi) * (1 + 2 * rm / tau)
+        assert acc["n_valid"] == nv
+        valid = oracle.fields(X, Y, tau)["lnphi"] >= np.log(th)
+        G = np.where(valid, np.abs(2 * (np.minimum(S, -tau * np.log(th)) - T)), 0.0)
+        C = np.stack([G, G * np.exp(np.log(th) - ln2)], axis=1)
+        ws = oracle.adjoint.source_weight_sums(X, Y, tau, C)
+        np.testing.assert_allclose(ws[:, 0], sY, rtol=1e-12)
+        np.testing.assert_allclose(ws[:, 1], sYt, rtol=1e-12)
+        np.testing.assert_allclose(acc["sens_Y"], sY, rtol=1e-12)
+        np.testing.assert_allclose(acc["sens_Y_theta"], sYt, rtol=1e-12)
+        assert acc["sens_tau"] == pytest.approx(st, rel=1e-12)
+        assert acc["sens_tau_theta"] == pytest.approx(stt, rel=1e-12)
+
+
+def test_worker_threads_do_not_change_results():
+    X, Y, T, tau = _l2_case(3, 60, n_src=1000, n_nodes=3000)   # several node chunks
+    G = np.random.default_rng(61).standard_normal(len(X))
+    a = oracle.loss_gradients(X, Y, tau, G, workers=1)
+    b = oracle.loss_gradients(X, Y, tau, G, workers=4)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+    f1 = oracle.fields(X, Y, tau, grad=True, hess=True, workers=1)
+    f4 = oracle.fields(X, Y, tau, grad=True, hess=True, workers=4)
+    for key in f1:
+        assert np.array_equal(f1[key], f4[key]), key
