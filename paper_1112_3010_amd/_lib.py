@@ -11,8 +11,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# DT_LIB_PATH selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("DT_LIB_PATH") or os.path.join(HERE, "libdt.so")
+LIB_PATH = os.path.join(HERE, "libdt.so")
 
 DT_OK, DT_E_ARG, DT_E_RANGE, DT_E_PRECISION, DT_E_WORKSPACE, DT_E_HIP, DT_E_UNSUPPORTED = range(7)
 DT_FP32_SCALED, DT_FP64, DT_AUTO, DT_FP64X2 = 0, 1, 2, 3

@@ -161,9 +161,6 @@ int ecap_for(int64_t elems, int nthr) {
   return e <= 8 ? 8 : e <= 16 ? 16 : e <= 32 ? 32 : 64;
 }
 
-#ifndef DT_BATCH_XCD_RUNS
-#define DT_BATCH_XCD_RUNS 1
-#endif
 constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 
 // The dispatcher deals a launch's blocks to the XCDs round-robin (block b to
@@ -239,7 +236,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
       lds[P_EPI] = std::max<size_t>(lds[P_EPI], (size_t)(c * p->C * (sx + 1) + 2 * sx) * 2 * w);
     }
   }
-  if (DT_BATCH_XCD_RUNS) lists[P_COL] = xcd_runs(lists[P_COL]);
+  lists[P_COL] = xcd_runs(lists[P_COL]);
   const int nthr[3] = {nt_row, nt_col, nt_row};
   for (int k = 0; k < 3; ++k) {
     if ((int64_t)lists[k].size() > p->blk_cap[k]) return DT_E_UNSUPPORTED;

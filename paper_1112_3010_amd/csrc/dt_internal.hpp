@@ -64,9 +64,6 @@ struct FusedSpec {
 struct ColParams {
   int64_t in_line, in_outer, in_ch;      // complex-element strides
   int64_t out_line, out_outer, out_ch;
-  // 0: the kx bins of a line are contiguous.  Otherwise (tile-major) bins
-  // come in groups of 8: bin kx sits at (kx / 8) * grp + kx % 8.
-  int64_t in_grp, out_grp;
   int inner;        // number of valid kx bins (M_x/2 + 1)
   int n_in;         // rows 0..n_in-1 of the input are present, the rest are zero
   int n_out;        // rows 0..n_out-1 of the output are stored

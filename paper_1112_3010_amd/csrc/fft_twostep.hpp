@@ -297,6 +297,7 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
   static __device__ __forceinline__ int slot_index(int p, int t, int k2) { return (p + P * t) + E * k2; }
   static __device__ __forceinline__ int slot(int p, int i) { return slot_index(p, i / P, i % P); }
   static constexpr bool LINEAR_FOLD = false;
+  static constexpr bool PAIR_PRODUCT = false;
 };
 
 // ---------------------------------------------------------------------------
@@ -319,10 +320,7 @@ __host__ __device__ constexpr int pair_E(int N) {
   return N == 32 ? 4 : N == 128 ? 8 : N == 512 ? 16 : N == 2048 ? 32 : 0;
 }
 
-#ifndef DT_PAIR_SPLIT
-#define DT_PAIR_SPLIT 0
-#endif
-template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT, bool TWL = false> struct PairFFT {
+template <typename T, int N, int NB, int SPLIT = 0, bool TWL = false> struct PairFFT {
   using V = Cx<T>;
   static constexpr int E = pair_E(N);
   static constexpr int P = 2 * E;
@@ -457,6 +455,59 @@ template <typename T, int N, int NB, int SPLIT = DT_PAIR_SPLIT, bool TWL = false
     for (int k = 1; k < E; ++k) v[k] = cmul(v[k], cconj(tw.get(k)));
     RegDFT<E, -1, V>::run(v);
   }
+  // --- The kernel-spectrum product taken in the pair basis -----------------
+  // After the second size-E DFT, lane h of the pair (2 k1, 2 k1 + 1) holds
+  // Z_h[j]; the forward transform then forms X_h = Z_0 + (-1)^h W^j Z_1
+  // (W = W_2E), the product is Y_h = K_h X_h with K_h the kernel spectrum at
+  // the lane's slot, and the inverse starts with the same butterfly and the
+  // conjugate twiddle on lane 1.  Composed, those steps are
+  //   Z'_h = (K_0 + K_1) Z_h + (K_0 - K_1) U_h,
+  //   U_0 = W^j Z_1,  U_1 = W^-j Z_0,
+  // so the partner's half is fetched and twiddled once per column (cross)
+  // and each kernel costs two real-by-complex products per slot.
+  // float64 keeps the plain product: the 16 extra complex registers of the
+  // partner's half would spill at N = 512
+  static constexpr bool PAIR_PRODUCT = sizeof(T) == 4;
+  // Forward up to the lane butterfly: on exit v[j] = Z_h[j].
+  static __device__ __forceinline__ void forward_half(V* v, T* ldsr, int p, int b, const Tw& tw) {
+    RegDFT<E, +1, V>::run(v);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw.get(k));
+    exchange<true>(v, ldsr, p, b);
+    RegDFT<E, +1, V>::run(v);
+  }
+  template <int J> static __device__ __forceinline__ void cross_j(const V* z, V* u, T sg) {
+    if constexpr (J < E) {
+      const T zx = lane_xor(z[J].x);
+      const T zy = lane_xor(z[J].y);
+      if constexpr (J == 0) {
+        u[J] = mk<V>(zx, zy);
+      } else if constexpr (2 * J == E) {
+        // W^(+-E/2) = -+i
+        u[J] = mk<V>(sg * zy, -sg * zx);
+      } else {
+        // lane 0: W^J = (c, -s); lane 1: W^-J = (c, s)
+        constexpr T c = (T)ct_cos2pi(J, 2 * E);
+        constexpr T s = (T)ct_sin2pi(J, 2 * E);
+        const T ss = sg * s;
+        u[J] = mk<V>(fma(c, zx, ss * zy), fma(c, zy, -ss * zx));
+      }
+      cross_j<J + 1>(z, u, sg);
+    }
+  }
+  // u[j] = U_h[j] from the pair's halves z
+  static __device__ __forceinline__ void cross(const V* z, V* u, int p) {
+    cross_j<0>(z, u, (p & 1) ? T(-1) : T(1));
+  }
+  // Inverse (unnormalised) from v[j] = Z'_h[j]; on exit v[e] = x[p + P e].
+  static __device__ __forceinline__ void inverse_half(V* v, T* ldsr, int p, int b, const Tw& tw) {
+    RegDFT<E, -1, V>::run(v);
+    exchange<false>(v, ldsr, p, b);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], cconj(tw.get(k)));
+    RegDFT<E, -1, V>::run(v);
+  }
+
   static __device__ __forceinline__ int slot(int p, int j) { return (p >> 1) + E * j + (N / 2) * (p & 1); }
   // Folded index |k| of slot j is linear in j: lanes with h = 0 hold k < N/2,
   // lanes with h = 1 hold k >= N/2 (negative frequencies; k = N/2 is the

@@ -32,9 +32,6 @@ __device__ __forceinline__ int row_swz(int i) { return i ^ ((i >> 3) & 31); }
 // ---------------------------------------------------------------------------
 // Row pass: real -> half spectrum
 // ---------------------------------------------------------------------------
-#ifndef DT_R2C_DMA
-#define DT_R2C_DMA 1
-#endif
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>* __restrict__ out, RowParams p) {
   using V = Cx<T>;
@@ -51,7 +48,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
   const bool active = line < p.n_lines;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
   V v[E];
-  if (DT_R2C_DMA && (p.nx * (int)sizeof(T)) % 16 == 0) {
+  if ((p.nx * (int)sizeof(T)) % 16 == 0) {
     // The block's rows are one contiguous run of LPB * nx reals: copy it
     // into LDS with direct global-to-LDS loads (16-byte words), then take
     // each thread's sample pairs from there.  The rows (nx <= 2N reals)
@@ -241,9 +238,6 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 // ---------------------------------------------------------------------------
 // Row pass: half spectrum -> real, fused with the epilogue
 // ---------------------------------------------------------------------------
-#ifndef DT_EPI_DMA
-#define DT_EPI_DMA 1
-#endif
 template <typename T, int N, bool CURV>
 __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
@@ -266,7 +260,6 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
   const bool active = row < e.n_rows;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
   V v[E];
-#if DT_EPI_DMA
   // Copy the block's half-spectrum lines into LDS with direct global-to-LDS
   // loads (16-byte words, one contiguous run per line, no registers), then
   // read each bin k and its mirror N - k from there.  A line of N + 1 bins
@@ -318,24 +311,6 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
     }
   // the staged lines alias the exchange buffer: B::run passes a barrier
   // before its first LDS store
-#else
-  const V* src = in + (int64_t)c * e.ch_stride + (active ? row : 0) * (int64_t)p.pitch;
-#pragma unroll
-  for (int s = 0; s < E / R0; ++s)
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int k = B::template in_index<0>(q, s, r);
-      V z = mk<V>(T(0), T(0));
-      if (active) {
-        const V xk = src[k];
-        const V xc = cconj(src[N - k]);
-        const V ev = cadd(xk, xc);
-        const V od = cmul(csub(xk, xc), cconj(tw[k]));
-        z = mk<V>(ev.x - od.y, ev.y + od.x);  // ev + i * od
-      }
-      v[s * R0 + r] = z;
-    }
-#endif
   auto addr = [b](int i) { return b * LP + row_swz(i); };
   B::run(v, lds, q, tw, 2, addr);
   __syncthreads();
@@ -367,36 +342,11 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
 // >= 128 bytes per row segment where the LDS budget allows), NT threads,
 // E = N * NB / NT elements per thread.  Separate shapes for the plain and the
 // fused column passes.
-#ifndef DT_C2C_NB32
-#define DT_C2C_NB32 16
-#endif
-#ifndef DT_C2C_NT32
-#define DT_C2C_NT32 512
-#endif
-#ifndef DT_FUSED_NB32
-#define DT_FUSED_NB32 16
-#endif
-#ifndef DT_FUSED_NT32
-#define DT_FUSED_NT32 512
-#endif
-#ifndef DT_C2C_NB64
-#define DT_C2C_NB64 8
-#endif
-#ifndef DT_C2C_NT64
-#define DT_C2C_NT64 512
-#endif
-#ifndef DT_FUSED_NB64
-#define DT_FUSED_NB64 8
-#endif
-#ifndef DT_FUSED_NT64
-#define DT_FUSED_NT64 512
-#endif
-
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 template <typename T, bool FUSED> struct ColShape {
   static constexpr bool F64 = sizeof(T) == 8;
-  static constexpr int NBP = F64 ? (FUSED ? DT_FUSED_NB64 : DT_C2C_NB64) : (FUSED ? DT_FUSED_NB32 : DT_C2C_NB32);
-  static constexpr int NTP = F64 ? (FUSED ? DT_FUSED_NT64 : DT_C2C_NT64) : (FUSED ? DT_FUSED_NT32 : DT_C2C_NT32);
+  static constexpr int NBP = F64 ? 8 : 16;
+  static constexpr int NTP = 512;
   static constexpr int nb(int N) { return cmin(NBP, 65536 / (N * (int)sizeof(Cx<T>))); }
   static constexpr int nt(int N) { return cmin(NTP, N * nb(N) / 8); }
 };
@@ -482,23 +432,21 @@ static bool launch_epi_kernel(const void* in, const RowParams& p, const EpiParam
   return true;
 }
 
-#ifndef DT_EPI_THREADS
-#define DT_EPI_THREADS 128
-#endif
+constexpr int kEpiThreads = 128;   // threads per block of the final row pass (whole rows per block)
 template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p, const EpiParams& e, int N,
                                               hipStream_t st) {
   const int Q = N / 8;
-  int rpb = DT_EPI_THREADS / (e.C * Q);
+  int rpb = kEpiThreads / (e.C * Q);
   if (rpb < 1) rpb = 1;
   const int threads = rpb * e.C * Q;
-  if (threads > 1024 || (DT_EPI_DMA && threads < 64)) return false;
+  if (threads > 1024 || threads < 64) return false;
   const int64_t blocks = (e.n_rows + rpb - 1) / rpb;
   // exchange lines of N + 1 values; the staged input lines are rounded up to
   // whole 16-byte words (and need that much row pitch)
   const size_t stage_line = ((size_t)(N + 1) * sizeof(Cx<T>) + 15) / 16 * 16;
-  if (DT_EPI_DMA && (size_t)p.pitch * sizeof(Cx<T>) < stage_line) return false;
+  if ((size_t)p.pitch * sizeof(Cx<T>) < stage_line) return false;
   const size_t shmem = std::max((size_t)rpb * e.C * (N + 1) * sizeof(Cx<T>),
-                                DT_EPI_DMA ? (size_t)rpb * e.C * stage_line : (size_t)0);
+                                (size_t)rpb * e.C * stage_line);
   // Beyond 64 KiB (long float64 rows with many channels) the kernel needs the
   // larger per-workgroup LDS of gfx950, granted per kernel.
   int dev = 0, lds_max = 65536;

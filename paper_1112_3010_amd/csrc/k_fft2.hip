@@ -4,15 +4,14 @@
 // transform lengths whose register footprint fits; the Stockham kernels in
 // k_fft.hip cover the rest.
 #include "dt_launch.hpp"
+#include <type_traits>
+
 #include "fft_twostep.hpp"
 
 namespace dt {
 
 // Factorisation N = E * P per length and precision (0 = not provided).
 template <typename T, bool FUSED> constexpr int twostep_E(int N) {
-#ifdef DT_NO_TWOSTEP
-  return 0;
-#endif
   if (sizeof(T) == 4) {
     if (FUSED) return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : 0;
     return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : N == 1024 ? 32 : 0;
@@ -21,11 +20,8 @@ template <typename T, bool FUSED> constexpr int twostep_E(int N) {
   if (FUSED) return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : 0;
   return N == 64 ? 8 : N == 128 ? 16 : N == 256 ? 16 : N == 512 ? 32 : 0;
 }
-#ifndef DT_FUSED2_NB32
-#define DT_FUSED2_NB32 8
-#endif
 template <typename T, bool FUSED = false> constexpr int twostep_NB() {
-  return sizeof(T) == 4 ? (FUSED ? DT_FUSED2_NB32 : 16) : 8;
+  return sizeof(T) == 4 ? (FUSED ? 8 : 16) : 8;
 }
 
 template <typename T, int N, int E, int NB, int DIR, bool HALF>
@@ -42,11 +38,9 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
   const int kxs = active ? kx : 0;
   ThreadTwiddles<T, N, E> tw;
   tw.load((const V*)p.tw, pt);
-  const int64_t kin = p.in_grp ? (int64_t)(kxs >> 3) * p.in_grp + (kxs & 7) : kxs;
-  const int64_t kout = p.out_grp ? (int64_t)(kxs >> 3) * p.out_grp + (kxs & 7) : kxs;
   const int64_t in_line = p.in_line, out_line = p.out_line;
-  const V* src = in + blockIdx.z * p.in_ch + (int64_t)blockIdx.y * p.in_outer + kin;
-  V* dst = out + blockIdx.z * p.out_ch + (int64_t)blockIdx.y * p.out_outer + kout;
+  const V* src = in + blockIdx.z * p.in_ch + (int64_t)blockIdx.y * p.in_outer + kxs;
+  V* dst = out + blockIdx.z * p.out_ch + (int64_t)blockIdx.y * p.out_outer + kxs;
   V v[E];
   if constexpr (DIR > 0) {
     // natural input rows pt + P e (pruned), outputs in slot order
@@ -230,9 +224,9 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 // 3D variant of the fused pass with the kernel tables staged in LDS.  The
 // tables are stored tile-major, so the slice a block needs (all folded kz of
 // one kx tile at one |ky|) is a contiguous run that is copied with 16-byte
-// loads.  With MIRROR the block owns the column pair (ky, M_y - ky), which
-// share the slice: every folded table entry then serves all four spectral
-// points (+-ky, +-kz) from one read.  The transform engine ENG is PairFFT
+// loads.  The block owns the column pair (ky, M_y - ky), which share the
+// slice: every folded table entry then serves all four spectral points
+// (+-ky, +-kz) from one read.  The transform engine ENG is PairFFT
 // (one complex LDS exchange) or TwoStep (real and imaginary parts exchanged in
 // two rounds through a real LDS buffer); the tables are staged kTabChunk
 // channels at a time.  Per precision: float32 stages all four slices at once
@@ -240,62 +234,20 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_fused(const Cx<T>* __rest
 // per CU).  float64 stages one slice at a time, exchanges in two rounds and
 // keeps the twiddles in LDS: 60 KB of LDS and at most 256 registers, so two
 // blocks share a CU instead of one.
-#ifndef DT_TAB_CHUNK
-#define DT_TAB_CHUNK 4
-#endif
-#ifndef DT_TAB_CHUNK64
-#define DT_TAB_CHUNK64 1
-#endif
-#ifndef DT_FUSED_SPLIT
-#define DT_FUSED_SPLIT DT_PAIR_SPLIT
-#endif
-#ifndef DT_FUSED_SPLIT64
-#define DT_FUSED_SPLIT64 1
-#endif
-#ifndef DT_FUSED_TWL
-#define DT_FUSED_TWL 0
-#endif
-#ifndef DT_FUSED_TWL64
-#define DT_FUSED_TWL64 1
-#endif
-#ifndef DT_FUSED_MIRROR
-#define DT_FUSED_MIRROR 1
-#endif
-#ifndef DT_FUSED_MINWAVES
-#define DT_FUSED_MINWAVES 1
-#endif
-#ifndef DT_FUSED_MINWAVES64
-#define DT_FUSED_MINWAVES64 2
-#endif
-template <typename T> constexpr int tab_chunk() { return sizeof(T) == 8 ? DT_TAB_CHUNK64 : DT_TAB_CHUNK; }
-template <typename T> constexpr int fused_split() { return sizeof(T) == 8 ? DT_FUSED_SPLIT64 : DT_FUSED_SPLIT; }
-template <typename T> constexpr bool fused_twl() { return (sizeof(T) == 8 ? DT_FUSED_TWL64 : DT_FUSED_TWL) != 0; }
+template <typename T> constexpr int tab_chunk() { return sizeof(T) == 8 ? 1 : 4; }
+template <typename T> constexpr int fused_split() { return sizeof(T) == 8 ? 1 : 0; }
+template <typename T> constexpr bool fused_twl() { return sizeof(T) == 8; }
 // the float64 hint applies to the 512-point pair engine (the 256^3 grids)
-template <typename T, int N> constexpr int fused_minwaves() {
-  return sizeof(T) == 8 ? (N == 512 ? DT_FUSED_MINWAVES64 : 1) : DT_FUSED_MINWAVES;
-}
-#ifndef DT_FUSED_PAIR
-#define DT_FUSED_PAIR 1
-#endif
+template <typename T, int N> constexpr int fused_minwaves() { return sizeof(T) == 8 && N == 512 ? 2 : 1; }
 
-// The pair-split engine serves the 3D fused pass where N = 2 E^2.
-#ifndef DT_FUSED_PAIR64
-#define DT_FUSED_PAIR64 1
-#endif
 // The float64 strided C2C passes use the pair-split engine at these lengths
 // (in float32 the two-step kernel with 16-column tiles streams faster).
-#ifndef DT_C2C_PAIR
-#define DT_C2C_PAIR 1
-#endif
 constexpr int kPairNB = 8;
-template <typename T> constexpr bool c2c_pair(int N) {
-  return DT_C2C_PAIR != 0 && sizeof(T) == 8 && (N == 128 || N == 512);
-}
-template <typename T> constexpr bool fused_pair(int N) {
-  return DT_FUSED_PAIR != 0 && (sizeof(T) == 4 || DT_FUSED_PAIR64 != 0) && pair_E(N) > 0 && N >= 128 && N <= 512;
-}
+template <typename T> constexpr bool c2c_pair(int N) { return sizeof(T) == 8 && (N == 128 || N == 512); }
+// The pair-split engine serves the 3D fused pass where N = 2 E^2.
+template <typename T> constexpr bool fused_pair(int N) { return pair_E(N) > 0 && N >= 128 && N <= 512; }
 
-template <typename T, int N, class ENG, int NB, bool HALF, bool MIRROR>
+template <typename T, int N, class ENG, int NB, bool HALF>
 __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_fused_staged(const Cx<T>* __restrict__ in,
                                                                                      Cx<T>* __restrict__ out,
                                                                                      ColParams p, FusedSpec fs) {
@@ -315,14 +267,9 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
   const int kx = blockIdx.x * NB + b;
   const bool active = kx < p.inner;
   const int kxs = active ? kx : 0;
-  int of, n_cols;
-  if (MIRROR) {
-    of = blockIdx.y;
-    n_cols = (of == 0 || 2 * of == p.outer_len) ? 1 : 2;
-  } else {
-    of = 2 * (int)blockIdx.y > p.outer_len ? p.outer_len - (int)blockIdx.y : (int)blockIdx.y;
-    n_cols = 1;
-  }
+  // block y serves the column pair (of, outer_len - of): one folded table slice
+  const int of = blockIdx.y;
+  const int n_cols = (of == 0 || 2 * of == p.outer_len) ? 1 : 2;
   const FusedItem& IT = fs.items[blockIdx.z];
   const FusedGroup& G = fs.g[IT.group];
   typename ENG::Tw tw;
@@ -366,9 +313,8 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
   };
-  const int64_t kin = p.in_grp ? (int64_t)(kxs >> 3) * p.in_grp + (kxs & 7) : kxs;
   auto issue_load = [&](int ch, int o, V* v) {
-    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kin;
+    const V* src = in + (int64_t)ch * p.in_ch + (int64_t)o * p.in_outer + kxs;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = pt + P * e;
@@ -376,10 +322,21 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
       else v[e] = (active && n < p.n_in) ? src[(int64_t)n * p.in_line] : mk<V>(T(0), T(0));
     }
   };
-  auto load_fwd = [&](int ch, int o, V* v) {
+  // Forward transform of a loaded column.  With the pair-basis product the
+  // transform stops before the lane butterfly and cr receives the partner's
+  // twiddled half (PairFFT::cross); otherwise cr is unused.
+  auto fwd = [&](V* v, V* cr) {
+    if constexpr (ENG::PAIR_PRODUCT) {
+      ENG::forward_half(v, xch, pt, b, tw);     // starts with a barrier
+      ENG::cross(v, cr, pt);
+    } else {
+      ENG::forward_split(v, xch, pt, b, tw);
+    }
+  };
+  auto load_fwd = [&](int ch, int o, V* v, V* cr) {
     issue_load(ch, o, v);
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the column and any table copy issued before it
-    ENG::forward_split(v, xch, pt, b, tw);      // starts with a barrier
+    fwd(v, cr);
   };
   // res[i] (+)= v[i] * kernel spectrum at slot i: the folded table entry with
   // the signs of the odd axes and the factor (-i)^phase
@@ -419,8 +376,48 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
       }
     }
   };
+  // res[j] (+)= the product in the pair basis (PairFFT): (K0 + K1) z[j] +
+  // (K0 - K1) cr[j], K0 and K1 the kernel spectrum at the slots k1 + E j and
+  // k1 + E j + N/2 of the lane pair k1; their folded table rows are k1 + E j
+  // and N/2 - k1 - E j.  A kernel odd along the line axis negates K1, which
+  // swaps the two coefficients; odd along the outer axis at a negative
+  // outer frequency negates both (a half turn of the phase).
+  auto pair_times = [&](int slot, int tab, bool o_neg, const V* z, const V* cr, V* res, bool accumulate) {
+    const TabRef& t = fs.tabs[tab];
+    const int k1 = pt >> 1;
+    const T* t0 = tab_lds + slot * SLICE + b + k1 * NB;
+    const T* t1 = tab_lds + slot * SLICE + b + (N / 2 - k1) * NB;
+    const int ph = (t.phase + ((t.odd_outer && o_neg) ? 2 : 0)) & 3;
+    auto apply = [&](auto rot, auto odd) {
+      constexpr bool ODD = decltype(odd)::value;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const T a0 = t0[j * E * NB];
+        const T a1 = t1[-j * E * NB];
+        const T cA = ODD ? a0 - a1 : a0 + a1;
+        const T cD = ODD ? a0 + a1 : a0 - a1;
+        const V prod = rot(mk<V>(fma(cA, z[j].x, cD * cr[j].x), fma(cA, z[j].y, cD * cr[j].y)));
+        res[j] = accumulate ? cadd(res[j], prod) : prod;
+      }
+    };
+    auto by_phase = [&](auto odd) {
+      switch (ph) {   // uniform: one branch per call, not per element
+        case 0: apply([](V a) { return a; }, odd); break;
+        case 1: apply([](V a) { return mul_mi(a); }, odd); break;
+        case 2: apply([](V a) { return mk<V>(-a.x, -a.y); }, odd); break;
+        default: apply([](V a) { return mul_pi(a); }, odd); break;
+      }
+    };
+    if (t.odd_line) by_phase(std::true_type{});
+    else by_phase(std::false_type{});
+  };
+  auto product = [&](int slot, int tab, bool o_neg, const V* z, const V* cr, V* res, bool accumulate) {
+    if constexpr (ENG::PAIR_PRODUCT) pair_times(slot, tab, o_neg, z, cr, res, accumulate);
+    else times(slot, tab, o_neg, z, res, accumulate);
+  };
   auto inv_store = [&](V* v, int ch, int o) {
-    ENG::inverse_split(v, xch, pt, b, tw);
+    if constexpr (ENG::PAIR_PRODUCT) ENG::inverse_half(v, xch, pt, b, tw);
+    else ENG::inverse_split(v, xch, pt, b, tw);
     if (!active) return;
     V* dst = out + (int64_t)ch * p.out_ch + (int64_t)o * p.out_outer + kx;
 #pragma unroll
@@ -430,7 +427,7 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
       if (n < p.n_out) dst[(int64_t)n * p.out_line] = v[n2];
     }
   };
-  auto column = [&](int col) { return MIRROR ? (col == 0 ? of : p.outer_len - of) : (int)blockIdx.y; };
+  auto column = [&](int col) { return col == 0 ? of : p.outer_len - of; };
 
   if (G.mode == 0) {
     if (IT.c1 - IT.c0 <= kTabChunk) {
@@ -439,8 +436,8 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
       // waiting for it does not wait for those stores (the vector memory
       // counter covers loads and stores in issue order).
       stage(&G.tab[IT.c0], IT.c1 - IT.c0);
-      V spec[E];
-      load_fwd(G.in_ch[0], column(0), spec);
+      V spec[E], cr[E];
+      load_fwd(G.in_ch[0], column(0), spec, cr);
       for (int col = 0; col < n_cols; ++col) {
         const int o = column(col);
         const bool o_neg = 2 * o > p.outer_len;
@@ -448,13 +445,13 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
         if (col + 1 < n_cols) issue_load(G.in_ch[0], column(col + 1), nxt);
         for (int c = IT.c0; c < IT.c1; ++c) {
           V v[E];
-          times(c - IT.c0, G.tab[c], o_neg, spec, v, false);
+          product(c - IT.c0, G.tab[c], o_neg, spec, cr, v, false);
           inv_store(v, G.out_ch[c], o);
         }
         if (col + 1 < n_cols) {
 #pragma unroll
           for (int e = 0; e < E; ++e) spec[e] = nxt[e];
-          ENG::forward_split(spec, xch, pt, b, tw);
+          fwd(spec, cr);
         }
       }
     } else {
@@ -463,15 +460,15 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
       for (int col = 0; col < n_cols; ++col) {
         const int o = column(col);
         const bool o_neg = 2 * o > p.outer_len;
-        V spec[E];
-        load_fwd(G.in_ch[0], o, spec);
+        V spec[E], cr[E];
+        load_fwd(G.in_ch[0], o, spec, cr);
         for (int c0 = IT.c0; c0 < IT.c1; c0 += kTabChunk) {
           const int nc = IT.c1 - c0 < kTabChunk ? IT.c1 - c0 : kTabChunk;
           stage(&G.tab[c0], nc);
           stage_wait();
           for (int c = 0; c < nc; ++c) {
             V v[E];
-            times(c, G.tab[c0 + c], o_neg, spec, v, false);
+            product(c, G.tab[c0 + c], o_neg, spec, cr, v, false);
             inv_store(v, G.out_ch[c0 + c], o);
           }
         }
@@ -487,13 +484,13 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
 #pragma unroll
       for (int e = 0; e < E; ++e) acc[e] = mk<V>(T(0), T(0));
       for (int i = 0; i < G.n_in; ++i) {
-        V v[E];
-        load_fwd(G.in_ch[i], o, v);
+        V v[E], cr[E];
+        load_fwd(G.in_ch[i], o, v, cr);
         if (!once) {
           stage(&G.tab[i], 1);
           stage_wait();
         }
-        times(once ? i : 0, G.tab[i], o_neg, v, acc, true);
+        product(once ? i : 0, G.tab[i], o_neg, v, cr, acc, true);
       }
       inv_store(acc, G.out_ch[0], o);
     }
@@ -567,8 +564,7 @@ template <typename T> bool launch_col2_fused(const void* in, void* out, const Co
   const bool half = 2 * p.n_in == N && 2 * p.n_out == N;
   const Cx<T>* i_ = (const Cx<T>*)in;
   Cx<T>* o_ = (Cx<T>*)out;
-  constexpr bool MIR = DT_FUSED_MIRROR != 0;
-  const dim3 gm(tiles, MIR ? p.outer_len / 2 + 1 : p.outer_len, fs.n_items);
+  const dim3 gm(tiles, p.outer_len / 2 + 1, fs.n_items);
   switch (N) {
 #define CASE(NN)                                                                                          \
   case NN: {                                                                                              \
@@ -578,14 +574,14 @@ template <typename T> bool launch_col2_fused(const void* in, void* out, const Co
       if constexpr (fused_pair<T>(NN)) {                                                                     \
         using ENG = PairFFT<T, NN, NB, fused_split<T>(), fused_twl<T>()>;                                 \
         constexpr int NT = ENG::P * NB;                                                                   \
-        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
-        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
+        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
+        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
         return true;                                                                                      \
       } else if constexpr (E > 0) {                                                                       \
         using ENG = TwoStep<T, NN, E, NB>;                                                                \
         constexpr int NT = ENG::P * NB;                                                                   \
-        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
-        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false, MIR>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
+        if (half) hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, true>), gm, dim3(NT), 0, st, i_, o_, p, fs); \
+        else hipLaunchKernelGGL((k_col2_fused_staged<T, NN, ENG, NB, false>), gm, dim3(NT), 0, st, i_, o_, p, fs);     \
         return true;                                                                                      \
       } else {                                                                                            \
         return false;                                                                                     \

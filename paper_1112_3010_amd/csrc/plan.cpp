@@ -617,9 +617,6 @@ struct Layout3 {
   int64_t lineD, zD, chD;   // after the inverse y pass [c][z][y][kx]
 };
 
-#ifndef DT_TILE_MAJOR
-#define DT_TILE_MAJOR 0
-#endif
 template <typename T>
 dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStream_t st) {
   const int D = p->ndim;
@@ -650,48 +647,31 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
     if (!launch_col_fused<T>(p->R2p(), p->R1p(), cp, fs, (int)My, tiles_for(My, true), 1, st)) return DT_E_UNSUPPORTED;
   } else {
     const int64_t Mz = p->M[2];
-    // Tile-major intermediate between the forward y pass and the fused pass
-    // ([ch][8-bin group][ky][z][8 bins]) when the fused pass reads 8-bin
-    // tiles of float32 bins (64 bytes): each of its columns is then one
-    // contiguous run instead of halves of 128-byte lines.  Both kernels must
-    // be the two-step C2C (16-bin tiles) and the staged fused pass.
-    const bool tile_major = DT_TILE_MAJOR && !p->fp64 && col_tile_width((int)My, false, false) == 16 &&
-                            col_tile_width((int)Mz, false, true) == 8 && My > 1;
     ColParams c2{};
     c2.in_line = MhP; c2.in_outer = ny * MhP; c2.in_ch = nz * ny * MhP;
     c2.out_line = MhP; c2.out_outer = My * MhP; c2.out_ch = nz * My * MhP;
-    if (tile_major) {
-      c2.out_line = nz * 8;          // ky
-      c2.out_outer = 8;              // z
-      c2.out_grp = My * nz * 8;
-    }
     c2.inner = p->Mh; c2.n_in = (int)ny; c2.n_out = (int)My; c2.outer_len = (int)nz;
     c2.tw = p->ws + p->off_tw[1]; c2.tw_stride = 1;
-    {
-      PassTimer t(p, st, "col_fwd_y");
-      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My, false), (int)nz, n_in, st))
-        return DT_E_UNSUPPORTED;
-    }
     ColParams c3{};
     c3.in_line = My * MhP; c3.in_outer = MhP; c3.in_ch = nz * My * MhP;
-    if (tile_major) {
-      c3.in_line = 8;                // z
-      c3.in_outer = nz * 8;          // ky
-      c3.in_grp = My * nz * 8;
-    }
     c3.out_line = My * MhP; c3.out_outer = MhP; c3.out_ch = nz * My * MhP;
     c3.inner = p->Mh; c3.n_in = (int)nz; c3.n_out = (int)nz; c3.outer_len = (int)My;
     c3.tw = p->ws + p->off_tw[2]; c3.tw_stride = 1;
-    {
-      PassTimer t(p, st, "col_fused");
-      if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz, true), (int)My, st))
-        return DT_E_UNSUPPORTED;
-    }
     ColParams c4{};
     c4.in_line = MhP; c4.in_outer = My * MhP; c4.in_ch = nz * My * MhP;
     c4.out_line = MhP; c4.out_outer = ny * MhP; c4.out_ch = nz * ny * MhP;
     c4.inner = p->Mh; c4.n_in = (int)My; c4.n_out = (int)ny; c4.outer_len = (int)nz;
     c4.tw = p->ws + p->off_tw[1]; c4.tw_stride = 1;
+    {
+      PassTimer t(p, st, "col_fwd_y");
+      if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c2, (int)My, +1, tiles_for(My, false), (int)nz, n_in, st))
+        return DT_E_UNSUPPORTED;
+    }
+    {
+      PassTimer t(p, st, "col_fused");
+      if (!launch_col_fused<T>(p->R1p(), p->R2p(), c3, fs, (int)Mz, tiles_for(Mz, true), (int)My, st))
+        return DT_E_UNSUPPORTED;
+    }
     {
       PassTimer t(p, st, "col_inv_y");
       if (!launch_col_c2c<T>(p->R2p(), p->R1p(), c4, (int)My, -1, tiles_for(My, false), (int)nz, n_out, st))
@@ -701,22 +681,13 @@ dt_status run_passes(dt_plan p, int n_in, const FusedSpec& fs, int n_out, hipStr
   return DT_OK;
 }
 
-#ifndef DT_FUSED_SLICE
-#define DT_FUSED_SLICE 0   // output channels per block column of the fused pass (0 = all)
-#endif
-// Work items of the fused pass: mode-0 groups are split into slices of
-// DT_FUSED_SLICE outputs (each block recomputes the forward transform of its
-// column, which keeps its register footprint that of a single transform).
-void fill_items(FusedSpec& fs, int slice) {
+// Work items of the fused pass: one per group (a mode-0 group's block
+// column computes all of its outputs from one forward transform).
+void fill_items(FusedSpec& fs) {
   fs.n_items = 0;
   for (int g = 0; g < fs.n_groups; ++g) {
     const FusedGroup& G = fs.g[g];
-    if (G.mode == 1 || slice <= 0) {
-      fs.items[fs.n_items++] = {g, 0, G.mode == 1 ? 1 : G.n_out};
-      continue;
-    }
-    for (int c = 0; c < G.n_out; c += slice)
-      fs.items[fs.n_items++] = {g, c, std::min(G.n_out, c + slice)};
+    fs.items[fs.n_items++] = {g, 0, G.mode == 1 ? 1 : G.n_out};
   }
 }
 
@@ -857,7 +828,7 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
     ep.scale_mu = std::ldexp(1.0, e_s + p->e_sign_tab);
   }
   fs.n_groups = gi;
-  fill_items(fs, DT_FUSED_SLICE);
+  fill_items(fs);
 
   dt_status s = run_passes<T>(p, n_in, fs, n_out, st);
   if (s != DT_OK) return s;
@@ -936,7 +907,7 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
   }
   Gr.out_ch[D] = D;
   Gr.tab[D] = p->t_rf;
-  fill_items(fs, DT_FUSED_SLICE);
+  fill_items(fs);
   dt_status s = run_passes<T>(p, 1, fs, D + 1, st);
   if (s != DT_OK) return s;
   GatherParams gp{};
