@@ -8,10 +8,12 @@ One step = one dt_forward call (splat -> FFT passes -> epilogue) with the
 mesh already resident in device memory.  The float32-with-scaling path is
 the headline value; the float64 path is reported beside it.
 
-Prints one JSON line with the metric, a roofline entry for the dominant
+Prints one JSON line with the metric (mean over the timed calls, with their
+median, minimum and 90th percentile), a roofline entry for the dominant
 kernel (algorithmic bytes per launch over its average duration, measured
-with HIP events on the launch stream), and a CPU baseline (the FP64 oracle
-on a bounded sample of grid nodes of the same workload, single core).
+with HIP events on the launch stream), the GPU clocks and power cap, and a
+CPU baseline (the FP64 oracle on a bounded sample of grid nodes of the same
+workload, on the host's cores).
 """
 
 from __future__ import annotations
@@ -52,7 +54,8 @@ def pass_bytes(dims, Mp, w, c_in, c_out, n_tab, out_fields):
     tab = n_tab * Mh * (My // 2 + 1) * ((Mz // 2 + 1) if D == 3 else 1) * w
     b = {
         "fill": c_in * N * w,
-        "validity": N * w,
+        # reads the splat's sum of squared multiplicities, writes Theta, S_max, ||g||_2
+        "validity": 4 * 8,
         "row_r2c": c_in * N * w + c_in * ny * nz * Mh * cs,
     }
     if D == 3:
@@ -66,7 +69,8 @@ def pass_bytes(dims, Mp, w, c_in, c_out, n_tab, out_fields):
 
 
 def counters_for(kernel_file_hash, precision, pass_name):
-    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) measured by
+    """HBM bytes of one call's launches of a pass (calibrated FETCH_SIZE +
+    WRITE_SIZE, summed over the pass's launches in one call) measured by
     rocprofv3 for the current kernel sources, else None.  The summary file
     holds lines `sources <sha256>` and `<precision> <pass> fetch=<B> write=<B>`."""
     try:
@@ -102,6 +106,79 @@ def kernel_hash(include_dd=False):
     return h.hexdigest()
 
 
+def per_call(per, calls):
+    """Per-pass time and launch count per call from the library's timings
+    (a pass may run as several launches per call, e.g. the kx chunks of the
+    3D column passes)."""
+    ms = {k: v[1] / calls for k, v in per.items() if v[0] > 0}
+    launches = {k: v[0] / calls for k, v in per.items() if v[0] > 0}
+    return ms, launches
+
+
+def roofline_entry(nbytes, ms, launches, dom, traffic=None):
+    """Roofline of the dominant pass: its algorithmic bytes per call over its
+    time per call (the same ratio as bytes per launch over the average launch
+    duration)."""
+    gbs = nbytes[dom] / (ms[dom] * 1e-3) / 1e9
+    per_launch = None if traffic is None else int(round(traffic / launches[dom]))
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": per_launch, "kernel": dom,
+            "bytes_per_launch": int(round(nbytes[dom] / launches[dom])), "launches_per_call": launches[dom],
+            "avg_launch_us": round(1e3 * ms[dom] / launches[dom], 2)}
+
+
+def timed_calls(fn, steps):
+    """Run fn() `steps` times on the current stream with an event between
+    consecutive calls.  Returns (mean ms per call over the whole span,
+    {"median", "min", "p90"} of the per-call durations)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    mean = ev[0].elapsed_time(ev[-1]) / steps
+    return mean, {"median": round(float(np.median(per)), 4), "min": round(float(per.min()), 4),
+                  "p90": round(float(np.percentile(per, 90)), 4)}
+
+
+def gpu_clocks():
+    """Current SCLK/MCLK levels and the power cap of the GPUs, read from the
+    amdgpu driver's sysfs files (plain reads: no other program is started)."""
+    import glob
+    out = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        card = dev.split("/")[-2]
+        info = {}
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk"):
+            try:
+                cur = [ln.strip() for ln in open(os.path.join(dev, name)) if ln.strip().endswith("*")]
+                info[name] = cur[0] if cur else None
+            except OSError:
+                pass
+        for cap in glob.glob(os.path.join(dev, "hwmon", "hwmon*", "power1_cap")):
+            try:
+                info["power_cap_w"] = int(open(cap).read()) / 1e6
+            except (OSError, ValueError):
+                pass
+        if info:
+            out[card] = info
+    return out or None
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def sample_cells(dims, n_cells, seed=0):
     """Random node sample shared by the CPU baseline and the accuracy report."""
     rng = np.random.default_rng(seed)
@@ -122,16 +199,7 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
         plan.forward_into(out, vertices=Vd, faces=Fd)
     torch.cuda.synchronize()
     assert plan.last_error() == 0
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
-        plan.forward_into(out, vertices=Vd, faces=Fd)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms, ms_stats = timed_calls(lambda: plan.forward_into(out, vertices=Vd, faces=Fd), steps)
     # per-pass timing in a separate set of calls (events inside the library)
     plan.set_timing(True)
     plan.timings(reset=True)
@@ -143,7 +211,7 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
     w = 8 if prec == "fp64" else 4
     Mp = plan.padded
     nbytes = pass_bytes(dims, Mp, w, c_in=1, c_out=1 + len(dims), n_tab=1 + len(dims), out_fields=1 + len(dims))
-    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    avg, launches = per_call(per, timing_calls)
     dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
     achieved = nbytes[dom] / (avg[dom] * 1e-3) / 1e9
     total_model = sum(nbytes.values())
@@ -151,12 +219,14 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
     res = {
         "value": N / (ms * 1e-3),
         "ms_per_step": ms,
+        "ms_stats": ms_stats,
         "plan_setup_s": plan_s,
         "dominant": dom,
         "achieved": achieved,
         "pass_ms": {k: round(v, 4) for k, v in avg.items()},
         "pass_gbs": {k: round(nbytes[k] / (avg[k] * 1e-3) / 1e9, 1) for k in avg if k in nbytes},
         "dom_bytes": nbytes[dom],
+        "launches": launches,
         "model_bytes": total_model,
         "pass_bytes": nbytes,
         "path_gbs": total_model / (ms * 1e-3) / 1e9,
@@ -210,14 +280,7 @@ def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
         plan.backward(Yd, S, G)
     torch.cuda.synchronize()
     assert plan.last_error() == 0
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        plan.backward(Yd, S, G)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms, ms_stats = timed_calls(lambda: plan.backward(Yd, S, G), steps)
     plan.set_timing(True)
     plan.timings(reset=True)
     for _ in range(timing_calls):
@@ -226,16 +289,13 @@ def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
     plan.set_timing(False)
     w = 8 if prec == "fp64" else 4
     nbytes = backward_bytes(dims, plan.padded, w, len(Y))
-    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    avg, launches = per_call(per, timing_calls)
     dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
     total = sum(nbytes.values())
     N = int(np.prod(dims))
     res = {"value": round(N / (ms * 1e-3), 1), "unit": "grid pts/s", "ms_per_call": round(ms, 4),
-           "sources": len(Y),
-           "roofline": {"bound": "hbm", "achieved": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": dom, "bytes_per_launch": nbytes[dom]},
+           "ms_stats": ms_stats, "sources": len(Y),
+           "roofline": roofline_entry(nbytes, avg, launches, dom),
            "path": {"model_bytes": total, "achieved_gbs": round(total / (ms * 1e-3) / 1e9, 1),
                     "frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "pass_ms": {k: round(v, 4) for k, v in avg.items()},
@@ -276,16 +336,13 @@ def run_curvature(prec, Y, dims, tau, steps, warmup, timing_calls):
     C = 1 + D + D * (D + 1) // 2
     w = 8 if prec == "fp64" else 4
     nbytes = pass_bytes(dims, plan.padded, w, c_in=1, c_out=C, n_tab=C, out_fields=5)
-    avg = {k: v[1] / v[0] for k, v in per.items() if v[0] > 0}
+    avg, launches = per_call(per, timing_calls)
     dom = max((k for k in avg if k in nbytes), key=lambda k: avg[k])
     total = sum(nbytes.values())
     N = int(np.prod(dims))
     res = {"value": round(N / (ms * 1e-3), 1), "unit": "grid pts/s", "ms_per_call": round(ms, 4),
            "outputs": "S + mean, Gaussian, k1, k2 (10 channels)",
-           "roofline": {"bound": "hbm", "achieved": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(nbytes[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": dom, "bytes_per_launch": nbytes[dom]},
+           "roofline": roofline_entry(nbytes, avg, launches, dom),
            "path": {"model_bytes": total, "achieved_gbs": round(total / (ms * 1e-3) / 1e9, 1),
                     "frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "pass_ms": {k: round(v, 4) for k, v in avg.items()}}}
@@ -296,7 +353,9 @@ def run_curvature(prec, Y, dims, tau, steps, warmup, timing_calls):
 
 def cpu_baseline(V, F, dims, tau, cells, gpu_results=()):
     """The oracle (FP64 direct sums, S and grad S) on a bounded random sample
-    of nodes of the same workload, one core.  Its fields also give the GPU
+    of nodes of the same workload, on the host's cores (one oracle thread per
+    core available to this process, at most 16; NumPy's BLAS pool held at one
+    thread so the threads do not oversubscribe).  Its fields also give the GPU
     results' errors on that sample: |S - min(S_exact, S_max)| on every sampled
     node, the gradient on nodes with phi >= 2 Theta."""
     import oracle
@@ -307,13 +366,15 @@ def cpu_baseline(V, F, dims, tau, cells, gpu_results=()):
     idx, valid = oracle.sign.snap_f64(inc, o, h, dims)
     Yh = oracle.node_coords(idx[valid], o, h)
     X = oracle.grid_nodes(dims, o, h, cells)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        f = oracle.fields(X, Yh, tau, grad=True)
+        f = oracle.fields(X, Yh, tau, grad=True, workers=workers)
         dt_s = time.perf_counter() - t0
-    out = {"value": len(cells) / dt_s, "unit": "grid pts/s", "cores": 1, "kind": "oracle",
+    out = {"value": len(cells) / dt_s, "unit": "grid pts/s", "cores": workers, "kind": "oracle",
+           "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
            "sample": f"{len(cells)} random nodes of the 256^3 grid, all {int(valid.sum())} sources each, "
-                     f"S and grad S in float64 ({dt_s:.1f} s)"}
+                     f"S and grad S in float64 on {workers} threads ({dt_s:.1f} s)"}
     _, mult = oracle.cell_multiplicities(idx[valid], dims)
     g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
     Mp = tuple(max(64, 1 << int(np.ceil(np.log2(2 * n)))) for n in dims)
@@ -596,7 +657,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--timing-calls", type=int, default=10)
-    ap.add_argument("--cpu-cells", type=int, default=12288)
+    ap.add_argument("--cpu-cells", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-curv", action="store_true", help="skip the 256^3 curvature timing")
@@ -652,6 +713,7 @@ def main():
         log("fp64:", json.dumps({k: v for k, v in r64.items() if not k.startswith("sample_")}))
         b64 = run_backward("fp64", Yc, dims, tau, max(5, args.steps // 4), args.warmup, args.timing_calls)
         log("fp64 backward:", json.dumps(b64))
+    clocks_after = gpu_clocks()
     khash = kernel_hash()
 
     def counter_frac(r, prec):
@@ -667,9 +729,7 @@ def main():
 
     def roof(r, prec):
         traffic = counters_for(khash, prec, r["dominant"])
-        return {"bound": "hbm", "achieved": round(r["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(r["achieved"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": r["dominant"],
-                "bytes_per_launch": r["dom_bytes"]}
+        return roofline_entry(r["pass_bytes"], r["pass_ms"], r["launches"], r["dominant"], traffic)
 
     line = {
         "metric": METRIC,
@@ -679,6 +739,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r32["ms_per_step"], 4),
+        "ms_stats": r32["ms_stats"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -692,12 +753,13 @@ def main():
                  "pass_gbs": r32["pass_gbs"], "s_max_over_tau": round(r32["s_max_over_tau"], 3),
                  "plan_setup_s": round(r32["plan_setup_s"], 3), "counters": counter_frac(r32, "fp32")},
     }
+    line["gpu_clocks"] = clocks_after
     line["backward"] = b32
     if c32 is not None:
         line["curvature"] = c32
     if r64 is not None:
         line["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
-                        "dtype": "f64", "roofline": roof(r64, "fp64"),
+                        "ms_stats": r64["ms_stats"], "dtype": "f64", "roofline": roof(r64, "fp64"),
                         "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
                                  "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
                                  "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3),
