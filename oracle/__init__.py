@@ -51,5 +51,5 @@ from .sign import (  # noqa: F401
 from .validity import kernel_l1, theta, s_max, UNIT_ROUNDOFF, C_THETA  # noqa: F401
 from .adjoint import loss_gradients, l2_loss_gradients  # noqa: F401
 from .metrics import percent_error  # noqa: F401
-from .table1 import table1_distance  # noqa: F401
+from .table1 import table1_distance, table1_phi  # noqa: F401
 from .curvature import curvature, graph_curvature, level_set_curvature, G_MIN  # noqa: F401

@@ -25,9 +25,20 @@ def _pad_len(n):
 def table1_distance(idx, dims, spacing, tau, workers=None):
     """S on the full grid ([z][y][x]) from snapped source indices ``idx``
     (K x D ints), by zero-padded FFT convolution in float64."""
+    phi = table1_phi(idx, dims, spacing, tau, workers=workers)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return -tau * np.log(phi)
+
+
+def table1_phi(idx, dims, spacing, tau, dtype=np.float64, padded=None, workers=None):
+    """phi on the full grid ([z][y][x]) by the zero-padded FFT convolution of
+    Table 1, with every step (kernel samples, indicator, transforms, product,
+    inverse) carried in ``dtype`` (float64 or float32; scipy's transforms keep
+    single precision for float32 data).  ``padded`` gives the padded lengths
+    (x first; default the next power of two >= 2n)."""
     dims = tuple(int(n) for n in dims)
     D = len(dims)
-    Ms = tuple(_pad_len(n) for n in dims)
+    Ms = tuple(_pad_len(n) for n in dims) if padded is None else tuple(int(m) for m in padded)
     # step 1: kernel on wrapped displacements, Nyquist planes zeroed
     grids = []
     for M, h in zip(Ms, spacing):
@@ -41,15 +52,14 @@ def table1_distance(idx, dims, spacing, tau, workers=None):
         sl = [slice(None)] * D
         sl[ax] = Ms[::-1][ax] // 2
         f[tuple(sl)] = 0.0
+    f = f.astype(dtype)
     # step 2: indicator (with multiplicity)
     g = np.zeros(Ms[::-1])
     np.add.at(g, tuple(np.asarray(idx)[:, ::-1].T), 1.0)
+    g = g.astype(dtype)
     # steps 3-5
     import scipy.fft as sfft
     F = sfft.rfftn(f, workers=workers)
     Gs = sfft.rfftn(g, workers=workers)
     phi = sfft.irfftn(F * Gs, s=Ms[::-1], workers=workers)
-    phi = phi[tuple(slice(0, n) for n in dims[::-1])]
-    # step 6
-    with np.errstate(divide="ignore", invalid="ignore"):
-        return -tau * np.log(phi)
+    return phi[tuple(slice(0, n) for n in dims[::-1])]

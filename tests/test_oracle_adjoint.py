@@ -161,3 +161,56 @@ def test_worker_threads_do_not_change_results():
     f4 = oracle.fields(X, Y, tau, grad=True, hess=True, workers=4)
     for key in f1:
         assert np.array_equal(f1[key], f4[key]), key
+
+
+def _fft32_error(dims, K, tau_cells, seed):
+    """Absolute error of phi from the Table 1 convolution carried out in
+    float32 (scipy.fft) against the direct sum, with the padding of the
+    library's rule, and the validity threshold's noise model for that case."""
+    rng = np.random.default_rng(seed)
+    D = len(dims)
+    h = tuple(1.0 / dims[0] for _ in dims)
+    tau = tau_cells * h[0]
+    idx = np.stack([rng.integers(0, n, K) for n in dims], axis=1)
+    Mp = tuple(max(64, 1 << int(np.ceil(np.log2(2 * n)))) for n in dims)
+    phi32 = oracle.table1_phi(idx, dims, h, tau, dtype=np.float32, padded=Mp).astype(np.float64).ravel()
+    f = oracle.fields(oracle.grid_nodes(dims, (0.0,) * D, h), oracle.node_coords(idx, (0.0,) * D, h), tau, workers=4)
+    _, mult = oracle.cell_multiplicities(idx, dims)
+    g_l2 = float(np.sqrt(np.sum(mult.astype(np.float64) ** 2)))
+    theta = oracle.theta("fp32", Mp, oracle.kernel_l1(Mp, h, tau), g_l2)
+    err = np.abs(phi32 - np.exp(f["lnphi"]))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dS = np.abs(-tau * np.log(phi32) - f["S"])
+    return float(np.prod(Mp)), err, theta / oracle.C_THETA, theta, np.exp(f["lnphi"]), dS, tau
+
+
+def test_theta_noise_model_against_float32_fft():
+    """The form of the validity threshold, pinned outside the library: the
+    Table 1 convolution in float32 (scipy's transforms) at padded sizes from
+    64^2 to 512^2 and 64^3 to 128^3.  (i) The rms error of phi over the grid
+    is the same fraction of the noise model u log2(N_pad) ||f||_1 ||g||_2 /
+    sqrt(N_pad) at every size (within [0.01, 0.5], and without a trend in
+    N_pad: a wrong power of N_pad would change it by the size ratio);
+    (ii) |dS| <= 0.02 tau on every node with phi >= Theta, the contract's
+    tolerance, and the largest error stays below c_theta * 0.02 noise units;
+    (iii) near the threshold (Theta <= phi < 4 Theta) the error is not
+    negligible: at least 1/2000 of the tolerance, so the threshold is not
+    placed far inside the region where float32 is exact."""
+    cases = [((n, n), 200, 1.0, n + 1) for n in (32, 64, 128, 256)] + \
+            [((n, n, n), 30, 1.5, n + 2) for n in (32, 48)]
+    npad, rms = [], []
+    for dims, K, tc, seed in cases:
+        N_pad, err, noise, theta, phi, dS, tau = _fft32_error(dims, K, tc, seed)
+        r = float(np.sqrt(np.mean(err ** 2)) / noise)
+        assert 0.01 <= r <= 0.5, (dims, r)
+        assert err.max() <= 0.02 * oracle.C_THETA * noise, dims
+        valid = phi >= theta
+        assert dS[valid].max() <= 0.02 * tau, dims
+        near = valid & (phi < 4 * theta)
+        if near.any():
+            assert dS[near].max() >= 0.02 * tau / 2000, dims
+        if len(dims) == 2:
+            npad.append(N_pad)
+            rms.append(r)
+    slope = np.polyfit(np.log(npad), np.log(rms), 1)[0]
+    assert abs(slope) < 0.25, slope
