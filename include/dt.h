@@ -165,7 +165,7 @@ typedef struct {
  * trunc_dist from an isolated source stays valid for k_hint distinct
  * sources, else float64 if that holds in float64, else (2D plans of S
  * and grad S) double-double if it holds there, else DT_E_PRECISION.
- * c_theta <= 0 selects the default safety factor 1024. Host only. */
+ * c_theta <= 0 selects the default safety factor 256. Host only. */
 dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
                          const double* origin, double tau, int precision, unsigned out_mask,
                          double trunc_dist, int64_t k_hint, double c_theta);
@@ -315,7 +315,7 @@ typedef struct {
 } dt_batch_tiles;
 
 /* precision: DT_FP32_SCALED or DT_FP64; out_mask: DT_OUT_S and/or
- * DT_OUT_GRAD; c_theta <= 0 selects 1024.  DT_E_UNSUPPORTED for n > 1024. */
+ * DT_OUT_GRAD; c_theta <= 0 selects 256.  DT_E_UNSUPPORTED for n > 1024. */
 dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const dt_instance_desc* inst, int precision,
                                unsigned out_mask, double c_theta);
 dt_status dt_batch_workspace_size(dt_batch_plan plan, size_t* bytes);

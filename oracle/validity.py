@@ -27,8 +27,14 @@ import numpy as np
 # compound operations are accurate to a few units of 2^-106, taken as 2^-104.
 UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53, "fp64x2": 2.0 ** -104}
 
-#: Safety factor between the noise estimate and the validity threshold.
-C_THETA = 1024.0
+#: Safety factor between the noise estimate and the validity threshold,
+#: calibrated against the error of the Table 1 convolution carried out in
+#: float32 (tests/test_oracle_adjoint.py): over every node of grids padded
+#: to 64^2 ... 1024^2 and 64^3, 128^3 the largest |error of phi| is at most
+#: 2.2 noise units, growing slowly with N_pad (the maximum of N roughly
+#: Gaussian errors), so at phi = Theta the relative error is at most about
+#: 2.2 / C_THETA and |dS| <= 0.02 tau holds up to 5 noise units.
+C_THETA = 256.0
 
 
 def kernel_l1(dims_pad, spacing, tau):

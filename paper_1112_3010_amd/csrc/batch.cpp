@@ -83,7 +83,7 @@ struct dt_batch_plan_s {
   bool fp64 = false;
   unsigned mask = 0;
   int C = 1;
-  double c_theta = 1024.0;
+  double c_theta = 256.0;
   std::vector<dt_instance_desc> desc;
   std::vector<BatchInst> inst;
   std::vector<int> geo_of;
@@ -429,7 +429,7 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
   p->fp64 = precision == DT_FP64;
   p->mask = out_mask;
   p->C = (out_mask & DT_OUT_GRAD) ? kBatchChan : 1;
-  p->c_theta = c_theta > 0 ? c_theta : 1024.0;
+  p->c_theta = c_theta > 0 ? c_theta : 256.0;
   p->desc.assign(d, d + n_inst);
   p->inst.resize(n_inst);
   p->geo_of.resize(n_inst);

@@ -61,7 +61,7 @@ struct dt_plan_s {
   double tau = 0;
   int prec = DT_FP32_SCALED;
   unsigned mask = 0;
-  double c_theta = 1024.0;
+  double c_theta = 256.0;
   bool fp64 = false;
   size_t w = 4;          // bytes per real
   int Mh = 0, MhP = 0;   // half spectrum length and pitch along x
@@ -313,7 +313,7 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   }
   p->tau = tau;
   p->mask = out_mask;
-  p->c_theta = c_theta > 0 ? c_theta : 1024.0;
+  p->c_theta = c_theta > 0 ? c_theta : 256.0;
 
   if (precision == DT_AUTO) {
     if (!(trunc_dist >= 0) || !std::isfinite(trunc_dist) || k_hint < 1) {
