@@ -90,15 +90,19 @@ def counters_for(kernel_file_hash, precision, pass_name):
 
 # sources of the double-double pipeline only (no float32/float64 launch uses them)
 DD_SOURCES = ("dd.hpp", "dt_dd.hpp", "k_dd.hip")
+# sources of the batched 2D path and of the fixed workspace only (the 3D
+# passes of the headline workload do not use them)
+OTHER_SOURCES = ("batch.cpp", "dt_batch.hpp", "fft_mixed.hpp", "k_batch.hip", "k_static_ws.hip", "dt_static.hpp")
 
 
 def kernel_hash(include_dd=False):
-    """Hash of the kernel and host sources of the library (without the
-    double-double pipeline's own files unless include_dd)."""
+    """Hash of the kernel and host sources that build the single-grid passes
+    (without the double-double pipeline's own files unless include_dd, and
+    without the batched path's)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1112_3010_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f in DD_SOURCES and not include_dd:
+        if (f in DD_SOURCES and not include_dd) or f in OTHER_SOURCES:
             continue
         if f.endswith((".hip", ".hpp", ".cpp")):
             with open(os.path.join(csrc, f), "rb") as fh:
@@ -108,8 +112,7 @@ def kernel_hash(include_dd=False):
 
 def per_call(per, calls):
     """Per-pass time and launch count per call from the library's timings
-    (a pass may run as several launches per call, e.g. the kx chunks of the
-    3D column passes)."""
+    (a pass may run as several launches per call)."""
     ms = {k: v[1] / calls for k, v in per.items() if v[0] > 0}
     launches = {k: v[0] / calls for k, v in per.items() if v[0] > 0}
     return ms, launches

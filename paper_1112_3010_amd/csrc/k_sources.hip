@@ -308,32 +308,81 @@ __global__ void __launch_bounds__(256) k_tab_sample(TabKernel kd, TabGeom tg, do
 }
 
 // One separable stage along `axis`: out(k) = sum_{d < M/2} c_d in(d) trig(2 pi k d / M),
-// trig = cos for an even axis, sin for an odd one, c_0 = 1, c_d = 2.
+// trig = cos for an even axis, sin for an odd one, c_0 = 1, c_d = 2, for every
+// line of the folded grid along that axis.  Written as the product of the
+// H x M/2 matrix C(k, d) = c_d trig(2 pi k d / M) with the lines: a block
+// computes a 64 x 64 tile of (k, line) outputs, staging 16-deep slices of C
+// and of the input lines in LDS; each thread keeps a 4 x 4 tile of sums,
+// accumulated in increasing d.
+constexpr int kTabTK = 64, kTabTC = 64, kTabTD = 16;
 __global__ void __launch_bounds__(256) k_tab_axis(TabGeom tg, int axis, int odd, const double2* __restrict__ trig,
                                                   const double* __restrict__ in, double* __restrict__ out) {
-  const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  int c[3];
-  c[0] = (int)(i % tg.H[0]);
-  c[1] = (int)((i / tg.H[0]) % tg.H[1]);
-  c[2] = (int)(i / ((int64_t)tg.H[0] * tg.H[1]));
-  const int k = c[axis];
-  const int M = tg.M[axis];
-  int64_t astride = 1;
-  for (int a = 0; a < axis; ++a) astride *= tg.H[a];
-  const int64_t base = i - (int64_t)k * astride;
-  double acc = 0.0;
-  int m = 0;  // (k * d) mod M
-  for (int d = 0; d < M / 2; ++d) {
-    const double2 w = trig[m];            // (cos, -sin) of 2 pi m / M
-    const double t = odd ? -w.y : w.x;
-    const double cd = d == 0 ? 1.0 : 2.0;
-    acc += cd * in[base + (int64_t)d * astride] * t;
-    m += k;
-    if (m >= M) m -= M;
+  __shared__ double sC[kTabTD][kTabTK + 1];
+  __shared__ double sX[kTabTD][kTabTC + 1];
+  const int H = tg.H[axis], M = tg.M[axis], Dn = M / 2;
+  int64_t L = 1, U = 1;   // line count below and above the axis
+  for (int a = 0; a < 3; ++a) {
+    if (a < axis) L *= tg.H[a];
+    if (a > axis) U *= tg.H[a];
   }
-  out[i] = acc;
+  const int64_t ncol = L * U;
+  const int k0 = blockIdx.y * kTabTK;
+  const int64_t c0 = (int64_t)blockIdx.x * kTabTC;
+  const int tid = threadIdx.x;
+  const int tk = tid / 16, tc = tid % 16;     // outputs k0 + 4 tk + i, columns c0 + tc + 16 j
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int d0 = 0; d0 < Dn; d0 += kTabTD) {
+    for (int e = tid; e < kTabTD * kTabTK; e += 256) {
+      const int dd = e / kTabTK, kk = e % kTabTK;
+      const int d = d0 + dd, k = k0 + kk;
+      double v = 0.0;
+      if (d < Dn && k < H) {
+        const double2 w = trig[(int)(((int64_t)k * d) % M)];   // (cos, -sin) of 2 pi k d / M
+        v = (d == 0 ? 1.0 : 2.0) * (odd ? -w.y : w.x);
+      }
+      sC[dd][kk] = v;
+    }
+    for (int e = tid; e < kTabTD * kTabTC; e += 256) {
+      const int dd = e / kTabTC, cc = e % kTabTC;
+      const int d = d0 + dd;
+      const int64_t col = c0 + cc;
+      double v = 0.0;
+      if (d < Dn && col < ncol) {
+        const int64_t hi = col / L, lo = col - hi * L;
+        v = in[(hi * H + d) * L + lo];
+      }
+      sX[dd][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int dd = 0; dd < kTabTD; ++dd) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sC[dd][4 * tk + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sX[dd][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = c0 + tc + 16 * j;
+    if (col >= ncol) continue;
+    const int64_t hi = col / L, lo = col - hi * L;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + 4 * tk + i;
+      if (k < H) out[(hi * H + k) * L + lo] = acc[i][j];
+    }
+  }
 }
 
 // Store in the tile-major layout read by the fused pass: element (x, y, z)
@@ -364,8 +413,9 @@ int launch_tab_sample(const TabKernel& kd, const TabGeom& tg, double* out, doubl
 void launch_tab_axis(const TabGeom& tg, int axis, int odd, const void* trig, const double* in, double* out,
                      hipStream_t st) {
   const int64_t total = (int64_t)tg.H[0] * tg.H[1] * tg.H[2];
-  hipLaunchKernelGGL(k_tab_axis, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, tg, axis, odd,
-                     (const double2*)trig, in, out);
+  const int64_t ncol = total / tg.H[axis];
+  const dim3 grid((unsigned)((ncol + kTabTC - 1) / kTabTC), (unsigned)((tg.H[axis] + kTabTK - 1) / kTabTK));
+  hipLaunchKernelGGL(k_tab_axis, grid, dim3(256), 0, st, tg, axis, odd, (const double2*)trig, in, out);
 }
 template <typename T> void launch_tab_store(const TabGeom& tg, const double* in, double scale, T* out, int nb,
                                             int tiles, hipStream_t st) {
