@@ -336,9 +336,23 @@ dt_status dt_batch_set_graph(dt_batch_plan plan, int enable);
  * workspace first (a synchronous host-to-device copy). */
 dt_status dt_forward_batched(dt_batch_plan plan, const float* Y, const int64_t* K_offsets, void* S, void* grad,
                              void* stream);
-/* Times every feasible tile choice (reps calls each, eager, on `stream`),
- * keeps the fastest and returns it in *best (may be NULL).  Overwrites S
- * and grad.  Synchronises the stream. */
+/* Radix schedule of the batched transforms: fams[3 i + k] is the schedule
+ * of pass k of instance i (k = 0: forward row transform, 1: column pass,
+ * 2: inverse row transform with the epilogue), one of four orders of the
+ * 7-smooth length's radices: 0 radix 8 while possible, then one 4 or 2, then
+ * 7, 5, 3; 1 the odd radices first, then as 0; 2 radix 4 while possible,
+ * then one 2, then 7, 5, 3; 3 the one 4 or 2 first, then radix 8, then 7, 5,
+ * 3.  All give the same transform up to rounding.  Default 0 everywhere;
+ * dt_batch_autotune chooses them per (pass, length).  fams holds 3 n_inst
+ * ints; values outside 0..3 give DT_E_ARG and change nothing. */
+dt_status dt_batch_set_schedule(dt_batch_plan plan, const int* fams);
+dt_status dt_batch_get_schedule(dt_batch_plan plan, int* fams);
+/* Times every feasible tile choice (reps calls each, eager, on `stream`)
+ * and keeps the fastest, returned in *best (may be NULL); then, per pass
+ * and per padded length, times that pass alone over the instances of that
+ * length under each distinct radix schedule and keeps the fastest (read it
+ * with dt_batch_get_schedule).  Overwrites S and grad.  Synchronises the
+ * stream. */
 dt_status dt_batch_autotune(dt_batch_plan plan, const float* Y, const int64_t* K_offsets, void* S, void* grad,
                             int reps, void* stream, dt_batch_tiles* best);
 /* Synchronises the plan's stream; returns and clears the sticky error. */

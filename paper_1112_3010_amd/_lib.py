@@ -25,7 +25,8 @@ EXPORTED = (
     "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
     "dt_last_error", "dt_last_stats", "dt_plan_set_timing", "dt_plan_timings", "dt_plan_reset_timings",
     "dt_create_batch_plan", "dt_batch_workspace_size", "dt_batch_set_workspace", "dt_batch_instance_info",
-    "dt_batch_set_tiles", "dt_batch_get_tiles", "dt_batch_set_graph", "dt_forward_batched", "dt_batch_autotune",
+    "dt_batch_set_tiles", "dt_batch_get_tiles", "dt_batch_set_schedule", "dt_batch_get_schedule",
+    "dt_batch_set_graph", "dt_forward_batched", "dt_batch_autotune",
     "dt_batch_last_error", "dt_batch_stats", "dt_destroy_batch_plan",
     "dt_status_str",
 )
@@ -155,6 +156,8 @@ def load():
     lib.dt_batch_instance_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(DtBatchInstanceInfo)]
     lib.dt_batch_set_tiles.argtypes = [vp, ctypes.POINTER(DtBatchTiles)]
     lib.dt_batch_get_tiles.argtypes = [vp, ctypes.POINTER(DtBatchTiles)]
+    lib.dt_batch_set_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.dt_batch_get_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.dt_batch_set_graph.argtypes = [vp, ctypes.c_int]
     lib.dt_forward_batched.argtypes = [vp, vp, ctypes.POINTER(i64), vp, vp, vp]
     lib.dt_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(i64), vp, vp, ctypes.c_int, vp,

@@ -155,6 +155,20 @@ class BatchPlan:
         t = L.DtBatchTiles(int(col_nb), int(col_threads), int(row_threads))
         L.check(L.load().dt_batch_set_tiles(self._h, ctypes.byref(t)), "dt_batch_set_tiles")
 
+    def schedule(self):
+        """Radix schedule family per instance and pass: a list of n_inst
+        triples (forward rows, columns, inverse rows), each in 0..3."""
+        arr = (ctypes.c_int * (3 * self.n))()
+        L.check(L.load().dt_batch_get_schedule(self._h, arr), "dt_batch_get_schedule")
+        return [list(arr[3 * i:3 * i + 3]) for i in range(self.n)]
+
+    def set_schedule(self, fams):
+        flat = [int(v) for triple in fams for v in triple]
+        if len(flat) != 3 * self.n:
+            raise ValueError("one (rows, columns, inverse rows) triple per instance")
+        arr = (ctypes.c_int * (3 * self.n))(*flat)
+        L.check(L.load().dt_batch_set_schedule(self._h, arr), "dt_batch_set_schedule")
+
     def _tune_key(self):
         h = hashlib.sha256()
         h.update(json.dumps([self.dims, self.precision, sorted(self.outputs)]).encode())
@@ -163,8 +177,9 @@ class BatchPlan:
         return h.hexdigest()
 
     def autotune(self, Y, offsets, reps=3, cache=True):
-        """Pick the fastest tiles (measured on this batch) and remember them in
-        a JSON cache keyed by the instance sizes, precision and device."""
+        """Pick the fastest tiles and radix schedules (measured on this batch)
+        and remember them in a JSON cache keyed by the instance sizes,
+        precision and device."""
         path = _cache_path()
         key = self._tune_key()
         table = {}
@@ -175,7 +190,11 @@ class BatchPlan:
             except (OSError, ValueError):
                 table = {}
             if key in table:
-                self.set_tiles(**table[key])
+                entry = dict(table[key])
+                sched = entry.pop("schedule", None)
+                self.set_tiles(**entry)
+                if sched is not None:
+                    self.set_schedule(sched)
                 return dict(table[key])
         S, G = self.empty_outputs()
         koff = self._args(Y, offsets)
@@ -184,7 +203,8 @@ class BatchPlan:
                                            None if S is None else ctypes.c_void_p(S.data_ptr()),
                                            None if G is None else ctypes.c_void_p(G.data_ptr()), int(reps),
                                            _stream(self.device), ctypes.byref(best)), "dt_batch_autotune")
-        res = {"col_nb": best.col_nb, "col_threads": best.col_threads, "row_threads": best.row_threads}
+        res = {"col_nb": best.col_nb, "col_threads": best.col_threads, "row_threads": best.row_threads,
+               "schedule": self.schedule()}
         if cache:
             table[key] = res
             try:

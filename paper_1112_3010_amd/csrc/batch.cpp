@@ -48,31 +48,56 @@ int64_t smooth7_at_least(int64_t n) {
   }
 }
 
-// Radix schedule of a 7-smooth length: radix 8 while possible, then one 4 or
-// 2, then 7, 5, 3.  Returns false if the length is not 7-smooth.
-bool mixed_plan_for(int64_t N, MixedPlan& mp) {
-  mp.n_st = 0;
+// Radix schedules of a 7-smooth length; dt_batch_autotune picks one per pass
+// and length:
+//   0: radix 8 while possible, then one 4 or 2, then 7, 5, 3;
+//   1: the odd radices 7, 5, 3 first, then as 0;
+//   2: radix 4 while possible, then one 2, then 7, 5, 3;
+//   3: the one 4 or 2 first, then radix 8, then 7, 5, 3.
+// Returns false if the length is not 7-smooth or needs too many stages.
+bool mixed_plan_for(int64_t N, int family, MixedPlan& mp) {
+  if (family < 0 || family >= kMixedFamilies || N < 1) return false;
   int64_t r = N;
-  auto push = [&](int R) {
-    if (mp.n_st >= kMixedMaxStages) return false;
-    mp.radix[mp.n_st++] = R;
-    r /= R;
-    return true;
-  };
-  while (r % 8 == 0)
-    if (!push(8)) return false;
-  if (r % 4 == 0 && !push(4)) return false;
-  if (r % 2 == 0 && !push(2)) return false;
-  for (int p : {7, 5, 3})
-    while (r % p == 0)
-      if (!push(p)) return false;
-  if (r != 1) return false;
-  int64_t ns = 1;
-  for (int s = 0; s < mp.n_st; ++s) {
-    mp.m_ns[s] = fastdiv_magic((uint32_t)ns);
-    mp.m_nbf[s] = fastdiv_magic((uint32_t)(N / mp.radix[s]));
-    ns *= mp.radix[s];
+  int a2 = 0;
+  while (r % 2 == 0) {
+    r /= 2;
+    ++a2;
   }
+  std::vector<int> odd, pow2;
+  for (int q : {7, 5, 3})
+    while (r % q == 0) {
+      r /= q;
+      odd.push_back(q);
+    }
+  if (r != 1) return false;
+  if (family == 2) {
+    for (; a2 >= 2; a2 -= 2) pow2.push_back(4);
+    if (a2) pow2.push_back(2);
+  } else {
+    const int small = a2 % 3 == 2 ? 4 : a2 % 3 == 1 ? 2 : 0;
+    if (family == 3 && small) pow2.push_back(small);
+    for (int i = 0; i < a2 / 3; ++i) pow2.push_back(8);
+    if (family != 3 && small) pow2.push_back(small);
+  }
+  std::vector<int> rad = family == 1 ? odd : pow2;
+  const std::vector<int>& rest = family == 1 ? pow2 : odd;
+  rad.insert(rad.end(), rest.begin(), rest.end());
+  if ((int)rad.size() > kMixedMaxStages) return false;
+  mp.n_st = (int)rad.size();
+  int64_t ns = 1;
+  for (int st = 0; st < mp.n_st; ++st) {
+    mp.radix[st] = rad[st];
+    mp.m_ns[st] = fastdiv_magic((uint32_t)ns);
+    mp.m_nbf[st] = fastdiv_magic((uint32_t)(N / rad[st]));
+    ns *= rad[st];
+  }
+  return true;
+}
+
+bool same_plan(const MixedPlan& a, const MixedPlan& b) {
+  if (a.n_st != b.n_st) return false;
+  for (int s = 0; s < a.n_st; ++s)
+    if (a.radix[s] != b.radix[s]) return false;
   return true;
 }
 
@@ -111,6 +136,7 @@ struct dt_batch_plan_s {
   int nblk[3] = {0, 0, 0}, ecap[3] = {0, 0, 0};
   size_t lds[3] = {0, 0, 0};
   bool blocks_valid = false;
+  std::vector<int> sched;          // radix schedule family per instance and pass (3 per instance)
   std::vector<int64_t> koff;       // offsets the device copy holds
   bool koff_valid = false;
   // graph replay
@@ -193,8 +219,10 @@ dt_batch_tiles default_tiles(dt_batch_plan p) {
   return t;
 }
 
-// Build the three block lists for the current tiles and upload them.
-dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
+// Build the three block lists for the current tiles and upload them (only
+// for the instances with keep[i] != 0 when keep is given: the autotuner times
+// one pass over the instances of one length).
+dt_status build_blocks(dt_batch_plan p, hipStream_t st, const std::vector<char>* keep = nullptr) {
   p->blocks_valid = false;
   const size_t w = p->wsz();
   std::vector<BatchBlock> lists[3];
@@ -205,6 +233,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st) {
   int64_t my_max = 0;
   for (const auto& I : p->inst) my_max = std::max<int64_t>(my_max, I.My);
   for (int i = 0; i < p->n; ++i) {
+    if (keep && !(*keep)[i]) continue;
     const BatchInst& I = p->inst[i];
     const int64_t sx = I.sx;
     // row r2c: one line per row
@@ -327,8 +356,26 @@ template <typename T> dt_status build_batch_tables(dt_batch_plan p, hipStream_t 
   return hip_st(hipGetLastError());
 }
 
-template <typename T> dt_status enqueue_forward(dt_batch_plan p, const float* Y, int64_t K_total, void* S,
-                                                void* grad, hipStream_t st) {
+// Radix schedules of every instance and pass from p->sched; the descriptors
+// are uploaded again once the workspace is attached.
+dt_status apply_schedule(dt_batch_plan p, hipStream_t st) {
+  for (int i = 0; i < p->n; ++i) {
+    BatchInst& I = p->inst[i];
+    if (!mixed_plan_for(I.sx, p->sched[3 * i + P_R2C], I.px) || !mixed_plan_for(I.My, p->sched[3 * i + P_COL], I.py) ||
+        !mixed_plan_for(I.sx, p->sched[3 * i + P_EPI], I.pxi))
+      return DT_E_ARG;
+  }
+  if (p->ready) {
+    if (hipMemcpyAsync(p->d_inst(), p->inst.data(), p->inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+      return DT_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
+    p->drop_graph();
+  }
+  return DT_OK;
+}
+
+BatchArgs base_args(dt_batch_plan p) {
   BatchArgs a{};
   a.inst = p->d_inst();
   a.n_inst = p->n;
@@ -338,6 +385,35 @@ template <typename T> dt_status enqueue_forward(dt_batch_plan p, const float* Y,
   a.tw = p->d_tw();
   a.tab = p->d_tab();
   a.C = p->C;
+  return a;
+}
+
+// One pass alone over the current block list (the autotuner's timing unit;
+// its input is whatever the buffers hold).
+template <typename T> dt_status enqueue_pass(dt_batch_plan p, int k, void* S, void* grad, hipStream_t st) {
+  BatchArgs a = base_args(p);
+  a.blocks = p->d_blk(k);
+  bool ok = false;
+  if (k == P_R2C) {
+    a.in = p->d_A();
+    a.out = p->d_B();
+    ok = launch_batch_row_r2c<T>(a, p->nblk[k], p->tiles.row_threads, p->ecap[k], p->lds[k], st);
+  } else if (k == P_COL) {
+    a.in = p->d_B();
+    a.out = p->d_A();
+    ok = launch_batch_col_fused<T>(a, p->nblk[k], p->tiles.col_threads, p->ecap[k], p->lds[k], st);
+  } else {
+    a.in = p->d_A();
+    a.S = S;
+    a.grad = grad;
+    ok = launch_batch_row_c2r_epi<T>(a, p->nblk[k], p->tiles.row_threads, p->ecap[k], p->lds[k], st);
+  }
+  return ok ? hip_st(hipGetLastError()) : DT_E_UNSUPPORTED;
+}
+
+template <typename T> dt_status enqueue_forward(dt_batch_plan p, const float* Y, int64_t K_total, void* S,
+                                                void* grad, hipStream_t st) {
+  BatchArgs a = base_args(p);
   T* img = (T*)p->d_A();
   launch_fill_zero<T>(img, p->n_img, st);
   launch_fill_zero<double>(p->d_scal(), 4 * (int64_t)p->n, st);
@@ -469,7 +545,11 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     I.ox = q.origin[0]; I.oy = q.origin[1];
     I.hx = q.spacing[0]; I.hy = q.spacing[1];
     I.tau = q.tau;
-    if (!mixed_plan_for(sx, I.px) || !mixed_plan_for(My, I.py)) { delete p; return DT_E_UNSUPPORTED; }
+    if (!mixed_plan_for(sx, 0, I.px) || !mixed_plan_for(My, 0, I.py) || !mixed_plan_for(sx, 0, I.pxi)) {
+      delete p;
+      return DT_E_UNSUPPORTED;
+    }
+    p->sched.insert(p->sched.end(), {0, 0, 0});
     I.m_sx = fastdiv_magic((uint32_t)sx);
     I.m_sx1 = fastdiv_magic((uint32_t)(sx + 1));
     I.m_nx = fastdiv_magic((uint32_t)I.nx);
@@ -697,13 +777,75 @@ extern "C" dt_status dt_batch_autotune(dt_batch_plan p, const float* Y, const in
     float ms;
     if (time_cfg(t, ms) && ms < best_ms) { best_ms = ms; win = t; }
   }
+  p->tiles = win;
+  // Radix schedule per (pass, length): every candidate schedule of a length
+  // is timed on that pass alone over the instances of that length.
+  auto time_pass = [&](int k, float& ms) -> bool {
+    const bool f64 = p->fp64;
+    auto run = [&]() { return f64 ? enqueue_pass<double>(p, k, S, grad, st) : enqueue_pass<float>(p, k, S, grad, st); };
+    if (run() != DT_OK) return false;   // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r)
+      if (run() != DT_OK) return false;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return false;
+    return hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  };
+  for (int k : {P_R2C, P_COL, P_EPI}) {
+    std::map<int64_t, std::vector<int>> by_len;
+    for (int i = 0; i < p->n; ++i) by_len[k == P_COL ? p->inst[i].My : p->inst[i].sx].push_back(i);
+    for (const auto& kv : by_len) {
+      std::vector<char> keep(p->n, 0);
+      for (int i : kv.second) keep[i] = 1;
+      int best_f = p->sched[3 * kv.second[0] + k];
+      float best_k = 1e30f;
+      std::vector<MixedPlan> seen;
+      for (int f = 0; f < kMixedFamilies; ++f) {
+        MixedPlan mp;
+        if (!mixed_plan_for(kv.first, f, mp)) continue;
+        bool dup = false;
+        for (const auto& q : seen) dup = dup || same_plan(q, mp);
+        if (dup) continue;
+        seen.push_back(mp);
+        for (int i : kv.second) p->sched[3 * i + k] = f;
+        float ms;
+        if (apply_schedule(p, st) == DT_OK && build_blocks(p, st, &keep) == DT_OK && time_pass(k, ms) &&
+            ms < best_k) {
+          best_k = ms;
+          best_f = f;
+        }
+      }
+      for (int i : kv.second) p->sched[3 * i + k] = best_f;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipGetLastError();
-  p->tiles = win;
+  s = apply_schedule(p, st);
+  if (s != DT_OK) return s;
   s = build_blocks(p, st);
   if (s != DT_OK) return s;
   if (best) *best = win;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_batch_set_schedule(dt_batch_plan p, const int* fams) {
+  if (!p || !fams) return DT_E_ARG;
+  for (int i = 0; i < 3 * p->n; ++i)
+    if (fams[i] < 0 || fams[i] >= kMixedFamilies) return DT_E_ARG;
+  const std::vector<int> old = p->sched;
+  std::copy(fams, fams + 3 * p->n, p->sched.begin());
+  const dt_status s = apply_schedule(p, p->stream);
+  if (s != DT_OK) {
+    p->sched = old;
+    (void)apply_schedule(p, p->stream);
+  }
+  return s;
+}
+
+extern "C" dt_status dt_batch_get_schedule(dt_batch_plan p, int* fams) {
+  if (!p || !fams) return DT_E_ARG;
+  for (int i = 0; i < 3 * p->n; ++i) fams[i] = p->sched[i];
   return DT_OK;
 }
 

@@ -10,6 +10,7 @@
 namespace dt {
 
 constexpr int kBatchChan = 3;   // f, u_x, u_y
+constexpr int kMixedFamilies = 4;   // radix schedules per length (batch.cpp, mixed_plan_for)
 
 // Device-resident description of one instance (set up once per plan).
 struct BatchInst {
@@ -28,8 +29,9 @@ struct BatchInst {
   int64_t tab_stride;   // elements between the three tables
   int64_t twx_off;      // complex elements: exp(-2 pi i m / M_x), m < M_x
   int64_t twy_off;      // complex elements: exp(-2 pi i m / M_y), m < M_y
-  MixedPlan px;         // radix schedule of length sx
-  MixedPlan py;         // radix schedule of length M_y
+  MixedPlan px;         // radix schedule of length sx (forward row transform)
+  MixedPlan py;         // radix schedule of length M_y (column pass)
+  MixedPlan pxi;        // radix schedule of length sx (inverse row transform)
   uint32_t m_sx, m_sx1, m_nx;   // fastdiv_magic of sx, sx + 1 and nx
 };
 

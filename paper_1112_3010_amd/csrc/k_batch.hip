@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
     lds[line * LP + k] = mk<V>(ev.x - od.y, ev.y + od.x);   // ev + i od
   }
   __syncthreads();
-  const MixedPlan& px = I->px;   // read per stage from the descriptor (no private copy)
+  const MixedPlan& px = I->pxi;   // read per stage from the descriptor (no private copy)
   mixed_fft<T, -1, ECAP, false>(lds, N, FastDiv((uint32_t)(L * C), (uint32_t)bb.magic), 1, LP, px, tw, 2, tid, nthr);
   const int64_t Ki = a.koff[ii + 1] - a.koff[ii];
   const int eg = ceil_log2_count(Ki);

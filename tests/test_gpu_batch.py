@@ -156,17 +156,69 @@ def test_batch_96_instances(dt):
     S, G = plan.forward(Y, offs)
     torch.cuda.synchronize()
     assert plan.last_error() == 0
-    tiles = plan.autotune(Y, offs, reps=1, cache=False)
+    # tiles and radix schedules tuned on this batch: the schedules change the
+    # order of the radix stages, so the tuned results are checked against the
+    # oracle as well
+    tuned = plan.autotune(Y, offs, reps=1, cache=False)
     S1, G1 = plan.forward(Y, offs)
     torch.cuda.synchronize()
-    assert torch.equal(S1, S) and torch.equal(G1, G), tiles
-    worst = 0.0
+    sched = np.array(plan.schedule())
+    assert sched.shape == (len(inst), 3) and sched.min() >= 0 and sched.max() <= 3
+    assert tuned["schedule"] == sched.tolist()
+    # instances of one padded length share each pass's schedule
+    for k, lens in ((0, [plan.padded(i)[0] for i in range(len(inst))]), (1, [plan.padded(i)[1] for i in
+                                                                              range(len(inst))])):
+        by = {}
+        for i, L in enumerate(lens):
+            by.setdefault(L, set()).add(int(sched[i, k]))
+        assert all(len(v) == 1 for v in by.values())
     for i, ((n, y), tau) in enumerate(zip(inst, taus)):
-        s, g = plan.views(S, G)[i]
-        cells = _cells((n, n), y, 24, 24, 970 + i)
-        _check_instance(f"c4 inst {i} n={n} K={len(y)}", "fp32", (n, n), tau, y, _np(s), _np(g), cells,
-                        plan.stats(i))
-    print(f"\n[batch 96] tuned tiles {tiles}; all instances within tolerance", flush=True)
+        cells = _cells((n, n), y, 250, 250, 970 + i)
+        for tag, (s, g), st in (("default", plan.views(S, G)[i], None), ("tuned", plan.views(S1, G1)[i], None)):
+            _check_instance(f"c4 inst {i} n={n} K={len(y)} {tag}", "fp32", (n, n), tau, y, _np(s), _np(g), cells,
+                            plan.stats(i))
+    fams = np.bincount(sched.ravel(), minlength=4).tolist()
+    print(f"\n[batch 96] tuned tiles {dict((k, v) for k, v in tuned.items() if k != 'schedule')}, "
+          f"schedule families used {fams}; all instances within tolerance on about 500 nodes each", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_every_radix_schedule(dt, prec, tmp_path, monkeypatch):
+    """Each of the four radix orders, on every pass of every instance, gives
+    the transform (checked against the oracle); the schedule round-trips
+    through the tuning cache."""
+    pts = _small_points()
+    taus = [2.0 / d[0] for d in SMALL_DIMS]
+    plan = dt.BatchPlan(SMALL_DIMS, taus, precision=prec, graph=False)
+    assert plan.schedule() == [[0, 0, 0]] * len(SMALL_DIMS)
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    Y = Y.cuda()
+    for fam in range(4):
+        mix = [[fam, (fam + i) % 4, (fam + 2 * i) % 4] for i in range(len(SMALL_DIMS))]
+        plan.set_schedule(mix)
+        assert plan.schedule() == mix
+        S, G = plan.forward(Y, offs)
+        torch.cuda.synchronize()
+        assert plan.last_error() == 0
+        for i, (dims, tau) in enumerate(zip(SMALL_DIMS, taus)):
+            s, g = plan.views(S, G)[i]
+            cells = None if dims[0] * dims[1] <= 40000 else _cells(dims, pts[i], 1000, 1000, 990 + i)
+            _check_instance(f"schedule {mix[i]} inst {i}", prec, dims, tau, pts[i], _np(s), _np(g), cells,
+                            plan.stats(i))
+    with pytest.raises(RuntimeError):
+        plan.set_schedule([[0, 4, 0]] + [[0, 0, 0]] * (len(SMALL_DIMS) - 1))
+    assert plan.schedule() == mix
+    # autotune writes tiles and schedule to the cache; a new plan restores both
+    monkeypatch.setenv("DT_TUNE_CACHE", str(tmp_path / "tiles.json"))
+    tuned = plan.autotune(Y, offs, reps=1, cache=True)
+    S1, G1 = plan.forward(Y, offs)
+    plan2 = dt.BatchPlan(SMALL_DIMS, taus, precision=prec, graph=False)
+    again = plan2.autotune(Y, offs, reps=1, cache=True)
+    assert again == tuned
+    assert plan2.schedule() == tuned["schedule"] == plan.schedule()
+    S2, G2 = plan2.forward(Y, offs)
+    torch.cuda.synchronize()
+    assert torch.equal(S2, S1) and torch.equal(G2, G1)
 
 
 RED_DIMS = [(300, 300), (200, 260), (128, 96), (90, 400)]
