@@ -195,6 +195,13 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
     plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "grad"])
     torch.cuda.synchronize()
     plan_s = time.time() - t0
+    # the kernel spectra alone (what a new tau costs once the workspace exists)
+    tab_s = []
+    for _ in range(3):
+        t0 = time.time()
+        plan.rebuild()
+        torch.cuda.synchronize()
+        tab_s.append(time.time() - t0)
     Vd = torch.from_numpy(V).cuda()
     Fd = torch.from_numpy(F).cuda()
     out = {"S": plan._empty(), "grad": plan._empty(len(dims))}
@@ -224,6 +231,7 @@ def run_gpu(prec, V, F, dims, tau, steps, warmup, timing_calls, cells=None):
         "ms_per_step": ms,
         "ms_stats": ms_stats,
         "plan_setup_s": plan_s,
+        "plan_tables_s": float(np.median(tab_s)),
         "dominant": dom,
         "achieved": achieved,
         "pass_ms": {k: round(v, 4) for k, v in avg.items()},
@@ -486,26 +494,25 @@ def run_batch(steps, warmup):
     Y = Y.cuda()
     nodes = sum(n * n for n, _ in inst)
 
+    def run(plan, S, G, graph):
+        plan.set_graph(graph)
+        for _ in range(warmup):
+            plan.forward_into(Y, offs, S, G)
+        ms, _ = timed_calls(lambda: plan.forward_into(Y, offs, S, G), steps)
+        return ms
+
     def timed(plan):
         S, G = plan.empty_outputs()
-        tiles = plan.autotune(Y, offs, reps=2, cache=False)
-        res = {}
-        for mode in ("eager", "graph"):
-            plan.set_graph(mode == "graph")
-            for _ in range(warmup):
-                plan.forward_into(Y, offs, S, G)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(steps):
-                plan.forward_into(Y, offs, S, G)
-            e1.record()
-            torch.cuda.synchronize()
-            res[mode] = e0.elapsed_time(e1) / steps
+        res = {"default": run(plan, S, G, True)}      # default tiles and radix schedules
+        tuned = plan.autotune(Y, offs, reps=2, cache=False)
+        res["eager"] = run(plan, S, G, False)
+        res["graph"] = run(plan, S, G, True)
         assert plan.last_error() == 0
+        sched = np.array(tuned.pop("schedule"))
+        tuned["schedule_families"] = {p: np.bincount(sched[:, k], minlength=4).tolist()
+                                      for k, p in enumerate(("rows", "columns", "inverse_rows"))}
         padded = [plan.padded(i) for i in range(len(dims))]
-        return res, tiles, batch_bytes(dims, padded, 4, 3), int(sum(a * b for a, b in padded))
+        return res, tuned, batch_bytes(dims, padded, 4, 3), int(sum(a * b for a, b in padded))
 
     taus = [2.0 / n for n, _ in inst]
     res, tiles, nbytes, full_points = timed(dt.BatchPlan(dims, taus, precision="fp32", graph=False))
@@ -513,6 +520,7 @@ def run_batch(steps, warmup):
     line = {"metric": "grid pts/s for S+grad S over a batch of 96 2D instances (n 128-1024)",
             "value": round(nodes / (ms * 1e-3), 1), "unit": "grid pts/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": round(ms, 4), "ms_per_step_eager": round(res["eager"], 4),
+            "ms_per_step_default_tuning": round(res["default"], 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "batch96_2d_n128-1024_K100-20000_tau2h_S_gradS", "instances": len(inst),
                        "nodes": nodes, "tiles": tiles},
@@ -524,7 +532,8 @@ def run_batch(steps, warmup):
     rms = rres["graph"]
     line["reduced_padding"] = {
         "value": round(nodes / (rms * 1e-3), 1), "unit": "grid pts/s", "ms_per_step": round(rms, 4),
-        "ms_per_step_eager": round(rres["eager"], 4), "tiles": rtiles,
+        "ms_per_step_eager": round(rres["eager"], 4), "ms_per_step_default_tuning": round(rres["default"], 4),
+        "tiles": rtiles,
         "padded_points": red_points, "padded_points_full": full_points,
         "path": {"model_bytes": rbytes, "achieved_gbs": round(rbytes / (rms * 1e-3) / 1e9, 1),
                  "frac": round(rbytes / (rms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
@@ -754,7 +763,8 @@ def main():
         "path": {"model_bytes": r32["model_bytes"], "achieved_gbs": round(r32["path_gbs"], 1),
                  "frac": round(r32["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r32["pass_ms"],
                  "pass_gbs": r32["pass_gbs"], "s_max_over_tau": round(r32["s_max_over_tau"], 3),
-                 "plan_setup_s": round(r32["plan_setup_s"], 3), "counters": counter_frac(r32, "fp32")},
+                 "plan_setup_s": round(r32["plan_setup_s"], 3), "plan_tables_s": round(r32["plan_tables_s"], 4),
+                 "counters": counter_frac(r32, "fp32")},
     }
     line["gpu_clocks"] = clocks_after
     line["backward"] = b32
@@ -766,6 +776,7 @@ def main():
                         "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
                                  "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
                                  "pass_gbs": r64["pass_gbs"], "s_max_over_tau": round(r64["s_max_over_tau"], 3),
+                                 "plan_tables_s": round(r64["plan_tables_s"], 4),
                                  "counters": counter_frac(r64, "fp64")},
                         "backward": b64}
     if not args.no_cpu:

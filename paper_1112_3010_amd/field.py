@@ -76,6 +76,20 @@ class Plan:
         self.info = self._info()
         self.dtype = torch.float64 if self.info.precision in (L.DT_FP64, L.DT_FP64X2) else torch.float32
 
+    def rebuild(self):
+        """Attach the same workspace again: the kernel spectra are sampled and
+        transformed anew (the plan-time cost that a new tau pays)."""
+        if self.workspace is None:
+            with torch.cuda.device(self.device):
+                L.check(L.load().dt_plan_set_static_workspace(self._h, _stream(self.device)),
+                        "dt_plan_set_static_workspace")
+            return
+        nbytes = ctypes.c_size_t()
+        L.check(L.load().dt_plan_workspace_size(self._h, ctypes.byref(nbytes)), "dt_plan_workspace_size")
+        base = self.workspace.data_ptr()
+        L.check(L.load().dt_plan_set_workspace(self._h, ctypes.c_void_p(base + (-base) % 256), int(nbytes.value),
+                                               _stream(self.device)), "dt_plan_set_workspace")
+
     def _info(self):
         info = L.DtPlanInfo()
         L.check(L.load().dt_plan_info(self._h, ctypes.byref(info)), "dt_plan_info")
