@@ -149,6 +149,8 @@ typedef struct {
   double unit_roundoff;
   size_t workspace_bytes;
   int n_tables;
+  int64_t k_max;         /* 0: full padding; else the source limit of a reduced plan */
+  int cut[3];            /* kernel truncation box in cells per axis (0: none) */
 } dt_plan_info_t;
 
 typedef struct {
@@ -169,6 +171,27 @@ typedef struct {
 dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
                          const double* origin, double tau, int precision, unsigned out_mask,
                          double trunc_dist, int64_t k_hint, double c_theta);
+
+/* A plan for calls that bring at most k_max sources (k_max >= 1), on a
+ * smaller padded grid (the convolution of Sec. 3 with kernels truncated where
+ * they fall below the rounding floor).  Every call's validity threshold is
+ * at least Theta_low, that of one source on the full padding.  A source
+ * farther than d_cut = tau (ln(c_theta k_max) - ln Theta_low) from a node
+ * adds at most e^(-d_cut/tau) to phi there, so the k_max sources together
+ * lose at most Theta_low / c_theta <= Theta / c_theta: results change only
+ * below the validity threshold (the same bound as the rounding model).  The
+ * kernels are truncated to the box |d_a| <= c_a = ceil(d_cut / h_a) cells,
+ * and axis a is padded to M_a, the smallest power of two (at least 64)
+ * >= n_a + c_a, which keeps a truncated kernel from wrapping onto a node;
+ * where that is not below the full padding the axis keeps it, untruncated
+ * (dt_plan_info reports M_a and c_a, 0 for such an axis).  Precision
+ * DT_FP32_SCALED or DT_FP64 (else DT_E_ARG); out_mask without DT_OUT_SIGN,
+ * whose kernels do not decay (else DT_E_UNSUPPORTED).  Compute calls with
+ * more than k_max sources (points, polygon points or mesh faces) return
+ * DT_E_ARG.  Otherwise as dt_create_plan. Host only. */
+dt_status dt_create_plan_reduced(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                                 const double* origin, double tau, int precision, unsigned out_mask,
+                                 int64_t k_max, double c_theta);
 
 /* Bytes of device workspace the plan needs (256-byte aligned pointer). */
 dt_status dt_plan_workspace_size(dt_plan plan, size_t* bytes);

@@ -20,7 +20,7 @@ DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
 DT_STATIC_WORKSPACE_BYTES = 64 << 20
 
 EXPORTED = (
-    "dt_create_plan", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_set_static_workspace",
+    "dt_create_plan", "dt_create_plan_reduced", "dt_plan_workspace_size", "dt_plan_set_workspace", "dt_plan_set_static_workspace",
     "dt_plan_info", "dt_destroy_plan",
     "dt_distance", "dt_gradient", "dt_hessian", "dt_sign", "dt_forward", "dt_backward",
     "dt_last_error", "dt_last_stats", "dt_plan_set_timing", "dt_plan_timings", "dt_plan_reset_timings",
@@ -71,6 +71,8 @@ class DtPlanInfo(ctypes.Structure):
         ("unit_roundoff", ctypes.c_double),
         ("workspace_bytes", ctypes.c_size_t),
         ("n_tables", ctypes.c_int),
+        ("k_max", ctypes.c_int64),
+        ("cut", ctypes.c_int * 3),
     ]
 
 
@@ -133,6 +135,9 @@ def load():
     vp, i64, dbl, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.dt_create_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), dbl, ctypes.c_int, ctypes.c_uint, dbl, i64, dbl]
+    lib.dt_create_plan_reduced.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(i64),
+                                           ctypes.POINTER(dbl), ctypes.POINTER(dbl), dbl, ctypes.c_int, ctypes.c_uint,
+                                           i64, dbl]
     lib.dt_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.dt_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.dt_plan_set_static_workspace.argtypes = [vp, vp]

@@ -77,6 +77,10 @@ struct dt_plan_s {
   hipStream_t stream = nullptr;
   double kernel_l1 = 0;
   bool ready = false;
+  // reduced padding: calls bring at most k_max sources (0: full padding);
+  // kernels are zero outside the box |d_a| <= cut[a] cells (0: no truncation)
+  int64_t k_max = 0;
+  int cut[3] = {0, 0, 0};
   // workspace = the library's fixed device array (dt_plan_set_static_workspace):
   // the device it lives on and the token that marks this plan as its holder
   int static_dev = -1;
@@ -284,9 +288,9 @@ template <typename T> size_t complex_bytes() { return 2 * sizeof(T); }
 // ---------------------------------------------------------------------------
 // Plan creation
 // ---------------------------------------------------------------------------
-extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
-                                    const double* origin, double tau, int precision, unsigned out_mask,
-                                    double trunc_dist, int64_t k_hint, double c_theta) {
+static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                             const double* origin, double tau, int precision, unsigned out_mask, double trunc_dist,
+                             int64_t k_hint, double c_theta, int64_t k_max) {
   if (!out) return DT_E_ARG;
   *out = nullptr;
   if (ndim != 2 && ndim != 3) return DT_E_ARG;
@@ -314,6 +318,40 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   p->tau = tau;
   p->mask = out_mask;
   p->c_theta = c_theta > 0 ? c_theta : 256.0;
+  if (k_max > 0) {
+    // Every call's Theta is at least Theta_low, the threshold of one source on
+    // the full padding (||g||_2 >= 1, ||f||_1 >= f(0) = 1, and log2(N)/sqrt(N)
+    // falls with N).  Sources farther than d_cut = tau (ln(c_theta k_max) -
+    // ln Theta_low) add at most k_max e^(-d_cut/tau) <= Theta / c_theta to phi,
+    // below what the contract treats as noise: the kernels are truncated to
+    // |d_a| <= c_a = ceil(d_cut / h_a) cells and each axis is padded to the
+    // smallest power of two (at least 64) >= n_a + c_a, so that no truncated
+    // kernel value wraps onto a node, where that is below the full padding.
+    // The winding-number and degree kernels do not decay: they are never truncated.
+    if (out_mask & DT_OUT_SIGN) {
+      delete p;
+      return DT_E_UNSUPPORTED;
+    }
+    if (precision != DT_FP32_SCALED && precision != DT_FP64) {
+      delete p;
+      return DT_E_ARG;
+    }
+    p->k_max = k_max;
+    const double u = precision == DT_FP64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+    const double np_full = p->npad();
+    const double theta_low = p->c_theta * u * std::log2(np_full) / std::sqrt(np_full);
+    const double d_cut = tau * (std::log(p->c_theta * (double)k_max) - std::log(theta_low));
+    for (int a = 0; a < ndim; ++a) {
+      const double c = std::ceil(d_cut / spacing[a]);
+      const int64_t ci = c < 1e9 ? (int64_t)c : (int64_t)1000000000;
+      int64_t m = 64;
+      while (m < dims[a] + ci) m *= 2;
+      if (m < p->M[a]) {
+        p->M[a] = m;
+        p->cut[a] = (int)ci;
+      }
+    }
+  }
 
   if (precision == DT_AUTO) {
     if (!(trunc_dist >= 0) || !std::isfinite(trunc_dist) || k_hint < 1) {
@@ -440,6 +478,19 @@ extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims,
   return DT_OK;
 }
 
+extern "C" dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                                    const double* origin, double tau, int precision, unsigned out_mask,
+                                    double trunc_dist, int64_t k_hint, double c_theta) {
+  return create_plan(out, ndim, dims, spacing, origin, tau, precision, out_mask, trunc_dist, k_hint, c_theta, 0);
+}
+
+extern "C" dt_status dt_create_plan_reduced(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
+                                            const double* origin, double tau, int precision, unsigned out_mask,
+                                            int64_t k_max, double c_theta) {
+  if (k_max < 1) return DT_E_ARG;
+  return create_plan(out, ndim, dims, spacing, origin, tau, precision, out_mask, 0.0, 0, c_theta, k_max);
+}
+
 extern "C" dt_status dt_plan_workspace_size(dt_plan p, size_t* bytes) {
   if (!p || !bytes) return DT_E_ARG;
   *bytes = p->ws_bytes;
@@ -471,6 +522,8 @@ extern "C" dt_status dt_plan_info(dt_plan p, dt_plan_info_t* info) {
   info->unit_roundoff = p->unit();
   info->workspace_bytes = p->ws_bytes;
   info->n_tables = (int)p->tabs.size();
+  info->k_max = p->k_max;
+  for (int a = 0; a < 3; ++a) info->cut[a] = p->cut[a];
   return DT_OK;
 }
 
@@ -501,6 +554,7 @@ template <typename T> dt_status build_tables(dt_plan p, hipStream_t st) {
     tg.M[a] = a < D ? (int)p->M[a] : 1;
     tg.H[a] = a < D ? (int)(p->M[a] / 2 + 1) : 1;
     tg.h[a] = a < D ? p->h[a] : 1.0;
+    tg.cut[a] = a < D ? p->cut[a] : 0;
   }
   double* buf0 = (double*)p->R1p();
   double* buf1 = (double*)p->R2p();
@@ -727,6 +781,8 @@ dt_status run_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shap
     if (s != DT_OK) return s;
   }
   if (rq.dist && Y && K < 1) return DT_E_ARG;
+  // the truncation holds for at most k_max sources
+  if (p->k_max > 0 && rq.dist && (Y ? K : (D == 2 ? shape->n_points : shape->n_faces)) > p->k_max) return DT_E_ARG;
   if (!p->usable()) return DT_E_WORKSPACE;
 
   const int nh = D == 2 ? 3 : 6;
@@ -1017,6 +1073,7 @@ extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const voi
                                  float* dL_dY, double* dL_dtau, void* stream) {
   if (!p || !Y || K < 1 || !S || !dL_dS || !dL_dY) return DT_E_ARG;
   if (!(p->mask & DT_OUT_BACKWARD)) return DT_E_ARG;
+  if (p->k_max > 0 && K > p->k_max) return DT_E_ARG;
   if (p->dd) return DT_E_UNSUPPORTED;
   if (!p->usable()) return DT_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;

@@ -32,11 +32,14 @@ class Plan:
 
     dims, spacing, origin are given x first.  ``outputs`` is an iterable of
     "S", "grad", "hess", "sign", "backward", "curv" (kernel families to
-    prepare; "curv" prepares the gradient and Hessian kernels).
+    prepare; "curv" prepares the gradient and Hessian kernels).  k_max (None
+    or 0: full padding): the most sources a call will bring; a smaller
+    padded grid with truncated kernels, which changes results only below the
+    validity threshold (calls with more sources are refused).
     """
 
     def __init__(self, dims, spacing=None, origin=None, tau=None, precision="fp32", outputs=("S", "grad"),
-                 trunc_dist=0.0, k_hint=0, c_theta=0.0, device="cuda", static_workspace=False):
+                 trunc_dist=0.0, k_hint=0, c_theta=0.0, device="cuda", static_workspace=False, k_max=None):
         lib = L.load()
         self.ndim = len(dims)
         if spacing is None:
@@ -56,8 +59,13 @@ class Plan:
         d = (ctypes.c_int64 * self.ndim)(*self.dims)
         s = (ctypes.c_double * self.ndim)(*self.spacing)
         o = (ctypes.c_double * self.ndim)(*self.origin)
-        L.check(lib.dt_create_plan(ctypes.byref(self._h), self.ndim, d, s, o, self.tau, PRECISIONS[precision],
-                                   mask, float(trunc_dist), int(k_hint), float(c_theta)), "dt_create_plan")
+        if k_max:
+            L.check(lib.dt_create_plan_reduced(ctypes.byref(self._h), self.ndim, d, s, o, self.tau,
+                                               PRECISIONS[precision], mask, int(k_max), float(c_theta)),
+                    "dt_create_plan_reduced")
+        else:
+            L.check(lib.dt_create_plan(ctypes.byref(self._h), self.ndim, d, s, o, self.tau, PRECISIONS[precision],
+                                       mask, float(trunc_dist), int(k_hint), float(c_theta)), "dt_create_plan")
         self.device = torch.device(device)
         if static_workspace:
             # the library's fixed per-device array (no allocation; see dt.h)
@@ -112,6 +120,11 @@ class Plan:
     @property
     def padded(self):
         return tuple(int(self.info.padded[a]) for a in range(self.ndim))
+
+    @property
+    def cut(self):
+        """Kernel truncation box in cells per axis (0: untruncated)."""
+        return tuple(int(self.info.cut[a]) for a in range(self.ndim))
 
     @property
     def precision(self):

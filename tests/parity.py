@@ -45,6 +45,32 @@ def padded(n):
     return m
 
 
+def padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA):
+    """Reduced padding of a single plan for calls with at most k_max sources:
+    Theta_low = the threshold of one source on the full padding (a lower
+    bound of every call's Theta); d_cut = tau (ln(c_theta k_max) - ln
+    Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = the smallest power of
+    two >= max(64, n_a + c_a) where that is below the full padding (else the
+    full padding, untruncated).  Returns ((M_a...), (c_a...)) with c = 0 on
+    a fully padded axis."""
+    full = [padded(n) for n in dims]
+    np_full = float(np.prod([float(m) for m in full]))
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    theta_low = c_theta * u * np.log2(np_full) / np.sqrt(np_full)
+    d_cut = tau * (np.log(c_theta * float(k_max)) - np.log(theta_low))
+    Ms, cuts = [], []
+    for n, h, Mf in zip(dims, spacing, full):
+        c = int(np.ceil(d_cut / h))
+        Mr = 1 << max(6, int(np.ceil(np.log2(n + c))))
+        if Mr < Mf:
+            Ms.append(Mr)
+            cuts.append(c)
+        else:
+            Ms.append(Mf)
+            cuts.append(0)
+    return tuple(Ms), tuple(cuts)
+
+
 def smooth7_at_least(n):
     """Smallest 2^a 3^b 5^c 7^d >= n."""
     m = max(int(n), 1)
@@ -134,6 +160,22 @@ def adjoint_noise(precision, padded_dims, l1, w_l2, c_theta=oracle.C_THETA):
     G/phi in place of the source image: c_theta u log2(N_pad) ||f||_1
     ||w||_2 / sqrt(N_pad) (|u_i| <= f, so ||u_i||_1 <= ||f||_1)."""
     return oracle.theta(precision, padded_dims, l1, w_l2, c_theta)
+
+
+# float64 adjoint: per component, the first-order effect of the forward's
+# per-node error bound (relative error of phi e = TOL_S_TAU_FP64 +
+# TOL_THETA_FRAC theta/phi, the bound the float64 S parity uses) on the node
+# weights G/phi, plus the adjoint correlation's own rounding floor and
+# float32 storage of dL/dY
+STORE32 = 2.0 ** -23
+
+
+def fp64_adjoint_bounds(sens_Y, sens_Y_theta, sens_tau, sens_tau_theta, noise, dY_ref):
+    """Bounds on |dL/dY - ref| (K x D) and |dL/dtau - ref| from the
+    sensitivities of oracle.l2_loss_gradients / source_weight_sums."""
+    bY = (TOL_S_TAU_FP64 * sens_Y + TOL_THETA_FRAC * sens_Y_theta)[:, None] + noise + STORE32 * np.abs(dY_ref)
+    bt = TOL_S_TAU_FP64 * sens_tau + TOL_THETA_FRAC * sens_tau_theta
+    return bY, bt
 
 
 def hess_components(H, D):

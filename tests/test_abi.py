@@ -181,3 +181,61 @@ def test_auto_picks_fp64x2_for_2d_distance(lib):
     lib.dt_destroy_plan(h)
     # with the Hessian requested there is no extended-precision candidate
     assert _plan(lib, dims=dims, tau=tau, prec=2, mask=5, trunc=45 * tau, khint=1000)[0] == 3
+
+
+def _reduced(lib, dims, tau, k_max, prec=0, mask=3, ndim=None):
+    h = ctypes.c_void_p()
+    nd = ndim or len(dims)
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    sp = (ctypes.c_double * len(dims))(*[1.0 / n for n in dims])
+    org = (ctypes.c_double * len(dims))(*([0.0] * len(dims)))
+    return lib.dt_create_plan_reduced(ctypes.byref(h), nd, d, sp, org, tau, prec, mask, k_max, 0.0), h
+
+
+@pytest.mark.parametrize("dims,tau_cells,k_max,prec", [
+    ((200, 200, 200), 2.0, 2000, 0), ((160, 160, 160), 2.0, 2000, 1), ((300, 130, 90), 1.5, 64, 0),
+    ((1000, 1000), 1.0, 5000, 0), ((100, 100), 20.0, 100, 0), ((640, 96), 2.5, 1, 1)])
+def test_reduced_padding_rule(lib, dims, tau_cells, k_max, prec):
+    """The library's reduced padded sizes and truncation boxes follow the
+    documented rule (recomputed in tests/parity.py)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import parity
+    from paper_1112_3010_amd import _lib
+    tau = tau_cells / dims[0]
+    st, h = _reduced(lib, dims, tau, k_max, prec)
+    assert st == 0
+    info = _lib.DtPlanInfo()
+    assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    Mp, cut = parity.padded_reduced(dims, [1.0 / n for n in dims], tau, k_max, "fp64" if prec else "fp32")
+    D = len(dims)
+    assert tuple(info.padded[:D]) == Mp and tuple(info.cut[:D]) == cut and info.k_max == k_max
+    full = tuple(parity.padded(n) for n in dims)
+    assert all(m <= f for m, f in zip(Mp, full))
+    for m, n, c in zip(Mp, dims, cut):
+        assert m >= 64 and m & (m - 1) == 0
+        assert c == 0 or m >= n + c
+    lib.dt_destroy_plan(h)
+
+
+def test_reduced_padding_shrinks_and_refuses(lib):
+    from paper_1112_3010_amd import _lib
+    # 160^3 with tau = 2 cells and 2000 sources: 512^3 -> 256^3
+    st, h = _reduced(lib, (160, 160, 160), 2.0 / 160, 2000)
+    assert st == 0
+    info = _lib.DtPlanInfo()
+    assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    assert tuple(info.padded[:3]) == (256, 256, 256) and all(0 < c <= 96 for c in info.cut[:3])
+    dummy = ctypes.c_void_p(4096)
+    # a call with more sources than k_max is refused before any device work
+    assert lib.dt_distance(h, dummy, 2001, dummy, None) == 1
+    lib.dt_destroy_plan(h)
+    assert _reduced(lib, (64, 64), 0.03, 0)[0] == 1                  # k_max >= 1
+    assert _reduced(lib, (64, 64), 0.03, 10, prec=2)[0] == 1         # AUTO
+    assert _reduced(lib, (64, 64), 0.03, 10, prec=3)[0] == 1         # double-double
+    assert _reduced(lib, (64, 64), 0.03, 10, mask=1 | 8)[0] == 6     # sign kernels do not decay
+    # a wide kernel keeps the full padding, untruncated
+    st, h = _reduced(lib, (100, 100), 0.5, 10)
+    assert st == 0 and lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    assert tuple(info.padded[:2]) == (256, 256) and tuple(info.cut[:2]) == (0, 0)
+    lib.dt_destroy_plan(h)

@@ -219,19 +219,6 @@ def test_mesh_256_sign(dt, c3, prec):
 # float32 bar of the contract: relative L2 error of dL/dY and relative error
 # of dL/dtau
 TOL_ADJ_FP32 = 1e-3
-# float64: per component, the first-order effect of the forward's per-node
-# error bound (relative error of phi e = TOL_S_TAU_FP64 + TOL_THETA_FRAC
-# theta/phi, the bound the float64 S parity uses) on the node weights
-# G/phi, plus the adjoint correlation's own rounding floor and float32
-# storage of dL/dY
-STORE32 = 2.0 ** -23
-
-
-def _fp64_adjoint_bounds(sens_Y, sens_Y_theta, sens_tau, sens_tau_theta, noise, dY_ref):
-    bY = (parity.TOL_S_TAU_FP64 * sens_Y + parity.TOL_THETA_FRAC * sens_Y_theta)[:, None] \
-        + noise + STORE32 * np.abs(dY_ref)
-    bt = parity.TOL_S_TAU_FP64 * sens_tau + parity.TOL_THETA_FRAC * sens_tau_theta
-    return bY, bt
 
 
 def _c5_tau32(w, Yh, h, Mp, g_l2):
@@ -325,7 +312,7 @@ def test_adjoint_128_full_grid(dt, prec):
         return
     w_l2 = float(np.sqrt(np.sum((G[valid] * np.exp(-c["lnphi"][valid])) ** 2)))
     noise = parity.adjoint_noise("fp64", c["Mp"], c["l1"], w_l2)
-    bY, bt = _fp64_adjoint_bounds(acc["sens_Y"], acc["sens_Y_theta"], acc["sens_tau"], acc["sens_tau_theta"],
+    bY, bt = parity.fp64_adjoint_bounds(acc["sens_Y"], acc["sens_Y_theta"], acc["sens_tau"], acc["sens_tau_theta"],
                                   noise, dY_ref)
     rY = float((np.abs(dY - dY_ref) / bY).max())
     rt = abs(dtau - dtau_ref) / bt
@@ -388,7 +375,7 @@ def test_backward_256_bench_configuration(dt, c3, prec, radius):
     tw = 1.0 + 2.0 * ref["rmean"] / tau
     w_l2 = float(np.sqrt(np.sum((Gs * np.exp(-lnphi)) ** 2)))
     noise = parity.adjoint_noise("fp64", ref["padded"], ref["kernel_l1"], w_l2)
-    bY, bt = _fp64_adjoint_bounds(sens[:, 0], sens[:, 1], float(aG @ tw), float((aG * ratio) @ tw), noise, dY_ref)
+    bY, bt = parity.fp64_adjoint_bounds(sens[:, 0], sens[:, 1], float(aG @ tw), float((aG * ratio) @ tw), noise, dY_ref)
     rY = float((np.abs(dY - dY_ref) / bY).max())
     rt = abs(dtau - dtau_ref) / bt
     print(f"\n{msg} max|ddY|/bound={rY:.3f} |ddtau|/bound={rt:.3f}", flush=True)
