@@ -279,12 +279,12 @@ def backward_bytes(dims, Mp, w, K):
     return b
 
 
-def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
+def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls, k_max=None):
     """Time dt_backward on the 256^3 grid with the mesh's triangle centres as
     sources and dL/dS = S (the loss S^2 / 2)."""
     import torch
     import paper_1112_3010_amd as dt
-    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "backward"])
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "backward"], k_max=k_max)
     Yd = torch.from_numpy(Y).cuda()
     S = plan.distance(Yd)
     G = S.clone()
@@ -306,7 +306,7 @@ def run_backward(prec, Y, dims, tau, steps, warmup, timing_calls):
     total = sum(nbytes.values())
     N = int(np.prod(dims))
     res = {"value": round(N / (ms * 1e-3), 1), "unit": "grid pts/s", "ms_per_call": round(ms, 4),
-           "ms_stats": ms_stats, "sources": len(Y),
+           "ms_stats": ms_stats, "sources": len(Y), "padded": list(plan.padded),
            "roofline": roofline_entry(nbytes, avg, launches, dom),
            "path": {"model_bytes": total, "achieved_gbs": round(total / (ms * 1e-3) / 1e9, 1),
                     "frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -665,37 +665,49 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
 
 
 def run_reduced(steps, warmup, timing_calls, no_cpu, cpu_cells):
-    """A grid whose full padding is far from tight: 180^3 nodes pad to 512^3
-    (the next power of two >= 2n).  With the call's source count known (the
-    mesh's triangles), the plan pads to 256^3 with truncated kernels; both
-    plans run on the same mesh and their fields are compared with the oracle
+    """The 256^3 mesh workload with its source count known to the plan
+    (k_max = the 60 000 triangles): y and z pad to 288 instead of 512 with
+    kernels truncated where they fall below the rounding floor (x keeps 512:
+    256 + c exceeds 256 and the row passes have power-of-two engines only).
+    Forward S+grad S and the backward, each beside the fully padded plan on
+    the same inputs; the forward fields of both are compared with the oracle
     on a node sample."""
     import synth
-    n = 180
+    n = 256
     dims = (n, n, n)
     tau = 1.0 / n
     V, F = synth.harmonic_star_mesh(seed=3)
-    log(f"workload: 180^3, {len(F)} triangles, tau = h, full vs reduced padding")
+    log(f"workload: 256^3, {len(F)} triangles, tau = h, full vs reduced padding")
     cells = sample_cells(dims, cpu_cells, seed=1)
     full = run_gpu("fp32", V, F, dims, tau, steps, warmup, timing_calls, cells)
     log("fp32 full padding:", json.dumps({k: v for k, v in full.items() if not k.startswith("sample_")}))
     red = run_gpu("fp32", V, F, dims, tau, steps, warmup, timing_calls, cells, k_max=len(F))
     log("fp32 reduced padding:", json.dumps({k: v for k, v in red.items() if not k.startswith("sample_")}))
+    Yc = triangle_centres(V, F)
+    bsteps = max(5, steps // 2)
+    b_full = run_backward("fp32", Yc, dims, tau, bsteps, warmup, timing_calls)
+    b_red = run_backward("fp32", Yc, dims, tau, bsteps, warmup, timing_calls, k_max=len(F))
+    log("fp32 backward full / reduced:", json.dumps(b_full), json.dumps(b_red))
     line = {
         "metric": METRIC, "value": round(red["value"], 1), "unit": "grid pts/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": round(red["ms_per_step"], 4), "ms_stats": red["ms_stats"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "3d_180cube_mesh60000_tau1h_S_gradS_reduced_padding", "grid": list(dims),
+        "config": {"workload": "3d_256cube_mesh60000_tau1h_S_gradS_reduced_padding", "grid": list(dims),
                    "padded": red["padded"], "cut": red["cut"], "k_max": int(len(F)), "sources": int(len(F)),
                    "tau_over_h": 1.0, "precision": "fp32_scaled"},
         "roofline": roofline_entry(red["pass_bytes"], red["pass_ms"], red["launches"], red["dominant"]),
         "path": {"model_bytes": red["model_bytes"], "achieved_gbs": round(red["path_gbs"], 1),
-                 "pass_ms": red["pass_ms"], "s_max_over_tau": round(red["s_max_over_tau"], 3),
+                 "frac": round(red["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": red["pass_ms"],
+                 "pass_gbs": red["pass_gbs"], "s_max_over_tau": round(red["s_max_over_tau"], 3),
                  "plan_setup_s": round(red["plan_setup_s"], 3), "plan_tables_s": round(red["plan_tables_s"], 4)},
         "full_padding": {"value": round(full["value"], 1), "ms_per_step": round(full["ms_per_step"], 4),
                          "padded": full["padded"], "pass_ms": full["pass_ms"],
-                         "plan_tables_s": round(full["plan_tables_s"], 4)},
+                         "s_max_over_tau": round(full["s_max_over_tau"], 3)},
         "speedup_vs_full_padding": round(full["ms_per_step"] / red["ms_per_step"], 3),
+        "backward": b_red,
+        "backward_full_padding": {"ms_per_call": b_full["ms_per_call"], "padded": b_full["padded"],
+                                  "path": b_full["path"]},
+        "backward_speedup_vs_full_padding": round(b_full["ms_per_call"] / b_red["ms_per_call"], 3),
     }
     if not no_cpu:
         cb, acc = cpu_baseline(V, F, dims, tau, cells, [("fp32_reduced", "fp32", red), ("fp32_full", "fp32", full)])
@@ -718,7 +730,7 @@ def main():
     ap.add_argument("--workload", choices=["mesh256", "batch", "protocol", "dd", "reduced"], default="mesh256",
                     help="mesh256: the 256^3 mesh headline (default); batch: 96 mixed-size 2D instances; "
                          "protocol: Example 1 of Sec. 6.1 against Table 2; dd: 1024^2 polygon S in double-double; "
-                         "reduced: 180^3 mesh grid, full against reduced padding")
+                         "reduced: the 256^3 mesh with k_max reduced padding, beside full padding")
     ap.add_argument("--trials", type=int, default=200, help="trials per tau of --workload protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (3 times) to calibrate HBM traffic counters, then exit")

@@ -174,17 +174,20 @@ dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const doub
 
 /* A plan for calls that bring at most k_max sources (k_max >= 1), on a
  * smaller padded grid (the convolution of Sec. 3 with kernels truncated where
- * they fall below the rounding floor).  Every call's validity threshold is
- * at least Theta_low, that of one source on the full padding.  A source
- * farther than d_cut = tau (ln(c_theta k_max) - ln Theta_low) from a node
- * adds at most e^(-d_cut/tau) to phi there, so the k_max sources together
- * lose at most Theta_low / c_theta <= Theta / c_theta: results change only
- * below the validity threshold (the same bound as the rounding model).  The
- * kernels are truncated to the box |d_a| <= c_a = ceil(d_cut / h_a) cells,
- * and axis a is padded to M_a, the smallest power of two (at least 64)
- * >= n_a + c_a, which keeps a truncated kernel from wrapping onto a node;
- * where that is not below the full padding the axis keeps it, untruncated
- * (dt_plan_info reports M_a and c_a, 0 for such an axis).  Precision
+ * they fall below the rounding floor).  A call with K sources in the grid
+ * has ||g||_2 >= sqrt(K) (integer multiplicities), so its validity threshold
+ * is at least sqrt(K) Theta_low, Theta_low that of one source on the full
+ * padding.  A source farther than d_cut = tau (ln(c_theta sqrt(k_max))
+ * - ln Theta_low) from a node adds at most e^(-d_cut/tau) to phi there, so
+ * the K sources together lose at most sqrt(K) Theta_low / c_theta <=
+ * Theta / c_theta: results change only below the validity threshold (the
+ * same bound as the rounding model).  The kernels are truncated to the box
+ * |d_a| <= c_a = ceil(d_cut / h_a) cells, and axis a is padded to M_a, the
+ * smallest length >= max(64, n_a + c_a) among the powers of two and, for
+ * y and z (the column axes), 288; that keeps a truncated kernel from
+ * wrapping onto a node.  Where M_a is not below the full padding the axis
+ * keeps it, untruncated (dt_plan_info reports M_a and c_a, 0 for such an
+ * axis).  Precision
  * DT_FP32_SCALED or DT_FP64 (else DT_E_ARG); out_mask without DT_OUT_SIGN,
  * whose kernels do not decay (else DT_E_UNSUPPORTED).  Compute calls with
  * more than k_max sources (points, polygon points or mesh faces) return
@@ -308,14 +311,15 @@ typedef struct {
   /* 0: linear-convolution padding M_a = 2 s_a, s_a the smallest 7-smooth
    * number >= n_a.  > 0: reduced padding for calls with at most k_max sources
    * in this instance.  The kernels are truncated to the box |d_a| <= c_a
-   * cells, c_a = ceil(d_cut / h_a) with d_cut = tau (ln(c_theta k_max)
-   * - ln Theta_low), Theta_low the validity threshold for one source on the
-   * full padding (a lower bound of every call's Theta).  The padded length
+   * cells, c_a = ceil(d_cut / h_a) with d_cut = tau (ln(c_theta
+   * sqrt(k_max)) - ln Theta_low), Theta_low the validity threshold for one
+   * source on the full padding (a call with K sources has ||g||_2 >=
+   * sqrt(K), so its Theta is at least sqrt(K) Theta_low).  The padded length
    * is M_a = 2 s'_a, s'_a the smallest 7-smooth number >= (n_a + c_a) / 2,
-   * and at most the full one.  The sources a truncated kernel drops add at most
-   * k_max e^(-d_cut/tau) <= Theta / c_theta to phi, so results change only
-   * below the validity threshold.  A call with more sources in the instance
-   * returns DT_E_ARG. */
+   * and at most the full one.  The K sources a truncated kernel drops add at
+   * most K e^(-d_cut/tau) <= sqrt(K) Theta_low / c_theta <= Theta / c_theta
+   * to phi, so results change only below the validity threshold.  A call
+   * with more sources in the instance returns DT_E_ARG. */
   int64_t k_max;
 } dt_instance_desc;
 

@@ -521,14 +521,16 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     int64_t My = 2 * smooth7_at_least(q.dims[1]);
     int cut[2] = {0, 0};
     if (q.k_max > 0) {
-      // Reduced padding: the validity threshold of one source on the full
-      // padding bounds every call's Theta from below (||g||_2 >= 1,
-      // ||f||_1 >= f(0) = 1, log2(N)/sqrt(N) falls with N); the truncation
-      // distance then keeps the dropped sources below Theta / c_theta.
+      // Reduced padding: a call with K <= k_max sources in the instance has
+      // Theta >= sqrt(K) Theta_low, Theta_low the validity threshold of one
+      // source on the full padding (||g||_2 >= sqrt(K) for integer
+      // multiplicities, ||f||_1 >= f(0) = 1, log2(N)/sqrt(N) falls with N);
+      // the truncation distance then keeps the K dropped tails below
+      // sqrt(K) Theta_low / c_theta <= Theta / c_theta.
       const double np_full = (double)(2 * sx) * (double)My;
       const double theta_low = p->c_theta * (p->fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24)) *
                                std::log2(np_full) / std::sqrt(np_full);
-      const double d_cut = q.tau * (std::log(p->c_theta * (double)q.k_max) - std::log(theta_low));
+      const double d_cut = q.tau * (std::log(p->c_theta * std::sqrt((double)q.k_max)) - std::log(theta_low));
       for (int a = 0; a < 2; ++a) {
         const double c = std::ceil(d_cut / q.spacing[a]);
         cut[a] = c < 1e9 ? (int)c : 1000000000;

@@ -73,6 +73,21 @@ template <int DIR, typename V> struct Bfly<2, DIR, V> {
   }
 };
 
+// 3-point DFT: y0 = a0 + t, y1,2 = a0 - t/2 -+ i DIR (sqrt(3)/2) d with
+// t = a1 + a2, d = a1 - a2 (the roots of unity exp(-+2 pi i DIR / 3)).
+template <int DIR, typename V> struct Bfly<3, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) {
+    using T = decltype(V::x);
+    const T h = T(0.86602540378443864676372317075293618347);   // sqrt(3) / 2
+    const V t = cadd(a[1], a[2]), d = csub(a[1], a[2]);
+    const V m = mk<V>(a[0].x - T(0.5) * t.x, a[0].y - T(0.5) * t.y);
+    const V s = DIR > 0 ? mk<V>(h * d.y, -h * d.x) : mk<V>(-h * d.y, h * d.x);
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(m, s);
+    a[2] = csub(m, s);
+  }
+};
+
 template <int DIR, typename V> struct Bfly<4, DIR, V> {
   static __device__ __forceinline__ void run(V* a) {
     V s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);

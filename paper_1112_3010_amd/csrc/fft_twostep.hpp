@@ -103,10 +103,11 @@ template <int DIR, int M, int R, typename V> __device__ __forceinline__ V cmul_w
   }
 }
 
-// In-register DFT of size R, natural order in and out (R = 2..64, power of
-// two): R = R1 x R2 Cooley-Tukey with compile-time twiddles W_R^(n1 k2).
+// In-register DFT of size R, natural order in and out (R = 2..64, a power
+// of two, or 12): R = R1 x R2 Cooley-Tukey with compile-time twiddles
+// W_R^(n1 k2).
 template <int R, int DIR, typename V> struct RegDFT {
-  static constexpr int R1 = R >= 32 ? 8 : 4;  // 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
+  static constexpr int R1 = R >= 32 ? 8 : 4;  // 12 = 4 x 3, 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
   static constexpr int R2 = R / R1;
 
   template <int N1, int K2> static __device__ __forceinline__ void twiddle(const V* t, V* b) {
@@ -149,7 +150,7 @@ template <int R, int DIR, typename V> struct RegDFT {
 template <typename T, int N, int E> struct ThreadTwiddles {
   using V = Cx<T>;
   static constexpr bool NEEDS_BARRIER = false;
-  static constexpr int NB8 = E / 8;
+  static constexpr int NB8 = (E + 7) / 8;
   V A[8];
   V B[NB8 > 0 ? NB8 : 1];
   __device__ __forceinline__ void load(const V* tw, int p) {
@@ -301,7 +302,8 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
 };
 
 // ---------------------------------------------------------------------------
-// Pair-split four-step FFT for N = E * P with P = 2E (32, 128, 512, 2048).
+// Pair-split four-step FFT for N = E * P with P = 2E (32, 128, 288, 512,
+// 2048).
 //
 // Thread p < P of a column holds x[p + P e] (e < E).  Step 1: size-E DFT in
 // registers and the thread twiddles W_N^(p k1).  One LDS exchange gives
@@ -317,7 +319,7 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
 // real LDS buffer of LDS elements.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int pair_E(int N) {
-  return N == 32 ? 4 : N == 128 ? 8 : N == 512 ? 16 : N == 2048 ? 32 : 0;
+  return N == 32 ? 4 : N == 128 ? 8 : N == 288 ? 12 : N == 512 ? 16 : N == 2048 ? 32 : 0;
 }
 
 template <typename T, int N, int NB, int SPLIT = 0, bool TWL = false> struct PairFFT {

@@ -241,9 +241,12 @@ template <typename T> constexpr bool fused_twl() { return sizeof(T) == 8; }
 template <typename T, int N> constexpr int fused_minwaves() { return sizeof(T) == 8 && N == 512 ? 2 : 1; }
 
 // The float64 strided C2C passes use the pair-split engine at these lengths
-// (in float32 the two-step kernel with 16-column tiles streams faster).
+// (in float32 the two-step kernel with 16-column tiles streams faster); 288
+// has only the pair-split factorisation.
 constexpr int kPairNB = 8;
-template <typename T> constexpr bool c2c_pair(int N) { return sizeof(T) == 8 && (N == 128 || N == 512); }
+template <typename T> constexpr bool c2c_pair(int N) {
+  return N == 288 || (sizeof(T) == 8 && (N == 128 || N == 512));
+}
 // The pair-split engine serves the 3D fused pass where N = 2 E^2.
 template <typename T> constexpr bool fused_pair(int N) { return pair_E(N) > 0 && N >= 128 && N <= 512; }
 
@@ -510,7 +513,7 @@ int col2_tile_width(int N, bool fp64, bool fused) {
   return fp64 ? twostep_NB<double>() : twostep_NB<float>();
 }
 
-#define DT_FOR_EACH_COL2_N(X) X(64) X(128) X(256) X(512) X(1024)
+#define DT_FOR_EACH_COL2_N(X) X(64) X(128) X(256) X(288) X(512) X(1024)
 
 template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
                                            int outer, int chans, hipStream_t st) {
@@ -529,7 +532,7 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
     else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
     return true;                                                                                          \
   }
-      CASEP(128) CASEP(512)
+      CASEP(128) CASEP(288) CASEP(512)
 #undef CASEP
       default: break;
     }
@@ -570,7 +573,7 @@ template <typename T> bool launch_col2_fused(const void* in, void* out, const Co
   case NN: {                                                                                              \
     constexpr int E = twostep_E<T, true>(NN);                                                             \
     constexpr int NB = twostep_NB<T, true>();                                                             \
-    if (p.outer_len > 1) {                                                                                \
+    if (p.outer_len > 1 || (E == 0 && fused_pair<T>(NN))) {                                              \
       if constexpr (fused_pair<T>(NN)) {                                                                     \
         using ENG = PairFFT<T, NN, NB, fused_split<T>(), fused_twl<T>()>;                                 \
         constexpr int NT = ENG::P * NB;                                                                   \

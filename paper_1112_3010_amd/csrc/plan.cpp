@@ -28,6 +28,16 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Reduced padded length: the smallest length >= need (at least 64) that the
+// passes have engines for: powers of two, and 288 = 2 * 12^2 for the column
+// axes (pair-split register engine).
+int64_t reduced_length(int64_t need, bool column) {
+  int64_t m = 64;
+  while (m < need) m *= 2;
+  if (column && need <= 288 && 288 < m) m = 288;
+  return m;
+}
+
 int64_t pad_length(int64_t n) {
   int64_t m = 64;
   while (m < 2 * n) m *= 2;
@@ -319,14 +329,16 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   p->mask = out_mask;
   p->c_theta = c_theta > 0 ? c_theta : 256.0;
   if (k_max > 0) {
-    // Every call's Theta is at least Theta_low, the threshold of one source on
-    // the full padding (||g||_2 >= 1, ||f||_1 >= f(0) = 1, and log2(N)/sqrt(N)
-    // falls with N).  Sources farther than d_cut = tau (ln(c_theta k_max) -
-    // ln Theta_low) add at most k_max e^(-d_cut/tau) <= Theta / c_theta to phi,
-    // below what the contract treats as noise: the kernels are truncated to
-    // |d_a| <= c_a = ceil(d_cut / h_a) cells and each axis is padded to the
-    // smallest power of two (at least 64) >= n_a + c_a, so that no truncated
-    // kernel value wraps onto a node, where that is below the full padding.
+    // A call with K <= k_max sources inside the grid has ||g||_2 >= sqrt(K)
+    // (integer multiplicities), ||f||_1 >= f(0) = 1, and log2(N)/sqrt(N) falls
+    // with N, so its Theta is at least sqrt(K) Theta_low, Theta_low the
+    // threshold of one source on the full padding.  Sources farther than
+    // d_cut = tau (ln(c_theta sqrt(k_max)) - ln Theta_low) add at most
+    // K e^(-d_cut/tau) <= sqrt(K) Theta_low / c_theta <= Theta / c_theta to
+    // phi, below what the contract treats as noise: the kernels are truncated
+    // to |d_a| <= c_a = ceil(d_cut / h_a) cells and each axis is padded to the
+    // smallest length with an engine >= n_a + c_a (so that no truncated kernel
+    // value wraps onto a node), where that is below the full padding.
     // The winding-number and degree kernels do not decay: they are never truncated.
     if (out_mask & DT_OUT_SIGN) {
       delete p;
@@ -340,12 +352,11 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     const double u = precision == DT_FP64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
     const double np_full = p->npad();
     const double theta_low = p->c_theta * u * std::log2(np_full) / std::sqrt(np_full);
-    const double d_cut = tau * (std::log(p->c_theta * (double)k_max) - std::log(theta_low));
+    const double d_cut = tau * (std::log(p->c_theta * std::sqrt((double)k_max)) - std::log(theta_low));
     for (int a = 0; a < ndim; ++a) {
       const double c = std::ceil(d_cut / spacing[a]);
       const int64_t ci = c < 1e9 ? (int64_t)c : (int64_t)1000000000;
-      int64_t m = 64;
-      while (m < dims[a] + ci) m *= 2;
+      const int64_t m = reduced_length(dims[a] + ci, a > 0);
       if (m < p->M[a]) {
         p->M[a] = m;
         p->cut[a] = (int)ci;

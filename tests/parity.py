@@ -47,21 +47,23 @@ def padded(n):
 
 def padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA):
     """Reduced padding of a single plan for calls with at most k_max sources:
-    Theta_low = the threshold of one source on the full padding (a lower
-    bound of every call's Theta); d_cut = tau (ln(c_theta k_max) - ln
-    Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = the smallest power of
-    two >= max(64, n_a + c_a) where that is below the full padding (else the
-    full padding, untruncated).  Returns ((M_a...), (c_a...)) with c = 0 on
-    a fully padded axis."""
+    Theta_low = the threshold of one source on the full padding (a call with
+    K sources has Theta >= sqrt(K) Theta_low); d_cut = tau (ln(c_theta
+    sqrt(k_max)) - ln Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = the
+    smallest length >= max(64, n_a + c_a) among the powers of two and, for
+    the column axes y and z, 288, where that is below the full padding (else
+    the full padding, untruncated).  Returns ((M_a...), (c_a...)) with c = 0
+    on a fully padded axis."""
     full = [padded(n) for n in dims]
     np_full = float(np.prod([float(m) for m in full]))
     u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
     theta_low = c_theta * u * np.log2(np_full) / np.sqrt(np_full)
-    d_cut = tau * (np.log(c_theta * float(k_max)) - np.log(theta_low))
+    d_cut = tau * (np.log(c_theta * np.sqrt(float(k_max))) - np.log(theta_low))
     Ms, cuts = [], []
-    for n, h, Mf in zip(dims, spacing, full):
+    for axis, (n, h, Mf) in enumerate(zip(dims, spacing, full)):
         c = int(np.ceil(d_cut / h))
-        Mr = 1 << max(6, int(np.ceil(np.log2(n + c))))
+        lengths = [1 << e for e in range(6, 13)] + ([288] if axis > 0 else [])
+        Mr = min(m for m in lengths if m >= n + c)
         if Mr < Mf:
             Ms.append(Mr)
             cuts.append(c)
@@ -92,16 +94,17 @@ def batch_padded(n):
 def batch_padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA):
     """Reduced padding rule of the batched path for calls with at most k_max
     sources: the validity threshold of one source on the full padding bounds
-    every call's Theta from below; d_cut = tau (ln(c_theta k_max) - ln
-    Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = 2 s, s the smallest
-    7-smooth >= (n_a + c_a) / 2, unless that is not below the full padding
-    (then full padding and no truncation on that axis).  Returns
+    every call's Theta from below, times sqrt(K) for K sources; d_cut = tau
+    (ln(c_theta sqrt(k_max)) - ln Theta_low); c_a = ceil(d_cut / h_a) cells;
+    M_a = 2 s, s the smallest 7-smooth >= (n_a + c_a) / 2, unless that is
+    not below the full padding (then full padding and no truncation on that
+    axis).  Returns
     ((M_x, M_y), (c_x, c_y)) with c = 0 on a fully padded axis."""
     full = [batch_padded(n) for n in dims]
     np_full = float(full[0]) * float(full[1])
     u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
     theta_low = c_theta * u * np.log2(np_full) / np.sqrt(np_full)
-    d_cut = tau * (np.log(c_theta * float(k_max)) - np.log(theta_low))
+    d_cut = tau * (np.log(c_theta * np.sqrt(float(k_max))) - np.log(theta_low))
     Ms, cuts = [], []
     for n, h, Mf in zip(dims, spacing, full):
         c = int(np.ceil(d_cut / h))

@@ -51,7 +51,7 @@ def _cells(dims, pts, n_uniform, n_near, seed):
     return np.unique(np.concatenate([a, pick[:, 0] + nx * pick[:, 1]]))
 
 
-def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats, Mp=None):
+def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats, Mp=None, theta_rel=1e-9):
     nx, ny = dims
     h = (1.0 / nx, 1.0 / ny)
     if len(pts) == 0:
@@ -61,7 +61,7 @@ def _check_instance(tag, prec, dims, tau, pts, S, G, cells, stats, Mp=None):
     if Mp is None:
         Mp = (parity.batch_padded(nx), parity.batch_padded(ny))
     ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, prec, grad=True, cells=cells, padded_dims=Mp)
-    assert stats["theta"] == pytest.approx(ref["theta"], rel=1e-9), tag
+    assert stats["theta"] == pytest.approx(ref["theta"], rel=theta_rel), tag
     S = S.ravel()[cells] if cells is not None else S.ravel()
     g = G.reshape(2, -1)[:, cells] if cells is not None else G.reshape(2, -1)
     dS = np.abs(S - ref["S_ref"])
@@ -245,8 +245,10 @@ def test_batch_reduced_padding_against_oracle(dt, prec):
     torch.cuda.synchronize()
     assert plan.last_error() == 0
     for i, ((Si, Gi), dims) in enumerate(zip(plan.views(S, G), RED_DIMS)):
+        # Theta: the truncated kernel's l1 norm lacks the tail beyond the box
+        # (about 1e-9 relative here); the oracle's is the untruncated sum
         msg = _check_instance(f"reduced {i} {dims} M={Mps[i]}", prec, dims, taus[i], pts[i], _np(Si), _np(Gi), None,
-                              plan.stats(i), Mp=Mps[i])
+                              plan.stats(i), Mp=Mps[i], theta_rel=1e-7)
         print("\n" + msg)
     # more sources than k_max in an instance is refused
     more = [synth.generators.uniform_points(2, K + (1 if i == 1 else 0), seed=950 + i) for i, K in enumerate(RED_K)]

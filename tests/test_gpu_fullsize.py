@@ -152,15 +152,30 @@ def c3():
     return w, Yh, Pk, idx
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_mesh_256_bench_configuration(dt, c3, prec):
-    """S and grad S exactly as the benchmark computes them (forward_into,
-    outputs S+grad, mesh given as vertices and faces)."""
-    w, Yh, Pk, idx = c3
+def _c3_plan(dt, w, prec, outputs, reduced):
+    """The benchmark's 256^3 plan; reduced: k_max = the mesh's triangle count,
+    which pads y and z to 288 (the pair-split engine at N = 2 * 12^2) in
+    float32 and truncates the kernels there."""
     dims = w.dims
     h = (1.0 / dims[0],) * 3
     tau = h[0]
-    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "grad"])
+    k_max = len(w.faces) if reduced else None
+    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=outputs, k_max=k_max)
+    if reduced:
+        Mp, cut = parity.padded_reduced(dims, h, tau, k_max, prec)
+        assert plan.padded == Mp == (512, 288, 288) and plan.cut == cut
+    else:
+        assert plan.padded == (512, 512, 512)
+    return plan, dims, h, tau
+
+
+@pytest.mark.parametrize("prec,reduced", [("fp32", False), ("fp64", False), ("fp32", True)])
+def test_mesh_256_bench_configuration(dt, c3, prec, reduced):
+    """S and grad S exactly as the benchmark computes them (forward_into,
+    outputs S+grad, mesh given as vertices and faces), with full and with
+    reduced padding."""
+    w, Yh, Pk, idx = c3
+    plan, dims, h, tau = _c3_plan(dt, w, prec, ["S", "grad"], reduced)
     Vd, Fd = torch.from_numpy(w.vertices).cuda(), torch.from_numpy(w.faces).cuda()
     out = {"S": plan._empty(), "grad": plan._empty(3)}
     for _ in range(2):      # a repeated call gives the same fields
@@ -168,11 +183,13 @@ def test_mesh_256_bench_configuration(dt, c3, prec):
     torch.cuda.synchronize()
     assert plan.last_error() == 0
     cells = _sample_cells(dims, idx, 600, 900, 5, seed=31)
-    ref = parity.reference(dims, h, (0.0,) * 3, tau, Yh.astype(np.float32), prec, grad=True, cells=cells)
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, Yh.astype(np.float32), prec, grad=True, cells=cells,
+                           padded_dims=plan.padded)
     S = _np(out["S"]).ravel()[cells]
     g = _np(out["grad"]).reshape(3, -1)[:, cells]
-    _check_fields("mesh 256^3", prec, tau, h, S, g, None, ref)
-    assert plan.last_stats()["theta"] == pytest.approx(ref["theta"], rel=1e-9)
+    _check_fields("mesh 256^3" + (" reduced" if reduced else ""), prec, tau, h, S, g, None, ref)
+    # the truncated kernels' l1 norm differs from the full one in the 8th digit at most
+    assert plan.last_stats()["theta"] == pytest.approx(ref["theta"], rel=1e-7 if reduced else 1e-9)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -326,19 +343,18 @@ def test_adjoint_128_full_grid(dt, prec):
 # padded 512^3, pair-split fused pass, 512-wide gather)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,radius", [("fp32", 10), ("fp64", 30)])
-def test_backward_256_bench_configuration(dt, c3, prec, radius):
+@pytest.mark.parametrize("prec,radius,reduced", [("fp32", 10, False), ("fp64", 30, False), ("fp32", 10, True)])
+def test_backward_256_bench_configuration(dt, c3, prec, radius, reduced):
     """dt_backward on the benchmark's 256^3 workload.  G is seeded normal on a
     node sample: uniform over the grid plus nodes within `radius` cells of the
     sources (out to and past the validity band's edge, about 7 tau in float32
     and 27 tau in float64), leaving out the shell phi in [Theta/2, 2 Theta]
-    where either side may call a node valid."""
+    where either side may call a node valid.  Full and reduced padding."""
     w, Yh, Pk, idx = c3
-    dims = w.dims
-    h = (1.0 / dims[0],) * 3
-    tau = h[0]
+    plan, dims, h, tau = _c3_plan(dt, w, prec, ["S", "backward"], reduced)
     cells = _sample_cells(dims, idx, 800, 2400, radius, seed=61 + radius)
-    ref = parity.reference(dims, h, (0.0,) * 3, tau, Yh.astype(np.float32), prec, cells=cells, rmean=True)
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, Yh.astype(np.float32), prec, cells=cells, rmean=True,
+                           padded_dims=plan.padded)
     lnphi = ref["lnphi"]
     keep = ref["valid"] & (np.abs(lnphi - np.log(ref["theta"])) >= np.log(2.0))
     edge = keep & (lnphi < np.log(ref["theta"]) + np.log(100.0))
@@ -346,7 +362,6 @@ def test_backward_256_bench_configuration(dt, c3, prec, radius):
     Gs = np.where(keep, rng.standard_normal(len(cells)), 0.0)
     G = np.zeros(int(np.prod(dims)))
     G[cells] = Gs
-    plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=["S", "backward"])
     Y = torch.from_numpy(Yh.astype(np.float32)).cuda()
     S = plan.distance(Y)
     Gt = torch.from_numpy(G).to(plan.dtype).cuda().reshape(plan.shape)
@@ -360,7 +375,7 @@ def test_backward_256_bench_configuration(dt, c3, prec, radius):
     dY_ref, dtau_ref = oracle.loss_gradients(ref["X"], ref["Yhat"], tau, Gs, ref["valid"], workers=parity.WORKERS)
     e_y = float(np.linalg.norm(dY - dY_ref) / np.linalg.norm(dY_ref))
     e_t = abs(dtau - dtau_ref) / abs(dtau_ref)
-    msg = (f"[backward 256^3 {prec}] G on {int(keep.sum())} nodes ({int(edge.sum())} within 100 Theta of the "
+    msg = (f"[backward 256^3 {prec}{' reduced' if reduced else ''}] G on {int(keep.sum())} nodes ({int(edge.sum())} within 100 Theta of the "
            f"band edge) rel L2 dL/dY={e_y:.3e} rel dL/dtau={e_t:.3e}")
     assert edge.sum() >= 50, msg
     if prec == "fp32":

@@ -37,13 +37,17 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def _plan(dt, dims, tau, K, prec, outputs):
-    h = tuple(1.0 / n for n in dims)
+def _plan(dt, dims, tau, K, prec, outputs, iso=False, expect_288=False):
+    """Reduced plan on the unit box (h_a = 1/n_a) or, iso, with cubic cells
+    h = 1/n_x on every axis."""
+    h = tuple(1.0 / dims[0] for _ in dims) if iso else tuple(1.0 / n for n in dims)
     plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=outputs, k_max=K)
     Mp, cut = parity.padded_reduced(dims, h, tau, K, prec)
     full = tuple(parity.padded(n) for n in dims)
     assert plan.padded == Mp and plan.cut == cut
     assert any(c > 0 for c in cut) and np.prod(Mp) < np.prod(full), "the case must reduce the padding"
+    if expect_288:
+        assert 288 in Mp[1:], "the case must use the 288-point column engine"
     return plan, h, Mp
 
 
@@ -54,13 +58,15 @@ def _clustered(D, K, seed, h):
     return pts.astype(np.float32)
 
 
-def _sample_cells(dims, n_random, seed):
+def _sample_cells(dims, n_random, seed, z_cluster=None):
     """Every node of three axis planes (through the cluster, at the far
-    faces) and n_random further nodes."""
+    faces), of the z plane z_cluster if given, and n_random further nodes."""
     nx, ny, nz = dims
     idx = np.arange(nx * ny * nz).reshape(nz, ny, nx)
     parts = [idx[:, :, nx // 3].ravel(), idx[:, ny - 1, :].ravel(), idx[nz - 1, :, :].ravel(),
              np.random.default_rng(seed).choice(nx * ny * nz, n_random, replace=False)]
+    if z_cluster is not None:
+        parts.append(idx[z_cluster].ravel())
     return np.unique(np.concatenate(parts))
 
 
@@ -128,19 +134,63 @@ def test_reduced_fields_3d(dt, prec):
     print("\n" + _check(f"reduced 3d M={Mp}", prec, tau, h, ref, plan.last_stats(), S, g))
 
 
+# The 288-point column engine (pair-split, N = 2 * 12^2): grids whose
+# y (and z) axis needs more than 256 points pad to 288 instead of 512.
+CASES_288_2D = [((300, 262), "fp32"), ((300, 240), "fp64")]
+CASES_288_3D = [((120, 250, 250), "fp32"), ((120, 230, 230), "fp64")]
+
+
+@pytest.mark.parametrize("dims,prec", CASES_288_2D)
+def test_reduced_288_2d(dt, dims, prec):
+    """2D, cubic cells, tau = h, 100 clustered sources: y padded to 288 (the
+    fused pass on the pair-split engine); S, grad S and H on every node."""
+    K = 100
+    tau = 1.0 / dims[0]
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad", "hess"], iso=True, expect_288=True)
+    pts = _clustered(2, K, 631, h[0])
+    res = plan.forward(torch.from_numpy(pts).cuda(), S=True, grad=True, hess=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, prec, grad=True, hess=True, padded_dims=Mp)
+    print("\n" + _check(f"reduced 2d M={Mp}", prec, tau, h, ref, plan.last_stats(), _np(res["S"]).ravel(),
+                        _np(res["grad"]).reshape(2, -1), _np(res["hess"]).reshape(3, -1)))
+
+
+@pytest.mark.parametrize("dims,prec", CASES_288_3D)
+def test_reduced_288_3d(dt, dims, prec):
+    """3D, cubic cells, tau = h, 300 sources on a small sphere: y and z padded
+    to 288 (strided y passes and the fused z pass on the pair-split engine);
+    S and grad S on four full planes and 150 000 further nodes."""
+    K = 300
+    tau = 1.0 / dims[0]
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad"], iso=True, expect_288=True)
+    pts = _clustered(3, K, 632, h[0])
+    res = plan.forward(torch.from_numpy(pts).cuda(), S=True, grad=True)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    cells = _sample_cells(dims, 150_000, 633, z_cluster=int(0.3 / h[2]))
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, pts, prec, grad=True, cells=cells, padded_dims=Mp)
+    S = _np(res["S"]).ravel()[cells]
+    g = _np(res["grad"]).reshape(3, -1)[:, cells]
+    print("\n" + _check(f"reduced 3d M={Mp}", prec, tau, h, ref, plan.last_stats(), S, g))
+
+
 # float32: relative L2 error of dL/dY and relative error of dL/dtau (the
 # bar of the fully padded adjoint tests)
 TOL_ADJ_FP32 = 1e-3
 
 
-@pytest.mark.parametrize("dims,tau_h,K,prec", [
-    ((300, 200), 1.0, 100, "fp64"), ((300, 200), 1.0, 100, "fp32"), ((72, 70, 66), 1.5, 100, "fp32")])
-def test_reduced_backward(dt, dims, tau_h, K, prec):
+@pytest.mark.parametrize("dims,tau_h,K,prec,iso", [
+    ((300, 200), 1.0, 100, "fp64", False), ((300, 200), 1.0, 100, "fp32", False),
+    ((72, 70, 66), 1.5, 100, "fp32", False), ((300, 262), 1.0, 100, "fp32", True),
+    ((40, 262, 250), 1.0, 100, "fp32", True)])
+def test_reduced_backward(dt, dims, tau_h, K, prec, iso):
     """dL/dY and dL/dtau of a reduced plan against the oracle (G = 0 on the
-    shell around the threshold, as for the fully padded plans)."""
+    shell around the threshold, as for the fully padded plans); the cubic-cell
+    cases pad y (and z) to 288."""
     D = len(dims)
     tau = tau_h / dims[0]
-    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "backward"])
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "backward"], iso=iso, expect_288=iso)
     pts = _clustered(D, K, 620 + D, 1.0 / dims[0])
     ref = parity.reference(dims, h, (0.0,) * D, tau, pts, prec, padded_dims=Mp, rmean=prec == "fp64")
     rng = np.random.default_rng(621)
