@@ -666,9 +666,8 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
 
 def run_reduced(steps, warmup, timing_calls, no_cpu, cpu_cells):
     """The 256^3 mesh workload with its source count known to the plan
-    (k_max = the 60 000 triangles): y and z pad to 288 instead of 512 with
-    kernels truncated where they fall below the rounding floor (x keeps 512:
-    256 + c exceeds 256 and the row passes have power-of-two engines only).
+    (k_max = the 60 000 triangles): every axis pads to 288 instead of 512,
+    with kernels truncated where they fall below the rounding floor.
     Forward S+grad S and the backward, each beside the fully padded plan on
     the same inputs; the forward fields of both are compared with the oracle
     on a node sample."""

@@ -145,6 +145,11 @@ template <int R, int DIR, typename V> struct RegDFT {
   }
 };
 
+// The 12-point DFT as a butterfly of the Stockham engine (rows of length 144).
+template <int DIR, typename V> struct Bfly<12, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) { RegDFT<12, DIR, V>::run(a); }
+};
+
 // Thread twiddles W_N^(DIR p k) for k < E from two small sets:
 // k = a + 8 b, W^(p k) = W^(p a) W^(8 p b).
 template <typename T, int N, int E> struct ThreadTwiddles {

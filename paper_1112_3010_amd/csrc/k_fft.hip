@@ -20,14 +20,21 @@
 
 #include "dt_launch.hpp"
 #include "fft_engine.hpp"
+#include "fft_twostep.hpp"
 #include "epilogue.hpp"
 
 namespace dt {
 
 // LDS position of element i of a row line: XOR-swizzling the low five bits
 // with bits 3..7 spreads the strided Stockham accesses over the 64 banks
-// (a bijection on [0, N) for power-of-two N).
-__device__ __forceinline__ int row_swz(int i) { return i ^ ((i >> 3) & 31); }
+// (a bijection on [0, N) for power-of-two N >= 256; other lengths keep the
+// natural order).
+template <int N> __device__ __forceinline__ int row_swz(int i) {
+  if constexpr ((N & (N - 1)) == 0) return i ^ ((i >> 3) & 31);
+  else return i;
+}
+// bin k of a half-spectrum line read from the length-N complex transform (bin N is bin 0)
+template <int N> __device__ __forceinline__ int row_wrap(int k) { return k == N ? 0 : k; }
 
 // ---------------------------------------------------------------------------
 // Row pass: real -> half spectrum
@@ -35,7 +42,7 @@ __device__ __forceinline__ int row_swz(int i) { return i ^ ((i >> 3) & 31); }
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>* __restrict__ out, RowParams p) {
   using V = Cx<T>;
-  constexpr int E = 8;
+  constexpr int E = row_E(N);
   constexpr int Q = N / E;
   constexpr int LPB = Q >= 256 ? 1 : 256 / Q;
   constexpr int LP = N + 1;
@@ -89,7 +96,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
         v[s * R0 + r] = mk<V>(a, c);
       }
   }
-  auto addr = [b](int i) { return b * LP + row_swz(i); };
+  auto addr = [b](int i) { return b * LP + row_swz<N>(i); };
   F::run(v, lds, q, tw, 2, addr);   // its first LDS store follows a barrier
   __syncthreads();
   F::store_last(lds, v, q, addr);
@@ -97,8 +104,8 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
   if (!active) return;
   V* dst = out + line * (int64_t)p.pitch;
   for (int k = q; k <= N; k += Q) {
-    const V zk = lds[addr(k & (N - 1))];
-    const V zc = cconj(lds[addr((N - k) & (N - 1))]);
+    const V zk = lds[addr(row_wrap<N>(k))];
+    const V zc = cconj(lds[addr(row_wrap<N>(N - k))]);
     const V ev = cscale(cadd(zk, zc), T(0.5));
     const V od = cscale(mul_mi(csub(zk, zc)), T(0.5));
     dst[k] = cadd(ev, cmul(tw[k], od));
@@ -241,7 +248,7 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 template <typename T, int N, bool CURV>
 __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
-  constexpr int E = 8;
+  constexpr int E = row_E(N);
   constexpr int Q = N / E;
   constexpr int LP = N + 1;
   constexpr int R0 = fft_radix(N, 0);
@@ -311,7 +318,7 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
     }
   // the staged lines alias the exchange buffer: B::run passes a barrier
   // before its first LDS store
-  auto addr = [b](int i) { return b * LP + row_swz(i); };
+  auto addr = [b](int i) { return b * LP + row_swz<N>(i); };
   B::run(v, lds, q, tw, 2, addr);
   __syncthreads();
   T* ldr = reinterpret_cast<T*>(lds);
@@ -365,11 +372,11 @@ int col_tile_width(int N, bool fp64, bool fused) {
 }
 
 // Row passes transform M_x/2 complex points, column passes M points; M >= 64.
-#define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(144) X(256) X(512) X(1024)
 #define DT_FOR_EACH_COL_N(X) X(64) X(128) X(256) X(512) X(1024) X(2048)
 
 template <typename T> bool launch_row_r2c(const T* in, void* out, const RowParams& p, int N, hipStream_t st) {
-  const int Q = N / 8;
+  const int Q = N / row_E(N);
   const int lpb = Q >= 256 ? 1 : 256 / Q;
   const int64_t blocks = (p.n_lines + lpb - 1) / lpb;
   if (blocks <= 0) return true;
@@ -435,9 +442,13 @@ static bool launch_epi_kernel(const void* in, const RowParams& p, const EpiParam
 constexpr int kEpiThreads = 128;   // threads per block of the final row pass (whole rows per block)
 template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p, const EpiParams& e, int N,
                                               hipStream_t st) {
-  const int Q = N / 8;
+  const int Q = N / row_E(N);
   int rpb = kEpiThreads / (e.C * Q);
   if (rpb < 1) rpb = 1;
+  // lines of 12 threads (N = 144): more rows per block, up to 256 threads,
+  // for whole wavefronts where that is possible
+  if (Q % 3 == 0)
+    while ((rpb * e.C * Q) % 64 != 0 && (rpb + 1) * e.C * Q <= 256) ++rpb;
   const int threads = rpb * e.C * Q;
   if (threads > 1024 || threads < 64) return false;
   const int64_t blocks = (e.n_rows + rpb - 1) / rpb;

@@ -29,12 +29,12 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Reduced padded length: the smallest length >= need (at least 64) that the
-// passes have engines for: powers of two, and 288 = 2 * 12^2 for the column
-// axes (pair-split register engine).
-int64_t reduced_length(int64_t need, bool column) {
+// passes have engines for: powers of two, and 288 = 2 * 12^2 (pair-split
+// register engine for the columns, 12 x 12 Stockham for the rows).
+int64_t reduced_length(int64_t need) {
   int64_t m = 64;
   while (m < need) m *= 2;
-  if (column && need <= 288 && 288 < m) m = 288;
+  if (need <= 288 && 288 < m) m = 288;
   return m;
 }
 
@@ -356,7 +356,7 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     for (int a = 0; a < ndim; ++a) {
       const double c = std::ceil(d_cut / spacing[a]);
       const int64_t ci = c < 1e9 ? (int64_t)c : (int64_t)1000000000;
-      const int64_t m = reduced_length(dims[a] + ci, a > 0);
+      const int64_t m = reduced_length(dims[a] + ci);
       if (m < p->M[a]) {
         p->M[a] = m;
         p->cut[a] = (int)ci;

@@ -50,19 +50,19 @@ def padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA)
     Theta_low = the threshold of one source on the full padding (a call with
     K sources has Theta >= sqrt(K) Theta_low); d_cut = tau (ln(c_theta
     sqrt(k_max)) - ln Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = the
-    smallest length >= max(64, n_a + c_a) among the powers of two and, for
-    the column axes y and z, 288, where that is below the full padding (else
-    the full padding, untruncated).  Returns ((M_a...), (c_a...)) with c = 0
-    on a fully padded axis."""
+    smallest length >= max(64, n_a + c_a) among the powers of two and 288,
+    where that is below the full padding (else the full padding,
+    untruncated).  Returns ((M_a...), (c_a...)) with c = 0 on a fully padded
+    axis."""
     full = [padded(n) for n in dims]
     np_full = float(np.prod([float(m) for m in full]))
     u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
     theta_low = c_theta * u * np.log2(np_full) / np.sqrt(np_full)
     d_cut = tau * (np.log(c_theta * np.sqrt(float(k_max))) - np.log(theta_low))
     Ms, cuts = [], []
-    for axis, (n, h, Mf) in enumerate(zip(dims, spacing, full)):
+    for n, h, Mf in zip(dims, spacing, full):
         c = int(np.ceil(d_cut / h))
-        lengths = [1 << e for e in range(6, 13)] + ([288] if axis > 0 else [])
+        lengths = [1 << e for e in range(6, 13)] + [288]
         Mr = min(m for m in lengths if m >= n + c)
         if Mr < Mf:
             Ms.append(Mr)

@@ -154,8 +154,9 @@ def c3():
 
 def _c3_plan(dt, w, prec, outputs, reduced):
     """The benchmark's 256^3 plan; reduced: k_max = the mesh's triangle count,
-    which pads y and z to 288 (the pair-split engine at N = 2 * 12^2) in
-    float32 and truncates the kernels there."""
+    which in float32 pads every axis to 288 (rows: 12 x 12 Stockham; columns:
+    the pair-split engine at N = 2 * 12^2) and truncates the kernels at 29
+    cells."""
     dims = w.dims
     h = (1.0 / dims[0],) * 3
     tau = h[0]
@@ -163,7 +164,7 @@ def _c3_plan(dt, w, prec, outputs, reduced):
     plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=outputs, k_max=k_max)
     if reduced:
         Mp, cut = parity.padded_reduced(dims, h, tau, k_max, prec)
-        assert plan.padded == Mp == (512, 288, 288) and plan.cut == cut
+        assert plan.padded == Mp == (288, 288, 288) and plan.cut == cut
     else:
         assert plan.padded == (512, 512, 512)
     return plan, dims, h, tau

@@ -47,13 +47,13 @@ def _plan(dt, dims, tau, K, prec, outputs, iso=False, expect_288=False):
     assert plan.padded == Mp and plan.cut == cut
     assert any(c > 0 for c in cut) and np.prod(Mp) < np.prod(full), "the case must reduce the padding"
     if expect_288:
-        assert 288 in Mp[1:], "the case must use the 288-point column engine"
+        assert 288 in Mp, "the case must use the 288-point engines"
     return plan, h, Mp
 
 
-def _clustered(D, K, seed, h):
+def _clustered(D, K, seed, h, centre=(0.3, 0.35, 0.3)):
     if D == 3:
-        return synth.generators.jittered_sphere_points(K, 0.12, 2 * h, seed=seed, centre=(0.3, 0.35, 0.3))
+        return synth.generators.jittered_sphere_points(K, 0.12, 2 * h, seed=seed, centre=centre)
     pts = synth.generators.uniform_points(2, K, seed=seed, lo=0.1, hi=0.35)
     return pts.astype(np.float32)
 
@@ -134,16 +134,19 @@ def test_reduced_fields_3d(dt, prec):
     print("\n" + _check(f"reduced 3d M={Mp}", prec, tau, h, ref, plan.last_stats(), S, g))
 
 
-# The 288-point column engine (pair-split, N = 2 * 12^2): grids whose
-# y (and z) axis needs more than 256 points pad to 288 instead of 512.
-CASES_288_2D = [((300, 262), "fp32"), ((300, 240), "fp64")]
-CASES_288_3D = [((120, 250, 250), "fp32"), ((120, 230, 230), "fp64")]
+# The 288-point engines (columns: pair-split, N = 2 * 12^2; rows: 12 x 12
+# Stockham on 144 complex points): an axis that needs more than 256 points
+# pads to 288 instead of 512.
+CASES_288_2D = [((300, 262), "fp32"), ((262, 240), "fp32"), ((240, 230), "fp64")]
+CASES_288_3D = [((120, 250, 250), "fp32"), ((250, 120, 250), "fp32"), ((120, 230, 230), "fp64"),
+                ((230, 120, 230), "fp64")]
 
 
 @pytest.mark.parametrize("dims,prec", CASES_288_2D)
 def test_reduced_288_2d(dt, dims, prec):
-    """2D, cubic cells, tau = h, 100 clustered sources: y padded to 288 (the
-    fused pass on the pair-split engine); S, grad S and H on every node."""
+    """2D, cubic cells, tau = h, 100 clustered sources: y (the fused pass on
+    the pair-split engine) and/or x (the row passes) padded to 288; S, grad S
+    and H on every node."""
     K = 100
     tau = 1.0 / dims[0]
     plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad", "hess"], iso=True, expect_288=True)
@@ -158,9 +161,9 @@ def test_reduced_288_2d(dt, dims, prec):
 
 @pytest.mark.parametrize("dims,prec", CASES_288_3D)
 def test_reduced_288_3d(dt, dims, prec):
-    """3D, cubic cells, tau = h, 300 sources on a small sphere: y and z padded
-    to 288 (strided y passes and the fused z pass on the pair-split engine);
-    S and grad S on four full planes and 150 000 further nodes."""
+    """3D, cubic cells, tau = h, 300 sources on a small sphere: two of the
+    three axes padded to 288 (x: row passes; y: strided passes; z: the fused
+    pass); S and grad S on four full planes and 150 000 further nodes."""
     K = 300
     tau = 1.0 / dims[0]
     plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad"], iso=True, expect_288=True)
@@ -183,15 +186,18 @@ TOL_ADJ_FP32 = 1e-3
 @pytest.mark.parametrize("dims,tau_h,K,prec,iso", [
     ((300, 200), 1.0, 100, "fp64", False), ((300, 200), 1.0, 100, "fp32", False),
     ((72, 70, 66), 1.5, 100, "fp32", False), ((300, 262), 1.0, 100, "fp32", True),
-    ((40, 262, 250), 1.0, 100, "fp32", True)])
+    ((40, 262, 250), 1.0, 100, "fp32", True), ((262, 90, 120), 1.0, 100, "fp32", True)])
 def test_reduced_backward(dt, dims, tau_h, K, prec, iso):
     """dL/dY and dL/dtau of a reduced plan against the oracle (G = 0 on the
     shell around the threshold, as for the fully padded plans); the cubic-cell
-    cases pad y (and z) to 288."""
+    cases pad one or two axes to 288."""
     D = len(dims)
     tau = tau_h / dims[0]
     plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "backward"], iso=iso, expect_288=iso)
-    pts = _clustered(D, K, 620 + D, 1.0 / dims[0])
+    # the sphere inside the box (cubic cells of 1/n_x leave y and z shorter)
+    centre = tuple(min(c, 0.5 * n * h[0]) for c, n in zip((0.3, 0.35, 0.3), (dims + (0,))[:3])) if D == 3 else None
+    pts = _clustered(D, K, 620 + D, 1.0 / dims[0], centre=centre) if D == 3 else _clustered(D, K, 620 + D, h[0])
+    assert np.all(pts >= 0) and np.all(pts < np.array(dims) * np.array(h)), "sources inside the grid"
     ref = parity.reference(dims, h, (0.0,) * D, tau, pts, prec, padded_dims=Mp, rmean=prec == "fp64")
     rng = np.random.default_rng(621)
     G = rng.standard_normal(ref["S_ref"].shape)
