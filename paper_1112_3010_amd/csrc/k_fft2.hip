@@ -79,7 +79,7 @@ __global__ void __launch_bounds__((N / E) * NB) k_col2_c2c(const Cx<T>* __restri
   }
 }
 
-// The same strided pass on the pair-split engine (N = 2 E^2, 8-column tiles).
+// The same strided pass on the pair-split engine (N = 2 E^2).
 template <typename T, int N, int NB, int DIR, bool HALF>
 __global__ void __launch_bounds__(2 * pair_E(N) * NB) k_col2_c2c_pair(const Cx<T>* __restrict__ in,
                                                                      Cx<T>* __restrict__ out, ColParams p) {
@@ -243,10 +243,11 @@ template <typename T, int N> constexpr int fused_minwaves() { return sizeof(T) =
 // The float64 strided C2C passes use the pair-split engine at these lengths
 // (in float32 the two-step kernel with 16-column tiles streams faster); 288
 // has only the pair-split factorisation.
-constexpr int kPairNB = 8;
 template <typename T> constexpr bool c2c_pair(int N) {
   return N == 288 || (sizeof(T) == 8 && (N == 128 || N == 512));
 }
+// column tile of the strided pair-split pass: 128-byte row segments
+template <typename T> constexpr int c2c_pair_NB() { return sizeof(T) == 4 ? 16 : 8; }
 // The pair-split engine serves the 3D fused pass where N = 2 E^2.
 template <typename T> constexpr bool fused_pair(int N) { return pair_E(N) > 0 && N >= 128 && N <= 512; }
 
@@ -507,7 +508,8 @@ int col2_tile_width(int N, bool fp64, bool fused) {
   int E = fp64 ? (fused ? twostep_E<double, true>(N) : twostep_E<double, false>(N))
                : (fused ? twostep_E<float, true>(N) : twostep_E<float, false>(N));
   if (fused && (fp64 ? fused_pair<double>(N) : fused_pair<float>(N))) E = pair_E(N);
-  if (!fused && (fp64 ? c2c_pair<double>(N) : c2c_pair<float>(N))) return kPairNB;
+  if (!fused && (fp64 ? c2c_pair<double>(N) : c2c_pair<float>(N)))
+    return fp64 ? c2c_pair_NB<double>() : c2c_pair_NB<float>();
   if (E == 0) return 0;
   if (fused) return fp64 ? twostep_NB<double, true>() : twostep_NB<float, true>();
   return fp64 ? twostep_NB<double>() : twostep_NB<float>();
@@ -525,11 +527,12 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
     switch (N) {
 #define CASEP(NN)                                                                                         \
   case NN: {                                                                                              \
-    constexpr int NT = 2 * pair_E(NN) * kPairNB;                                                          \
-    if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, true>), grid1, dim3(NT), 0, st, i_, o_, p);  \
-    else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, 1, false>), grid1, dim3(NT), 0, st, i_, o_, p);    \
-    else if (half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, true>), grid1, dim3(NT), 0, st, i_, o_, p);       \
-    else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, kPairNB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
+    constexpr int NB = c2c_pair_NB<T>();                                                                  \
+    constexpr int NT = 2 * pair_E(NN) * NB;                                                               \
+    if (dir > 0 && half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, NB, 1, true>), grid1, dim3(NT), 0, st, i_, o_, p);  \
+    else if (dir > 0) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, NB, 1, false>), grid1, dim3(NT), 0, st, i_, o_, p);    \
+    else if (half) hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, NB, -1, true>), grid1, dim3(NT), 0, st, i_, o_, p);       \
+    else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, NB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
     return true;                                                                                          \
   }
       CASEP(128) CASEP(288) CASEP(512)
