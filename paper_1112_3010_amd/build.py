@@ -36,8 +36,11 @@ FLAGS = [
 # sum being rounded as written (error-free transformations); the global
 # -ffp-contract=fast lets the backend fuse a product into a later add even
 # where the product's rounding error is taken separately, so that file turns
-# contraction off (its explicit fma calls remain).
-FILE_FLAGS = {"k_dd.hip": ["-ffp-contract=off"]}
+# contraction off (its explicit fma calls remain).  The register FFTs of the
+# column passes add literal zeros where inputs are pruned (rows beyond n);
+# x + 0 may be folded to x only if the sign of a zero result does not matter,
+# which holds for transforms whose outputs are only summed and stored.
+FILE_FLAGS = {"k_dd.hip": ["-ffp-contract=off"], "k_fft2.hip": ["-fno-signed-zeros"]}
 
 
 def _hipcc():
