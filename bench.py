@@ -687,6 +687,11 @@ def run_reduced(steps, warmup, timing_calls, no_cpu, cpu_cells):
     b_full = run_backward("fp32", Yc, dims, tau, bsteps, warmup, timing_calls)
     b_red = run_backward("fp32", Yc, dims, tau, bsteps, warmup, timing_calls, k_max=len(F))
     log("fp32 backward full / reduced:", json.dumps(b_full), json.dumps(b_red))
+    # float64: the truncation distance is longer (c = 49), and every axis pads to 392
+    f64 = run_gpu("fp64", V, F, dims, tau, bsteps, warmup, timing_calls, cells)
+    r64 = run_gpu("fp64", V, F, dims, tau, bsteps, warmup, timing_calls, cells, k_max=len(F))
+    log("fp64 full / reduced:", json.dumps({k: v for k, v in f64.items() if not k.startswith("sample_")}),
+        json.dumps({k: v for k, v in r64.items() if not k.startswith("sample_")}))
     line = {
         "metric": METRIC, "value": round(red["value"], 1), "unit": "grid pts/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": round(red["ms_per_step"], 4), "ms_stats": red["ms_stats"],
@@ -707,9 +712,19 @@ def run_reduced(steps, warmup, timing_calls, no_cpu, cpu_cells):
         "backward_full_padding": {"ms_per_call": b_full["ms_per_call"], "padded": b_full["padded"],
                                   "path": b_full["path"]},
         "backward_speedup_vs_full_padding": round(b_full["ms_per_call"] / b_red["ms_per_call"], 3),
+        "fp64": {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4),
+                 "ms_stats": r64["ms_stats"], "dtype": "f64", "padded": r64["padded"], "cut": r64["cut"],
+                 "roofline": roofline_entry(r64["pass_bytes"], r64["pass_ms"], r64["launches"], r64["dominant"]),
+                 "path": {"model_bytes": r64["model_bytes"], "achieved_gbs": round(r64["path_gbs"], 1),
+                          "frac": round(r64["path_gbs"] / HBM_PEAK_GBS, 4), "pass_ms": r64["pass_ms"],
+                          "s_max_over_tau": round(r64["s_max_over_tau"], 3)},
+                 "full_padding": {"ms_per_step": round(f64["ms_per_step"], 4), "padded": f64["padded"],
+                                  "pass_ms": f64["pass_ms"], "s_max_over_tau": round(f64["s_max_over_tau"], 3)},
+                 "speedup_vs_full_padding": round(f64["ms_per_step"] / r64["ms_per_step"], 3)},
     }
     if not no_cpu:
-        cb, acc = cpu_baseline(V, F, dims, tau, cells, [("fp32_reduced", "fp32", red), ("fp32_full", "fp32", full)])
+        cb, acc = cpu_baseline(V, F, dims, tau, cells, [("fp32_reduced", "fp32", red), ("fp32_full", "fp32", full),
+                                                        ("fp64_reduced", "fp64", r64), ("fp64_full", "fp64", f64)])
         cb["value"] = round(cb["value"], 2)
         line["cpu_baseline"] = cb
         line["accuracy_vs_oracle"] = dict(acc, sample=f"the cpu_baseline's {len(cells)} nodes")

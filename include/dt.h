@@ -183,7 +183,8 @@ dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const doub
  * Theta / c_theta: results change only below the validity threshold (the
  * same bound as the rounding model).  The kernels are truncated to the box
  * |d_a| <= c_a = ceil(d_cut / h_a) cells, and axis a is padded to M_a, the
- * smallest length >= max(64, n_a + c_a) among the powers of two and 288;
+ * smallest length >= max(64, n_a + c_a) among the powers of two, 288 and
+ * 392;
  * that keeps a truncated kernel from wrapping onto a node.  Where M_a is not below the full padding the axis
  * keeps it, untruncated (dt_plan_info reports M_a and c_a, 0 for such an
  * axis).  Precision

@@ -115,12 +115,14 @@ template <int DIR, typename V> struct Bfly<8, DIR, V> {
 };
 
 // Radix schedules (first and last stage radix 8 for power-of-two N >= 64;
-// 144 = 12 x 12 for the rows of a 288-point padded axis).
+// 144 = 12 x 12 and 196 = 14 x 14 for the rows of 288- and 392-point padded
+// axes).
 __host__ __device__ constexpr int fft_stages(int N) {
-  return N == 144 ? 2 : N <= 64 ? 2 : (N <= 512 ? 3 : 4);
+  return N == 144 || N == 196 ? 2 : N <= 64 ? 2 : (N <= 512 ? 3 : 4);
 }
 __host__ __device__ constexpr int fft_radix(int N, int s) {
   return N == 144 ? 12
+       : N == 196 ? 14
        : N == 16 ? 4
        : N == 32 ? (s == 0 ? 8 : 4)
        : N == 64 ? 8
@@ -142,14 +144,14 @@ template <int DIR, typename V> __device__ __forceinline__ V twiddle(const V* tw,
 }
 
 // Elements per thread of the row passes: whole butterflies of every stage.
-__host__ __device__ constexpr int row_E(int N) { return N == 144 ? 12 : 8; }
+__host__ __device__ constexpr int row_E(int N) { return N == 144 ? 12 : N == 196 ? 14 : 8; }
 
 // Per-thread view of one line.  Addr maps a within-line index to an LDS slot.
 template <typename T, int N, int E, int DIR> struct Stockham {
   using V = Cx<T>;
   static constexpr int Q = N / E;
   static constexpr int S = fft_stages(N);
-  static_assert(E % 8 == 0 || (N == 16 && E % 4 == 0) || (N == 144 && E == 12),
+  static_assert(E % 8 == 0 || (N == 16 && E % 4 == 0) || (N == 144 && E == 12) || (N == 196 && E == 14),
                 "elements per thread must hold whole butterflies");
 
   // Index of slot (s, r) for the input of stage `st` (or the output of the last stage).

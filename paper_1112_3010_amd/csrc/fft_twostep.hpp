@@ -103,11 +103,43 @@ template <int DIR, int M, int R, typename V> __device__ __forceinline__ V cmul_w
   }
 }
 
+// 7-point DFT from the pairs (a_j, a_(7-j)): with t_j = a_j + a_(7-j),
+// d_j = a_j - a_(7-j) and theta = 2 pi j k / 7,
+//   y_k, y_(7-k) = a_0 + sum_j t_j cos(theta) -+ i DIR sum_j d_j sin(theta).
+template <int DIR, typename V> struct Bfly<7, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) {
+    using T = decltype(V::x);
+    V t[4], d[4];
+#pragma unroll
+    for (int j = 1; j <= 3; ++j) {
+      t[j] = cadd(a[j], a[7 - j]);
+      d[j] = csub(a[j], a[7 - j]);
+    }
+    const V a0 = a[0];
+    a[0] = cadd(a0, cadd(t[1], cadd(t[2], t[3])));
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+      V re = a0, im = mk<V>(T(0), T(0));
+#pragma unroll
+      for (int j = 1; j <= 3; ++j) {
+        const T c = (T)ct_cos2pi(j * k, 7), sn = (T)ct_sin2pi(j * k, 7);
+        re = mk<V>(fma(c, t[j].x, re.x), fma(c, t[j].y, re.y));
+        im = mk<V>(fma(sn, d[j].x, im.x), fma(sn, d[j].y, im.y));
+      }
+      // -i DIR im
+      const V r = DIR > 0 ? mk<V>(im.y, -im.x) : mk<V>(-im.y, im.x);
+      a[k] = cadd(re, r);
+      a[7 - k] = csub(re, r);
+    }
+  }
+};
+
 // In-register DFT of size R, natural order in and out (R = 2..64, a power
-// of two, or 12): R = R1 x R2 Cooley-Tukey with compile-time twiddles
+// of two, or 12 or 14): R = R1 x R2 Cooley-Tukey with compile-time twiddles
 // W_R^(n1 k2).
 template <int R, int DIR, typename V> struct RegDFT {
-  static constexpr int R1 = R >= 32 ? 8 : 4;  // 12 = 4 x 3, 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
+  // 12 = 4 x 3, 14 = 2 x 7, 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
+  static constexpr int R1 = R >= 32 ? 8 : (R % 4 == 0 ? 4 : 2);
   static constexpr int R2 = R / R1;
 
   template <int N1, int K2> static __device__ __forceinline__ void twiddle(const V* t, V* b) {
@@ -145,9 +177,13 @@ template <int R, int DIR, typename V> struct RegDFT {
   }
 };
 
-// The 12-point DFT as a butterfly of the Stockham engine (rows of length 144).
+// The 12- and 14-point DFTs as butterflies of the Stockham engine (rows of
+// length 144 and 196).
 template <int DIR, typename V> struct Bfly<12, DIR, V> {
   static __device__ __forceinline__ void run(V* a) { RegDFT<12, DIR, V>::run(a); }
+};
+template <int DIR, typename V> struct Bfly<14, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) { RegDFT<14, DIR, V>::run(a); }
 };
 
 // Thread twiddles W_N^(DIR p k) for k < E from two small sets:
@@ -307,8 +343,8 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
 };
 
 // ---------------------------------------------------------------------------
-// Pair-split four-step FFT for N = E * P with P = 2E (32, 128, 288, 512,
-// 2048).
+// Pair-split four-step FFT for N = E * P with P = 2E (32, 128, 288, 392,
+// 512, 2048).
 //
 // Thread p < P of a column holds x[p + P e] (e < E).  Step 1: size-E DFT in
 // registers and the thread twiddles W_N^(p k1).  One LDS exchange gives
@@ -324,7 +360,7 @@ template <typename T, int N, int E_, int NB> struct TwoStep {
 // real LDS buffer of LDS elements.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int pair_E(int N) {
-  return N == 32 ? 4 : N == 128 ? 8 : N == 288 ? 12 : N == 512 ? 16 : N == 2048 ? 32 : 0;
+  return N == 32 ? 4 : N == 128 ? 8 : N == 288 ? 12 : N == 392 ? 14 : N == 512 ? 16 : N == 2048 ? 32 : 0;
 }
 
 template <typename T, int N, int NB, int SPLIT = 0, bool TWL = false> struct PairFFT {

@@ -372,7 +372,7 @@ int col_tile_width(int N, bool fp64, bool fused) {
 }
 
 // Row passes transform M_x/2 complex points, column passes M points; M >= 64.
-#define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(144) X(256) X(512) X(1024)
+#define DT_FOR_EACH_N(X) X(32) X(64) X(128) X(144) X(196) X(256) X(512) X(1024)
 #define DT_FOR_EACH_COL_N(X) X(64) X(128) X(256) X(512) X(1024) X(2048)
 
 template <typename T> bool launch_row_r2c(const T* in, void* out, const RowParams& p, int N, hipStream_t st) {
@@ -445,9 +445,9 @@ template <typename T> bool launch_row_c2r_epi(const void* in, const RowParams& p
   const int Q = N / row_E(N);
   int rpb = kEpiThreads / (e.C * Q);
   if (rpb < 1) rpb = 1;
-  // lines of 12 threads (N = 144): more rows per block, up to 256 threads,
-  // for whole wavefronts where that is possible
-  if (Q % 3 == 0)
+  // lines of 12 or 14 threads (N = 144, 196): more rows per block, up to
+  // 256 threads, for whole wavefronts where that is possible
+  if ((Q & (Q - 1)) != 0)
     while ((rpb * e.C * Q) % 64 != 0 && (rpb + 1) * e.C * Q <= 256) ++rpb;
   const int threads = rpb * e.C * Q;
   if (threads > 1024 || threads < 64) return false;

@@ -238,13 +238,13 @@ template <typename T> constexpr int tab_chunk() { return sizeof(T) == 8 ? 1 : 4;
 template <typename T> constexpr int fused_split() { return sizeof(T) == 8 ? 1 : 0; }
 template <typename T> constexpr bool fused_twl() { return sizeof(T) == 8; }
 // the float64 hint applies to the 512-point pair engine (the 256^3 grids)
-template <typename T, int N> constexpr int fused_minwaves() { return sizeof(T) == 8 && N == 512 ? 2 : 1; }
+template <typename T, int N> constexpr int fused_minwaves() { return sizeof(T) == 8 && (N == 512 || N == 392) ? 2 : 1; }
 
 // The float64 strided C2C passes use the pair-split engine at these lengths
 // (in float32 the two-step kernel with 16-column tiles streams faster); 288
-// has only the pair-split factorisation.
+// and 392 have only the pair-split factorisation.
 template <typename T> constexpr bool c2c_pair(int N) {
-  return N == 288 || (sizeof(T) == 8 && (N == 128 || N == 512));
+  return N == 288 || N == 392 || (sizeof(T) == 8 && (N == 128 || N == 512));
 }
 // column tile of the strided pair-split pass: 128-byte row segments
 template <typename T> constexpr int c2c_pair_NB() { return sizeof(T) == 4 ? 16 : 8; }
@@ -299,12 +299,13 @@ __global__ void __launch_bounds__(ENG::P * NB, (fused_minwaves<T, N>())) k_col2_
                       : nullptr;
     __syncthreads();                                  // earlier readers of tab_lds are done
     constexpr int RUNS = (SLICE16 + 63) / 64;         // 64-lane runs per slice
-    constexpr int NW = NT / 64;
+    constexpr int NW = NT / 64;                       // whole waves (a partial last wave does not copy)
+    static_assert(NW >= 1, "the block needs a whole wave");
     const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int c = 0; c < kTabChunk; ++c) {
       if (c >= nt) break;
-      for (int r = w; r < RUNS; r += NW) {
+      for (int r = w; w < NW && r < RUNS; r += NW) {
         const int idx = r * 64 + lane;
         if (idx < SLICE16)
           __builtin_amdgcn_global_load_lds(
@@ -515,7 +516,7 @@ int col2_tile_width(int N, bool fp64, bool fused) {
   return fp64 ? twostep_NB<double>() : twostep_NB<float>();
 }
 
-#define DT_FOR_EACH_COL2_N(X) X(64) X(128) X(256) X(288) X(512) X(1024)
+#define DT_FOR_EACH_COL2_N(X) X(64) X(128) X(256) X(288) X(392) X(512) X(1024)
 
 template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColParams& p, int N, int dir, int tiles,
                                            int outer, int chans, hipStream_t st) {
@@ -535,7 +536,7 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
     else hipLaunchKernelGGL((k_col2_c2c_pair<T, NN, NB, -1, false>), grid1, dim3(NT), 0, st, i_, o_, p);                \
     return true;                                                                                          \
   }
-      CASEP(128) CASEP(288) CASEP(512)
+      CASEP(128) CASEP(288) CASEP(392) CASEP(512)
 #undef CASEP
       default: break;
     }

@@ -29,12 +29,14 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Reduced padded length: the smallest length >= need (at least 64) that the
-// passes have engines for: powers of two, and 288 = 2 * 12^2 (pair-split
-// register engine for the columns, 12 x 12 Stockham for the rows).
+// passes have engines for: powers of two, 288 = 2 * 12^2 and 392 = 2 * 14^2
+// (pair-split register engines for the columns, 12 x 12 and 14 x 14
+// Stockham for the rows).
 int64_t reduced_length(int64_t need) {
   int64_t m = 64;
   while (m < need) m *= 2;
-  if (need <= 288 && 288 < m) m = 288;
+  for (const int64_t l : {288, 392})
+    if (need <= l && l < m) m = l;
   return m;
 }
 

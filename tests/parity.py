@@ -50,8 +50,8 @@ def padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA)
     Theta_low = the threshold of one source on the full padding (a call with
     K sources has Theta >= sqrt(K) Theta_low); d_cut = tau (ln(c_theta
     sqrt(k_max)) - ln Theta_low); c_a = ceil(d_cut / h_a) cells; M_a = the
-    smallest length >= max(64, n_a + c_a) among the powers of two and 288,
-    where that is below the full padding (else the full padding,
+    smallest length >= max(64, n_a + c_a) among the powers of two, 288 and
+    392, where that is below the full padding (else the full padding,
     untruncated).  Returns ((M_a...), (c_a...)) with c = 0 on a fully padded
     axis."""
     full = [padded(n) for n in dims]
@@ -62,7 +62,7 @@ def padded_reduced(dims, spacing, tau, k_max, precision, c_theta=oracle.C_THETA)
     Ms, cuts = [], []
     for n, h, Mf in zip(dims, spacing, full):
         c = int(np.ceil(d_cut / h))
-        lengths = [1 << e for e in range(6, 13)] + [288]
+        lengths = [1 << e for e in range(6, 13)] + [288, 392]
         Mr = min(m for m in lengths if m >= n + c)
         if Mr < Mf:
             Ms.append(Mr)

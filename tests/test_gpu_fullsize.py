@@ -154,9 +154,9 @@ def c3():
 
 def _c3_plan(dt, w, prec, outputs, reduced):
     """The benchmark's 256^3 plan; reduced: k_max = the mesh's triangle count,
-    which in float32 pads every axis to 288 (rows: 12 x 12 Stockham; columns:
-    the pair-split engine at N = 2 * 12^2) and truncates the kernels at 29
-    cells."""
+    which pads every axis to 288 in float32 (kernels truncated at 29 cells)
+    and to 392 in float64 (49 cells): rows on 12 x 12 or 14 x 14 Stockham,
+    columns on the pair-split engine at N = 2 * 12^2 or 2 * 14^2."""
     dims = w.dims
     h = (1.0 / dims[0],) * 3
     tau = h[0]
@@ -164,13 +164,13 @@ def _c3_plan(dt, w, prec, outputs, reduced):
     plan = dt.Plan(dims, None, None, tau, precision=prec, outputs=outputs, k_max=k_max)
     if reduced:
         Mp, cut = parity.padded_reduced(dims, h, tau, k_max, prec)
-        assert plan.padded == Mp == (288, 288, 288) and plan.cut == cut
+        assert plan.padded == Mp == ((288,) * 3 if prec == "fp32" else (392,) * 3) and plan.cut == cut
     else:
         assert plan.padded == (512, 512, 512)
     return plan, dims, h, tau
 
 
-@pytest.mark.parametrize("prec,reduced", [("fp32", False), ("fp64", False), ("fp32", True)])
+@pytest.mark.parametrize("prec,reduced", [("fp32", False), ("fp64", False), ("fp32", True), ("fp64", True)])
 def test_mesh_256_bench_configuration(dt, c3, prec, reduced):
     """S and grad S exactly as the benchmark computes them (forward_into,
     outputs S+grad, mesh given as vertices and faces), with full and with
@@ -344,7 +344,8 @@ def test_adjoint_128_full_grid(dt, prec):
 # padded 512^3, pair-split fused pass, 512-wide gather)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec,radius,reduced", [("fp32", 10, False), ("fp64", 30, False), ("fp32", 10, True)])
+@pytest.mark.parametrize("prec,radius,reduced", [("fp32", 10, False), ("fp64", 30, False), ("fp32", 10, True),
+                                                  ("fp64", 30, True)])
 def test_backward_256_bench_configuration(dt, c3, prec, radius, reduced):
     """dt_backward on the benchmark's 256^3 workload.  G is seeded normal on a
     node sample: uniform over the grid plus nodes within `radius` cells of the

@@ -37,7 +37,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def _plan(dt, dims, tau, K, prec, outputs, iso=False, expect_288=False):
+def _plan(dt, dims, tau, K, prec, outputs, iso=False, expect=None):
     """Reduced plan on the unit box (h_a = 1/n_a) or, iso, with cubic cells
     h = 1/n_x on every axis."""
     h = tuple(1.0 / dims[0] for _ in dims) if iso else tuple(1.0 / n for n in dims)
@@ -46,8 +46,8 @@ def _plan(dt, dims, tau, K, prec, outputs, iso=False, expect_288=False):
     full = tuple(parity.padded(n) for n in dims)
     assert plan.padded == Mp and plan.cut == cut
     assert any(c > 0 for c in cut) and np.prod(Mp) < np.prod(full), "the case must reduce the padding"
-    if expect_288:
-        assert 288 in Mp, "the case must use the 288-point engines"
+    if expect:
+        assert expect in Mp, f"the case must use the {expect}-point engines"
     return plan, h, Mp
 
 
@@ -134,22 +134,28 @@ def test_reduced_fields_3d(dt, prec):
     print("\n" + _check(f"reduced 3d M={Mp}", prec, tau, h, ref, plan.last_stats(), S, g))
 
 
-# The 288-point engines (columns: pair-split, N = 2 * 12^2; rows: 12 x 12
-# Stockham on 144 complex points): an axis that needs more than 256 points
-# pads to 288 instead of 512.
-CASES_288_2D = [((300, 262), "fp32"), ((262, 240), "fp32"), ((240, 230), "fp64")]
-CASES_288_3D = [((120, 250, 250), "fp32"), ((250, 120, 250), "fp32"), ((120, 230, 230), "fp64"),
-                ((230, 120, 230), "fp64")]
+def _inside(centre, dims, h):
+    """The sphere's centre moved into the box where an axis is short."""
+    return tuple(min(c, 0.5 * n * hh) for c, n, hh in zip(centre, dims, h))
 
 
-@pytest.mark.parametrize("dims,prec", CASES_288_2D)
-def test_reduced_288_2d(dt, dims, prec):
+# The engines at 288 = 2 * 12^2 and 392 = 2 * 14^2 (columns: pair-split;
+# rows: 12 x 12 and 14 x 14 Stockham on 144 and 196 complex points): an axis
+# that needs more than 256 (384) points pads to 288 (392) instead of 512 (1024).
+CASES_EXT_2D = [((300, 262), "fp32", 288), ((262, 240), "fp32", 288), ((240, 230), "fp64", 288),
+                ((350, 300), "fp32", 392), ((330, 300), "fp64", 392)]
+CASES_EXT_3D = [((120, 250, 250), "fp32", 288), ((250, 120, 250), "fp32", 288), ((120, 230, 230), "fp64", 288),
+                ((230, 120, 230), "fp64", 288), ((300, 120, 300), "fp32", 392), ((280, 120, 280), "fp64", 392)]
+
+
+@pytest.mark.parametrize("dims,prec,length", CASES_EXT_2D)
+def test_reduced_nonpow2_2d(dt, dims, prec, length):
     """2D, cubic cells, tau = h, 100 clustered sources: y (the fused pass on
-    the pair-split engine) and/or x (the row passes) padded to 288; S, grad S
-    and H on every node."""
+    the pair-split engine) and/or x (the row passes) padded to 288 or 392; S,
+    grad S and H on every node."""
     K = 100
     tau = 1.0 / dims[0]
-    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad", "hess"], iso=True, expect_288=True)
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad", "hess"], iso=True, expect=length)
     pts = _clustered(2, K, 631, h[0])
     res = plan.forward(torch.from_numpy(pts).cuda(), S=True, grad=True, hess=True)
     torch.cuda.synchronize()
@@ -159,15 +165,16 @@ def test_reduced_288_2d(dt, dims, prec):
                         _np(res["grad"]).reshape(2, -1), _np(res["hess"]).reshape(3, -1)))
 
 
-@pytest.mark.parametrize("dims,prec", CASES_288_3D)
-def test_reduced_288_3d(dt, dims, prec):
+@pytest.mark.parametrize("dims,prec,length", CASES_EXT_3D)
+def test_reduced_nonpow2_3d(dt, dims, prec, length):
     """3D, cubic cells, tau = h, 300 sources on a small sphere: two of the
-    three axes padded to 288 (x: row passes; y: strided passes; z: the fused
-    pass); S and grad S on four full planes and 150 000 further nodes."""
+    three axes padded to 288 or 392 (x: row passes; y: strided passes; z: the
+    fused pass); S and grad S on four full planes and 150 000 further nodes."""
     K = 300
     tau = 1.0 / dims[0]
-    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad"], iso=True, expect_288=True)
-    pts = _clustered(3, K, 632, h[0])
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "grad"], iso=True, expect=length)
+    pts = _clustered(3, K, 632, h[0], centre=_inside((0.3, 0.35, 0.3), dims, h))
+    assert np.all(pts >= 0) and np.all(pts < np.array(dims) * np.array(h)), "sources inside the grid"
     res = plan.forward(torch.from_numpy(pts).cuda(), S=True, grad=True)
     torch.cuda.synchronize()
     assert plan.last_error() == 0
@@ -193,10 +200,12 @@ def test_reduced_backward(dt, dims, tau_h, K, prec, iso):
     cases pad one or two axes to 288."""
     D = len(dims)
     tau = tau_h / dims[0]
-    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "backward"], iso=iso, expect_288=iso)
+    plan, h, Mp = _plan(dt, dims, tau, K, prec, ["S", "backward"], iso=iso, expect=288 if iso else None)
     # the sphere inside the box (cubic cells of 1/n_x leave y and z shorter)
-    centre = tuple(min(c, 0.5 * n * h[0]) for c, n in zip((0.3, 0.35, 0.3), (dims + (0,))[:3])) if D == 3 else None
-    pts = _clustered(D, K, 620 + D, 1.0 / dims[0], centre=centre) if D == 3 else _clustered(D, K, 620 + D, h[0])
+    if D == 3:
+        pts = _clustered(D, K, 620 + D, 1.0 / dims[0], centre=_inside((0.3, 0.35, 0.3), dims, h))
+    else:
+        pts = _clustered(D, K, 620 + D, h[0])
     assert np.all(pts >= 0) and np.all(pts < np.array(dims) * np.array(h)), "sources inside the grid"
     ref = parity.reference(dims, h, (0.0,) * D, tau, pts, prec, padded_dims=Mp, rmean=prec == "fp64")
     rng = np.random.default_rng(621)
