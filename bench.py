@@ -510,7 +510,7 @@ def run_batch(steps, warmup):
         res["graph"] = run(plan, S, G, True)
         assert plan.last_error() == 0
         sched = np.array(tuned.pop("schedule"))
-        tuned["schedule_families"] = {p: np.bincount(sched[:, k], minlength=4).tolist()
+        tuned["schedule_families"] = {p: np.bincount(sched[:, k], minlength=6).tolist()
                                       for k, p in enumerate(("rows", "columns", "inverse_rows"))}
         padded = [plan.padded(i) for i in range(len(dims))]
         return res, tuned, batch_bytes(dims, padded, 4, 3), int(sum(a * b for a, b in padded))

@@ -365,13 +365,18 @@ dt_status dt_forward_batched(dt_batch_plan plan, const float* Y, const int64_t* 
                              void* stream);
 /* Radix schedule of the batched transforms: fams[3 i + k] is the schedule
  * of pass k of instance i (k = 0: forward row transform, 1: column pass,
- * 2: inverse row transform with the epilogue), one of four orders of the
- * 7-smooth length's radices: 0 radix 8 while possible, then one 4 or 2, then
+ * 2: inverse row transform with the epilogue), one of six radix schedules
+ * of the 7-smooth length: 0 radix 8 while possible, then one 4 or 2, then
  * 7, 5, 3; 1 the odd radices first, then as 0; 2 radix 4 while possible,
  * then one 2, then 7, 5, 3; 3 the one 4 or 2 first, then radix 8, then 7, 5,
- * 3.  All give the same transform up to rounding.  Default 0 everywhere;
+ * 3; 4 fused radices up to 16 (two prime-power stages per register DFT):
+ * radix 16 while possible, a leftover 2 joined to the smallest odd factor
+ * (6, 10, 14) and a leftover 4 to a factor 3 (12), else alone, then the odd
+ * factors paired largest with smallest where the product is at most 15 (9,
+ * 15); 5 the same with the odd radices first.
+ * All give the same transform up to rounding.  Default 4 everywhere;
  * dt_batch_autotune chooses them per (pass, length).  fams holds 3 n_inst
- * ints; values outside 0..3 give DT_E_ARG and change nothing. */
+ * ints; values outside 0..5 give DT_E_ARG and change nothing. */
 dt_status dt_batch_set_schedule(dt_batch_plan plan, const int* fams);
 dt_status dt_batch_get_schedule(dt_batch_plan plan, int* fams);
 /* Times every feasible tile choice (reps calls each, eager, on `stream`)

@@ -157,7 +157,7 @@ class BatchPlan:
 
     def schedule(self):
         """Radix schedule family per instance and pass: a list of n_inst
-        triples (forward rows, columns, inverse rows), each in 0..3."""
+        triples (forward rows, columns, inverse rows), each in 0..5."""
         arr = (ctypes.c_int * (3 * self.n))()
         L.check(L.load().dt_batch_get_schedule(self._h, arr), "dt_batch_get_schedule")
         return [list(arr[3 * i:3 * i + 3]) for i in range(self.n)]

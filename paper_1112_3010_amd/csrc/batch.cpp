@@ -70,6 +70,47 @@ bool mixed_plan_for(int64_t N, int family, MixedPlan& mp) {
       odd.push_back(q);
     }
   if (r != 1) return false;
+  if (family >= 4) {
+    // Fused radices up to 16: radix 16 while possible; a leftover 2 joins the
+    // smallest odd factor (6, 10, 14), a leftover 4 a factor 3 (12); the odd
+    // factors pair largest with smallest where the product is at most 15
+    // (9, 15).  Family 4 puts the powers of two first, family 5 the odd
+    // radices.
+    std::vector<int> p2, od;
+    for (; a2 >= 4; a2 -= 4) p2.push_back(16);
+    std::sort(odd.begin(), odd.end());
+    if (a2 > 0 && !odd.empty() && (1 << a2) * odd.front() <= 14) {
+      od.push_back((1 << a2) * odd.front());
+      odd.erase(odd.begin());
+    } else if (a2 > 0) {
+      p2.push_back(1 << a2);
+    }
+    size_t lo = 0, hi = odd.size();
+    while (hi > lo) {
+      if (hi - lo >= 2 && odd[hi - 1] * odd[lo] <= 15) {
+        od.push_back(odd[hi - 1] * odd[lo]);
+        ++lo;
+        --hi;
+      } else {
+        od.push_back(odd[hi - 1]);
+        --hi;
+      }
+    }
+    std::vector<int> rad = family == 4 ? p2 : od;
+    const std::vector<int>& rest = family == 4 ? od : p2;
+    rad.insert(rad.end(), rest.begin(), rest.end());
+    if ((int)rad.size() > kMixedMaxStages) return false;
+    mp.n_st = (int)rad.size();
+    int64_t ns = 1;
+    for (int st = 0; st < mp.n_st; ++st) {
+      if (!mixed_radix_supported(rad[st])) return false;
+      mp.radix[st] = rad[st];
+      mp.m_ns[st] = fastdiv_magic((uint32_t)ns);
+      mp.m_nbf[st] = fastdiv_magic((uint32_t)(N / rad[st]));
+      ns *= rad[st];
+    }
+    return true;
+  }
   if (family == 2) {
     for (; a2 >= 2; a2 -= 2) pow2.push_back(4);
     if (a2) pow2.push_back(2);
@@ -206,13 +247,14 @@ template <typename B> std::vector<B> xcd_runs(const std::vector<B>& v) {
 }
 
 // Default tiles: 512 threads per column block and the widest power-of-two
-// tile whose longest column set fits 32 elements per thread and the LDS.
+// tile whose longest column set fits 8 elements per thread (the lightest
+// instantiation in registers) and the LDS.
 dt_batch_tiles default_tiles(dt_batch_plan p) {
   int64_t my = 0;
   for (const auto& I : p->inst) my = std::max<int64_t>(my, I.My);
   dt_batch_tiles t{1, 512, 256};
   for (int nb : {16, 8, 4, 2, 1})
-    if (my * nb <= 32 * 512 && (size_t)(2 * my * nb + my) * 2 * p->wsz() <= (size_t)p->lds_max) {
+    if (my * nb <= 8 * 512 && (size_t)(2 * my * nb + my) * 2 * p->wsz() <= (size_t)p->lds_max) {
       t.col_nb = nb;
       break;
     }
@@ -547,11 +589,12 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
     I.ox = q.origin[0]; I.oy = q.origin[1];
     I.hx = q.spacing[0]; I.hy = q.spacing[1];
     I.tau = q.tau;
-    if (!mixed_plan_for(sx, 0, I.px) || !mixed_plan_for(My, 0, I.py) || !mixed_plan_for(sx, 0, I.pxi)) {
+    if (!mixed_plan_for(sx, kDefaultFamily, I.px) || !mixed_plan_for(My, kDefaultFamily, I.py) ||
+        !mixed_plan_for(sx, kDefaultFamily, I.pxi)) {
       delete p;
       return DT_E_UNSUPPORTED;
     }
-    p->sched.insert(p->sched.end(), {0, 0, 0});
+    p->sched.insert(p->sched.end(), {kDefaultFamily, kDefaultFamily, kDefaultFamily});
     I.m_sx = fastdiv_magic((uint32_t)sx);
     I.m_sx1 = fastdiv_magic((uint32_t)(sx + 1));
     I.m_nx = fastdiv_magic((uint32_t)I.nx);

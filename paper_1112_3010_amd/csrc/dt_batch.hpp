@@ -10,7 +10,8 @@
 namespace dt {
 
 constexpr int kBatchChan = 3;   // f, u_x, u_y
-constexpr int kMixedFamilies = 4;   // radix schedules per length (batch.cpp, mixed_plan_for)
+constexpr int kMixedFamilies = 6;   // radix schedules per length (batch.cpp, mixed_plan_for)
+constexpr int kDefaultFamily = 4;   // fused radices, powers of two first
 
 // Device-resident description of one instance (set up once per plan).
 struct BatchInst {

@@ -2,7 +2,10 @@
 //
 // Batched instances have padded lengths that are 7-smooth (2^a 3^b 5^c 7^d)
 // rather than powers of two, and their lengths differ inside one launch, so
-// the radix schedule is a runtime list (radices 8, 4, 2, 7, 5, 3).  A block
+// the radix schedule is a runtime list: the prime-power radices 8, 4, 2, 7,
+// 5, 3, and fused radices up to 16 (16, 6, 10, 12, 14, 9, 15) whose register
+// DFT takes two of those stages at once and saves an LDS round trip and its
+// barriers.  A block
 // holds L independent lines of length N in LDS; element i of line l sits at
 // lds[i * istride + l * lstride].  Each stage is a self-sorting (Stockham,
 // decimation in time) pass: butterfly j (k = j mod Ns, Ns = product of the
@@ -69,7 +72,14 @@ template <int R, int DIR, typename V> __device__ __forceinline__ void dft_odd(V*
 
 template <int R, int DIR, typename V> __device__ __forceinline__ void dft_small(V* x) {
   if constexpr (R == 2 || R == 4 || R == 8) Bfly<R, DIR, V>::run(x);
-  else dft_odd<R, DIR, V>(x);
+  else if constexpr (R == 3 || R == 5 || R == 7) dft_odd<R, DIR, V>(x);
+  else RegDFT<R, DIR, V>::run(x);
+}
+
+// The radices a schedule may use (mixed_plan_for builds schedules from these).
+__host__ __device__ constexpr bool mixed_radix_supported(int R) {
+  return R == 2 || R == 3 || R == 4 || R == 5 || R == 7 || R == 8 || R == 16 || R == 6 || R == 10 || R == 12 ||
+         R == 14 || R == 9 || R == 15;
 }
 
 // Division by a block-uniform divisor d in [1, 4096] through a multiply-high:
@@ -164,6 +174,13 @@ __device__ void mixed_fft(Cx<T>* lds, int N, const FastDiv& fL, int istride, int
       case 2: DT_MIXED_STAGE(2); break;
       case 7: DT_MIXED_STAGE(7); break;
       case 5: DT_MIXED_STAGE(5); break;
+      case 16: DT_MIXED_STAGE(16); break;
+      case 6: DT_MIXED_STAGE(6); break;
+      case 10: DT_MIXED_STAGE(10); break;
+      case 12: DT_MIXED_STAGE(12); break;
+      case 14: DT_MIXED_STAGE(14); break;
+      case 9: DT_MIXED_STAGE(9); break;
+      case 15: DT_MIXED_STAGE(15); break;
       default: DT_MIXED_STAGE(3); break;
 #undef DT_MIXED_STAGE
     }

@@ -103,43 +103,53 @@ template <int DIR, int M, int R, typename V> __device__ __forceinline__ V cmul_w
   }
 }
 
-// 7-point DFT from the pairs (a_j, a_(7-j)): with t_j = a_j + a_(7-j),
-// d_j = a_j - a_(7-j) and theta = 2 pi j k / 7,
-//   y_k, y_(7-k) = a_0 + sum_j t_j cos(theta) -+ i DIR sum_j d_j sin(theta).
-template <int DIR, typename V> struct Bfly<7, DIR, V> {
-  static __device__ __forceinline__ void run(V* a) {
-    using T = decltype(V::x);
-    V t[4], d[4];
+// Odd prime-length DFT (5, 7) from the pairs (a_j, a_(R-j)): with
+// t_j = a_j + a_(R-j), d_j = a_j - a_(R-j) and theta = 2 pi j k / R,
+//   y_k, y_(R-k) = a_0 + sum_j t_j cos(theta) -+ i DIR sum_j d_j sin(theta).
+template <int R, int DIR, typename V> __device__ __forceinline__ void odd_prime_dft(V* a) {
+  using T = decltype(V::x);
+  constexpr int H = (R - 1) / 2;
+  V t[H + 1], d[H + 1];
 #pragma unroll
-    for (int j = 1; j <= 3; ++j) {
-      t[j] = cadd(a[j], a[7 - j]);
-      d[j] = csub(a[j], a[7 - j]);
-    }
-    const V a0 = a[0];
-    a[0] = cadd(a0, cadd(t[1], cadd(t[2], t[3])));
-#pragma unroll
-    for (int k = 1; k <= 3; ++k) {
-      V re = a0, im = mk<V>(T(0), T(0));
-#pragma unroll
-      for (int j = 1; j <= 3; ++j) {
-        const T c = (T)ct_cos2pi(j * k, 7), sn = (T)ct_sin2pi(j * k, 7);
-        re = mk<V>(fma(c, t[j].x, re.x), fma(c, t[j].y, re.y));
-        im = mk<V>(fma(sn, d[j].x, im.x), fma(sn, d[j].y, im.y));
-      }
-      // -i DIR im
-      const V r = DIR > 0 ? mk<V>(im.y, -im.x) : mk<V>(-im.y, im.x);
-      a[k] = cadd(re, r);
-      a[7 - k] = csub(re, r);
-    }
+  for (int j = 1; j <= H; ++j) {
+    t[j] = cadd(a[j], a[R - j]);
+    d[j] = csub(a[j], a[R - j]);
   }
+  const V a0 = a[0];
+  V s0 = a0;
+#pragma unroll
+  for (int j = 1; j <= H; ++j) s0 = cadd(s0, t[j]);
+  a[0] = s0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    V re = a0, im = mk<V>(T(0), T(0));
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const T c = (T)ct_cos2pi((long)j * k, R), sn = (T)ct_sin2pi((long)j * k, R);
+      re = mk<V>(fma(c, t[j].x, re.x), fma(c, t[j].y, re.y));
+      im = mk<V>(fma(sn, d[j].x, im.x), fma(sn, d[j].y, im.y));
+    }
+    // -i DIR im
+    const V r = DIR > 0 ? mk<V>(im.y, -im.x) : mk<V>(-im.y, im.x);
+    a[k] = cadd(re, r);
+    a[R - k] = csub(re, r);
+  }
+}
+template <int DIR, typename V> struct Bfly<5, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) { odd_prime_dft<5, DIR, V>(a); }
+};
+template <int DIR, typename V> struct Bfly<7, DIR, V> {
+  static __device__ __forceinline__ void run(V* a) { odd_prime_dft<7, DIR, V>(a); }
 };
 
-// In-register DFT of size R, natural order in and out (R = 2..64, a power
-// of two, or 12 or 14): R = R1 x R2 Cooley-Tukey with compile-time twiddles
-// W_R^(n1 k2).
+// In-register DFT of size R, natural order in and out, R a 7-smooth number
+// up to 64: R = R1 x R2 Cooley-Tukey with compile-time twiddles W_R^(n1 k2),
+// down to the butterflies of size 2, 3, 4, 5, 7 and 8.
 template <int R, int DIR, typename V> struct RegDFT {
-  // 12 = 4 x 3, 14 = 2 x 7, 16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8
-  static constexpr int R1 = R >= 32 ? 8 : (R % 4 == 0 ? 4 : 2);
+  // 12 = 4 x 3, 14 = 2 x 7, 15 = 3 x 5, 16 = 4 x 4, 25 = 5 x 5, 32 = 8 x 4, 64 = 8 x 8
+  static constexpr int R1 = (R >= 32 && R % 8 == 0) ? 8
+                          : R % 4 == 0 ? 4 : R % 2 == 0 ? 2 : R % 3 == 0 ? 3 : R % 5 == 0 ? 5 : 7;
+  static constexpr bool LEAF = R == 2 || R == 3 || R == 4 || R == 5 || R == 7 || R == 8;
   static constexpr int R2 = R / R1;
 
   template <int N1, int K2> static __device__ __forceinline__ void twiddle(const V* t, V* b) {
@@ -159,7 +169,7 @@ template <int R, int DIR, typename V> struct RegDFT {
     }
   }
   static __device__ __forceinline__ void run(V* a) {
-    if constexpr (R <= 8) {
+    if constexpr (LEAF) {
       Bfly<R, DIR, V>::run(a);
     } else {
       V b[R];

@@ -163,7 +163,7 @@ def test_batch_96_instances(dt):
     S1, G1 = plan.forward(Y, offs)
     torch.cuda.synchronize()
     sched = np.array(plan.schedule())
-    assert sched.shape == (len(inst), 3) and sched.min() >= 0 and sched.max() <= 3
+    assert sched.shape == (len(inst), 3) and sched.min() >= 0 and sched.max() <= 5
     assert tuned["schedule"] == sched.tolist()
     # instances of one padded length share each pass's schedule
     for k, lens in ((0, [plan.padded(i)[0] for i in range(len(inst))]), (1, [plan.padded(i)[1] for i in
@@ -177,24 +177,25 @@ def test_batch_96_instances(dt):
         for tag, (s, g), st in (("default", plan.views(S, G)[i], None), ("tuned", plan.views(S1, G1)[i], None)):
             _check_instance(f"c4 inst {i} n={n} K={len(y)} {tag}", "fp32", (n, n), tau, y, _np(s), _np(g), cells,
                             plan.stats(i))
-    fams = np.bincount(sched.ravel(), minlength=4).tolist()
+    fams = np.bincount(sched.ravel(), minlength=6).tolist()
     print(f"\n[batch 96] tuned tiles {dict((k, v) for k, v in tuned.items() if k != 'schedule')}, "
           f"schedule families used {fams}; all instances within tolerance on about 500 nodes each", flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batch_every_radix_schedule(dt, prec, tmp_path, monkeypatch):
-    """Each of the four radix orders, on every pass of every instance, gives
+    """Each of the six radix schedules (four orders of the prime-power
+    radices, two with fused radices), on every pass of every instance, gives
     the transform (checked against the oracle); the schedule round-trips
     through the tuning cache."""
     pts = _small_points()
     taus = [2.0 / d[0] for d in SMALL_DIMS]
     plan = dt.BatchPlan(SMALL_DIMS, taus, precision=prec, graph=False)
-    assert plan.schedule() == [[0, 0, 0]] * len(SMALL_DIMS)
+    assert plan.schedule() == [[4, 4, 4]] * len(SMALL_DIMS)
     Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
     Y = Y.cuda()
-    for fam in range(4):
-        mix = [[fam, (fam + i) % 4, (fam + 2 * i) % 4] for i in range(len(SMALL_DIMS))]
+    for fam in range(6):
+        mix = [[fam, (fam + i) % 6, (fam + 2 * i) % 6] for i in range(len(SMALL_DIMS))]
         plan.set_schedule(mix)
         assert plan.schedule() == mix
         S, G = plan.forward(Y, offs)
@@ -206,7 +207,7 @@ def test_batch_every_radix_schedule(dt, prec, tmp_path, monkeypatch):
             _check_instance(f"schedule {mix[i]} inst {i}", prec, dims, tau, pts[i], _np(s), _np(g), cells,
                             plan.stats(i))
     with pytest.raises(RuntimeError):
-        plan.set_schedule([[0, 4, 0]] + [[0, 0, 0]] * (len(SMALL_DIMS) - 1))
+        plan.set_schedule([[0, 6, 0]] + [[0, 0, 0]] * (len(SMALL_DIMS) - 1))
     assert plan.schedule() == mix
     # autotune writes tiles and schedule to the cache; a new plan restores both
     monkeypatch.setenv("DT_TUNE_CACHE", str(tmp_path / "tiles.json"))
@@ -219,6 +220,35 @@ def test_batch_every_radix_schedule(dt, prec, tmp_path, monkeypatch):
     S2, G2 = plan2.forward(Y, offs)
     torch.cuda.synchronize()
     assert torch.equal(S2, S1) and torch.equal(G2, G1)
+
+
+# Lengths whose fused schedules use the fused radices the every-schedule
+# test leaves out, and the fallbacks: rows 27 (9, 3), 45 (15, 3), 63 (7, 9),
+# 28 (4, 7), 245 (7, 7, 5); columns 144 (16, 9), 336 (16, 7, 3), 560
+# (16, 7, 5), 28 (4, 7), 200 (8, 5, 5).
+FUSED_DIMS = [(27, 72), (45, 168), (63, 280), (28, 14), (245, 100)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_fused_radices(dt, prec):
+    """Schedules 4 and 5 (fused radices, powers of two first or last) on
+    every pass of lengths that use 9 and 15 and the leftover rules (the
+    every-schedule test covers 6, 10, 12, 14, 15, 16): every node against the
+    oracle."""
+    pts = [synth.generators.uniform_points(2, 40 + 10 * i, seed=970 + i) for i in range(len(FUSED_DIMS))]
+    taus = [2.0 / d[0] for d in FUSED_DIMS]
+    plan = dt.BatchPlan(FUSED_DIMS, taus, precision=prec, graph=False)
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(p) for p in pts])
+    Y = Y.cuda()
+    for fam in (4, 5):
+        plan.set_schedule([[fam, fam, fam]] * len(FUSED_DIMS))
+        S, G = plan.forward(Y, offs)
+        torch.cuda.synchronize()
+        assert plan.last_error() == 0
+        for i, (dims, tau) in enumerate(zip(FUSED_DIMS, taus)):
+            s, g = plan.views(S, G)[i]
+            _check_instance(f"fused schedule {fam} inst {i} {dims}", prec, dims, tau, pts[i], _np(s), _np(g), None,
+                            plan.stats(i))
 
 
 RED_DIMS = [(300, 300), (200, 260), (128, 96), (90, 400)]
