@@ -161,7 +161,9 @@ typedef struct {
   uint32_t error_bits;   /* sticky device error bits (1 = range, 2 = non-finite) */
 } dt_call_stats;
 
-/* Create a plan.  dims/spacing/origin have ndim entries (x first); tau > 0.
+/* Create a plan.  dims/spacing/origin have ndim entries (x first); tau > 0
+ * is fixed for the plan's lifetime (its kernel spectra are built for it; a
+ * different tau needs a new plan).
  * out_mask selects the kernel families to prepare.  trunc_dist and k_hint
  * only matter for DT_AUTO: the plan uses float32 if a node at distance
  * trunc_dist from an isolated source stays valid for k_hint distinct

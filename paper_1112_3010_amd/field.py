@@ -296,11 +296,19 @@ class Plan:
 
 class DistanceField(torch.autograd.Function):
     """S = distance field of the sources Y on ``plan``'s grid; the backward
-    pass runs the library's adjoint and returns dL/dY and dL/dtau.  The tau
-    gradient holds the kernel spectra (built for the plan's tau) fixed."""
+    pass runs the library's adjoint and returns dL/dY and dL/dtau.  The plan's
+    kernel spectra are built for one tau: the tau input must equal plan.tau
+    (checked, ValueError otherwise; the check reads the value on the host and
+    is skipped while a stream is being captured), and a step in tau needs a
+    new plan."""
 
     @staticmethod
     def forward(ctx, Y, tau, plan):
+        if not (tau.is_cuda and torch.cuda.is_current_stream_capturing()):
+            t = float(tau)
+            if abs(t - plan.tau) > 1e-12 * abs(plan.tau):
+                raise ValueError(f"tau = {t!r} differs from the plan's tau = {plan.tau!r}: "
+                                 "the kernel spectra are built for the plan's tau; create a plan for the new tau")
         S = plan.distance(Y)
         ctx.plan = plan
         ctx.save_for_backward(Y, S)

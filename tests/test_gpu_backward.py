@@ -84,6 +84,22 @@ def test_autograd_matches_oracle_gradient(dt):
     assert e_y <= 2e-7 and e_t <= 1e-10
 
 
+def test_autograd_refuses_a_tau_other_than_the_plans(dt):
+    """The kernel spectra belong to the plan's tau: a different tau input is
+    an error, not a silent forward at the old tau."""
+    dims = (40, 36)
+    h = tuple(1.0 / n for n in dims)
+    plan = dt.Plan(dims, h, None, 2.0 * h[0], precision="fp32", outputs=["S", "backward"])
+    Y = torch.from_numpy(synth.generators.uniform_points(2, 10, seed=505)).cuda().requires_grad_(True)
+    import paper_1112_3010_amd as dtm
+    ok = torch.tensor(plan.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    dtm.distance_field(Y, plan, ok).sum().backward()
+    assert ok.grad is not None and Y.grad is not None
+    bad = torch.tensor(plan.tau * 1.01, dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(ValueError):
+        dtm.distance_field(Y, plan, bad)
+
+
 # dL/dY of the float64 path is held to float32 storage rounding (2e-7); the
 # other bounds are about 50 times the errors measured on an MI355X (float32:
 # 1.8e-7 and 2.7e-8; float64 dL/dtau: 4e-15).
