@@ -617,6 +617,33 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
     grad_ms = e0.elapsed_time(e1) / steps
     log(f"fp64x2 S + grad: {grad_ms:.3f} ms")
     del plan
+    # 3D: 128^3 with 4096 points near a sphere, tau = h (256^3 padded), S and
+    # S + grad S in double-double beside float64
+    n3 = 128
+    dims3 = (n3,) * 3
+    h3 = (1.0 / n3,) * 3
+    Y3 = torch.from_numpy(synth.jittered_sphere_points(4096, 0.3, 2.0 / n3, seed=11)).cuda()
+    d3 = {}
+    for prec, outs in (("fp64x2", ["S"]), ("fp64x2", ["S", "grad"]), ("fp64", ["S", "grad"])):
+        plan = dt.Plan(dims3, h3, None, h3[0], precision=prec, outputs=outs)
+        fwd = (lambda: plan.distance(Y3)) if outs == ["S"] else (lambda: plan.gradient(Y3))
+        for _ in range(max(1, warmup // 2)):
+            fwd()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = max(3, steps // 4)
+        for _ in range(reps):
+            fwd()
+        e1.record()
+        torch.cuda.synchronize()
+        key = f"{prec}_{'_'.join(outs)}"
+        d3[key] = {"ms": round(e0.elapsed_time(e1) / reps, 3),
+                   "s_max_over_tau": round(plan.last_stats()["s_max"] / h3[0], 2), "padded": list(plan.padded)}
+        log(f"3D 128^3 {key}: {d3[key]}")
+        del plan
+    torch.cuda.empty_cache()
     r = res["fp64x2"]
     Mx, My = r["padded"]
     col_ms = r["pass_ms"]["dd_col_fused"]
@@ -633,6 +660,7 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
                          "kernel": "dd_col_fused", "ops_per_launch": ops},
             "pass_ms": r["pass_ms"], "s_max_over_tau": round(r["s_max_over_tau"], 2),
             "with_grad_ms_per_step": round(grad_ms, 4),
+            "3d_128cube_sphere4096_tau1h": d3,
             "fp64": {"ms_per_step": round(res["fp64"]["ms"], 4), "pass_ms": res["fp64"]["pass_ms"],
                      "s_max_over_tau": round(res["fp64"]["s_max_over_tau"], 2)}}
     if not no_cpu:

@@ -6,20 +6,24 @@
 
 namespace dt {
 
-// Geometry of a 2D double-double plan; Mx, My are powers of two.
+// Geometry of a double-double plan; Mx, My, Mz are powers of two (a 2D
+// plan has nz = Mz = 1, logMz = 0).
 struct DDGeom {
   int nx, ny, Mx, My, logMx, logMy;
   double hx, hy, ox, oy, tau;
+  int ndim, nz, Mz, logMz;
+  double hz, oz;
 };
 
 // Bytes of one complex double-double value and one real one.
 constexpr size_t kDDComplexBytes = 32, kDDRealBytes = 16;
 
-// Plan time: twiddles of both axes, then for each table t < n_tabs (0: f,
-// 1 + a: the gradient kernel of axis a) the samples into G (scratch,
-// My x Mx complex) and their transform; tabs receives the scaled real
-// (t = 0) or imaginary (t > 0) spectra, My x Mx each.
-hipError_t dd_build_tables(void* twx, void* twy, void* tabs, int n_tabs, void* G, const DDGeom& g, hipStream_t st);
+// Plan time: twiddles of every axis (twz unused in 2D), then for each table
+// t < n_tabs (0: f, 1 + a: the gradient kernel of axis a) the samples into G
+// (scratch, Mz x My x Mx complex) and their transform; tabs receives the
+// scaled real (t = 0) or imaginary (t > 0) spectra, Mz x My x Mx each.
+hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
+                           hipStream_t st);
 // Multiplicities into cnt (cleared by the caller) and sum m^2 into *msq
 // (left at 0 by dd_launch_finalize, which consumes it).
 hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
@@ -36,5 +40,14 @@ hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, in
 // and, for C = 3, grad (2 x ny x nx); either may be null.
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, const double* scal,
                                  const DDGeom& g, hipStream_t st);
+
+// 3D: the forward S (and grad S) pipeline of a double-double plan with
+// C = 1 (f) or 4 (f and the three gradient kernels): rows of the nz x ny
+// source rows into G, forward y into Gc, z columns forward / times each
+// spectrum / inverse into G (C x nz x My x Mx), inverse y into Gc
+// (C x nz x ny x Mx), inverse rows with the epilogue.
+hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
+                                const void* twy, const void* twz, double* S, double* grad, const double* scal,
+                                const DDGeom& g, hipStream_t st);
 
 }  // namespace dt

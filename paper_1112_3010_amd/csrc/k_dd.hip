@@ -1,4 +1,4 @@
-// Extended-precision (double-double) pipeline for 2D distance fields.
+// Extended-precision (double-double) pipeline for 2D and 3D distance fields.
 //
 // The same zero-padded FFT convolution as the float32/float64 paths
 // (Sec. 3, Table 1: splat the indicator, transform, multiply by the kernel
@@ -8,7 +8,7 @@
 // convolution fails far from the sources for small tau and resorts to
 // multiple-precision arithmetic; this pipeline plays that role on the GPU.
 //
-// Layout in the plan's workspace (x fastest, M = padded lengths):
+// Layout in the plan's workspace (x fastest, M = padded lengths; 2D):
 //   twx, twy  M/2 complex double-double twiddles exp(-2 pi i k / M)
 //   tabs      C spectra, My x Mx double-double each, scaled by 1/(Mx My): the
 //             real spectrum of f, then the imaginary parts of the gradient
@@ -16,6 +16,8 @@
 //   cnt       ny x nx float64 multiplicities (the indicator g)
 //   G         My x Mx complex double-double work grid (row spectra)
 //   Gc        C x ny x Mx complex double-double (column-pass outputs)
+// 3D plans add twz, take Mz x My x Mx spectra (C = 4 with the gradient) and
+// run the y and z axes as strided line passes (dd_launch_forward_3d).
 // The transforms are radix-2 in LDS (stages fused in pairs), one row or
 // column per block:
 // decimation in time (bit-reversed in, natural out) forward and decimation
@@ -166,21 +168,75 @@ __global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
 // product.
 __global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)g.Mx * g.My) return;
-  const int x = (int)(i % g.Mx), y = (int)(i / g.Mx);
+  if (i >= (int64_t)g.Mx * g.My * g.Mz) return;
+  const int x = (int)(i % g.Mx), y = (int)((i / g.Mx) % g.My), z = (int)(i / ((int64_t)g.Mx * g.My));
   ddc v = zero_c();
-  if (x != g.Mx / 2 && y != g.My / 2) {
+  if (x != g.Mx / 2 && y != g.My / 2 && (g.ndim == 2 || z != g.Mz / 2)) {
     const int dx = x < g.Mx / 2 ? x : x - g.Mx;
     const int dy = y < g.My / 2 ? y : y - g.My;
+    const int dz = z < g.Mz / 2 ? z : z - g.Mz;
     const dd px = ddm::two_prod(g.hx, (double)dx), py = ddm::two_prod(g.hy, (double)dy);
-    const dd r = ddm::sqrt(ddm::add(ddm::mul(px, px), ddm::mul(py, py)));
+    const dd pz = g.ndim == 3 ? ddm::two_prod(g.hz, (double)dz) : dd{0.0, 0.0};
+    dd r2 = ddm::add(ddm::mul(px, px), ddm::mul(py, py));
+    if (g.ndim == 3) r2 = ddm::add(r2, ddm::mul(pz, pz));
+    const dd r = ddm::sqrt(r2);
     const dd f = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
     if (kind == 0)
       v.re = f;
     else if (r.hi > 0.0)
-      v.re = ddm::mul(ddm::div(kind == 1 ? px : py, r), f);
+      v.re = ddm::mul(ddm::div(kind == 1 ? px : kind == 2 ? py : pz, r), f);
   }
   G[i] = v;
+}
+
+// Strided lines of one axis: line l < n_lines is (o, i) = (l / n_inner,
+// l % n_inner), its element j at o * outer + j * stride + i.
+struct DDLines {
+  int M, logM, n_inner, n_in, n_out;
+  int64_t n_lines, in_outer, in_stride, out_outer, out_stride;
+};
+
+// Forward transform of each line (input elements j >= n_in are zero).
+// MODE 0: complex spectrum to out; 1 / 2: its real / imaginary part times
+// 2^scale_e to tab.  A block reads its whole line before writing, so in and
+// out may be the same array.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const ddc* __restrict__ in, ddc* __restrict__ out,
+                                                          dd* __restrict__ tab, const ddc* __restrict__ tw,
+                                                          DDLines L, int scale_e) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int64_t l = blockIdx.x;
+  const int64_t o = l / L.n_inner, i = l % L.n_inner;
+  const ddc* src = in + o * L.in_outer + i;
+  for (int j = threadIdx.x; j < L.M; j += blockDim.x)
+    buf[brev(j, L.logM)] = j < L.n_in ? src[(int64_t)j * L.in_stride] : zero_c();
+  __syncthreads();
+  fft_dit<false>(buf, L.M, L.logM, tw);
+  if (MODE == 0) {
+    ddc* dst = out + o * L.out_outer + i;
+    for (int k = threadIdx.x; k < L.M; k += blockDim.x) dst[(int64_t)k * L.out_stride] = buf[k];
+  } else {
+    dd* dst = tab + o * L.out_outer + i;
+    for (int k = threadIdx.x; k < L.M; k += blockDim.x)
+      dst[(int64_t)k * L.out_stride] = ddm::scale2(MODE == 2 ? buf[k].im : buf[k].re, scale_e);
+  }
+}
+
+// Inverse (unnormalised) transform of each line from its natural-order
+// spectrum; the first n_out samples are kept.
+__global__ __launch_bounds__(kThreads) void k_dd_line_inv(const ddc* __restrict__ in, ddc* __restrict__ out,
+                                                          const ddc* __restrict__ tw, DDLines L) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int64_t l = blockIdx.x;
+  const int64_t o = l / L.n_inner, i = l % L.n_inner;
+  const ddc* src = in + o * L.in_outer + i;
+  for (int k = threadIdx.x; k < L.M; k += blockDim.x) buf[k] = src[(int64_t)k * L.in_stride];
+  __syncthreads();
+  fft_dif<true>(buf, L.M, L.logM, tw);
+  ddc* dst = out + o * L.out_outer + i;
+  for (int y = threadIdx.x; y < L.n_out; y += blockDim.x) dst[(int64_t)y * L.out_stride] = buf[brev(y, L.logM)];
 }
 
 // Forward transform of rows.  REAL_IN: row y of the ny x nx multiplicities,
@@ -233,19 +289,27 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_table(const ddc* __restrict
 // (My <= kSpecPerThread * blockDim.x), so the forward transform runs once.
 constexpr int kSpecPerThread = 8;
 
+// The last axis of a plan: transform length M, a line every `stride`
+// elements (2D: Mx, line kx; 3D: My Mx, line ky Mx + kx), n rows present and
+// kept, output channels `plane` apart, spectra `tab_chan` apart.
+struct DDFused {
+  int M, logM, n;
+  int64_t stride, plane, tab_chan;
+};
+
 template <bool MULTI>
 __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
                                                            const dd* __restrict__ tabs, const ddc* __restrict__ tw,
-                                                           DDGeom g, int C) {
+                                                           DDFused F, int C) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
-  const int kx = blockIdx.x;
-  const int M = g.My;
-  const int64_t npad = (int64_t)g.Mx * g.My, plane = (int64_t)g.ny * g.Mx;
+  const int64_t kx = blockIdx.x;   // the line
+  const int M = F.M;
+  const int64_t npad = F.tab_chan, plane = F.plane;
   for (int y = threadIdx.x; y < M; y += blockDim.x)
-    buf[brev(y, g.logMy)] = y < g.ny ? Gin[(int64_t)y * g.Mx + kx] : zero_c();
+    buf[brev(y, F.logM)] = y < F.n ? Gin[(int64_t)y * F.stride + kx] : zero_c();
   __syncthreads();
-  fft_dit<false>(buf, M, g.logMy, tw);
+  fft_dit<false>(buf, M, F.logM, tw);
   ddc sp[MULTI ? kSpecPerThread : 1];
   if (MULTI) {
 #pragma unroll
@@ -260,14 +324,14 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
     for (int k = 0; k < (MULTI ? kSpecPerThread : M / kThreads + 1); ++k) {
       const int ky = threadIdx.x + k * blockDim.x;
       if (ky >= M) break;
-      const dd t = tab[(int64_t)ky * g.Mx + kx];
+      const dd t = tab[(int64_t)ky * F.stride + kx];
       const ddc a = MULTI ? sp[k] : buf[ky];
       // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
       buf[ky] = c == 0 ? ddm::cmul_real(a, t) : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
     }
     __syncthreads();
-    fft_dif<true>(buf, M, g.logMy, tw);
-    for (int y = threadIdx.x; y < g.ny; y += blockDim.x) Gout[c * plane + (int64_t)y * g.Mx + kx] = buf[brev(y, g.logMy)];
+    fft_dif<true>(buf, M, F.logM, tw);
+    for (int y = threadIdx.x; y < F.n; y += blockDim.x) Gout[c * plane + (int64_t)y * F.stride + kx] = buf[brev(y, F.logM)];
     __syncthreads();
   }
 }
@@ -325,15 +389,17 @@ __global__ __launch_bounds__(256) void k_dd_splat(const float* __restrict__ Y, i
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double inc = 0.0;
   if (k < K) {
-    const double y0 = Y[2 * k], y1 = Y[2 * k + 1];
-    if (!__builtin_isfinite(y0) || !__builtin_isfinite(y1)) {
+    const int D = g.ndim;
+    const double y0 = Y[D * k], y1 = Y[D * k + 1], y2 = D == 3 ? Y[D * k + 2] : 0.0;
+    if (!__builtin_isfinite(y0) || !__builtin_isfinite(y1) || !__builtin_isfinite(y2)) {
       atomicOr(err, 2u);
     } else {
       const double fx = __builtin_floor((y0 - g.ox) / g.hx), fy = __builtin_floor((y1 - g.oy) / g.hy);
-      if (!(fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny)) {
+      const double fz = D == 3 ? __builtin_floor((y2 - g.oz) / g.hz) : 0.0;
+      if (!(fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny && fz >= 0.0 && fz < (double)g.nz)) {
         atomicOr(err, 1u);
       } else {
-        const double old = atomicAdd(&cnt[(int64_t)fy * g.nx + (int64_t)fx], 1.0);
+        const double old = atomicAdd(&cnt[((int64_t)fz * g.ny + (int64_t)fy) * g.nx + (int64_t)fx], 1.0);
         inc = 2.0 * old + 1.0;
       }
     }
@@ -348,10 +414,10 @@ __global__ __launch_bounds__(256) void k_dd_splat(const float* __restrict__ Y, i
 __global__ void k_dd_finalize(double* __restrict__ msq, double* __restrict__ scal, DDGeom g, double c_theta,
                               double unit, double l1) {
   if (threadIdx.x != 0) return;
-  const double npad = (double)g.Mx * (double)g.My;
+  const double npad = (double)g.Mx * (double)g.My * (double)g.Mz;
   const double gl2 = __builtin_sqrt(*msq);
   *msq = 0.0;
-  const double theta = c_theta * unit * (double)(g.logMx + g.logMy) * l1 * gl2 / __builtin_sqrt(npad);
+  const double theta = c_theta * unit * (double)(g.logMx + g.logMy + g.logMz) * l1 * gl2 / __builtin_sqrt(npad);
   scal[0] = theta;
   scal[1] = -g.tau * log(theta);
   scal[2] = gl2;
@@ -369,9 +435,44 @@ hipError_t allow_lds(F kern, size_t lds) {
 
 }  // namespace
 
-hipError_t dd_build_tables(void* twx, void* twy, void* tabs, int n_tabs, void* G, const DDGeom& g, hipStream_t st) {
+// 3D tables: rows of the Mz x My sample rows in place, then the y lines in
+// place, then the z lines into the real or imaginary spectrum.
+hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
+                              hipStream_t st) {
+  k_dd_twiddles<<<(g.Mz / 2 + 255) / 256, 256, 0, st>>>((ddc*)twz, g.Mz);
+  const int64_t plane = (int64_t)g.Mx * g.My, total = plane * g.Mz;
+  const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc), lz = (size_t)g.Mz * sizeof(ddc);
+  hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
+  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<0>, ly);
+  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<1>, lz);
+  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<2>, lz);
+  if (e != hipSuccess) return e;
+  DDGeom rows = g;
+  rows.ny = g.My * g.Mz;   // every sample row
+  DDLines ly_{g.My, g.logMy, g.Mx, g.My, g.My, (int64_t)g.Mz * g.Mx, plane, g.Mx, plane, g.Mx};
+  DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane};
+  for (int t = 0; t < n_tabs; ++t) {
+    dd* tab = (dd*)tabs + t * total;
+    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t);
+    k_dd_row_fwd<false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, rows);
+    k_dd_line_fwd<0><<<(unsigned)ly_.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy,
+                                                                  ly_, 0);
+    const int e_scale = -(g.logMx + g.logMy + g.logMz);
+    if (t == 0)
+      k_dd_line_fwd<1><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
+                                                                    e_scale);
+    else
+      k_dd_line_fwd<2><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
+                                                                    e_scale);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
+                           hipStream_t st) {
   k_dd_twiddles<<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((ddc*)twx, g.Mx);
   k_dd_twiddles<<<(g.My / 2 + 255) / 256, 256, 0, st>>>((ddc*)twy, g.My);
+  if (g.ndim == 3) return dd_build_tables_3d(twx, twy, twz, tabs, n_tabs, G, g, st);
   const int64_t total = (int64_t)g.Mx * g.My;
   const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc);
   hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
@@ -410,20 +511,57 @@ hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const 
   return hipGetLastError();
 }
 
-hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
-                               hipStream_t st) {
-  const size_t lds = (size_t)g.My * sizeof(ddc);
+static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* tw, const DDFused& F,
+                               int64_t lines, hipStream_t st) {
+  const size_t lds = (size_t)F.M * sizeof(ddc);
   if (C > 1) {
-    if (g.My > kSpecPerThread * kThreads) return hipErrorInvalidValue;
+    if (F.M > kSpecPerThread * kThreads) return hipErrorInvalidValue;
     const hipError_t e = allow_lds(k_dd_col_fused<true>, lds);
     if (e != hipSuccess) return e;
-    k_dd_col_fused<true><<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
+    k_dd_col_fused<true><<<(unsigned)lines, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs,
+                                                                 (const ddc*)tw, F, C);
   } else {
     const hipError_t e = allow_lds(k_dd_col_fused<false>, lds);
     if (e != hipSuccess) return e;
-    k_dd_col_fused<false><<<g.Mx, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs, (const ddc*)twy, g, C);
+    k_dd_col_fused<false><<<(unsigned)lines, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs,
+                                                                  (const ddc*)tw, F, C);
   }
   return hipGetLastError();
+}
+
+hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
+                               hipStream_t st) {
+  const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My};
+  return launch_fused(Gin, Gout, tabs, C, twy, F, g.Mx, st);
+}
+
+hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
+                                const void* twy, const void* twz, double* S, double* grad, const double* scal,
+                                const DDGeom& g, hipStream_t st) {
+  if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
+  const int64_t MyMx = (int64_t)g.My * g.Mx;
+  DDGeom rows = g;
+  rows.ny = g.ny * g.nz;   // the source rows (z, y), y fastest
+  hipError_t e = dd_launch_row_fwd(cnt, G, twx, rows, st);
+  if (e != hipSuccess) return e;
+  // forward y: G [z][y < ny][kx] -> Gc [z][ky][kx]
+  const size_t ly = (size_t)g.My * sizeof(ddc);
+  e = allow_lds(k_dd_line_fwd<0>, ly);
+  if (e == hipSuccess) e = allow_lds(k_dd_line_inv, ly);
+  if (e != hipSuccess) return e;
+  const DDLines yf{g.My, g.logMy, g.Mx, g.ny, g.My, (int64_t)g.nz * g.Mx, (int64_t)g.ny * g.Mx, g.Mx, MyMx, g.Mx};
+  k_dd_line_fwd<0><<<(unsigned)yf.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf,
+                                                               0);
+  // z lines (ky, kx): forward, times each spectrum, inverse -> G [c][z < nz][ky][kx]
+  const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz};
+  e = launch_fused(Gc, G, tabs, C, twz, F, MyMx, st);
+  if (e != hipSuccess) return e;
+  // inverse y: G [c z][ky][kx] -> Gc [c z][y < ny][kx]
+  const DDLines yi{g.My, g.logMy, g.Mx, g.My, g.ny, (int64_t)C * g.nz * g.Mx, MyMx, g.Mx, (int64_t)g.ny * g.Mx, g.Mx};
+  k_dd_line_inv<<<(unsigned)yi.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, scal, rows, st);
 }
 
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, const double* scal,

@@ -107,8 +107,8 @@ struct dt_plan_s {
   // double-double plans (2D, S only) use their own workspace regions
   bool dd = false;
   DDGeom ddg{};
-  int dd_tabs = 1;       // 1: f; 3: f and the two gradient kernels
-  size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0, off_dd_Gc = 0;
+  int dd_tabs = 1;       // 1: f; 1 + ndim: f and the gradient kernels
+  size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_twz = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0, off_dd_Gc = 0;
   // optional per-pass timing
   bool timing = false;
   struct Pending { std::string name; hipEvent_t a, b; };
@@ -264,32 +264,45 @@ int log2_exact(int64_t m) {
 // outputs.
 void setup_dd(dt_plan p) {
   p->dd = true;
-  p->dd_tabs = (p->mask & DT_OUT_GRAD) ? 3 : 1;
+  const bool d3 = p->ndim == 3;
+  p->dd_tabs = (p->mask & DT_OUT_GRAD) ? 1 + p->ndim : 1;
   p->fp64 = true;  // outputs are float64
   p->w = 8;
   DDGeom& g = p->ddg;
+  g.ndim = p->ndim;
   g.nx = (int)p->n[0];
   g.ny = (int)p->n[1];
+  g.nz = d3 ? (int)p->n[2] : 1;
   g.Mx = (int)p->M[0];
   g.My = (int)p->M[1];
+  g.Mz = d3 ? (int)p->M[2] : 1;
   g.logMx = log2_exact(p->M[0]);
   g.logMy = log2_exact(p->M[1]);
+  g.logMz = d3 ? log2_exact(p->M[2]) : 0;
   g.hx = p->h[0];
   g.hy = p->h[1];
+  g.hz = d3 ? p->h[2] : 1.0;
   g.ox = p->o[0];
   g.oy = p->o[1];
+  g.oz = d3 ? p->o[2] : 0.0;
   g.tau = p->tau;
-  const size_t npad = (size_t)g.Mx * g.My;
+  const size_t npad = (size_t)g.Mx * g.My * g.Mz, C = (size_t)p->dd_tabs;
+  // 2D: G holds the row spectra, Gc the column-pass outputs.  3D: G holds
+  // the table samples, the row spectra and the z-pass outputs; Gc the y-pass
+  // outputs in both directions.
+  const size_t Gsz = d3 ? std::max(npad, C * g.nz * g.My * g.Mx) : npad;
+  const size_t Gcsz = d3 ? std::max((size_t)g.nz * g.My * g.Mx, C * g.nz * g.ny * g.Mx) : C * g.ny * g.Mx;
   size_t off = 0;
   p->off_scal = off; off = align_up(off + 64 * sizeof(double));
   p->off_err = off; off = align_up(off + sizeof(uint32_t));
   p->off_R1 = off;  // end of the region cleared at attach
   p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * kDDComplexBytes);
   p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * kDDComplexBytes);
-  p->off_dd_tab = off; off = align_up(off + (size_t)p->dd_tabs * npad * kDDRealBytes);
-  p->off_dd_cnt = off; off = align_up(off + (size_t)g.nx * g.ny * sizeof(double));
-  p->off_dd_G = off; off = align_up(off + npad * kDDComplexBytes);
-  p->off_dd_Gc = off; off = align_up(off + (size_t)p->dd_tabs * g.ny * g.Mx * kDDComplexBytes);
+  p->off_dd_twz = off; off = align_up(off + (size_t)std::max(g.Mz / 2, 1) * kDDComplexBytes);
+  p->off_dd_tab = off; off = align_up(off + C * npad * kDDRealBytes);
+  p->off_dd_cnt = off; off = align_up(off + (size_t)g.nx * g.ny * g.nz * sizeof(double));
+  p->off_dd_G = off; off = align_up(off + Gsz * kDDComplexBytes);
+  p->off_dd_Gc = off; off = align_up(off + Gcsz * kDDComplexBytes);
   p->ws_bytes = off;
 }
 
@@ -374,8 +387,12 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    // double-double is a candidate only where it is built: 2D plans of S and grad S
-    const int n_cand = (ndim == 2 && !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD))) ? 3 : 2;
+    // double-double is a candidate only where it is built: plans of S and grad S
+    // (3D up to 256 nodes per axis)
+    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD));
+    if (ndim == 3)
+      for (int a = 0; a < 3; ++a) dd_ok = dd_ok && dims[a] <= 256;
+    const int n_cand = dd_ok ? 3 : 2;
     const int cands[3] = {DT_FP32_SCALED, DT_FP64, DT_FP64X2};
     const int ubits[3] = {24, 53, 104};
     for (int c = 0; c < n_cand && chosen < 0; ++c) {
@@ -391,7 +408,10 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   }
   p->prec = precision;
   if (precision == DT_FP64X2) {
-    if (ndim != 2 || (out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD))) {
+    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD));
+    if (ndim == 3)
+      for (int a = 0; a < 3; ++a) ok = ok && dims[a] <= 256;   // 512^3 padded: about 22 GB of workspace
+    if (!ok) {
       delete p;
       return DT_E_UNSUPPORTED;
     }
@@ -635,11 +655,11 @@ dt_status dt::plan_attach(dt_plan p, void* dev_ptr, size_t bytes, void* stream) 
   // clear the scalars, the error word and the pitch padding of the table region
   launch_fill_zero<double>((double*)p->ws, (int64_t)(p->off_R1 / sizeof(double)), st);
   if (p->dd) {
-    hipError_t e = dd_build_tables(p->ws + p->off_dd_twx, p->ws + p->off_dd_twy, p->ws + p->off_dd_tab,
-                                   p->dd_tabs, p->ws + p->off_dd_G, p->ddg, st);
+    hipError_t e = dd_build_tables(p->ws + p->off_dd_twx, p->ws + p->off_dd_twy, p->ws + p->off_dd_twz,
+                                   p->ws + p->off_dd_tab, p->dd_tabs, p->ws + p->off_dd_G, p->ddg, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return DT_E_HIP;
-    p->kernel_l1 = host_kernel_l1(p->M, p->h, 2, p->tau);
+    p->kernel_l1 = host_kernel_l1(p->M, p->h, p->ndim, p->tau);
     p->ready = true;
     return DT_OK;
   }
@@ -1010,8 +1030,8 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
                          hipStream_t st) {
   if (out->hess || out->label || out->mu || out->curv || out->signed_outputs || shape) return DT_E_UNSUPPORTED;
   if ((!out->S && !out->grad) || !Y || K < 1) return DT_E_ARG;
-  if (out->grad && p->dd_tabs < 3) return DT_E_ARG;   // gradient kernels not prepared
-  const int C = out->grad ? 3 : 1;
+  if (out->grad && p->dd_tabs < 1 + p->ndim) return DT_E_ARG;   // gradient kernels not prepared
+  const int C = out->grad ? 1 + p->ndim : 1;
   if (!p->usable()) return DT_E_WORKSPACE;
   const DDGeom& g = p->ddg;
   double* cnt = (double*)(p->ws + p->off_dd_cnt);
@@ -1019,11 +1039,18 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   hipError_t e;
   {
     PassTimer t(p, st, "splat");
-    launch_fill_zero<double>(cnt, (int64_t)g.nx * g.ny, st);
+    launch_fill_zero<double>(cnt, (int64_t)g.nx * g.ny * g.nz, st);
     e = dd_launch_splat(Y, K, cnt, p->msq(), p->err(), g, st);
     if (e == hipSuccess) e = dd_launch_finalize(p->msq(), p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
+  if (g.ndim == 3) {
+    PassTimer t(p, st, "dd_forward_3d");
+    e = dd_launch_forward_3d(cnt, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, C, p->ws + p->off_dd_twx,
+                             p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, (double*)out->S, (double*)out->grad,
+                             p->scal(), g, st);
+    return hip_status(e);
+  }
   {
     PassTimer t(p, st, "dd_row_fwd");
     e = dd_launch_row_fwd(cnt, G, p->ws + p->off_dd_twx, g, st);

@@ -166,7 +166,16 @@ def test_fp64x2_plans(lib):
     assert st == 0
     lib.dt_destroy_plan(h)
     assert _plan(lib, prec=3, mask=5)[0] == 6                        # Hessian not built
-    assert _plan(lib, ndim=3, dims=(32, 32, 32), prec=3, mask=1)[0] == 6
+    st, h = _plan(lib, ndim=3, dims=(32, 32, 30), prec=3, mask=3)    # 3D S and grad S
+    assert st == 0
+    assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+    assert info.precision == 3 and tuple(info.padded[:3]) == (64, 64, 64)
+    assert lib.dt_plan_workspace_size(h, ctypes.byref(size)) == 0
+    # four spectra (f and three gradient kernels), the complex work grids
+    assert size.value >= 64 ** 3 * (4 * 16 + 32)
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, ndim=3, dims=(257, 32, 32), prec=3, mask=1)[0] == 6   # 3D up to 256 per axis
+    assert _plan(lib, ndim=3, dims=(32, 32, 32), prec=3, mask=9)[0] == 6    # no sign channels
 
 
 def test_auto_picks_fp64x2_for_2d_distance(lib):

@@ -171,4 +171,91 @@ def test_dd_rejects_what_it_does_not_build(dt):
     with pytest.raises(Exception):
         dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "hess"])
     with pytest.raises(Exception):
-        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S"])
+        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S", "hess"])
+    with pytest.raises(Exception):
+        dt.Plan((300, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S"])
+
+
+# ---------------------------------------------------------------------------
+# 3D double-double plans (S and grad S)
+# ---------------------------------------------------------------------------
+
+def _clustered3(n_pts, frac, seed):
+    rng = np.random.default_rng(seed)
+    p = rng.random((n_pts, 3))
+    p[:, 0] *= frac
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("dims,K,tau_h", [((40, 36, 33), 5, 1.0), ((96, 40, 30), 12, 0.5)])
+def test_dd3d_distance_and_gradient_vs_oracle(dt, dims, K, tau_h):
+    """3D (rows, strided y lines, fused z lines, all in double-double): S and
+    grad S on every node against the oracle, to the float64 per-node bound
+    with the double-double unit; nodes beyond the float64 band are resolved;
+    S of the S + grad S plan equals the S-only plan's."""
+    pts = _clustered3(K, 0.25, seed=720 + K)
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    Y = torch.from_numpy(pts).cuda()
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad"])
+    assert plan.precision == "fp64x2" and plan.padded == tuple(parity.padded(n) for n in dims)
+    S, g = plan.gradient(Y)
+    S_only = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S"]).distance(Y)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    assert torch.equal(S, S_only)
+    ref = parity.reference(dims, h, (0.0,) * 3, tau, pts, "fp64x2", grad=True)
+    stats = plan.last_stats()
+    assert stats["g_l2"] == pytest.approx(ref["g_l2"], rel=1e-12)
+    assert stats["theta"] == pytest.approx(ref["theta"], rel=1e-9)
+    S = S.cpu().numpy().ravel()
+    g = g.cpu().numpy().reshape(3, -1)
+    dS = np.abs(S - ref["S_ref"])
+    dG = np.abs(g - ref["grad"].T)
+    deep, valid = ref["deep"], ref["valid"]
+    theta64 = oracle.theta("fp64", ref["padded"], ref["kernel_l1"], ref["g_l2"])
+    beyond64 = deep & (ref["lnphi"] < np.log(theta64))
+    print(f"\n[dd3d {dims}] max|dS|/tau all={dS.max() / tau:.3e} deep={dS[deep].max() / tau:.3e} "
+          f"max|dgrad| deep={dG[:, deep].max():.3e} S_max/tau={ref['s_max'] / tau:.2f} "
+          f"(fp64 {oracle.s_max(tau, theta64) / tau:.2f}) valid={valid.mean():.3f} beyond fp64={beyond64.sum()}")
+    assert dS.max() <= parity.TOL_S_TAU * tau
+    assert np.all(dS[deep] <= parity.bound(ref, TOL_S_TAU_DD, tau)[deep])
+    assert np.all(dG[:, deep] <= parity.bound(ref, TOL_GRAD_DD)[deep])
+    assert dG[:, valid].max() <= parity.TOL_GRAD
+    assert beyond64.sum() > 0
+    inval = ~valid & (ref["S_exact"] > ref["s_max"] + 0.05 * tau)
+    if tau_h < 1:
+        assert inval.sum() > 1000, "the grid must reach past the double-double band"
+    if inval.any():
+        np.testing.assert_allclose(S[inval], ref["s_max"], rtol=1e-12)
+        assert np.all(g[:, inval] == 0)
+
+
+def test_dd3d_single_source_is_exact_distance(dt):
+    """One source in 3D: S = r and grad S = (X - Y)/r over the whole
+    double-double band, without the oracle.  The source sits on a node."""
+    dims = (48, 40, 36)
+    h = (1.0 / 48,) * 3
+    tau = 0.5 * h[0]
+    node = (5, 20, 18)
+    Yc = np.array([[(node[a] + 0.5) * h[a] for a in range(3)]], dtype=np.float32)
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad"])
+    S, g = plan.gradient(torch.from_numpy(Yc).cuda())
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    s_max = plan.last_stats()["s_max"]
+    S = S.cpu().numpy().ravel()
+    g = g.cpu().numpy().reshape(3, -1)
+    zz, yy, xx = np.meshgrid(*[np.arange(dims[a]) for a in (2, 1, 0)], indexing="ij")
+    d = np.stack([(xx.ravel() - node[0]) * h[0], (yy.ravel() - node[1]) * h[1], (zz.ravel() - node[2]) * h[2]])
+    r = np.sqrt((d ** 2).sum(axis=0))
+    inside = r < s_max - np.log(2.0) * tau   # phi >= 2 Theta
+    assert inside.sum() > 20000 and s_max / tau > 55
+    # the per-node bound of the parity tests with Theta / phi = exp((r - S_max) / tau)
+    ratio = np.exp((r - s_max) / tau)
+    assert np.all(np.abs(S[inside] - r[inside]) <= tau * (TOL_S_TAU_DD + parity.TOL_THETA_FRAC * ratio[inside]))
+    away = inside & (r > 0)
+    dG = np.abs(g[:, away] - d[:, away] / r[away])
+    assert np.all(dG <= TOL_GRAD_DD + parity.TOL_THETA_FRAC * ratio[away])
+    beyond = r > s_max + 2.0 * tau
+    assert np.all(S[beyond] == s_max) and np.all(g[:, beyond] == 0)
