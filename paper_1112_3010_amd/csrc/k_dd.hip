@@ -42,6 +42,21 @@ __device__ __forceinline__ int brev(int x, int logM) { return (int)(__builtin_bi
 
 __device__ __forceinline__ ddc zero_c() { return {{0.0, 0.0}, {0.0, 0.0}}; }
 
+// Channels and spectra of a plan: 0 f, 1 .. ndim the gradient kernels (odd:
+// imaginary spectra), then the Hessian kernels in the order xx, xy, [xz,]
+// yy, [yz,] zz (even or odd in two axes: real spectra).
+__host__ __device__ __forceinline__ bool dd_imag_channel(int c, int ndim) { return c >= 1 && c <= ndim; }
+__device__ __forceinline__ void dd_hess_pair(int ndim, int h, int& i, int& j) {
+  if (ndim == 2) {
+    i = h == 2 ? 1 : 0;
+    j = h == 0 ? 0 : 1;
+  } else {
+    const int a[6] = {0, 0, 0, 1, 1, 2}, b[6] = {0, 1, 2, 1, 2, 2};
+    i = a[h];
+    j = b[h];
+  }
+}
+
 __device__ __forceinline__ ddc twiddle(const ddc* __restrict__ tw, int k, bool inv) {
   ddc w = tw[k];
   if (inv) w.im = ddm::neg(w.im);
@@ -181,10 +196,20 @@ __global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
     if (g.ndim == 3) r2 = ddm::add(r2, ddm::mul(pz, pz));
     const dd r = ddm::sqrt(r2);
     const dd f = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
-    if (kind == 0)
+    const dd p[3] = {px, py, pz};
+    if (kind == 0) {
       v.re = f;
-    else if (r.hi > 0.0)
-      v.re = ddm::mul(ddm::div(kind == 1 ? px : kind == 2 ? py : pz, r), f);
+    } else if (r.hi > 0.0 && kind <= g.ndim) {
+      v.re = ddm::mul(ddm::div(p[kind - 1], r), f);
+    } else if (r.hi > 0.0) {
+      // Hessian kernel (-n_i n_j / tau + (delta_ij - n_i n_j) / r) f
+      int a, b;
+      dd_hess_pair(g.ndim, kind - 1 - g.ndim, a, b);
+      const dd nn = ddm::mul(ddm::div(p[a], r), ddm::div(p[b], r));
+      const dd t1 = ddm::neg(ddm::div_d(nn, g.tau));
+      const dd t2 = ddm::div(a == b ? ddm::sub(dd{1.0, 0.0}, nn) : ddm::neg(nn), r);
+      v.re = ddm::mul(ddm::add(t1, t2), f);
+    }
   }
   G[i] = v;
 }
@@ -295,6 +320,7 @@ constexpr int kSpecPerThread = 8;
 struct DDFused {
   int M, logM, n;
   int64_t stride, plane, tab_chan;
+  int ndim;
 };
 
 template <bool MULTI>
@@ -327,7 +353,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
       const dd t = tab[(int64_t)ky * F.stride + kx];
       const ddc a = MULTI ? sp[k] : buf[ky];
       // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
-      buf[ky] = c == 0 ? ddm::cmul_real(a, t) : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
+      buf[ky] = !dd_imag_channel(c, F.ndim) ? ddm::cmul_real(a, t)
+                                            : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
     }
     __syncthreads();
     fft_dif<true>(buf, M, F.logM, tw);
@@ -338,14 +365,16 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
 
 // Inverse transforms of row y and the epilogue: phi = Re of channel 0,
 // S = -tau log phi where phi >= Theta, else S_max (scal[0] = Theta,
-// scal[1] = S_max); with C = 3 also grad_a S = psi_a / phi (eq. SxSyconv),
-// 0 where phi < Theta.  S or grad may be null.  phi stays in registers
-// (nx <= kMaxPerThread * blockDim.x) while the gradient channels are
-// transformed.
+// scal[1] = S_max); with the gradient channels also grad_a S = psi_a / phi
+// (eq. SxSyconv), and with the Hessian channels H_ij = chi_ij / phi +
+// S_i S_j / tau (eqs. Sxx, Syy, Sxy), all 0 where phi < Theta.  S, grad or
+// hess may be null.  phi and grad S stay in registers (nx <= kMaxPerThread
+// * blockDim.x) while the later channels are transformed.
 constexpr int kMaxPerThread = 4;
 
 __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
                                                              double* __restrict__ S, double* __restrict__ grad,
+                                                             double* __restrict__ hess,
                                                              const double* __restrict__ scal, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
@@ -353,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
   const int M = g.Mx;
   const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
   const double theta = scal[0], smax = scal[1];
-  double phi[kMaxPerThread];
+  double phi[kMaxPerThread], gs[kMaxPerThread][3];
   for (int c = 0; c < C; ++c) {
     for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
     __syncthreads();
@@ -370,9 +399,18 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
           const bool ok0 = v.hi > 0.0 && v.hi >= theta;
           S[(int64_t)y * g.nx + x] = ok0 ? -g.tau * (log(v.hi) + v.lo / v.hi) : smax;
         }
-      } else if (grad) {
+      } else {
         const bool ok = phi[k] > 0.0 && phi[k] >= theta;
-        grad[(c - 1) * nodes + (int64_t)y * g.nx + x] = ok ? v.hi / phi[k] : 0.0;
+        if (c <= g.ndim) {
+          const double gv = ok ? v.hi / phi[k] : 0.0;
+          gs[k][c - 1] = gv;
+          if (grad) grad[(c - 1) * nodes + (int64_t)y * g.nx + x] = gv;
+        } else if (hess) {
+          int a, b;
+          dd_hess_pair(g.ndim, c - 1 - g.ndim, a, b);
+          hess[(c - 1 - g.ndim) * nodes + (int64_t)y * g.nx + x] =
+              ok ? v.hi / phi[k] + gs[k][a] * gs[k][b] / g.tau : 0.0;
+        }
       }
     }
     __syncthreads();
@@ -458,7 +496,7 @@ hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n
     k_dd_line_fwd<0><<<(unsigned)ly_.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy,
                                                                   ly_, 0);
     const int e_scale = -(g.logMx + g.logMy + g.logMz);
-    if (t == 0)
+    if (!dd_imag_channel(t, g.ndim))
       k_dd_line_fwd<1><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
                                                                     e_scale);
     else
@@ -483,7 +521,7 @@ hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_ta
     dd* tab = (dd*)tabs + t * total;
     k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t);
     k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
-    if (t == 0)
+    if (!dd_imag_channel(t, g.ndim))
       k_dd_col_table<false><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
     else
       k_dd_col_table<true><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
@@ -531,13 +569,13 @@ static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, in
 
 hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
                                hipStream_t st) {
-  const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My};
+  const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My, g.ndim};
   return launch_fused(Gin, Gout, tabs, C, twy, F, g.Mx, st);
 }
 
 hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
-                                const void* twy, const void* twz, double* S, double* grad, const double* scal,
-                                const DDGeom& g, hipStream_t st) {
+                                const void* twy, const void* twz, double* S, double* grad, double* hess,
+                                const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
   const int64_t MyMx = (int64_t)g.My * g.Mx;
   DDGeom rows = g;
@@ -553,7 +591,7 @@ hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void
   k_dd_line_fwd<0><<<(unsigned)yf.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf,
                                                                0);
   // z lines (ky, kx): forward, times each spectrum, inverse -> G [c][z < nz][ky][kx]
-  const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz};
+  const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz, g.ndim};
   e = launch_fused(Gc, G, tabs, C, twz, F, MyMx, st);
   if (e != hipSuccess) return e;
   // inverse y: G [c z][ky][kx] -> Gc [c z][y < ny][kx]
@@ -561,16 +599,16 @@ hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void
   k_dd_line_inv<<<(unsigned)yi.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, scal, rows, st);
+  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, hess, scal, rows, st);
 }
 
-hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, const double* scal,
-                                 const DDGeom& g, hipStream_t st) {
+hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
+                                 const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
   const size_t lds = (size_t)g.Mx * sizeof(ddc);
   const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, scal, g, C);
+  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, scal, g, C);
   return hipGetLastError();
 }
 

@@ -165,7 +165,12 @@ def test_fp64x2_plans(lib):
     st, h = _plan(lib, prec=3, mask=3)                               # S and grad S
     assert st == 0
     lib.dt_destroy_plan(h)
-    assert _plan(lib, prec=3, mask=5)[0] == 6                        # Hessian not built
+    st, h = _plan(lib, prec=3, mask=5)                               # S and the Hessian
+    assert st == 0
+    assert lib.dt_hessian(h, dummy, 10, dummy, None) == 4            # no workspace yet
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, prec=3, mask=1 | 32)[0] == 6                   # curvatures not built
+    assert _plan(lib, prec=3, mask=1 | 16)[0] == 6                   # nor the adjoint
     st, h = _plan(lib, ndim=3, dims=(32, 32, 30), prec=3, mask=3)    # 3D S and grad S
     assert st == 0
     assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
@@ -188,8 +193,11 @@ def test_auto_picks_fp64x2_for_2d_distance(lib):
     assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
     assert info.precision == 3
     lib.dt_destroy_plan(h)
-    # with the Hessian requested there is no extended-precision candidate
-    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=5, trunc=45 * tau, khint=1000)[0] == 3
+    # with the Hessian too; with the sign channels there is no extended-precision candidate
+    st, h = _plan(lib, dims=dims, tau=tau, prec=2, mask=5, trunc=45 * tau, khint=1000)
+    assert st == 0 and lib.dt_plan_info(h, ctypes.byref(info)) == 0 and info.precision == 3
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=1 | 8, trunc=45 * tau, khint=1000)[0] == 3
 
 
 def _reduced(lib, dims, tau, k_max, prec=0, mask=3, ndim=None):

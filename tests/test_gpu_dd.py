@@ -169,9 +169,9 @@ def test_dd_source_outside_grid_sets_sticky_error(dt):
 
 def test_dd_rejects_what_it_does_not_build(dt):
     with pytest.raises(Exception):
-        dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "hess"])
+        dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "sign"])
     with pytest.raises(Exception):
-        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S", "hess"])
+        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S", "backward"])
     with pytest.raises(Exception):
         dt.Plan((300, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S"])
 
@@ -259,3 +259,43 @@ def test_dd3d_single_source_is_exact_distance(dt):
     assert np.all(dG <= TOL_GRAD_DD + parity.TOL_THETA_FRAC * ratio[away])
     beyond = r > s_max + 2.0 * tau
     assert np.all(S[beyond] == s_max) and np.all(g[:, beyond] == 0)
+
+
+@pytest.mark.parametrize("dims,K,tau_h", [((100, 77), 5, 1.0), ((40, 36, 33), 5, 1.0), ((96, 40, 30), 12, 0.5)])
+def test_dd_hessian_vs_oracle(dt, dims, K, tau_h):
+    """The Hessian of eqs. Sxx, Syy, Sxy (and its 3D form) in double-double:
+    on every node the extended precision resolves, within the per-node
+    bound with the double-double unit; S and grad S of the Hessian plan equal
+    those of the S + grad S plan (the extra channels leave them untouched)."""
+    D = len(dims)
+    pts = _clustered(K, 0.25, seed=740 + K) if D == 2 else _clustered3(K, 0.25, seed=740 + K)
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    Y = torch.from_numpy(pts).cuda()
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad", "hess"])
+    res = plan.forward(Y, S=True, grad=True, hess=True)
+    S2, g2 = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "grad"]).gradient(Y)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    assert torch.equal(res["S"], S2) and torch.equal(res["grad"], g2)
+    ref = parity.reference(dims, h, (0.0,) * D, tau, pts, "fp64x2", grad=True, hess=True)
+    H = res["hess"].cpu().numpy().reshape(3 if D == 2 else 6, -1)
+    Href = parity.hess_components(ref["hess"], D)
+    deep, valid = ref["deep"], ref["valid"]
+    scale = 1.0 / tau + 1.0 / min(h)
+    dH = np.abs(H - Href)
+    theta64 = oracle.theta("fp64", ref["padded"], ref["kernel_l1"], ref["g_l2"])
+    beyond64 = deep & (ref["lnphi"] < np.log(theta64))
+    print(f"\n[dd hess {dims}] max|dH|/(1/tau+1/h) deep={dH[:, deep].max() / scale:.3e} "
+          f"beyond fp64={beyond64.sum()} valid={valid.mean():.3f}")
+    assert beyond64.sum() > 0
+    assert np.all(dH[:, deep] <= parity.bound(ref, TOL_HESS_DD, scale)[deep])
+    assert dH[:, valid].max() <= parity.TOL_HESS * scale
+    inval = ~valid & (ref["S_exact"] > ref["s_max"] + 0.05 * tau)
+    assert np.all(H[:, inval] == 0)
+
+
+# The Hessian's two terms are each of order 1/tau and cancel to order 1/r far
+# from the sources; in float64 output that costs a few units of 1e-16 times
+# r/tau <= 70 on top of the double-double convolution
+TOL_HESS_DD = 1e-12
