@@ -40,10 +40,10 @@
  *         fails far from the sources: S_max grows from about 25-30 tau to
  *         about 60 tau.  It is built for 2D plans and for 3D plans of at
  *         most 256 nodes per axis whose out_mask holds only DT_OUT_S,
- *         DT_OUT_GRAD and DT_OUT_HESS (dt_distance, dt_gradient, dt_hessian,
- *         dt_forward with S, grad and/or hess; float64 output; other
- *         requests return DT_E_UNSUPPORTED); DT_AUTO considers it for such
- *         plans after float32 and float64.
+ *         DT_OUT_GRAD, DT_OUT_HESS and DT_OUT_CURV (dt_distance,
+ *         dt_gradient, dt_hessian, dt_forward with S, grad, hess and/or
+ *         curv; float64 output; other requests return DT_E_UNSUPPORTED);
+ *         DT_AUTO considers it for such plans after float32 and float64.
  * Validity. An FFT convolution in finite precision has an absolute error
  *         floor; nodes where phi falls below the threshold
  *           Theta = c_theta * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
@@ -168,9 +168,9 @@ typedef struct {
  * out_mask selects the kernel families to prepare.  trunc_dist and k_hint
  * only matter for DT_AUTO: the plan uses float32 if a node at distance
  * trunc_dist from an isolated source stays valid for k_hint distinct
- * sources, else float64 if that holds in float64, else (plans of S, grad S
- * and the Hessian; 3D up to 256 nodes per axis) double-double if it holds
- * there, else DT_E_PRECISION.
+ * sources, else float64 if that holds in float64, else (plans of S, grad S,
+ * the Hessian and curvatures; 3D up to 256 nodes per axis) double-double if
+ * it holds there, else DT_E_PRECISION.
  * c_theta <= 0 selects the default safety factor 256. Host only. */
 dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
                          const double* origin, double tau, int precision, unsigned out_mask,

@@ -41,9 +41,10 @@ hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, in
 // Inverse row transforms of the C channels and the epilogue: S (ny x nx),
 // with the gradient channels (C >= 1 + ndim) grad (ndim x ny x nx), with the
 // Hessian channels (C = 1 + ndim + ndim (ndim + 1) / 2) hess (xx, xy, [xz,]
-// yy, [yz,] zz, each ny x nx); any of them may be null.
+// yy, [yz,] zz, each ny x nx) and curv (mean, Gaussian, k1, k2, each
+// ny x nx; needs the Hessian channels); any of them may be null.
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
-                                 const double* scal, const DDGeom& g, hipStream_t st);
+                                 double* curv, const double* scal, const DDGeom& g, hipStream_t st);
 
 // 3D: the forward pipeline of a double-double plan with C = 1 (f), 4 (f
 // and the three gradient kernels) or 10 (and the six Hessian kernels): rows
@@ -52,6 +53,6 @@ hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double*
 // (C x nz x ny x Mx), inverse rows with the epilogue.
 hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
                                 const void* twy, const void* twz, double* S, double* grad, double* hess,
-                                const double* scal, const DDGeom& g, hipStream_t st);
+                                double* curv, const double* scal, const DDGeom& g, hipStream_t st);
 
 }  // namespace dt

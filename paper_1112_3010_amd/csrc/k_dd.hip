@@ -29,6 +29,7 @@
 
 #include "dd.hpp"
 #include "dt_dd.hpp"
+#include "epilogue.hpp"
 
 namespace dt {
 namespace {
@@ -367,14 +368,16 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
 // S = -tau log phi where phi >= Theta, else S_max (scal[0] = Theta,
 // scal[1] = S_max); with the gradient channels also grad_a S = psi_a / phi
 // (eq. SxSyconv), and with the Hessian channels H_ij = chi_ij / phi +
-// S_i S_j / tau (eqs. Sxx, Syy, Sxy), all 0 where phi < Theta.  S, grad or
-// hess may be null.  phi and grad S stay in registers (nx <= kMaxPerThread
-// * blockDim.x) while the later channels are transformed.
+// S_i S_j / tau (eqs. Sxx, Syy, Sxy), all 0 where phi < Theta, and from those
+// the curvatures (mean, Gaussian, k1, k2; the same formulas as the other
+// precisions).  S, grad, hess or curv may be null.  phi, grad S and H stay in
+// registers (nx <= kMaxPerThread * blockDim.x) while the later channels are
+// transformed.
 constexpr int kMaxPerThread = 4;
 
 __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
                                                              double* __restrict__ S, double* __restrict__ grad,
-                                                             double* __restrict__ hess,
+                                                             double* __restrict__ hess, double* __restrict__ curv,
                                                              const double* __restrict__ scal, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
   const int M = g.Mx;
   const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
   const double theta = scal[0], smax = scal[1];
-  double phi[kMaxPerThread], gs[kMaxPerThread][3];
+  double phi[kMaxPerThread], gs[kMaxPerThread][3], hs[kMaxPerThread][6];
   for (int c = 0; c < C; ++c) {
     for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
     __syncthreads();
@@ -405,15 +408,28 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
           const double gv = ok ? v.hi / phi[k] : 0.0;
           gs[k][c - 1] = gv;
           if (grad) grad[(c - 1) * nodes + (int64_t)y * g.nx + x] = gv;
-        } else if (hess) {
+        } else {
+          const int hh = c - 1 - g.ndim;
           int a, b;
-          dd_hess_pair(g.ndim, c - 1 - g.ndim, a, b);
-          hess[(c - 1 - g.ndim) * nodes + (int64_t)y * g.nx + x] =
-              ok ? v.hi / phi[k] + gs[k][a] * gs[k][b] / g.tau : 0.0;
+          dd_hess_pair(g.ndim, hh, a, b);
+          const double hv = ok ? v.hi / phi[k] + gs[k][a] * gs[k][b] / g.tau : 0.0;
+          hs[k][hh] = hv;
+          if (hess) hess[hh * nodes + (int64_t)y * g.nx + x] = hv;
         }
       }
     }
     __syncthreads();
+  }
+  if (curv) {
+#pragma unroll
+    for (int k = 0; k < kMaxPerThread; ++k) {
+      const int x = threadIdx.x + k * blockDim.x;
+      if (x >= g.nx) break;
+      double cv[4];
+      if (g.ndim == 2) curvature_graph(gs[k], hs[k], cv);
+      else curvature_level_set(gs[k], hs[k], cv);
+      for (int q = 0; q < 4; ++q) curv[q * nodes + (int64_t)y * g.nx + x] = cv[q];
+    }
   }
 }
 
@@ -575,7 +591,7 @@ hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, in
 
 hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
                                 const void* twy, const void* twz, double* S, double* grad, double* hess,
-                                const double* scal, const DDGeom& g, hipStream_t st) {
+                                double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
   const int64_t MyMx = (int64_t)g.My * g.Mx;
   DDGeom rows = g;
@@ -599,16 +615,16 @@ hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void
   k_dd_line_inv<<<(unsigned)yi.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, hess, scal, rows, st);
+  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, hess, curv, scal, rows, st);
 }
 
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
-                                 const double* scal, const DDGeom& g, hipStream_t st) {
+                                 double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
   const size_t lds = (size_t)g.Mx * sizeof(ddc);
   const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, scal, g, C);
+  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, curv, scal, g, C);
   return hipGetLastError();
 }
 

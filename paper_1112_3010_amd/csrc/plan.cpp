@@ -104,7 +104,7 @@ struct dt_plan_s {
     static_dev = -1;
     static_token = 0;
   }
-  // double-double plans (S, grad S, Hessian) use their own workspace regions
+  // double-double plans (S, grad S, Hessian, curvatures) use their own workspace regions
   bool dd = false;
   DDGeom ddg{};
   int dd_tabs = 1;       // 1: f; 1 + ndim: and the gradient kernels; + ndim (ndim + 1) / 2: and the Hessian's
@@ -266,7 +266,7 @@ void setup_dd(dt_plan p) {
   p->dd = true;
   const bool d3 = p->ndim == 3;
   const int nh = p->ndim == 2 ? 3 : 6;
-  p->dd_tabs = (p->mask & DT_OUT_HESS) ? 1 + p->ndim + nh : (p->mask & DT_OUT_GRAD) ? 1 + p->ndim : 1;
+  p->dd_tabs = (p->mask & (DT_OUT_HESS | DT_OUT_CURV)) ? 1 + p->ndim + nh : (p->mask & DT_OUT_GRAD) ? 1 + p->ndim : 1;
   p->fp64 = true;  // outputs are float64
   p->w = 8;
   DDGeom& g = p->ddg;
@@ -388,9 +388,9 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    // double-double is a candidate only where it is built: plans of S, grad S and the Hessian
+    // double-double is a candidate only where it is built: plans of S, grad S, the Hessian and curvatures
     // (3D up to 256 nodes per axis)
-    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS));
+    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV));
     if (ndim == 3)
       for (int a = 0; a < 3; ++a) dd_ok = dd_ok && dims[a] <= 256;
     const int n_cand = dd_ok ? 3 : 2;
@@ -409,7 +409,7 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   }
   p->prec = precision;
   if (precision == DT_FP64X2) {
-    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS));
+    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV));
     if (ndim == 3)
       for (int a = 0; a < 3; ++a) ok = ok && dims[a] <= 256;   // 512^3 padded: about 22 GB of workspace
     if (!ok) {
@@ -1026,15 +1026,16 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
 
 }  // namespace
 
-// The double-double pipeline: S, grad S and the Hessian from explicit sources.
+// The double-double pipeline: S, grad S, the Hessian and curvatures from explicit sources.
 static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
                          hipStream_t st) {
-  if (out->label || out->mu || out->curv || out->signed_outputs || shape) return DT_E_UNSUPPORTED;
-  if ((!out->S && !out->grad && !out->hess) || !Y || K < 1) return DT_E_ARG;
+  if (out->label || out->mu || out->signed_outputs || shape) return DT_E_UNSUPPORTED;
+  if ((!out->S && !out->grad && !out->hess && !out->curv) || !Y || K < 1) return DT_E_ARG;
   const int nh = p->ndim == 2 ? 3 : 6;
-  if (out->grad && p->dd_tabs < 1 + p->ndim) return DT_E_ARG;        // gradient kernels not prepared
-  if (out->hess && p->dd_tabs < 1 + p->ndim + nh) return DT_E_ARG;   // Hessian kernels not prepared
-  const int C = out->hess ? 1 + p->ndim + nh : out->grad ? 1 + p->ndim : 1;
+  const bool second = out->hess || out->curv;
+  if (out->grad && p->dd_tabs < 1 + p->ndim) return DT_E_ARG;   // gradient kernels not prepared
+  if (second && p->dd_tabs < 1 + p->ndim + nh) return DT_E_ARG;  // Hessian kernels not prepared
+  const int C = second ? 1 + p->ndim + nh : out->grad ? 1 + p->ndim : 1;
   if (!p->usable()) return DT_E_WORKSPACE;
   const DDGeom& g = p->ddg;
   double* cnt = (double*)(p->ws + p->off_dd_cnt);
@@ -1051,7 +1052,7 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
     PassTimer t(p, st, "dd_forward_3d");
     e = dd_launch_forward_3d(cnt, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, C, p->ws + p->off_dd_twx,
                              p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, (double*)out->S, (double*)out->grad,
-                             (double*)out->hess, p->scal(), g, st);
+                             (double*)out->hess, (double*)out->curv, p->scal(), g, st);
     return hip_status(e);
   }
   {
@@ -1067,7 +1068,7 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   {
     PassTimer t(p, st, "dd_row_inv_epi");
     e = dd_launch_row_inv_epi(p->ws + p->off_dd_Gc, C, p->ws + p->off_dd_twx, (double*)out->S, (double*)out->grad,
-                              (double*)out->hess, p->scal(), g, st);
+                              (double*)out->hess, (double*)out->curv, p->scal(), g, st);
   }
   return hip_status(e);
 }
