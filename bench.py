@@ -624,9 +624,17 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
     h3 = (1.0 / n3,) * 3
     Y3 = torch.from_numpy(synth.jittered_sphere_points(4096, 0.3, 2.0 / n3, seed=11)).cuda()
     d3 = {}
-    for prec, outs in (("fp64x2", ["S"]), ("fp64x2", ["S", "grad"]), ("fp64", ["S", "grad"])):
+    for prec, outs in (("fp64x2", ["S"]), ("fp64x2", ["S", "grad"]), ("fp64", ["S", "grad"]),
+                       ("fp64x2", ["S", "backward"])):
         plan = dt.Plan(dims3, h3, None, h3[0], precision=prec, outputs=outs)
-        fwd = (lambda: plan.distance(Y3)) if outs == ["S"] else (lambda: plan.gradient(Y3))
+        if outs == ["S"]:
+            fwd = lambda: plan.distance(Y3)
+        elif outs == ["S", "grad"]:
+            fwd = lambda: plan.gradient(Y3)
+        else:
+            S3 = plan.distance(Y3)
+            G3 = S3.clone()
+            fwd = lambda: plan.backward(Y3, S3, G3)
         for _ in range(max(1, warmup // 2)):
             fwd()
         torch.cuda.synchronize()

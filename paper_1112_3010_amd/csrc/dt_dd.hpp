@@ -18,26 +18,40 @@ struct DDGeom {
 // Bytes of one complex double-double value and one real one.
 constexpr size_t kDDComplexBytes = 32, kDDRealBytes = 16;
 
+// Channels of one convolution pass: channel c multiplies the image spectrum
+// by spectrum tab_of[c], imaginary (the odd gradient kernels: the product
+// takes the factor i) where bit c of imag is set.
+constexpr int kDDMaxChannels = 12;
+struct DDChannels {
+  int C;
+  int tab_of[kDDMaxChannels];
+  unsigned imag;
+};
+// Sample kind of the r f kernel (the adjoint's tau channel) in the table builder.
+constexpr int kDDKindRF = 100;
+
 // Plan time: twiddles of every axis (twz unused in 2D), then for each table
 // t < n_tabs (0: f, 1 + a: the gradient kernel of axis a, then the Hessian
-// kernels xx, xy, [xz,] yy, [yz,] zz) the samples into G
-// (scratch, Mz x My x Mx complex) and their transform; tabs receives the
-// scaled real (f, Hessian) or imaginary (gradient) spectra, Mz x My x Mx
-// each.
-hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
-                           hipStream_t st);
+// kernels xx, xy, [xz,] yy, [yz,] zz; table rf_tab, if >= 0, the r f kernel)
+// the samples into G (scratch, Mz x My x Mx complex) and their transform;
+// tabs receives the scaled real (f, Hessian, r f) or imaginary (gradient)
+// spectra, Mz x My x Mx each.
+hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
+                           const DDGeom& g, hipStream_t st);
 // Multiplicities into cnt (cleared by the caller) and sum m^2 into *msq
 // (left at 0 by dd_launch_finalize, which consumes it).
 hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
                            hipStream_t st);
 hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double c_theta, double unit, double l1,
                               hipStream_t st);
-// Forward row transforms of the ny source rows into G.
+// Forward row transforms of the image rows (ny x nx, or nz x ny x nx) into G.
 hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st);
-// Columns of G: forward, times each of the C spectra, inverse, into Gout
-// (C x ny x Mx).
-hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
-                               hipStream_t st);
+// The convolution of the real image img with each channel's kernel up to the
+// last (x) inverse transform: Gc receives C x (nz ny) x Mx row spectra.  2D:
+// rows into G, then the fused y pass into Gc.  3D: rows into G, forward y
+// into Gc, the fused z pass into G (C x nz x My x Mx), inverse y into Gc.
+hipError_t dd_convolve(const double* img, void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twx,
+                       const void* twy, const void* twz, const DDGeom& g, hipStream_t st);
 // Inverse row transforms of the C channels and the epilogue: S (ny x nx),
 // with the gradient channels (C >= 1 + ndim) grad (ndim x ny x nx), with the
 // Hessian channels (C = 1 + ndim + ndim (ndim + 1) / 2) hess (xx, xy, [xz,]
@@ -46,13 +60,14 @@ hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, in
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
                                  double* curv, const double* scal, const DDGeom& g, hipStream_t st);
 
-// 3D: the forward pipeline of a double-double plan with C = 1 (f), 4 (f
-// and the three gradient kernels) or 10 (and the six Hessian kernels): rows
-// of the nz x ny source rows into G, forward y into Gc, z columns forward /
-// times each spectrum / inverse into G (C x nz x My x Mx), inverse y into Gc
-// (C x nz x ny x Mx), inverse rows with the epilogue.
-hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
-                                const void* twy, const void* twz, double* S, double* grad, double* hess,
-                                double* curv, const double* scal, const DDGeom& g, hipStream_t st);
+// Inverse row transforms of C channels into plain float64 fields
+// (C x nodes), for the adjoint.
+hipError_t dd_launch_row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
+                                   hipStream_t st);
+// The adjoint at the sources from the fields (ndim gradient channels, then
+// r f): dY (K x ndim float32) and per-block sums of the r f term in
+// partials (at most max_blocks blocks; the count goes to *n_blocks).
+hipError_t dd_launch_gather(const float* Y, int64_t K, const double* fields, const double* scal, float* dY,
+                            double* partials, int max_blocks, int* n_blocks, const DDGeom& g, hipStream_t st);
 
 }  // namespace dt

@@ -17,7 +17,7 @@
 //   G         My x Mx complex double-double work grid (row spectra)
 //   Gc        C x ny x Mx complex double-double (column-pass outputs)
 // 3D plans add twz, take Mz x My x Mx spectra (C = 4 with the gradient) and
-// run the y and z axes as strided line passes (dd_launch_forward_3d).
+// run the y and z axes as strided line passes (dd_convolve).
 // The transforms are radix-2 in LDS (stages fused in pairs), one row or
 // column per block:
 // decimation in time (bit-reversed in, natural out) forward and decimation
@@ -200,6 +200,8 @@ __global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
     const dd p[3] = {px, py, pz};
     if (kind == 0) {
       v.re = f;
+    } else if (kind == kDDKindRF) {
+      v.re = ddm::mul(r, f);                     // r f (the adjoint's tau kernel), 0 at r = 0
     } else if (r.hi > 0.0 && kind <= g.ndim) {
       v.re = ddm::mul(ddm::div(p[kind - 1], r), f);
     } else if (r.hi > 0.0) {
@@ -321,7 +323,7 @@ constexpr int kSpecPerThread = 8;
 struct DDFused {
   int M, logM, n;
   int64_t stride, plane, tab_chan;
-  int ndim;
+  DDChannels ch;
 };
 
 template <bool MULTI>
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
     }
   }
   for (int c = 0; c < C; ++c) {
-    const dd* tab = tabs + c * npad;
+    const dd* tab = tabs + F.ch.tab_of[c] * npad;
 #pragma unroll
     for (int k = 0; k < (MULTI ? kSpecPerThread : M / kThreads + 1); ++k) {
       const int ky = threadIdx.x + k * blockDim.x;
@@ -354,8 +356,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
       const dd t = tab[(int64_t)ky * F.stride + kx];
       const ddc a = MULTI ? sp[k] : buf[ky];
       // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
-      buf[ky] = !dd_imag_channel(c, F.ndim) ? ddm::cmul_real(a, t)
-                                            : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
+      buf[ky] = !((F.ch.imag >> c) & 1u) ? ddm::cmul_real(a, t)
+                                         : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
     }
     __syncthreads();
     fft_dif<true>(buf, M, F.logM, tw);
@@ -433,6 +435,56 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
   }
 }
 
+// Inverse transforms of row y of C channels into plain fields (the float64
+// leading part of the real part), out[c][row][x] for x < nx (the adjoint's
+// convolutions w * u_a and w * r f).
+__global__ __launch_bounds__(kThreads) void k_dd_row_inv_plain(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
+                                                               double* __restrict__ out, DDGeom g, int C) {
+  extern __shared__ __align__(16) char smem[];
+  ddc* buf = (ddc*)smem;
+  const int y = blockIdx.x;
+  const int M = g.Mx;
+  const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
+  for (int c = 0; c < C; ++c) {
+    for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
+    __syncthreads();
+    fft_dif<true>(buf, M, g.logMx, tw);
+    for (int x = threadIdx.x; x < g.nx; x += blockDim.x) out[c * nodes + (int64_t)y * g.nx + x] = buf[brev(x, g.logMx)].re.hi;
+    __syncthreads();
+  }
+}
+
+// The adjoint at the sources: dL/dY_k = (w * u_a)(Y_k) / p2 from the channel
+// fields (a < ndim), and per-block sums of (w * r f)(Y_k) / p2 for dL/dtau
+// (scal[3] = p2, the power of two that scaled w).  Sources outside the grid
+// get 0 (the forward call has already raised the sticky range error).
+__global__ __launch_bounds__(256) void k_dd_gather(const float* __restrict__ Y, int64_t K,
+                                                   const double* __restrict__ fields, const double* __restrict__ scal,
+                                                   float* __restrict__ dY, double* __restrict__ partials, DDGeom g) {
+  __shared__ double red[256];
+  const int D = g.ndim;
+  const int64_t nodes = (int64_t)g.nx * g.ny * g.nz;
+  const double inv_p2 = 1.0 / scal[3];
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+    const double y0 = Y[D * k], y1 = Y[D * k + 1], y2 = D == 3 ? Y[D * k + 2] : 0.0;
+    const double fx = __builtin_floor((y0 - g.ox) / g.hx), fy = __builtin_floor((y1 - g.oy) / g.hy);
+    const double fz = D == 3 ? __builtin_floor((y2 - g.oz) / g.hz) : 0.0;
+    const bool in = fx >= 0.0 && fx < (double)g.nx && fy >= 0.0 && fy < (double)g.ny && fz >= 0.0 &&
+                    fz < (double)g.nz;
+    const int64_t node = in ? ((int64_t)fz * g.ny + (int64_t)fy) * g.nx + (int64_t)fx : 0;
+    for (int a = 0; a < D; ++a) dY[D * k + a] = in ? (float)(fields[a * nodes + node] * inv_p2) : 0.0f;
+    if (in) acc += fields[D * nodes + node] * inv_p2;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
 // Node assignment idx = floor((y - o) / h) in float64; multiplicities by
 // atomic adds (integers, exact in float64).  Each add that raises a count
 // from c to c + 1 raises sum m^2 by 2c + 1; those increments are summed per
@@ -475,6 +527,9 @@ __global__ void k_dd_finalize(double* __restrict__ msq, double* __restrict__ sca
   scal[0] = theta;
   scal[1] = -g.tau * log(theta);
   scal[2] = gl2;
+  int e2;
+  frexp(theta, &e2);
+  scal[3] = ldexp(1.0, e2 - 1);   // the largest power of two <= Theta (scales the adjoint's weights)
 }
 
 // Kernels whose dynamic LDS exceeds the default 64 KiB limit must opt in.
@@ -491,8 +546,8 @@ hipError_t allow_lds(F kern, size_t lds) {
 
 // 3D tables: rows of the Mz x My sample rows in place, then the y lines in
 // place, then the z lines into the real or imaginary spectrum.
-hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
-                              hipStream_t st) {
+hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
+                              const DDGeom& g, hipStream_t st) {
   k_dd_twiddles<<<(g.Mz / 2 + 255) / 256, 256, 0, st>>>((ddc*)twz, g.Mz);
   const int64_t plane = (int64_t)g.Mx * g.My, total = plane * g.Mz;
   const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc), lz = (size_t)g.Mz * sizeof(ddc);
@@ -507,12 +562,12 @@ hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n
   DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane};
   for (int t = 0; t < n_tabs; ++t) {
     dd* tab = (dd*)tabs + t * total;
-    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t);
+    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t == rf_tab ? kDDKindRF : t);
     k_dd_row_fwd<false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, rows);
     k_dd_line_fwd<0><<<(unsigned)ly_.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy,
                                                                   ly_, 0);
     const int e_scale = -(g.logMx + g.logMy + g.logMz);
-    if (!dd_imag_channel(t, g.ndim))
+    if (t == rf_tab || !dd_imag_channel(t, g.ndim))
       k_dd_line_fwd<1><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
                                                                     e_scale);
     else
@@ -522,11 +577,11 @@ hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n
   return hipGetLastError();
 }
 
-hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, void* G, const DDGeom& g,
-                           hipStream_t st) {
+hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
+                           const DDGeom& g, hipStream_t st) {
   k_dd_twiddles<<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((ddc*)twx, g.Mx);
   k_dd_twiddles<<<(g.My / 2 + 255) / 256, 256, 0, st>>>((ddc*)twy, g.My);
-  if (g.ndim == 3) return dd_build_tables_3d(twx, twy, twz, tabs, n_tabs, G, g, st);
+  if (g.ndim == 3) return dd_build_tables_3d(twx, twy, twz, tabs, n_tabs, rf_tab, G, g, st);
   const int64_t total = (int64_t)g.Mx * g.My;
   const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc);
   hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
@@ -535,9 +590,9 @@ hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_ta
   if (e != hipSuccess) return e;
   for (int t = 0; t < n_tabs; ++t) {
     dd* tab = (dd*)tabs + t * total;
-    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t);
+    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t == rf_tab ? kDDKindRF : t);
     k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
-    if (!dd_imag_channel(t, g.ndim))
+    if (t == rf_tab || !dd_imag_channel(t, g.ndim))
       k_dd_col_table<false><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
     else
       k_dd_col_table<true><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
@@ -565,9 +620,10 @@ hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const 
   return hipGetLastError();
 }
 
-static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* tw, const DDFused& F,
+static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, const void* tw, const DDFused& F,
                                int64_t lines, hipStream_t st) {
   const size_t lds = (size_t)F.M * sizeof(ddc);
+  const int C = F.ch.C;
   if (C > 1) {
     if (F.M > kSpecPerThread * kThreads) return hipErrorInvalidValue;
     const hipError_t e = allow_lds(k_dd_col_fused<true>, lds);
@@ -583,21 +639,18 @@ static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, in
   return hipGetLastError();
 }
 
-hipError_t dd_launch_col_fused(const void* Gin, void* Gout, const void* tabs, int C, const void* twy, const DDGeom& g,
-                               hipStream_t st) {
-  const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My, g.ndim};
-  return launch_fused(Gin, Gout, tabs, C, twy, F, g.Mx, st);
-}
-
-hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void* tabs, int C, const void* twx,
-                                const void* twy, const void* twz, double* S, double* grad, double* hess,
-                                double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
-  if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
-  const int64_t MyMx = (int64_t)g.My * g.Mx;
+hipError_t dd_convolve(const double* img, void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twx,
+                       const void* twy, const void* twz, const DDGeom& g, hipStream_t st) {
+  if (ch.C < 1 || ch.C > kDDMaxChannels) return hipErrorInvalidValue;
   DDGeom rows = g;
-  rows.ny = g.ny * g.nz;   // the source rows (z, y), y fastest
-  hipError_t e = dd_launch_row_fwd(cnt, G, twx, rows, st);
+  rows.ny = g.ny * g.nz;   // the image rows (z, y), y fastest
+  hipError_t e = dd_launch_row_fwd(img, G, twx, rows, st);
   if (e != hipSuccess) return e;
+  if (g.ndim == 2) {
+    const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My, ch};
+    return launch_fused(G, Gc, tabs, twy, F, g.Mx, st);
+  }
+  const int64_t MyMx = (int64_t)g.My * g.Mx;
   // forward y: G [z][y < ny][kx] -> Gc [z][ky][kx]
   const size_t ly = (size_t)g.My * sizeof(ddc);
   e = allow_lds(k_dd_line_fwd<0>, ly);
@@ -607,24 +660,47 @@ hipError_t dd_launch_forward_3d(const double* cnt, void* G, void* Gc, const void
   k_dd_line_fwd<0><<<(unsigned)yf.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf,
                                                                0);
   // z lines (ky, kx): forward, times each spectrum, inverse -> G [c][z < nz][ky][kx]
-  const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz, g.ndim};
-  e = launch_fused(Gc, G, tabs, C, twz, F, MyMx, st);
+  const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz, ch};
+  e = launch_fused(Gc, G, tabs, twz, F, MyMx, st);
   if (e != hipSuccess) return e;
   // inverse y: G [c z][ky][kx] -> Gc [c z][y < ny][kx]
-  const DDLines yi{g.My, g.logMy, g.Mx, g.My, g.ny, (int64_t)C * g.nz * g.Mx, MyMx, g.Mx, (int64_t)g.ny * g.Mx, g.Mx};
+  const DDLines yi{g.My, g.logMy, g.Mx, g.My, g.ny, (int64_t)ch.C * g.nz * g.Mx, MyMx, g.Mx, (int64_t)g.ny * g.Mx,
+                   g.Mx};
   k_dd_line_inv<<<(unsigned)yi.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return dd_launch_row_inv_epi(Gc, C, twx, S, grad, hess, curv, scal, rows, st);
+  return hipGetLastError();
 }
 
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
                                  double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
+  DDGeom rows = g;
+  rows.ny = g.ny * g.nz;
   const size_t lds = (size_t)g.Mx * sizeof(ddc);
   const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<<<g.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, curv, scal, g, C);
+  k_dd_row_inv_epi<<<(unsigned)rows.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, curv,
+                                                              scal, rows, C);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
+                                   hipStream_t st) {
+  DDGeom rows = g;
+  rows.ny = g.ny * g.nz;
+  const size_t lds = (size_t)g.Mx * sizeof(ddc);
+  const hipError_t e = allow_lds(k_dd_row_inv_plain, lds);
+  if (e != hipSuccess) return e;
+  k_dd_row_inv_plain<<<(unsigned)rows.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, out, rows, C);
+  return hipGetLastError();
+}
+
+hipError_t dd_launch_gather(const float* Y, int64_t K, const double* fields, const double* scal, float* dY,
+                            double* partials, int max_blocks, int* n_blocks, const DDGeom& g, hipStream_t st) {
+  int64_t blocks = (K + 255) / 256;
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  *n_blocks = (int)blocks;
+  k_dd_gather<<<(unsigned)blocks, 256, 0, st>>>(Y, K, fields, scal, dY, partials, g);
   return hipGetLastError();
 }
 

@@ -108,6 +108,7 @@ struct dt_plan_s {
   bool dd = false;
   DDGeom ddg{};
   int dd_tabs = 1;       // 1: f; 1 + ndim: and the gradient kernels; + ndim (ndim + 1) / 2: and the Hessian's
+  int dd_rf_tab = -1;    // table of r f (adjoint plans), else -1
   size_t off_dd_twx = 0, off_dd_twy = 0, off_dd_twz = 0, off_dd_tab = 0, off_dd_cnt = 0, off_dd_G = 0, off_dd_Gc = 0;
   // optional per-pass timing
   bool timing = false;
@@ -266,7 +267,11 @@ void setup_dd(dt_plan p) {
   p->dd = true;
   const bool d3 = p->ndim == 3;
   const int nh = p->ndim == 2 ? 3 : 6;
-  p->dd_tabs = (p->mask & (DT_OUT_HESS | DT_OUT_CURV)) ? 1 + p->ndim + nh : (p->mask & DT_OUT_GRAD) ? 1 + p->ndim : 1;
+  // tables: f, the gradient kernels (also for the adjoint), the Hessian's, then r f for the adjoint
+  const int n_fwd = (p->mask & (DT_OUT_HESS | DT_OUT_CURV)) ? 1 + p->ndim + nh
+                    : (p->mask & (DT_OUT_GRAD | DT_OUT_BACKWARD)) ? 1 + p->ndim : 1;
+  p->dd_rf_tab = (p->mask & DT_OUT_BACKWARD) ? n_fwd : -1;
+  p->dd_tabs = n_fwd + ((p->mask & DT_OUT_BACKWARD) ? 1 : 0);
   p->fp64 = true;  // outputs are float64
   p->w = 8;
   DDGeom& g = p->ddg;
@@ -296,6 +301,8 @@ void setup_dd(dt_plan p) {
   size_t off = 0;
   p->off_scal = off; off = align_up(off + 64 * sizeof(double));
   p->off_err = off; off = align_up(off + sizeof(uint32_t));
+  p->off_partA = off; off = align_up(off + kPartials * sizeof(double));
+  p->off_partB = off; off = align_up(off + kPartials * sizeof(double));
   p->off_R1 = off;  // end of the region cleared at attach
   p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * kDDComplexBytes);
   p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * kDDComplexBytes);
@@ -388,9 +395,9 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    // double-double is a candidate only where it is built: plans of S, grad S, the Hessian and curvatures
+    // double-double is a candidate wherever it is built: every output but the sign
     // (3D up to 256 nodes per axis)
-    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV));
+    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV | DT_OUT_BACKWARD));
     if (ndim == 3)
       for (int a = 0; a < 3; ++a) dd_ok = dd_ok && dims[a] <= 256;
     const int n_cand = dd_ok ? 3 : 2;
@@ -409,7 +416,7 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   }
   p->prec = precision;
   if (precision == DT_FP64X2) {
-    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV));
+    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV | DT_OUT_BACKWARD));
     if (ndim == 3)
       for (int a = 0; a < 3; ++a) ok = ok && dims[a] <= 256;   // 512^3 padded: about 22 GB of workspace
     if (!ok) {
@@ -657,7 +664,7 @@ dt_status dt::plan_attach(dt_plan p, void* dev_ptr, size_t bytes, void* stream) 
   launch_fill_zero<double>((double*)p->ws, (int64_t)(p->off_R1 / sizeof(double)), st);
   if (p->dd) {
     hipError_t e = dd_build_tables(p->ws + p->off_dd_twx, p->ws + p->off_dd_twy, p->ws + p->off_dd_twz,
-                                   p->ws + p->off_dd_tab, p->dd_tabs, p->ws + p->off_dd_G, p->ddg, st);
+                                   p->ws + p->off_dd_tab, p->dd_tabs, p->dd_rf_tab, p->ws + p->off_dd_G, p->ddg, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return DT_E_HIP;
     p->kernel_l1 = host_kernel_l1(p->M, p->h, p->ndim, p->tau);
@@ -1048,21 +1055,16 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
     if (e == hipSuccess) e = dd_launch_finalize(p->msq(), p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
-  if (g.ndim == 3) {
-    PassTimer t(p, st, "dd_forward_3d");
-    e = dd_launch_forward_3d(cnt, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, C, p->ws + p->off_dd_twx,
-                             p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, (double*)out->S, (double*)out->grad,
-                             (double*)out->hess, (double*)out->curv, p->scal(), g, st);
-    return hip_status(e);
+  DDChannels ch{};
+  ch.C = C;
+  for (int c = 0; c < C; ++c) {
+    ch.tab_of[c] = c;
+    if (c >= 1 && c <= p->ndim) ch.imag |= 1u << c;
   }
   {
-    PassTimer t(p, st, "dd_row_fwd");
-    e = dd_launch_row_fwd(cnt, G, p->ws + p->off_dd_twx, g, st);
-  }
-  if (e != hipSuccess) return DT_E_HIP;
-  {
-    PassTimer t(p, st, "dd_col_fused");
-    e = dd_launch_col_fused(G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, C, p->ws + p->off_dd_twy, g, st);
+    PassTimer t(p, st, "dd_convolve");
+    e = dd_convolve(cnt, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twx,
+                    p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, g, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
   {
@@ -1071,6 +1073,52 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
                               (double*)out->hess, (double*)out->curv, p->scal(), g, st);
   }
   return hip_status(e);
+}
+
+// The double-double adjoint (as run_backward): w = G exp(S / tau) p2 on valid
+// nodes, its convolutions with the gradient kernels and with r f in
+// double-double, their values at the sources' nodes.
+static dt_status run_backward_dd(dt_plan p, const float* Y, int64_t K, const double* S, const double* Gr, float* dY,
+                                 double* dtau, hipStream_t st) {
+  const DDGeom& g = p->ddg;
+  const int D = p->ndim;
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  double* img = (double*)(p->ws + p->off_dd_cnt);
+  char* G = p->ws + p->off_dd_G;
+  hipError_t e;
+  int ngs = 0, nrf = 0;
+  {
+    PassTimer t(p, st, "splat");
+    launch_fill_zero<double>(img, N, st);
+    e = dd_launch_splat(Y, K, img, p->msq(), p->err(), g, st);
+    if (e == hipSuccess) e = dd_launch_finalize(p->msq(), p->scal(), g, p->c_theta, p->unit(), p->kernel_l1, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, "prep_w");
+    ngs = launch_prep_w<double>(S, Gr, N, p->scal(), p->tau, img, p->partA(), st);
+  }
+  DDChannels ch{};
+  ch.C = D + 1;
+  for (int a = 0; a < D; ++a) {
+    ch.tab_of[a] = 1 + a;
+    ch.imag |= 1u << a;
+  }
+  ch.tab_of[D] = p->dd_rf_tab;
+  {
+    PassTimer t(p, st, "dd_convolve");
+    e = dd_convolve(img, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twx,
+                    p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, g, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, "dd_gather");
+    e = dd_launch_row_inv_plain(p->ws + p->off_dd_Gc, D + 1, p->ws + p->off_dd_twx, (double*)G, g, st);
+    if (e == hipSuccess) e = dd_launch_gather(Y, K, (const double*)G, p->scal(), dY, p->partB(), kPartials, &nrf, g, st);
+    if (e == hipSuccess) launch_finalize_dtau(p->partA(), ngs, p->partB(), nrf, 1.0, p->tau, p->scal(), dtau, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  return hip_status(hipGetLastError());
 }
 
 extern "C" dt_status dt_forward(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
@@ -1118,10 +1166,10 @@ extern "C" dt_status dt_backward(dt_plan p, const float* Y, int64_t K, const voi
   if (!p || !Y || K < 1 || !S || !dL_dS || !dL_dY) return DT_E_ARG;
   if (!(p->mask & DT_OUT_BACKWARD)) return DT_E_ARG;
   if (p->k_max > 0 && K > p->k_max) return DT_E_ARG;
-  if (p->dd) return DT_E_UNSUPPORTED;
   if (!p->usable()) return DT_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;
+  if (p->dd) return run_backward_dd(p, Y, K, (const double*)S, (const double*)dL_dS, dL_dY, dL_dtau, st);
   return p->fp64 ? run_backward<double>(p, Y, K, S, dL_dS, dL_dY, dL_dtau, st)
                  : run_backward<float>(p, Y, K, S, dL_dS, dL_dY, dL_dtau, st);
 }

@@ -172,7 +172,10 @@ def test_fp64x2_plans(lib):
     st, h = _plan(lib, prec=3, mask=1 | 32)                          # S and curvatures
     assert st == 0
     lib.dt_destroy_plan(h)
-    assert _plan(lib, prec=3, mask=1 | 16)[0] == 6                   # the adjoint is not built
+    st, h = _plan(lib, prec=3, mask=1 | 16)                          # S and the adjoint
+    assert st == 0
+    lib.dt_destroy_plan(h)
+    assert _plan(lib, prec=3, mask=1 | 8)[0] == 6                    # the sign channels are not built
     st, h = _plan(lib, ndim=3, dims=(32, 32, 30), prec=3, mask=3)    # 3D S and grad S
     assert st == 0
     assert lib.dt_plan_info(h, ctypes.byref(info)) == 0

@@ -171,7 +171,7 @@ def test_dd_rejects_what_it_does_not_build(dt):
     with pytest.raises(Exception):
         dt.Plan((64, 64), None, None, 0.02, precision="fp64x2", outputs=["S", "sign"])
     with pytest.raises(Exception):
-        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S", "backward"])
+        dt.Plan((32, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S", "sign"])
     with pytest.raises(Exception):
         dt.Plan((300, 32, 32), None, None, 0.05, precision="fp64x2", outputs=["S"])
 
@@ -299,3 +299,48 @@ def test_dd_hessian_vs_oracle(dt, dims, K, tau_h):
 # from the sources; in float64 output that costs a few units of 1e-16 times
 # r/tau <= 70 on top of the double-double convolution
 TOL_HESS_DD = 1e-12
+
+
+@pytest.mark.parametrize("dims,K,tau_h", [((100, 77), 5, 1.0), ((40, 36, 33), 5, 1.0), ((96, 40, 30), 12, 0.5)])
+def test_dd_backward_vs_oracle(dt, dims, K, tau_h):
+    """The adjoint (dL/dY, dL/dtau) in double-double against the oracle's
+    analytic sums, with G on every valid node off the threshold's shell,
+    including nodes beyond the float64 band; per component within the bound
+    of the float64 adjoint tests, taken at the double-double threshold."""
+    D = len(dims)
+    pts = _clustered(K, 0.25, seed=760 + K) if D == 2 else _clustered3(K, 0.25, seed=760 + K)
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    plan = dt.Plan(dims, h, None, tau, precision="fp64x2", outputs=["S", "backward"])
+    ref = parity.reference(dims, h, (0.0,) * D, tau, pts, "fp64x2", rmean=True)
+    lnphi = ref["lnphi"]
+    G = np.random.default_rng(761).standard_normal(lnphi.shape)
+    G[np.abs(lnphi - np.log(ref["theta"])) < np.log(2.0)] = 0.0
+    G[~ref["valid"]] = 0.0
+    theta64 = oracle.theta("fp64", ref["padded"], ref["kernel_l1"], ref["g_l2"])
+    beyond64 = (G != 0) & (lnphi < np.log(theta64))
+    assert beyond64.sum() > 100
+    Y = torch.from_numpy(pts).cuda()
+    S = plan.distance(Y)
+    dY, dtau = plan.backward(Y, S, torch.from_numpy(G).cuda().reshape(plan.shape))
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    dY = dY.cpu().numpy().astype(np.float64)
+    dtau = float(dtau.cpu())
+    dY_ref, dtau_ref = oracle.loss_gradients(ref["X"], ref["Yhat"], tau, G, ref["valid"], workers=parity.WORKERS)
+    ratio = np.exp(np.log(ref["theta"]) - lnphi)
+    aG = np.abs(G)
+    C = np.stack([aG, aG * ratio], axis=1)
+    sens = oracle.adjoint.source_weight_sums(ref["X"], ref["Yhat"], tau, C, workers=parity.WORKERS)
+    tw = 1.0 + 2.0 * ref["rmean"] / tau
+    w_l2 = float(np.sqrt(np.sum((G * np.exp(-lnphi)) ** 2)))
+    noise = parity.adjoint_noise("fp64x2", ref["padded"], ref["kernel_l1"], w_l2)
+    bY, bt = parity.fp64_adjoint_bounds(sens[:, 0], sens[:, 1], float(aG @ tw), float((aG * ratio) @ tw), noise,
+                                        dY_ref)
+    rY = float((np.abs(dY - dY_ref) / bY).max())
+    rt = abs(dtau - dtau_ref) / bt
+    e_y = float(np.linalg.norm(dY - dY_ref) / np.linalg.norm(dY_ref))
+    print(f"\n[dd backward {dims}] rel L2 dL/dY={e_y:.3e} rel dL/dtau={abs(dtau - dtau_ref) / abs(dtau_ref):.3e} "
+          f"G beyond fp64={beyond64.sum()} max|ddY|/bound={rY:.3f} |ddtau|/bound={rt:.3f}")
+    assert rY <= 1.0
+    assert rt <= 1.0
