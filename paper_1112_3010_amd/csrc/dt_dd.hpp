@@ -47,11 +47,13 @@ hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double
 // Forward row transforms of the image rows (ny x nx, or nz x ny x nx) into G.
 hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st);
 // The convolution of the real image img with each channel's kernel up to the
-// last (x) inverse transform: Gc receives C x (nz ny) x Mx row spectra.  2D:
-// rows into G, then the fused y pass into Gc.  3D: rows into G, forward y
-// into Gc, the fused z pass into G (C x nz x My x Mx), inverse y into Gc.
-hipError_t dd_convolve(const double* img, void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twx,
-                       const void* twy, const void* twz, const DDGeom& g, hipStream_t st);
+// last (x) inverse transform, in two steps: the forward row transforms into
+// G, then the column passes, after which Gc holds C x (nz ny) x Mx row
+// spectra.  2D: the fused y pass into Gc.  3D: forward y into Gc, the fused
+// z pass into G (C x nz x My x Mx), inverse y into Gc.
+hipError_t dd_convolve_rows(const double* img, void* G, const void* twx, const DDGeom& g, hipStream_t st);
+hipError_t dd_convolve_columns(void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twy,
+                               const void* twz, const DDGeom& g, hipStream_t st);
 // Inverse row transforms of the C channels and the epilogue: S (ny x nx),
 // with the gradient channels (C >= 1 + ndim) grad (ndim x ny x nx), with the
 // Hessian channels (C = 1 + ndim + ndim (ndim + 1) / 2) hess (xx, xy, [xz,]

@@ -17,7 +17,7 @@
 //   G         My x Mx complex double-double work grid (row spectra)
 //   Gc        C x ny x Mx complex double-double (column-pass outputs)
 // 3D plans add twz, take Mz x My x Mx spectra (C = 4 with the gradient) and
-// run the y and z axes as strided line passes (dd_convolve).
+// run the y and z axes as strided line passes (dd_convolve_columns).
 // The transforms are radix-2 in LDS (stages fused in pairs), one row or
 // column per block:
 // decimation in time (bit-reversed in, natural out) forward and decimation
@@ -639,13 +639,16 @@ static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, co
   return hipGetLastError();
 }
 
-hipError_t dd_convolve(const double* img, void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twx,
-                       const void* twy, const void* twz, const DDGeom& g, hipStream_t st) {
-  if (ch.C < 1 || ch.C > kDDMaxChannels) return hipErrorInvalidValue;
+hipError_t dd_convolve_rows(const double* img, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
   DDGeom rows = g;
   rows.ny = g.ny * g.nz;   // the image rows (z, y), y fastest
-  hipError_t e = dd_launch_row_fwd(img, G, twx, rows, st);
-  if (e != hipSuccess) return e;
+  return dd_launch_row_fwd(img, G, twx, rows, st);
+}
+
+hipError_t dd_convolve_columns(void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twy,
+                               const void* twz, const DDGeom& g, hipStream_t st) {
+  if (ch.C < 1 || ch.C > kDDMaxChannels) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
   if (g.ndim == 2) {
     const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My, ch};
     return launch_fused(G, Gc, tabs, twy, F, g.Mx, st);

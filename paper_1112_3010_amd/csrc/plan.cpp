@@ -1062,9 +1062,14 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
     if (c >= 1 && c <= p->ndim) ch.imag |= 1u << c;
   }
   {
-    PassTimer t(p, st, "dd_convolve");
-    e = dd_convolve(cnt, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twx,
-                    p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, g, st);
+    PassTimer t(p, st, "dd_row_fwd");
+    e = dd_convolve_rows(cnt, G, p->ws + p->off_dd_twx, g, st);
+  }
+  if (e != hipSuccess) return DT_E_HIP;
+  {
+    PassTimer t(p, st, g.ndim == 2 ? "dd_col_fused" : "dd_columns_3d");
+    e = dd_convolve_columns(G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twy,
+                            p->ws + p->off_dd_twz, g, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
   {
@@ -1107,8 +1112,10 @@ static dt_status run_backward_dd(dt_plan p, const float* Y, int64_t K, const dou
   ch.tab_of[D] = p->dd_rf_tab;
   {
     PassTimer t(p, st, "dd_convolve");
-    e = dd_convolve(img, G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twx,
-                    p->ws + p->off_dd_twy, p->ws + p->off_dd_twz, g, st);
+    e = dd_convolve_rows(img, G, p->ws + p->off_dd_twx, g, st);
+    if (e == hipSuccess)
+      e = dd_convolve_columns(G, p->ws + p->off_dd_Gc, p->ws + p->off_dd_tab, ch, p->ws + p->off_dd_twy,
+                              p->ws + p->off_dd_twz, g, st);
   }
   if (e != hipSuccess) return DT_E_HIP;
   {
