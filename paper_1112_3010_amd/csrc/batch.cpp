@@ -7,11 +7,13 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <tuple>
 #include <vector>
 
 #include "dt.h"
 #include "dt_batch.hpp"
+#include "dt_log.hpp"
 
 using namespace dt;
 
@@ -261,6 +263,28 @@ dt_batch_tiles default_tiles(dt_batch_plan p) {
   return t;
 }
 
+// -- plan log (DT_LOG) --------------------------------------------------------
+std::string radices(const MixedPlan& mp) {
+  std::string r;
+  for (int s = 0; s < mp.n_st; ++s) r += (s ? "x" : "") + std::to_string(mp.radix[s]);
+  return r;
+}
+
+void log_blocks(dt_batch_plan p) {
+  if (!log_enabled()) return;
+  static const char* pass[3] = {"rows", "columns", "epilogue rows"};
+  logf("batch plan %p blocks: tiles col_nb %d, col_threads %d, row_threads %d", (void*)p, p->tiles.col_nb,
+       p->tiles.col_threads, p->tiles.row_threads);
+  for (int k = 0; k < 3; ++k)
+    logf("  %s: %d blocks, up to %d points per thread, %zu B of LDS", pass[k], p->nblk[k], p->ecap[k], p->lds[k]);
+  for (int i = 0; i < p->n; ++i) {
+    const BatchInst& I = p->inst[i];
+    logf("  inst %d: schedule families %d/%d/%d, radices rows %s, columns %s, inverse rows %s", i, p->sched[3 * i],
+         p->sched[3 * i + 1], p->sched[3 * i + 2], radices(I.px).c_str(), radices(I.py).c_str(),
+         radices(I.pxi).c_str());
+  }
+}
+
 // Build the three block lists for the current tiles and upload them (only
 // for the instances with keep[i] != 0 when keep is given: the autotuner times
 // one pass over the instances of one length).
@@ -326,6 +350,7 @@ dt_status build_blocks(dt_batch_plan p, hipStream_t st, const std::vector<char>*
   if (hipStreamSynchronize(st) != hipSuccess) return DT_E_HIP;
   p->blocks_valid = true;
   p->drop_graph();
+  if (!keep) log_blocks(p);
   return DT_OK;
 }
 
@@ -390,6 +415,8 @@ template <typename T> dt_status build_batch_tables(dt_batch_plan p, hipStream_t 
     I.e_f = g.e[0];
     I.e_u[0] = p->C > 1 ? g.e[1] : 0;
     I.e_u[1] = p->C > 1 ? g.e[2] : 0;
+    logf("batch plan %p inst %d: ||f||_1 = %.9g; one source: Theta = %.4g, S_max = %.3f tau", (void*)p, i, g.l1,
+         I.theta_coef, -std::log(I.theta_coef));
   }
   if (hipMemcpyAsync(p->d_inst(), p->inst.data(), p->inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice, st) !=
       hipSuccess)
@@ -664,6 +691,20 @@ extern "C" dt_status dt_create_batch_plan(dt_batch_plan* out, int n_inst, const 
   p->off_A = off; off = align_b(off + a_bytes);
   p->off_B = off; off = align_b(off + b_bytes);
   p->ws_bytes = off;
+  if (log_enabled()) {
+    char mb[64];
+    logf("batch plan %p created: %d 2D instances, precision %s, outputs %s, c_theta = %g, workspace %.1f MB",
+         (void*)p, n_inst, precision_name(precision), mask_names(out_mask, mb, sizeof(mb)), p->c_theta,
+         p->ws_bytes / 1e6);
+    for (int i = 0; i < n_inst; ++i) {
+      const BatchInst& I = p->inst[i];
+      const auto& g = p->geos[p->geo_of[i]];
+      logf("  inst %d: grid %dx%d, h = %.6g %.6g, tau = %.6g, padded %lldx%lld, kernels truncated to %dx%d cells "
+           "(0: none), k_max %lld",
+           i, I.nx, I.ny, I.hx, I.hy, I.tau, (long long)g.Mx, (long long)g.My, g.cut[0], g.cut[1],
+           (long long)d[i].k_max);
+    }
+  }
   *out = p;
   return DT_OK;
 }
@@ -915,6 +956,8 @@ extern "C" dt_status dt_batch_stats(dt_batch_plan p, int i, dt_call_stats* out) 
   out->theta = s[0];
   out->s_max = s[1];
   out->g_l2 = s[2];
+  logf("batch plan %p inst %d last call: ||g||_2 = %.6g, Theta = %.4g, S_max = %.3f tau", (void*)p, i, out->g_l2,
+       out->theta, out->s_max / p->inst[i].tau);
   return DT_OK;
 }
 

@@ -364,6 +364,15 @@ template <typename T> bool launch_col2_c2c(const void* in, void* out, const ColP
 template <typename T> bool launch_col2_fused(const void* in, void* out, const ColParams& p, const FusedSpec& fs,
                                              int N, int tiles, int outer, hipStream_t st);
 
+// Row engine of an N-point line, for the plan log: points per thread and
+// the radix of each stage (returns the stage count).
+int row_points_per_thread(int N) { return row_E(N); }
+int row_radices(int N, int* radix, int cap) {
+  const int S = fft_stages(N);
+  for (int s = 0; s < S && s < cap; ++s) radix[s] = fft_radix(N, s);
+  return S;
+}
+
 int col_tile_width(int N, bool fp64, bool fused) {
   const int nb2 = col2_tile_width(N, fp64, fused);
   if (nb2 > 0) return nb2;

@@ -12,12 +12,15 @@
 #include "dt.h"
 #include "dt_dd.hpp"
 #include "dt_launch.hpp"
+#include "dt_log.hpp"
 #include "dt_static.hpp"
 
 using namespace dt;
 
 namespace dt {
 int col_tile_width(int N, bool fp64, bool fused);
+int row_points_per_thread(int N);
+int row_radices(int N, int* radix, int cap);
 }
 
 namespace {
@@ -316,6 +319,96 @@ void setup_dd(dt_plan p) {
 
 template <typename T> size_t complex_bytes() { return 2 * sizeof(T); }
 
+// -- plan log (DT_LOG) --------------------------------------------------------
+// "256x256x256" / "0.01 0.01" for the plan's axes
+std::string axes_i(const int64_t* v, int n) {
+  std::string s;
+  for (int a = 0; a < n; ++a) s += (a ? "x" : "") + std::to_string((long long)v[a]);
+  return s;
+}
+std::string axes_d(const double* v, int n) {
+  std::string s;
+  char b[32];
+  for (int a = 0; a < n; ++a) {
+    std::snprintf(b, sizeof(b), "%s%.6g", a ? " " : "", v[a]);
+    s += b;
+  }
+  return s;
+}
+std::string table_name(const Table& t) {
+  static const char ax[3] = {'x', 'y', 'z'};
+  switch (t.kd.kind) {
+    case KER_F: return "f";
+    case KER_U: return std::string("u_") + ax[t.kd.i];
+    case KER_H: return std::string("h_") + ax[t.kd.i] + ax[t.kd.j];
+    case KER_W2: return std::string("w_") + ax[t.kd.i];
+    case KER_D3: return std::string("d_") + ax[t.kd.i];
+    case KER_RF: return "rf";
+    default: return "?";
+  }
+}
+// Threshold of one source of multiplicity one (||g||_2 = 1): Theta of a call
+// with K distinct sources is sqrt(K) times this.
+double theta_one(dt_plan p) {
+  const double np = p->npad();
+  return p->c_theta * p->unit() * std::log2(np) * p->kernel_l1 / std::sqrt(np);
+}
+
+void log_created(dt_plan p) {
+  if (!log_enabled()) return;
+  const int D = p->ndim;
+  char mb[96];
+  logf("plan %p created: %dD grid %s, h = %s, origin = %s, tau = %.6g (%.3g h_x), precision %s (u = 2^-%d), "
+       "outputs %s, c_theta = %g",
+       (void*)p, D, axes_i(p->n, D).c_str(), axes_d(p->h, D).c_str(), axes_d(p->o, D).c_str(), p->tau,
+       p->tau / p->h[0], precision_name(p->prec), p->dd ? 104 : p->fp64 ? 53 : 24, mask_names(p->mask, mb, sizeof(mb)),
+       p->c_theta);
+  if (p->k_max > 0) {
+    int64_t cut[3] = {p->cut[0], p->cut[1], p->cut[2]};
+    logf("  padded %s, reduced for at most %lld sources: kernels truncated to %s cells (0: axis untruncated)",
+         axes_i(p->M, D).c_str(), (long long)p->k_max, axes_i(cut, D).c_str());
+  } else {
+    logf("  padded %s (full zero padding)", axes_i(p->M, D).c_str());
+  }
+  if (p->dd) {
+    logf("  passes: double-double radix-2 transforms staged in LDS (rows %lld, columns %s); %d spectra; "
+         "workspace %.1f MB",
+         (long long)p->M[0], axes_i(p->M + 1, D - 1).c_str(), p->dd_tabs, p->ws_bytes / 1e6);
+    return;
+  }
+  const int Q = (int)(p->M[0] / 2);
+  int rad[8];
+  const int ns = row_radices(Q, rad, 8);
+  std::string rs;
+  for (int i = 0; i < ns && i < 8; ++i) rs += (i ? "x" : "") + std::to_string(rad[i]);
+  logf("  passes: rows R2C / C2R of %lld points (%d-point complex, radices %s, %d points per thread); "
+       "half spectrum %d bins (pitch %d)",
+       (long long)p->M[0], Q, rs.c_str(), row_points_per_thread(Q), p->Mh, p->MhP);
+  if (D == 3)
+    logf("  columns: y %lld points, tiles of %d bins; fused z pass (forward, tables, inverse) %lld points, "
+         "tiles of %d bins",
+         (long long)p->M[1], p->NB, (long long)p->M[2], p->NBf);
+  else
+    logf("  columns: fused y pass (forward, tables, inverse) %lld points, tiles of %d bins", (long long)p->M[1],
+         p->NBf);
+  std::string names;
+  for (const auto& t : p->tabs) names += (names.empty() ? "" : " ") + table_name(t);
+  logf("  tables: %s (%zu of %.1f MB); channels in <= %d, out <= %d; workspace %.1f MB", names.c_str(),
+       p->tabs.size(), p->tab_elems * p->w / 1e6, p->in_max, p->out_max, p->ws_bytes / 1e6);
+}
+
+void log_attached(dt_plan p) {
+  if (!log_enabled()) return;
+  const double th = theta_one(p);
+  logf("plan %p attached: ||f||_1 = %.9g; one source: Theta = %.4g, S_max = %.3f tau", (void*)p, p->kernel_l1, th,
+       -std::log(th));
+  if (p->k_max > 0)
+    logf("  at k_max = %lld distinct sources: Theta = %.4g, S_max = %.3f tau", (long long)p->k_max,
+         th * std::sqrt((double)p->k_max), -std::log(th * std::sqrt((double)p->k_max)));
+  for (const auto& t : p->tabs)
+    logf("  table %-4s ||.||_1 = %.6g, stored scaled by 2^-%d / N_pad", table_name(t).c_str(), t.l1, t.e);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -424,6 +517,7 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
       return DT_E_UNSUPPORTED;
     }
     setup_dd(p);
+    log_created(p);
     *out = p;
     return DT_OK;
   }
@@ -515,6 +609,7 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   p->R1 = R1;
   p->R2 = R2;
   p->ws_bytes = off;
+  log_created(p);
   *out = p;
   return DT_OK;
 }
@@ -669,11 +764,13 @@ dt_status dt::plan_attach(dt_plan p, void* dev_ptr, size_t bytes, void* stream) 
     if (e != hipSuccess) return DT_E_HIP;
     p->kernel_l1 = host_kernel_l1(p->M, p->h, p->ndim, p->tau);
     p->ready = true;
+    log_attached(p);
     return DT_OK;
   }
   const dt_status s = p->fp64 ? build_tables<double>(p, st) : build_tables<float>(p, st);
   if (s != DT_OK) return s;
   p->ready = true;
+  log_attached(p);
   return DT_OK;
 }
 
@@ -1205,6 +1302,8 @@ extern "C" dt_status dt_last_stats(dt_plan p, dt_call_stats* st) {
   st->g_l2 = s[2];
   st->dL_dtau = s[4];
   st->error_bits = bits;
+  logf("plan %p last call: ||g||_2 = %.6g, Theta = %.4g, S_max = %.3f tau, error bits %u", (void*)p, st->g_l2,
+       st->theta, st->s_max / p->tau, bits);
   return DT_OK;
 }
 
@@ -1255,7 +1354,11 @@ extern "C" dt_status dt_plan_reset_timings(dt_plan p) {
 }
 
 extern "C" const char* dt_status_str(dt_status s) {
-  switch (s) {
+  // A C caller may pass any int: read the bits as an int rather than load a
+  // C++ enum value outside the enumerators' range.
+  int v;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case DT_OK: return "ok";
     case DT_E_ARG: return "invalid argument";
     case DT_E_RANGE: return "a source was outside the grid or non-finite";
