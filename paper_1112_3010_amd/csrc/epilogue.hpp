@@ -16,16 +16,6 @@ __device__ __forceinline__ double epi_log(double x) { return log(x); }
 __device__ __forceinline__ float epi_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double epi_rcp(double x) { return 1.0 / x; }
 
-__device__ __forceinline__ void hess_pair(int ndim, int h, int& i, int& j) {
-  if (ndim == 2) {
-    const int a[3] = {0, 0, 1}, c[3] = {0, 1, 1};
-    i = a[h]; j = c[h];
-  } else {
-    const int a[6] = {0, 0, 0, 1, 1, 2}, c[6] = {0, 1, 2, 1, 2, 2};
-    i = a[h]; j = c[h];
-  }
-}
-
 // Curvatures from grad S (g) and the Hessian (h, library channel order), the
 // derived quantities named at the end of Sec. 5.  c = mean, Gaussian, k1, k2
 // with k1,2 = mean +/- sqrt(max(mean^2 - Gaussian, 0)).
@@ -68,58 +58,103 @@ template <typename T> __device__ __forceinline__ void curvature_level_set(const 
   principal(mean, gauss, c);
 }
 
+// Per-call constants of the epilogue, read once per thread (the threshold
+// from the device and the power-of-two scales), so that the per-node code
+// reads nothing but the node's channels.
+template <typename T> struct EpiConst {
+  T theta, smax, tau, inv_tau, scale_phi, scale_mu;
+  T scale_u[3], scale_h[6];
+};
+template <typename T> __device__ __forceinline__ EpiConst<T> epi_const(const EpiParams& e) {
+  EpiConst<T> k;
+  k.theta = (T)e.theta[0];
+  k.smax = (T)e.theta[1];
+  k.tau = (T)e.tau;
+  k.inv_tau = (T)(1.0 / e.tau);
+  k.scale_phi = (T)e.scale_phi;
+  k.scale_mu = (T)e.scale_mu;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) k.scale_u[a] = (T)e.scale_u[a];
+#pragma unroll
+  for (int h = 0; h < 6; ++h) k.scale_h[h] = (T)e.scale_h[h];
+  return k;
+}
+
+// Hessian of S in D dimensions from the channels: h / phi + S_i S_j / tau, in
+// the library's channel order (xx, xy, [xz,] yy, [yz,] zz).
+template <typename T, int D, typename Ch>
+__device__ __forceinline__ void hessian_of(const EpiParams& e, const EpiConst<T>& k, const Ch& ch, bool valid, T inv,
+                                           const T* g, T* hv) {
+  constexpr int NH = D == 2 ? 3 : 6;
+  constexpr int I[6] = {0, 0, D == 2 ? 1 : 0, 1, 1, 2};
+  constexpr int J[6] = {0, 1, D == 2 ? 1 : 2, 1, 2, 2};
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+    hv[h] = valid ? ch(e.ch_h[h]) * inv * k.scale_h[h] + g[I[h]] * g[J[h]] * k.inv_tau : T(0);
+}
+
+// One node of the final row pass.  ch(c) returns channel c of the node.
 // CURV: the instantiation that also writes curvatures (kept apart so that the
 // other outputs' final pass keeps its register budget).
-template <typename T, bool CURV = false>
-__device__ __forceinline__ void epilogue_cell(const EpiParams& e, const T* vals, int64_t node) {
-  const T theta = (T)e.theta[0];
-  const T smax = (T)e.theta[1];
-  const T tau = (T)e.tau;
+template <typename T, bool CURV, typename Ch>
+__device__ __forceinline__ void epilogue_node(const EpiParams& e, const EpiConst<T>& k, const Ch& ch, int64_t node) {
   T label = T(1);
   if (e.ch_mu >= 0) {
-    const T mu = vals[e.ch_mu] * (T)e.scale_mu;
+    const T mu = ch(e.ch_mu) * k.scale_mu;
     label = mu >= T(0.5) ? T(1) : T(-1);
     if (e.label) e.label[node] = (int8_t)(mu >= T(0.5) ? 1 : -1);
     if (e.mu) ((T*)e.mu)[node] = mu;
   }
   if (e.ch_phi < 0) return;
-  const T cphi = vals[e.ch_phi];
-  const T phi = cphi * (T)e.scale_phi;
-  const bool valid = phi >= theta;
+  const T cphi = ch(e.ch_phi);
+  const T phi = cphi * k.scale_phi;
+  const bool valid = phi >= k.theta;
   const T sgn = (e.signed_out && e.ch_mu >= 0) ? label : T(1);
-  if (e.S) ((T*)e.S)[node] = sgn * (valid ? -tau * epi_log(phi) : smax);
+  if (e.S) ((T*)e.S)[node] = sgn * (valid ? -k.tau * epi_log(phi) : k.smax);
   if (e.ch_u[0] < 0) return;
-  T g[3] = {T(0), T(0), T(0)};
+  const bool d3 = e.ndim == 3;
   const T inv = valid ? epi_rcp(cphi) : T(0);
-  for (int a = 0; a < e.ndim; ++a) g[a] = valid ? vals[e.ch_u[a]] * inv * (T)e.scale_u[a] : T(0);
-  if (e.grad)
-    for (int a = 0; a < e.ndim; ++a) ((T*)e.grad)[a * e.plane + node] = sgn * g[a];
+  T g[3];
+  g[0] = valid ? ch(e.ch_u[0]) * inv * k.scale_u[0] : T(0);
+  g[1] = valid ? ch(e.ch_u[1]) * inv * k.scale_u[1] : T(0);
+  g[2] = (d3 && valid) ? ch(e.ch_u[2]) * inv * k.scale_u[2] : T(0);
+  if (e.grad) {
+    T* gr = (T*)e.grad;
+    gr[node] = sgn * g[0];
+    gr[e.plane + node] = sgn * g[1];
+    if (d3) gr[2 * e.plane + node] = sgn * g[2];
+  }
   if constexpr (!CURV) {
     if (e.hess && e.ch_h[0] >= 0) {
-      const int nh = e.ndim == 2 ? 3 : 6;
-      for (int h = 0; h < nh; ++h) {
-        int i, j;
-        hess_pair(e.ndim, h, i, j);
-        const T hv = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
-        ((T*)e.hess)[h * e.plane + node] = hv;
+      T hv[6];
+      T* hs = (T*)e.hess;
+      if (d3) {
+        hessian_of<T, 3>(e, k, ch, valid, inv, g, hv);
+#pragma unroll
+        for (int h = 0; h < 6; ++h) hs[h * e.plane + node] = hv[h];
+      } else {
+        hessian_of<T, 2>(e, k, ch, valid, inv, g, hv);
+#pragma unroll
+        for (int h = 0; h < 3; ++h) hs[h * e.plane + node] = hv[h];
       }
     }
   } else {
-    const int nh = e.ndim == 2 ? 3 : 6;
     T hv[6];
-#pragma unroll
-    for (int h = 0; h < 6; ++h) {
-      if (h >= nh) break;
-      int i, j;
-      hess_pair(e.ndim, h, i, j);
-      hv[h] = valid ? vals[e.ch_h[h]] * inv * (T)e.scale_h[h] + g[i] * g[j] / tau : T(0);
-      if (e.hess) ((T*)e.hess)[h * e.plane + node] = hv[h];
-    }
     T c[4];
-    if (e.ndim == 2) curvature_graph(g, hv, c);
-    else curvature_level_set(g, hv, c);
+    if (d3) {
+      hessian_of<T, 3>(e, k, ch, valid, inv, g, hv);
+      curvature_level_set(g, hv, c);
+    } else {
+      hessian_of<T, 2>(e, k, ch, valid, inv, g, hv);
+      curvature_graph(g, hv, c);
+    }
+    if (e.hess) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ((T*)e.curv)[k * e.plane + node] = c[k];
+      for (int h = 0; h < 6; ++h)
+        if (h < (d3 ? 6 : 3)) ((T*)e.hess)[h * e.plane + node] = hv[h];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ((T*)e.curv)[q * e.plane + node] = c[q];
   }
 }
 

@@ -266,6 +266,7 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
   const int64_t row = (int64_t)blockIdx.x * RPB + rl;
   const bool active = row < e.n_rows;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
+  const EpiConst<T> kc = epi_const<T>(e);
   V v[E];
   // Copy the block's half-spectrum lines into LDS with direct global-to-LDS
   // loads (16-byte words, one contiguous run per line, no registers), then
@@ -331,14 +332,20 @@ __global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ 
       ldr[(int64_t)b * 2 * LP + 2 * j + 1] = v[s * RL + r].y;
     }
   __syncthreads();
+  // channel c of a node sits 2 LP values after channel c - 1
   const int nx = p.nx;
-  for (int t = tid; t < RPB * nx; t += blockDim.x) {
-    const int r2 = t / nx, x = t % nx;
-    const int64_t row2 = (int64_t)blockIdx.x * RPB + r2;
-    if (row2 >= e.n_rows) continue;
-    T vals[kMaxChan];
-    for (int cc = 0; cc < C; ++cc) vals[cc] = ldr[(int64_t)(r2 * C + cc) * 2 * LP + x];
-    epilogue_cell<T, CURV>(e, vals, row2 * nx + x);
+  if (RPB == 1) {
+    if (active)
+      for (int x = tid; x < nx; x += blockDim.x)
+        epilogue_node<T, CURV>(e, kc, [&](int cc) { return ldr[cc * 2 * LP + x]; }, row * nx + x);
+  } else {
+    for (int t = tid; t < RPB * nx; t += blockDim.x) {
+      const int r2 = t / nx, x = t % nx;
+      const int64_t row2 = (int64_t)blockIdx.x * RPB + r2;
+      if (row2 >= e.n_rows) continue;
+      const T* base = ldr + (int64_t)r2 * C * 2 * LP + x;
+      epilogue_node<T, CURV>(e, kc, [&](int cc) { return base[cc * 2 * LP]; }, row2 * nx + x);
+    }
   }
 }
 
