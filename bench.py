@@ -767,6 +767,169 @@ def run_reduced(steps, warmup, timing_calls, no_cpu, cpu_cells):
     print(json.dumps(line), flush=True)
 
 
+def run_configs(steps, warmup, no_cpu):
+    """Every workload configuration once: the GPU forward call in float32 with
+    scaling and in float64 (median of `steps` calls), and on the host's cores
+    the oracle's direct sums timed on a bounded node sample (throughput, and
+    the full grid's time extrapolated from it), beside the paper's Table 1
+    FFT convolution in float64 with scipy (context)."""
+    import torch
+    import oracle
+    import synth
+    import paper_1112_3010_amd as dt
+    from oracle import table1
+    from threadpoolctl import threadpool_limits
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def gpu_ms(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        _, st = timed_calls(fn, steps)
+        return st["median"]
+
+    def oracle_rate(dims, h, Y, tau, n_cells, hess=False, sign=None, seed=0):
+        """Nodes per second of the oracle's S, grad S (and H, and the sign
+        sum) on n_cells sampled nodes; the sign sums run on one thread."""
+        X = oracle.grid_nodes(dims, (0.0,) * len(dims), h, sample_cells(dims, n_cells, seed))
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            oracle.fields(X, Y, tau, grad=True, hess=hess, workers=workers)
+            t_f = time.perf_counter() - t0
+        out = {"sample_nodes": n_cells, "fields_s": round(t_f, 2), "cores": workers}
+        rate = n_cells / t_f
+        if sign is not None:
+            m = max(64, n_cells // 8)
+            t0 = time.perf_counter()
+            sign(X[:m])
+            t_s = (time.perf_counter() - t0) * n_cells / m
+            out["sign_s"] = round(t_s, 2)
+            out["sign_cores"] = 1
+            rate = n_cells / (t_f + t_s)
+        out["nodes_per_s"] = round(rate, 1)
+        out["full_grid_s_extrapolated"] = round(float(np.prod(dims)) / rate, 1)
+        return out
+
+    def table1_s(idx, dims, h, tau):
+        t0 = time.perf_counter()
+        table1.table1_phi(idx, dims, h, tau, workers=workers)
+        return round(time.perf_counter() - t0, 3)
+
+    res = {}
+    # C1: 2D 128^2, 64 points at random cells, tau = 2h, S and grad S
+    w = synth.workload("c1_2d_128")
+    dims, h, tau = w.dims, (1.0 / 128,) * 2, w.taus[0]
+    Yd = torch.from_numpy(w.points).cuda()
+    c = {"grid": list(dims), "K": len(w.points), "tau_over_h": 2.0, "outputs": "S, grad S"}
+    for prec in ("fp32", "fp64"):
+        plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad"])
+        c[f"gpu_{prec}_ms"] = gpu_ms(lambda: plan.gradient(Yd))
+    idx, valid = oracle.snap(w.points, (0.0, 0.0), h, dims)
+    Yh = oracle.node_coords(idx[valid], (0.0, 0.0), h)
+    if not no_cpu:
+        c["oracle"] = oracle_rate(dims, h, Yh, tau, 16384)
+        c["table1_fft_f64_s"] = table1_s(idx[valid], dims, h, tau)
+    res["c1_2d_128"] = c
+    log("c1:", json.dumps(c))
+
+    # C2: 2D 1024^2, 8000 points on a star polygon, tau in {0.5, 2, 8} h, S, grad S, Hessian, winding number
+    w = synth.workload("c2_2d_1024_polygon")
+    dims, h = w.dims, (1.0 / 1024,) * 2
+    poly = torch.from_numpy(w.polygon).cuda()
+    idx, valid = oracle.snap(w.points, (0.0, 0.0), h, dims)
+    Yh = oracle.node_coords(idx[valid], (0.0, 0.0), h)
+    for tau in w.taus:
+        c = {"grid": list(dims), "K": len(w.points), "tau_over_h": tau * 1024,
+             "outputs": "S, grad S, Hessian, winding-number label"}
+        for prec in ("fp32", "fp64"):
+            plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad", "hess", "sign"])
+            out = {"S": plan._empty(), "grad": plan._empty(2), "hess": plan._empty(3),
+                   "label": plan._empty(dtype=torch.int8)}
+            c[f"gpu_{prec}_ms"] = gpu_ms(lambda: plan.forward_into(out, polygon=poly))
+            c[f"gpu_{prec}_s_max_over_tau"] = round(plan.last_stats()["s_max"] / tau, 2)
+        if not no_cpu:
+            c["oracle"] = oracle_rate(dims, h, Yh, tau, 16384, hess=True,
+                                      sign=lambda X: oracle.sign.winding_number(X, w.polygon))
+            c["table1_fft_f64_s"] = table1_s(idx[valid], dims, h, tau)
+        res[f"c2_2d_1024_tau{tau * 1024:g}h"] = c
+        log("c2:", json.dumps(c))
+
+    # C3: 3D 256^3, the mesh's 60 000 triangles, tau = h, S, grad S, topological degree
+    w = synth.workload("c3_3d_256_mesh")
+    dims, h, tau = w.dims, (1.0 / 256,) * 3, w.taus[0]
+    Vd, Fd = torch.from_numpy(w.vertices).cuda(), torch.from_numpy(w.faces).cuda()
+    c = {"grid": list(dims), "K": len(w.faces), "tau_over_h": 1.0, "outputs": "S, grad S, degree label"}
+    for prec in ("fp32", "fp64"):
+        plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad", "sign"])
+        out = {"S": plan._empty(), "grad": plan._empty(3), "label": plan._empty(dtype=torch.int8)}
+        c[f"gpu_{prec}_ms"] = gpu_ms(lambda: plan.forward_into(out, vertices=Vd, faces=Fd))
+        del plan, out
+        torch.cuda.empty_cache()
+    if not no_cpu:
+        Ym, P, idx, valid = oracle.sign.snapped_mesh_sources(w.vertices, w.faces, (0.0,) * 3, h, dims)
+        c["oracle"] = oracle_rate(dims, h, Ym[valid], tau, 4096,
+                                  sign=lambda X: oracle.sign.topological_degree(X, Ym[valid], P[valid]))
+        c["table1_fft_f64_s"] = table1_s(idx[valid], dims, h, tau)
+    res["c3_3d_256_mesh"] = c
+    log("c3:", json.dumps(c))
+
+    # C4: 96 2D instances in one batched call (graph replay, default tiles and schedules)
+    inst = synth.workload("c4_batch_2d").extra["instances"]
+    bd = [(n, n) for n, _ in inst]
+    Y, offs = dt.BatchPlan.pack([torch.from_numpy(y) for _, y in inst])
+    Y = Y.cuda()
+    c = {"instances": len(inst), "nodes": int(sum(n * n for n, _ in inst)), "outputs": "S, grad S"}
+    for prec in ("fp32", "fp64"):
+        plan = dt.BatchPlan(bd, [2.0 / n for n, _ in inst], precision=prec, graph=True)
+        S, G = plan.empty_outputs()
+        c[f"gpu_{prec}_ms"] = gpu_ms(lambda: plan.forward_into(Y, offs, S, G))
+        del plan, S, G
+    if not no_cpu:
+        # 256 sampled nodes of every instance, all of its sources
+        n_nodes, t_all = 0, 0.0
+        for i, (n, y) in enumerate(inst):
+            hh = (1.0 / n,) * 2
+            ii, vv = oracle.snap(y, (0.0, 0.0), hh, (n, n))
+            X = oracle.grid_nodes((n, n), (0.0, 0.0), hh, sample_cells((n, n), 256, i))
+            with threadpool_limits(1):
+                t0 = time.perf_counter()
+                oracle.fields(X, oracle.node_coords(ii[vv], (0.0, 0.0), hh), 2.0 / n, grad=True, workers=workers)
+                t_all += time.perf_counter() - t0
+            n_nodes += 256
+        c["oracle"] = {"sample_nodes": n_nodes, "fields_s": round(t_all, 2), "cores": workers,
+                       "nodes_per_s_of_an_average_instance": round(n_nodes / t_all, 1),
+                       "full_batch_s_extrapolated": round(c["nodes"] / (n_nodes / t_all), 1)}
+    res["c4_batch_2d"] = c
+    log("c4:", json.dumps(c))
+
+    # C5: 3D 128^3, 4096 points around a sphere, tau = 4h: forward S and grad S,
+    # and the backward of sum (S - S_target)^2
+    w = synth.workload("c5_3d_128_grad")
+    dims, h, tau = w.dims, (1.0 / 128,) * 3, w.taus[0]
+    Yd = torch.from_numpy(w.points).cuda()
+    T = torch.from_numpy(np.ascontiguousarray(w.target)).cuda()
+    c = {"grid": list(dims), "K": len(w.points), "tau_over_h": tau * 128,
+         "outputs": "forward S, grad S; backward dL/dY, dL/dtau"}
+    for prec in ("fp32", "fp64"):
+        plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad", "backward"])
+        c[f"gpu_{prec}_forward_ms"] = gpu_ms(lambda: plan.gradient(Yd))
+        S = plan.distance(Yd)
+        G = (2.0 * (S - T.to(S.dtype))).contiguous()
+        c[f"gpu_{prec}_backward_ms"] = gpu_ms(lambda: plan.backward(Yd, S, G))
+    if not no_cpu:
+        idx, valid = oracle.snap(w.points, (0.0,) * 3, h, dims)
+        Yh = oracle.node_coords(idx[valid], (0.0,) * 3, h)
+        c["oracle"] = oracle_rate(dims, h, Yh, tau, 32768)
+        c["table1_fft_f64_s"] = table1_s(idx[valid], dims, h, tau)
+    res["c5_3d_128_grad"] = c
+    log("c5:", json.dumps(c))
+    line = {"metric": "per-configuration GPU call time and oracle throughput", "unit": "ms", "n_gpus": 1,
+            "steps": steps, "warmup": warmup, "higher_is_better": False, "data": "synthetic",
+            "host": {"cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "oracle_threads": workers},
+            "config": {"workload": "all_configurations"}, "configs": res}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -777,10 +940,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-curv", action="store_true", help="skip the 256^3 curvature timing")
-    ap.add_argument("--workload", choices=["mesh256", "batch", "protocol", "dd", "reduced"], default="mesh256",
+    ap.add_argument("--workload", choices=["mesh256", "batch", "protocol", "dd", "reduced", "configs"],
+                    default="mesh256",
                     help="mesh256: the 256^3 mesh headline (default); batch: 96 mixed-size 2D instances; "
                          "protocol: Example 1 of Sec. 6.1 against Table 2; dd: 1024^2 polygon S in double-double; "
-                         "reduced: the 256^3 mesh with k_max reduced padding, beside full padding")
+                         "reduced: the 256^3 mesh with k_max reduced padding, beside full padding; "
+                         "configs: every workload configuration, GPU beside the oracle")
     ap.add_argument("--trials", type=int, default=200, help="trials per tau of --workload protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy (3 times) to calibrate HBM traffic counters, then exit")
@@ -810,6 +975,9 @@ def main():
         return
     if args.workload == "reduced":
         run_reduced(args.steps, args.warmup, args.timing_calls, args.no_cpu, min(args.cpu_cells, 8192))
+        return
+    if args.workload == "configs":
+        run_configs(min(args.steps, 20), args.warmup, args.no_cpu)
         return
     import synth
     n = 256

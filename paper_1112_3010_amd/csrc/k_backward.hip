@@ -88,14 +88,31 @@ __global__ void __launch_bounds__(256) k_gather(GatherParams p) {
       // (x < n <= 1024, M <= 2048: the products fit 32 bits)
       const int step = (64 * idx[0]) % p.Mx;
       int m = (lane * idx[0]) % p.Mx;
-      for (int kk = lane; kk <= half; kk += 64) {
-        const V w = cconj(tw[m]);  // exp(+2 pi i kk x / M)
-        m += step;
-        if (m >= p.Mx) m -= p.Mx;
-        const double wt = (kk == 0 || kk == half) ? 1.0 : 2.0;
-        for (int c = 0; c < nch; ++c) {
-          const V X = ((const V*)p.spec)[(int64_t)c * p.ch_stride + row * p.pitch + kk];
-          accs[c] += wt * (double)(X.x * w.x - X.y * w.y);
+      const V* base = (const V*)p.spec + row * p.pitch;
+      // kU bins per lane per round, all loads issued before the sums (the
+      // order of the sums is that of kk, as one bin at a time)
+      constexpr int kU = 4;
+      for (int kk0 = lane; kk0 <= half; kk0 += 64 * kU) {
+        V w[kU], X[kU][4];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int kk = kk0 + 64 * u;
+          const bool on = kk <= half;
+          w[u] = on ? cconj(tw[m]) : mk<V>(T(0), T(0));   // exp(+2 pi i kk x / M)
+          m += step;
+          if (m >= p.Mx) m -= p.Mx;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            X[u][c] = (on && c < nch) ? base[(int64_t)c * p.ch_stride + kk] : mk<V>(T(0), T(0));
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int kk = kk0 + 64 * u;
+          if (kk > half) break;
+          const double wt = (kk == 0 || kk == half) ? 1.0 : 2.0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (c < nch) accs[c] += wt * (double)(X[u][c].x * w[u].x - X[u][c].y * w[u].y);
         }
       }
     }

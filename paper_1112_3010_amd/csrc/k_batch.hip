@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "dt_batch.hpp"
+#include "epilogue.hpp"
 
 namespace dt {
 
@@ -250,9 +251,9 @@ __global__ void __launch_bounds__(512) k_batch_row_c2r_epi(BatchArgs a) {
     const T cphi = ldr[(int64_t)(l * C) * 2 * LP + x];
     const T phi = cphi * scale_phi;
     const bool valid = phi >= theta;
-    if (S) S[I->out_off + node] = valid ? -tau * log(phi) : smax;
+    if (S) S[I->out_off + node] = valid ? -tau * epi_log(phi) : smax;
     if (G && C == kBatchChan) {
-      const T inv = valid ? T(1) / cphi : T(0);
+      const T inv = valid ? epi_rcp(cphi) : T(0);
       const T g0 = valid ? ldr[(int64_t)(l * C + 1) * 2 * LP + x] * inv * su0 : T(0);
       const T g1 = valid ? ldr[(int64_t)(l * C + 2) * 2 * LP + x] * inv * su1 : T(0);
       G[2 * I->out_off + node] = g0;
