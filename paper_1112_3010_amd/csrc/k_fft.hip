@@ -102,13 +102,21 @@ __global__ void __launch_bounds__(256) k_row_r2c(const T* __restrict__ in, Cx<T>
   F::store_last(lds, v, q, addr);
   __syncthreads();
   if (!active) return;
+  // twiddles of this thread's output bins k = q + Q j (k <= N), all loads issued at once
+  constexpr int NK = N / Q + 1;
+  V twk[NK];
+#pragma unroll
+  for (int j = 0; j < NK; ++j) twk[j] = q + Q * j <= N ? tw[q + Q * j] : mk<V>(T(0), T(0));
   V* dst = out + line * (int64_t)p.pitch;
-  for (int k = q; k <= N; k += Q) {
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int k = q + Q * j;
+    if (k > N) break;
     const V zk = lds[addr(row_wrap<N>(k))];
     const V zc = cconj(lds[addr(row_wrap<N>(N - k))]);
     const V ev = cscale(cadd(zk, zc), T(0.5));
     const V od = cscale(mul_mi(csub(zk, zc)), T(0.5));
-    dst[k] = cadd(ev, cmul(tw[k], od));
+    dst[k] = cadd(ev, cmul(twk[j], od));
   }
 }
 
