@@ -253,8 +253,12 @@ __global__ void __launch_bounds__(NT) k_col_fused(const Cx<T>* __restrict__ in, 
 // ---------------------------------------------------------------------------
 // Row pass: half spectrum -> real, fused with the epilogue
 // ---------------------------------------------------------------------------
+// The float32 S/grad instantiation is held to eight waves per SIMD: left to
+// itself the compiler keeps about 106 scalar registers (seven waves), and the
+// pass is VALU-bound, so the eighth wave pays for the few scalar spills.
 template <typename T, int N, bool CURV>
-__global__ void __launch_bounds__(1024) k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && !CURV) ? 8 : 1)))
+k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   using V = Cx<T>;
   constexpr int E = row_E(N);
   constexpr int Q = N / E;
