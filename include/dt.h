@@ -384,11 +384,12 @@ dt_status dt_forward_batched(dt_batch_plan plan, const float* Y, const int64_t* 
 dt_status dt_batch_set_schedule(dt_batch_plan plan, const int* fams);
 dt_status dt_batch_get_schedule(dt_batch_plan plan, int* fams);
 /* Times every feasible tile choice (reps calls each, eager, on `stream`)
- * and keeps the fastest, returned in *best (may be NULL); then, per pass
- * and per padded length, times that pass alone over the instances of that
- * length under each distinct radix schedule and keeps the fastest (read it
- * with dt_batch_get_schedule).  Overwrites S and grad.  Synchronises the
- * stream. */
+ * and keeps the fastest; then, per pass and per padded length, times that
+ * pass alone over the instances of that length under each distinct radix
+ * schedule and keeps the fastest (read it with dt_batch_get_schedule); then
+ * times the tile choices once more under those schedules.  The final tiles
+ * are returned in *best (may be NULL).  Overwrites S and grad.
+ * Synchronises the stream. */
 dt_status dt_batch_autotune(dt_batch_plan plan, const float* Y, const int64_t* K_offsets, void* S, void* grad,
                             int reps, void* stream, dt_batch_tiles* best);
 /* Synchronises the plan's stream; returns and clears the sticky error. */

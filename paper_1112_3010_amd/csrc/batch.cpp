@@ -849,21 +849,24 @@ extern "C" dt_status dt_batch_autotune(dt_batch_plan p, const float* Y, const in
     if (time_cfg(cur, ms)) best_ms = ms;
   }
   // column pass first (tile width and threads), then the row passes
-  for (int nb : {2, 4, 8, 16, 32})
-    for (int nt : {256, 512, 1024}) {
+  auto sweep_tiles = [&]() {
+    for (int nb : {2, 4, 8, 16, 32})
+      for (int nt : {128, 256, 512, 1024}) {
+        dt_batch_tiles t = win;
+        t.col_nb = nb;
+        t.col_threads = nt;
+        float ms;
+        if (time_cfg(t, ms) && ms < best_ms) { best_ms = ms; win = t; }
+      }
+    for (int nt : {128, 256, 512}) {
       dt_batch_tiles t = win;
-      t.col_nb = nb;
-      t.col_threads = nt;
+      t.row_threads = nt;
       float ms;
       if (time_cfg(t, ms) && ms < best_ms) { best_ms = ms; win = t; }
     }
-  for (int nt : {128, 256, 512}) {
-    dt_batch_tiles t = win;
-    t.row_threads = nt;
-    float ms;
-    if (time_cfg(t, ms) && ms < best_ms) { best_ms = ms; win = t; }
-  }
-  p->tiles = win;
+    p->tiles = win;
+  };
+  sweep_tiles();
   // Radix schedule per (pass, length): every candidate schedule of a length
   // is timed on that pass alone over the instances of that length.
   auto time_pass = [&](int k, float& ms) -> bool {
@@ -903,6 +906,13 @@ extern "C" dt_status dt_batch_autotune(dt_batch_plan p, const float* Y, const in
       }
       for (int i : kv.second) p->sched[3 * i + k] = best_f;
     }
+  }
+  // the tiles again, under the chosen schedules (the best tiles depend on them)
+  s = apply_schedule(p, st);
+  if (s == DT_OK) {
+    float ms;
+    best_ms = time_cfg(win, ms) ? ms : 1e30f;
+    sweep_tiles();
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
