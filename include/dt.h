@@ -29,7 +29,8 @@
  *         A source outside the grid, or non-finite, is skipped and raises
  *         a sticky device error (DT_E_RANGE) reported by dt_last_error().
  * Padding. Every axis is zero-padded to M_d >= 2 n_d (a power of two), so
- *         the FFT evaluates the linear (not circular) convolution.
+ *         the FFT evaluates the linear (not circular) convolution; plans
+ *         made by dt_create_plan_reduced pad less, with truncated kernels.
  * Precision. DT_FP32_SCALED works in float32 with power-of-two scaling of
  *         the source image and kernel spectra (exact, so only the range is
  *         affected); DT_FP64 works in float64.  Output fields have the
@@ -40,10 +41,11 @@
  *         fails far from the sources: S_max grows from about 25-30 tau to
  *         about 60 tau.  It is built for 2D plans and for 3D plans of at
  *         most 256 nodes per axis whose out_mask holds only DT_OUT_S,
- *         DT_OUT_GRAD, DT_OUT_HESS and DT_OUT_CURV (dt_distance,
- *         dt_gradient, dt_hessian, dt_forward with S, grad, hess and/or
- *         curv; float64 output; other requests return DT_E_UNSUPPORTED);
- *         DT_AUTO considers it for such plans after float32 and float64.
+ *         DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_CURV and DT_OUT_BACKWARD
+ *         (dt_distance, dt_gradient, dt_hessian, dt_backward, dt_forward
+ *         with S, grad, hess and/or curv; float64 output; other requests
+ *         return DT_E_UNSUPPORTED); DT_AUTO considers it for such plans
+ *         after float32 and float64.
  * Validity. An FFT convolution in finite precision has an absolute error
  *         floor; nodes where phi falls below the threshold
  *           Theta = c_theta * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
@@ -56,6 +58,12 @@
  *         the default stream) and returns without synchronising.  Argument
  *         errors are detected on the host, return at once and enqueue
  *         nothing.  A plan is not thread-safe; distinct plans are.
+ * Logging. With the environment variable DT_LOG set (not "0"), plan
+ *         creation, workspace attach and dt_last_stats / dt_batch_stats print
+ *         the plan's choices to stderr: padded lengths and truncation box,
+ *         precision, row radices, column tiles, tables, ||f||_1, Theta and
+ *         S_max for one source, the last call's Theta; for batched plans the
+ *         per-instance padding, radix schedules and tiles.
  * Memory. The library never allocates device memory: the caller provides
  *         one workspace per plan (dt_plan_workspace_size) and owns all
  *         inputs and outputs.  Kernel spectra live in the workspace.  For
