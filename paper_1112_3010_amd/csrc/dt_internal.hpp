@@ -9,7 +9,6 @@ namespace dt {
 constexpr int kMaxTables = 16;
 constexpr int kMaxIn = 4;     // input channels of one fused group
 constexpr int kMaxOut = 12;   // output channels of one fused group
-constexpr int kMaxChan = 16;  // channels reaching the final row pass
 // s_waitcnt immediate with vmcnt = 0 and expcnt, lgkmcnt at their maxima (no wait on those)
 constexpr int kWaitVmcnt0 = 0x0F70;
 

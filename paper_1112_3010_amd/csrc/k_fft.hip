@@ -274,7 +274,7 @@ k_row_c2r_epi(const Cx<T>* __restrict__ in, RowParams p, EpiParams e) {
   const int RPB = lines / C;
   const int tid = threadIdx.x;
   const int q = tid % Q, b = tid / Q;
-  const int rl = b / C, c = b % C;
+  const int rl = b / C;
   const int64_t row = (int64_t)blockIdx.x * RPB + rl;
   const bool active = row < e.n_rows;
   const V* tw = (const V*)p.tw;  // exp(-2 pi i m / M), M = 2N
