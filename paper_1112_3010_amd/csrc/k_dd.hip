@@ -68,39 +68,45 @@ __device__ __forceinline__ ddc twiddle(const ddc* __restrict__ tw, int k, bool i
 // order out.  tw[k] = exp(-2 pi i k / M); INV conjugates it.  Stages s and
 // s + 1 are taken together: a thread carries four elements through both in
 // registers (the same butterflies as two radix-2 stages), which halves the
-// LDS round trips and barriers; an odd last stage runs alone.
-template <bool INV>
-__device__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+// LDS round trips and barriers; an odd last stage runs alone.  NL lines of
+// M elements stored back to back are transformed together (the same
+// arithmetic per line).
+template <bool INV, int NL = 1>
+__device__ __forceinline__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
   int s = 1;
   for (; s + 1 <= logM; s += 2) {
     const int half = 1 << (s - 1);
-    for (int q = threadIdx.x; q < (M >> 2); q += blockDim.x) {
+    for (int qa = threadIdx.x; qa < NL * (M >> 2); qa += blockDim.x) {
+      ddc* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);   // line qa / (M / 4)
+      const int q = NL == 1 ? qa : qa & ((M >> 2) - 1);
       const int j = q & (half - 1);
       const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
       const ddc wa = twiddle(tw, j * (M >> s), INV);
       const ddc wb = twiddle(tw, j * (M >> (s + 1)), INV);
       const ddc wc = twiddle(tw, (j + half) * (M >> (s + 1)), INV);
-      const ddc a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      const ddc a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
       const ddc t1 = ddm::cmul(a1, wa), t3 = ddm::cmul(a3, wa);
       const ddc x0 = ddm::cadd(a0, t1), x1 = ddm::csub(a0, t1);
       const ddc x2 = ddm::cadd(a2, t3), x3 = ddm::csub(a2, t3);
       const ddc u2 = ddm::cmul(x2, wb), u3 = ddm::cmul(x3, wc);
-      buf[i0] = ddm::cadd(x0, u2);
-      buf[i0 + 2 * half] = ddm::csub(x0, u2);
-      buf[i0 + half] = ddm::cadd(x1, u3);
-      buf[i0 + 3 * half] = ddm::csub(x1, u3);
+      b[i0] = ddm::cadd(x0, u2);
+      b[i0 + 2 * half] = ddm::csub(x0, u2);
+      b[i0 + half] = ddm::cadd(x1, u3);
+      b[i0 + 3 * half] = ddm::csub(x1, u3);
     }
     __syncthreads();
   }
   if (s == logM) {
     const int half = 1 << (s - 1);
-    for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
-      const int j = b & (half - 1);
-      const int i0 = ((b >> (s - 1)) << s) + j;
-      const ddc v = ddm::cmul(buf[i0 + half], twiddle(tw, j * (M >> s), INV));
-      const ddc u = buf[i0];
-      buf[i0] = ddm::cadd(u, v);
-      buf[i0 + half] = ddm::csub(u, v);
+    for (int ba = threadIdx.x; ba < NL * (M >> 1); ba += blockDim.x) {
+      ddc* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
+      const int bb = NL == 1 ? ba : ba & ((M >> 1) - 1);
+      const int j = bb & (half - 1);
+      const int i0 = ((bb >> (s - 1)) << s) + j;
+      const ddc v = ddm::cmul(bu[i0 + half], twiddle(tw, j * (M >> s), INV));
+      const ddc u = bu[i0];
+      bu[i0] = ddm::cadd(u, v);
+      bu[i0 + half] = ddm::csub(u, v);
     }
     __syncthreads();
   }
@@ -108,18 +114,20 @@ __device__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
 
 // In-place radix-2 decimation in frequency over natural-order input;
 // bit-reversed order out.  An odd top stage runs alone, then stages t and
-// t - 1 are taken together as in fft_dit.
-template <bool INV>
-__device__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+// t - 1 are taken together as in fft_dit; NL lines as in fft_dit.
+template <bool INV, int NL = 1>
+__device__ __forceinline__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
   int t = logM;
   if (logM & 1) {
     const int half = 1 << (t - 1);
-    for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
-      const int j = b & (half - 1);
-      const int i0 = ((b >> (t - 1)) << t) + j;
-      const ddc u = buf[i0], v = buf[i0 + half];
-      buf[i0] = ddm::cadd(u, v);
-      buf[i0 + half] = ddm::cmul(ddm::csub(u, v), twiddle(tw, j * (M >> t), INV));
+    for (int ba = threadIdx.x; ba < NL * (M >> 1); ba += blockDim.x) {
+      ddc* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
+      const int bb = NL == 1 ? ba : ba & ((M >> 1) - 1);
+      const int j = bb & (half - 1);
+      const int i0 = ((bb >> (t - 1)) << t) + j;
+      const ddc u = bu[i0], v = bu[i0 + half];
+      bu[i0] = ddm::cadd(u, v);
+      bu[i0 + half] = ddm::cmul(ddm::csub(u, v), twiddle(tw, j * (M >> t), INV));
     }
     __syncthreads();
     --t;
@@ -127,19 +135,21 @@ __device__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
   for (; t >= 2; t -= 2) {
     const int s = t - 1;              // lower stage of the pair
     const int half = 1 << (s - 1);
-    for (int q = threadIdx.x; q < (M >> 2); q += blockDim.x) {
+    for (int qa = threadIdx.x; qa < NL * (M >> 2); qa += blockDim.x) {
+      ddc* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);
+      const int q = NL == 1 ? qa : qa & ((M >> 2) - 1);
       const int j = q & (half - 1);
       const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
       const ddc wb = twiddle(tw, j * (M >> t), INV);
       const ddc wc = twiddle(tw, (j + half) * (M >> t), INV);
       const ddc wa = twiddle(tw, j * (M >> s), INV);
-      const ddc a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      const ddc a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
       const ddc y0 = ddm::cadd(a0, a2), y2 = ddm::cmul(ddm::csub(a0, a2), wb);
       const ddc y1 = ddm::cadd(a1, a3), y3 = ddm::cmul(ddm::csub(a1, a3), wc);
-      buf[i0] = ddm::cadd(y0, y1);
-      buf[i0 + half] = ddm::cmul(ddm::csub(y0, y1), wa);
-      buf[i0 + 2 * half] = ddm::cadd(y2, y3);
-      buf[i0 + 3 * half] = ddm::cmul(ddm::csub(y2, y3), wa);
+      b[i0] = ddm::cadd(y0, y1);
+      b[i0 + half] = ddm::cmul(ddm::csub(y0, y1), wa);
+      b[i0 + 2 * half] = ddm::cadd(y2, y3);
+      b[i0 + 3 * half] = ddm::cmul(ddm::csub(y2, y3), wa);
     }
     __syncthreads();
   }
@@ -222,49 +232,69 @@ __global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
 struct DDLines {
   int M, logM, n_inner, n_in, n_out;
   int64_t n_lines, in_outer, in_stride, out_outer, out_stride;
+  int log_lb;   // a block takes 2^log_lb adjacent lines (n_inner a multiple of that)
 };
 
 // Forward transform of each line (input elements j >= n_in are zero).
 // MODE 0: complex spectrum to out; 1 / 2: its real / imaginary part times
-// 2^scale_e to tab.  A block reads its whole line before writing, so in and
-// out may be the same array.
-template <int MODE>
+// 2^scale_e to tab.  A block takes LB = 2^log_lb adjacent lines (the inner
+// index is the fastest in memory, so element j of the LB lines is one
+// contiguous run) and reads them whole before writing, so in and out may be
+// the same array.
+template <int MODE, int LB>
 __global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const ddc* __restrict__ in, ddc* __restrict__ out,
                                                           dd* __restrict__ tab, const ddc* __restrict__ tw,
                                                           DDLines L, int scale_e) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
-  const int64_t l = blockIdx.x;
+  constexpr int lb = LB;
+  const int64_t l = (int64_t)blockIdx.x << L.log_lb;
   const int64_t o = l / L.n_inner, i = l % L.n_inner;
   const ddc* src = in + o * L.in_outer + i;
-  for (int j = threadIdx.x; j < L.M; j += blockDim.x)
-    buf[brev(j, L.logM)] = j < L.n_in ? src[(int64_t)j * L.in_stride] : zero_c();
+  for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
+    const int t = u & (lb - 1), j = u >> L.log_lb;
+    buf[(t << L.logM) + brev(j, L.logM)] = j < L.n_in ? src[(int64_t)j * L.in_stride + t] : zero_c();
+  }
   __syncthreads();
-  fft_dit<false>(buf, L.M, L.logM, tw);
+  fft_dit<false, LB>(buf, L.M, L.logM, tw);
   if (MODE == 0) {
     ddc* dst = out + o * L.out_outer + i;
-    for (int k = threadIdx.x; k < L.M; k += blockDim.x) dst[(int64_t)k * L.out_stride] = buf[k];
+    for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
+      const int t = u & (lb - 1), k = u >> L.log_lb;
+      dst[(int64_t)k * L.out_stride + t] = buf[(t << L.logM) + k];
+    }
   } else {
     dd* dst = tab + o * L.out_outer + i;
-    for (int k = threadIdx.x; k < L.M; k += blockDim.x)
-      dst[(int64_t)k * L.out_stride] = ddm::scale2(MODE == 2 ? buf[k].im : buf[k].re, scale_e);
+    for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
+      const int t = u & (lb - 1), k = u >> L.log_lb;
+      const ddc v = buf[(t << L.logM) + k];
+      dst[(int64_t)k * L.out_stride + t] = ddm::scale2(MODE == 2 ? v.im : v.re, scale_e);
+    }
   }
 }
 
 // Inverse (unnormalised) transform of each line from its natural-order
-// spectrum; the first n_out samples are kept.
+// spectrum; the first n_out samples are kept.  LB adjacent lines per block.
+template <int LB>
 __global__ __launch_bounds__(kThreads) void k_dd_line_inv(const ddc* __restrict__ in, ddc* __restrict__ out,
                                                           const ddc* __restrict__ tw, DDLines L) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
-  const int64_t l = blockIdx.x;
+  constexpr int lb = LB;
+  const int64_t l = (int64_t)blockIdx.x << L.log_lb;
   const int64_t o = l / L.n_inner, i = l % L.n_inner;
   const ddc* src = in + o * L.in_outer + i;
-  for (int k = threadIdx.x; k < L.M; k += blockDim.x) buf[k] = src[(int64_t)k * L.in_stride];
+  for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
+    const int t = u & (lb - 1), k = u >> L.log_lb;
+    buf[(t << L.logM) + k] = src[(int64_t)k * L.in_stride + t];
+  }
   __syncthreads();
-  fft_dif<true>(buf, L.M, L.logM, tw);
+  fft_dif<true, LB>(buf, L.M, L.logM, tw);
   ddc* dst = out + o * L.out_outer + i;
-  for (int y = threadIdx.x; y < L.n_out; y += blockDim.x) dst[(int64_t)y * L.out_stride] = buf[brev(y, L.logM)];
+  for (int u = threadIdx.x; u < (L.n_out << L.log_lb); u += blockDim.x) {
+    const int t = u & (lb - 1), y = u >> L.log_lb;
+    dst[(int64_t)y * L.out_stride + t] = buf[(t << L.logM) + brev(y, L.logM)];
+  }
 }
 
 // Forward transform of rows.  REAL_IN: row y of the ny x nx multiplicities,
@@ -324,45 +354,62 @@ struct DDFused {
   int M, logM, n;
   int64_t stride, plane, tab_chan;
   DDChannels ch;
+  int log_lb;   // a block takes 2^log_lb adjacent lines
 };
 
-template <bool MULTI>
+template <bool MULTI, int LB>
 __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
                                                            const dd* __restrict__ tabs, const ddc* __restrict__ tw,
                                                            DDFused F, int C) {
   extern __shared__ __align__(16) char smem[];
   ddc* buf = (ddc*)smem;
-  const int64_t kx = blockIdx.x;   // the line
+  constexpr int lb = LB;
+  const int64_t kx = (int64_t)blockIdx.x << F.log_lb;   // the block's first line
   const int M = F.M;
+  const int ML = M << F.log_lb;   // elements of the block's lines; element u: line u mod LB, row u / LB
   const int64_t npad = F.tab_chan, plane = F.plane;
-  for (int y = threadIdx.x; y < M; y += blockDim.x)
-    buf[brev(y, F.logM)] = y < F.n ? Gin[(int64_t)y * F.stride + kx] : zero_c();
+  for (int u = threadIdx.x; u < ML; u += blockDim.x) {
+    const int t = u & (lb - 1), y = u >> F.log_lb;
+    buf[(t << F.logM) + brev(y, F.logM)] = y < F.n ? Gin[(int64_t)y * F.stride + kx + t] : zero_c();
+  }
   __syncthreads();
-  fft_dit<false>(buf, M, F.logM, tw);
+  fft_dit<false, LB>(buf, M, F.logM, tw);
   ddc sp[MULTI ? kSpecPerThread : 1];
   if (MULTI) {
 #pragma unroll
     for (int k = 0; k < kSpecPerThread; ++k) {
-      const int ky = threadIdx.x + k * blockDim.x;
-      if (ky < M) sp[k] = buf[ky];
+      const int u = threadIdx.x + k * blockDim.x;
+      if (u < ML) sp[k] = buf[((u & (lb - 1)) << F.logM) + (u >> F.log_lb)];
     }
   }
   for (int c = 0; c < C; ++c) {
     const dd* tab = tabs + F.ch.tab_of[c] * npad;
+    if (MULTI) __syncthreads();   // every thread has read its spectrum bins (or its last outputs)
+    // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t; each
+    // thread rewrites only the slots whose spectrum it holds
+    const bool imag = (F.ch.imag >> c) & 1u;
+    auto product = [&](int u, const ddc& a) {
+      const int t = u & (lb - 1), ky = u >> F.log_lb;
+      const dd tv = tab[(int64_t)ky * F.stride + kx + t];
+      buf[(t << F.logM) + ky] = !imag ? ddm::cmul_real(a, tv) : ddc{ddm::neg(ddm::mul(a.im, tv)), ddm::mul(a.re, tv)};
+    };
+    if (MULTI) {
 #pragma unroll
-    for (int k = 0; k < (MULTI ? kSpecPerThread : M / kThreads + 1); ++k) {
-      const int ky = threadIdx.x + k * blockDim.x;
-      if (ky >= M) break;
-      const dd t = tab[(int64_t)ky * F.stride + kx];
-      const ddc a = MULTI ? sp[k] : buf[ky];
-      // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t
-      buf[ky] = !((F.ch.imag >> c) & 1u) ? ddm::cmul_real(a, t)
-                                         : ddc{ddm::neg(ddm::mul(a.im, t)), ddm::mul(a.re, t)};
+      for (int k = 0; k < kSpecPerThread; ++k) {
+        const int u = threadIdx.x + k * blockDim.x;
+        if (u < ML) product(u, sp[k]);
+      }
+    } else {
+      for (int u = threadIdx.x; u < ML; u += blockDim.x)
+        product(u, buf[((u & (lb - 1)) << F.logM) + (u >> F.log_lb)]);
     }
     __syncthreads();
-    fft_dif<true>(buf, M, F.logM, tw);
-    for (int y = threadIdx.x; y < F.n; y += blockDim.x) Gout[c * plane + (int64_t)y * F.stride + kx] = buf[brev(y, F.logM)];
-    __syncthreads();
+    fft_dif<true, LB>(buf, M, F.logM, tw);
+    for (int u = threadIdx.x; u < (F.n << F.log_lb); u += blockDim.x) {
+      const int t = u & (lb - 1), y = u >> F.log_lb;
+      Gout[c * plane + (int64_t)y * F.stride + kx + t] = buf[(t << F.logM) + brev(y, F.logM)];
+    }
+    if (!MULTI) __syncthreads();
   }
 }
 
@@ -544,35 +591,65 @@ hipError_t allow_lds(F kern, size_t lds) {
 
 }  // namespace
 
+// Adjacent lines per block of the strided line passes, as a power of two:
+// four (a 128-byte run of double-double complex values per row) where the
+// block's lines stay within 64 KiB of LDS, else one.
+static int dd_log_lb(int M, int64_t n_inner) { return (M <= 512 && n_inner % 4 == 0) ? 2 : 0; }
+
+// Launches of the strided line passes with L.log_lb adjacent lines per block.
+template <int MODE>
+static hipError_t launch_line_fwd(const ddc* in, ddc* out, dd* tab, const ddc* tw, const DDLines& L, int scale_e,
+                                  hipStream_t st) {
+  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(ddc);
+  const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
+  hipError_t e;
+  if (L.log_lb == 2) {
+    if ((e = allow_lds(k_dd_line_fwd<MODE, 4>, lds)) != hipSuccess) return e;
+    k_dd_line_fwd<MODE, 4><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+  } else {
+    if ((e = allow_lds(k_dd_line_fwd<MODE, 1>, lds)) != hipSuccess) return e;
+    k_dd_line_fwd<MODE, 1><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+  }
+  return hipSuccess;
+}
+static hipError_t launch_line_inv(const ddc* in, ddc* out, const ddc* tw, const DDLines& L, hipStream_t st) {
+  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(ddc);
+  const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
+  hipError_t e;
+  if (L.log_lb == 2) {
+    if ((e = allow_lds(k_dd_line_inv<4>, lds)) != hipSuccess) return e;
+    k_dd_line_inv<4><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+  } else {
+    if ((e = allow_lds(k_dd_line_inv<1>, lds)) != hipSuccess) return e;
+    k_dd_line_inv<1><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+  }
+  return hipSuccess;
+}
+
 // 3D tables: rows of the Mz x My sample rows in place, then the y lines in
 // place, then the z lines into the real or imaginary spectrum.
 hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
                               const DDGeom& g, hipStream_t st) {
   k_dd_twiddles<<<(g.Mz / 2 + 255) / 256, 256, 0, st>>>((ddc*)twz, g.Mz);
   const int64_t plane = (int64_t)g.Mx * g.My, total = plane * g.Mz;
-  const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc), lz = (size_t)g.Mz * sizeof(ddc);
+  const size_t lx = (size_t)g.Mx * sizeof(ddc);
   hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
-  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<0>, ly);
-  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<1>, lz);
-  if (e == hipSuccess) e = allow_lds(k_dd_line_fwd<2>, lz);
   if (e != hipSuccess) return e;
   DDGeom rows = g;
   rows.ny = g.My * g.Mz;   // every sample row
-  DDLines ly_{g.My, g.logMy, g.Mx, g.My, g.My, (int64_t)g.Mz * g.Mx, plane, g.Mx, plane, g.Mx};
-  DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane};
+  DDLines ly_{g.My, g.logMy, g.Mx, g.My, g.My, (int64_t)g.Mz * g.Mx, plane, g.Mx, plane, g.Mx, dd_log_lb(g.My, g.Mx)};
+  DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane, dd_log_lb(g.Mz, plane)};
   for (int t = 0; t < n_tabs; ++t) {
     dd* tab = (dd*)tabs + t * total;
     k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t == rf_tab ? kDDKindRF : t);
     k_dd_row_fwd<false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, rows);
-    k_dd_line_fwd<0><<<(unsigned)ly_.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy,
-                                                                  ly_, 0);
+    if ((e = launch_line_fwd<0>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy, ly_, 0, st)) != hipSuccess) return e;
     const int e_scale = -(g.logMx + g.logMy + g.logMz);
     if (t == rf_tab || !dd_imag_channel(t, g.ndim))
-      k_dd_line_fwd<1><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
-                                                                    e_scale);
+      e = launch_line_fwd<1>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_, e_scale, st);
     else
-      k_dd_line_fwd<2><<<(unsigned)lz_.n_lines, kThreads, lz, st>>>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_,
-                                                                    e_scale);
+      e = launch_line_fwd<2>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_, e_scale, st);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -620,21 +697,35 @@ hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const 
   return hipGetLastError();
 }
 
-static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, const void* tw, const DDFused& F,
+static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, const void* tw, const DDFused& F0,
                                int64_t lines, hipStream_t st) {
-  const size_t lds = (size_t)F.M * sizeof(ddc);
+  DDFused F = F0;
+  F.log_lb = dd_log_lb(F.M, lines);
+  const size_t lds = ((size_t)F.M << F.log_lb) * sizeof(ddc);
+  const unsigned blocks = (unsigned)(lines >> F.log_lb);
   const int C = F.ch.C;
+  const ddc* gi = (const ddc*)Gin;
+  ddc* go = (ddc*)Gout;
+  const dd* tb = (const dd*)tabs;
+  const ddc* w = (const ddc*)tw;
+  hipError_t e;
   if (C > 1) {
-    if (F.M > kSpecPerThread * kThreads) return hipErrorInvalidValue;
-    const hipError_t e = allow_lds(k_dd_col_fused<true>, lds);
-    if (e != hipSuccess) return e;
-    k_dd_col_fused<true><<<(unsigned)lines, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs,
-                                                                 (const ddc*)tw, F, C);
+    if ((F.M << F.log_lb) > kSpecPerThread * kThreads) return hipErrorInvalidValue;
+    if (F.log_lb == 2) {
+      if ((e = allow_lds(k_dd_col_fused<true, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<true, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    } else {
+      if ((e = allow_lds(k_dd_col_fused<true, 1>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<true, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    }
   } else {
-    const hipError_t e = allow_lds(k_dd_col_fused<false>, lds);
-    if (e != hipSuccess) return e;
-    k_dd_col_fused<false><<<(unsigned)lines, kThreads, lds, st>>>((const ddc*)Gin, (ddc*)Gout, (const dd*)tabs,
-                                                                  (const ddc*)tw, F, C);
+    if (F.log_lb == 2) {
+      if ((e = allow_lds(k_dd_col_fused<false, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<false, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    } else {
+      if ((e = allow_lds(k_dd_col_fused<false, 1>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<false, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    }
   }
   return hipGetLastError();
 }
@@ -655,21 +746,18 @@ hipError_t dd_convolve_columns(void* G, void* Gc, const void* tabs, const DDChan
   }
   const int64_t MyMx = (int64_t)g.My * g.Mx;
   // forward y: G [z][y < ny][kx] -> Gc [z][ky][kx]
-  const size_t ly = (size_t)g.My * sizeof(ddc);
-  e = allow_lds(k_dd_line_fwd<0>, ly);
-  if (e == hipSuccess) e = allow_lds(k_dd_line_inv, ly);
-  if (e != hipSuccess) return e;
-  const DDLines yf{g.My, g.logMy, g.Mx, g.ny, g.My, (int64_t)g.nz * g.Mx, (int64_t)g.ny * g.Mx, g.Mx, MyMx, g.Mx};
-  k_dd_line_fwd<0><<<(unsigned)yf.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf,
-                                                               0);
+  const int log_lb = dd_log_lb(g.My, g.Mx);
+  const DDLines yf{g.My, g.logMy, g.Mx, g.ny, g.My, (int64_t)g.nz * g.Mx, (int64_t)g.ny * g.Mx, g.Mx, MyMx, g.Mx,
+                   log_lb};
+  if ((e = launch_line_fwd<0>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf, 0, st)) != hipSuccess) return e;
   // z lines (ky, kx): forward, times each spectrum, inverse -> G [c][z < nz][ky][kx]
   const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz, ch};
   e = launch_fused(Gc, G, tabs, twz, F, MyMx, st);
   if (e != hipSuccess) return e;
   // inverse y: G [c z][ky][kx] -> Gc [c z][y < ny][kx]
   const DDLines yi{g.My, g.logMy, g.Mx, g.My, g.ny, (int64_t)ch.C * g.nz * g.Mx, MyMx, g.Mx, (int64_t)g.ny * g.Mx,
-                   g.Mx};
-  k_dd_line_inv<<<(unsigned)yi.n_lines, kThreads, ly, st>>>((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi);
+                   g.Mx, log_lb};
+  if ((e = launch_line_inv((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi, st)) != hipSuccess) return e;
   return hipGetLastError();
 }
 
