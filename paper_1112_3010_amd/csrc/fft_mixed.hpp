@@ -158,7 +158,7 @@ __device__ __forceinline__ void mixed_stage(Cx<T>* lds, int N, int L, int istrid
 // stages comes with its constant from the plan, so no integer division runs
 // on the device.
 template <typename T, int DIR, int ECAP, bool LINE_FAST>
-__device__ void mixed_fft(Cx<T>* lds, int N, const FastDiv& fL, int istride, int lstride, const MixedPlan& mp,
+__device__ __forceinline__ void mixed_fft(Cx<T>* lds, int N, const FastDiv& fL, int istride, int lstride, const MixedPlan& mp,
                           const Cx<T>* __restrict__ tw, int twstride, int tid, int nthr) {
   const int L = (int)fL.d;
   int Ns = 1;
