@@ -357,7 +357,7 @@ struct DDFused {
   int log_lb;   // a block takes 2^log_lb adjacent lines
 };
 
-template <bool MULTI, int LB>
+template <bool MULTI, int LB, int SPT = kSpecPerThread>
 __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
                                                            const dd* __restrict__ tabs, const ddc* __restrict__ tw,
                                                            DDFused F, int C) {
@@ -374,10 +374,10 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
   }
   __syncthreads();
   fft_dit<false, LB>(buf, M, F.logM, tw);
-  ddc sp[MULTI ? kSpecPerThread : 1];
+  ddc sp[MULTI ? SPT : 1];
   if (MULTI) {
 #pragma unroll
-    for (int k = 0; k < kSpecPerThread; ++k) {
+    for (int k = 0; k < SPT; ++k) {
       const int u = threadIdx.x + k * blockDim.x;
       if (u < ML) sp[k] = buf[((u & (lb - 1)) << F.logM) + (u >> F.log_lb)];
     }
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
     };
     if (MULTI) {
 #pragma unroll
-      for (int k = 0; k < kSpecPerThread; ++k) {
+      for (int k = 0; k < SPT; ++k) {
         const int u = threadIdx.x + k * blockDim.x;
         if (u < ML) product(u, sp[k]);
       }
@@ -711,9 +711,15 @@ static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, co
   hipError_t e;
   if (C > 1) {
     if ((F.M << F.log_lb) > kSpecPerThread * kThreads) return hipErrorInvalidValue;
-    if (F.log_lb == 2) {
+    if (F.log_lb == 2 && (F.M << 2) <= 4 * kThreads) {   // four spectrum bins per thread suffice
+      if ((e = allow_lds(k_dd_col_fused<true, 4, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<true, 4, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    } else if (F.log_lb == 2) {
       if ((e = allow_lds(k_dd_col_fused<true, 4>, lds)) != hipSuccess) return e;
       k_dd_col_fused<true, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+    } else if (F.M <= 4 * kThreads) {
+      if ((e = allow_lds(k_dd_col_fused<true, 1, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<true, 1, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
     } else {
       if ((e = allow_lds(k_dd_col_fused<true, 1>, lds)) != hipSuccess) return e;
       k_dd_col_fused<true, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
