@@ -45,11 +45,16 @@
  *         (dt_distance, dt_gradient, dt_hessian, dt_backward, dt_forward
  *         with S, grad, hess and/or curv; float64 output; other requests
  *         return DT_E_UNSUPPORTED); DT_AUTO considers it for such plans
- *         after float32 and float64.
+ *         after float32 and float64.  DT_FP64X4 carries it in quad-double
+ *         arithmetic (four float64 parts, about 212 bits; u taken as
+ *         2^-208), which doubles the band again (S_max about 130 tau),
+ *         for the same outputs, 2D plans and 3D plans of at most 128 nodes
+ *         per axis; DT_AUTO considers it last.  The paper's experiments
+ *         use 512-bit arithmetic; quad-double is the widest format here.
  * Validity. An FFT convolution in finite precision has an absolute error
  *         floor; nodes where phi falls below the threshold
  *           Theta = c_theta * u * log2(N_pad) * ||f||_1 * ||g||_2 / sqrt(N_pad)
- *         (u = 2^-24, 2^-53 or 2^-104, N_pad = prod M_d, ||f||_1 = sum of the padded
+ *         (u = 2^-24, 2^-53, 2^-104 or 2^-208, N_pad = prod M_d, ||f||_1 = sum of the padded
  *         kernel, ||g||_2 = sqrt(sum of squared multiplicities)) report
  *         S = S_max = -tau log Theta and zero derivatives.  The paper notes
  *         the effect (Sec. 3.2) but gives no rule; this threshold is the
@@ -92,7 +97,7 @@ typedef enum {
   DT_E_UNSUPPORTED = 6   /* valid request this build does not implement */
 } dt_status;
 
-typedef enum { DT_FP32_SCALED = 0, DT_FP64 = 1, DT_AUTO = 2, DT_FP64X2 = 3 } dt_precision;
+typedef enum { DT_FP32_SCALED = 0, DT_FP64 = 1, DT_AUTO = 2, DT_FP64X2 = 3, DT_FP64X4 = 4 } dt_precision;
 
 /* Kernel families a plan prepares (bit mask for dt_create_plan). */
 enum {
@@ -151,7 +156,7 @@ typedef struct {
   double spacing[3];
   double origin[3];
   double tau;
-  int precision;         /* DT_FP32_SCALED, DT_FP64 or DT_FP64X2 after DT_AUTO resolves */
+  int precision;         /* DT_FP32_SCALED, DT_FP64, DT_FP64X2 or DT_FP64X4 after DT_AUTO resolves */
   unsigned out_mask;
   double c_theta;
   double kernel_l1;      /* ||f||_1 over the padded grid (after set_workspace) */
@@ -178,7 +183,8 @@ typedef struct {
  * trunc_dist from an isolated source stays valid for k_hint distinct
  * sources, else float64 if that holds in float64, else (plans of S, grad S,
  * the Hessian and curvatures; 3D up to 256 nodes per axis) double-double if
- * it holds there, else DT_E_PRECISION.
+ * it holds there, else (3D up to 128 nodes per axis) quad-double if it holds
+ * there, else DT_E_PRECISION.
  * c_theta <= 0 selects the default safety factor 256. Host only. */
 dt_status dt_create_plan(dt_plan* out, int ndim, const int64_t* dims, const double* spacing,
                          const double* origin, double tau, int precision, unsigned out_mask,

@@ -25,7 +25,9 @@ import numpy as np
 
 # "fp64x2": double-double (pairs of float64, 106 significand bits); its
 # compound operations are accurate to a few units of 2^-106, taken as 2^-104.
-UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53, "fp64x2": 2.0 ** -104}
+# "fp64x4": quad-double (four float64 parts, 212 bits); its operations are
+# accurate to a few units of 2^-211, taken as 2^-208.
+UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53, "fp64x2": 2.0 ** -104, "fp64x4": 2.0 ** -208}
 
 #: Safety factor between the noise estimate and the validity threshold,
 #: calibrated against the error of the Table 1 convolution carried out in

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdt.so")
 
 DT_OK, DT_E_ARG, DT_E_RANGE, DT_E_PRECISION, DT_E_WORKSPACE, DT_E_HIP, DT_E_UNSUPPORTED = range(7)
-DT_FP32_SCALED, DT_FP64, DT_AUTO, DT_FP64X2 = 0, 1, 2, 3
+DT_FP32_SCALED, DT_FP64, DT_AUTO, DT_FP64X2, DT_FP64X4 = 0, 1, 2, 3, 4
 DT_OUT_S, DT_OUT_GRAD, DT_OUT_HESS, DT_OUT_SIGN, DT_OUT_BACKWARD, DT_OUT_CURV = 1, 2, 4, 8, 16, 32
 DT_SHAPE_POLYGON, DT_SHAPE_MESH = 1, 2
 DT_STATIC_WORKSPACE_BYTES = 64 << 20

@@ -136,16 +136,37 @@ __device__ inline void sincos_reduced(dd a, dd& s, dd& c) {
   c = pc;
 }
 
-struct ddc {
-  dd re, im;
+// Complex values over an extended real type R (dd here, qd in qd.hpp); the
+// operations resolve to R's add, sub and mul.
+template <class R> struct cplx {
+  R re, im;
 };
+using ddc = cplx<dd>;
 
-__device__ __forceinline__ ddc cadd(ddc a, ddc b) { return {add(a.re, b.re), add(a.im, b.im)}; }
-__device__ __forceinline__ ddc csub(ddc a, ddc b) { return {sub(a.re, b.re), sub(a.im, b.im)}; }
-__device__ __forceinline__ ddc cmul(ddc a, ddc b) {
+template <class R> __device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) {
+  return {add(a.re, b.re), add(a.im, b.im)};
+}
+template <class R> __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) {
+  return {sub(a.re, b.re), sub(a.im, b.im)};
+}
+template <class R> __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
   return {sub(mul(a.re, b.re), mul(a.im, b.im)), add(mul(a.re, b.im), mul(a.im, b.re))};
 }
-__device__ __forceinline__ ddc cmul_real(ddc a, dd b) { return {mul(a.re, b), mul(a.im, b)}; }
+template <class R> __device__ __forceinline__ cplx<R> cmul_real(cplx<R> a, R b) { return {mul(a.re, b), mul(a.im, b)}; }
+
+// What the pipeline needs of an extended real type beyond its arithmetic:
+// constants, the exact product of two float64 numbers, its leading float64
+// part and the part after it.
+template <class R> struct xp;
+template <> struct xp<dd> {
+  static constexpr double kUnitLog2 = -104;   // unit roundoff 2^-104
+  __device__ static dd zero() { return {0.0, 0.0}; }
+  __device__ static dd from(double a) { return {a, 0.0}; }
+  __device__ static dd prod(double a, double b) { return two_prod(a, b); }
+  __device__ static dd two_pi() { return {kTwoPiHi, kTwoPiLo}; }
+  __device__ static double lead(dd a) { return a.hi; }
+  __device__ static double next(dd a) { return a.lo; }
+};
 
 }  // namespace ddm
 }  // namespace dt

@@ -1,4 +1,5 @@
-// Host interface of the double-double pipeline (kernels in k_dd.hip).
+// Host interface of the extended-precision pipelines, double-double and
+// quad-double (kernels in k_dd.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -6,17 +7,20 @@
 
 namespace dt {
 
-// Geometry of a double-double plan; Mx, My, Mz are powers of two (a 2D
-// plan has nz = Mz = 1, logMz = 0).
+// Geometry of an extended-precision plan; Mx, My, Mz are powers of two (a
+// 2D plan has nz = Mz = 1, logMz = 0).  quad selects quad-double values
+// (four float64 parts) instead of double-double (two).
 struct DDGeom {
   int nx, ny, Mx, My, logMx, logMy;
   double hx, hy, ox, oy, tau;
   int ndim, nz, Mz, logMz;
   double hz, oz;
+  int quad;
 };
 
-// Bytes of one complex double-double value and one real one.
-constexpr size_t kDDComplexBytes = 32, kDDRealBytes = 16;
+// Bytes of one real extended value (16 or 32) and of one complex one.
+inline size_t dd_real_bytes(const DDGeom& g) { return g.quad ? 32 : 16; }
+inline size_t dd_complex_bytes(const DDGeom& g) { return 2 * dd_real_bytes(g); }
 
 // Channels of one convolution pass: channel c multiplies the image spectrum
 // by spectrum tab_of[c], imaginary (the odd gradient kernels: the product

@@ -28,20 +28,23 @@
 #include <cstdint>
 
 #include "dd.hpp"
+#include "qd.hpp"
 #include "dt_dd.hpp"
 #include "epilogue.hpp"
 
 namespace dt {
 namespace {
 
+using ddm::cplx;
 using ddm::dd;
-using ddm::ddc;
+using ddm::qd;
+using ddm::xp;
 
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ int brev(int x, int logM) { return (int)(__builtin_bitreverse32((uint32_t)x) >> (32 - logM)); }
 
-__device__ __forceinline__ ddc zero_c() { return {{0.0, 0.0}, {0.0, 0.0}}; }
+template <class R> __device__ __forceinline__ cplx<R> zero_c() { return {xp<R>::zero(), xp<R>::zero()}; }
 
 // Channels and spectra of a plan: 0 f, 1 .. ndim the gradient kernels (odd:
 // imaginary spectra), then the Hessian kernels in the order xx, xy, [xz,]
@@ -58,8 +61,8 @@ __device__ __forceinline__ void dd_hess_pair(int ndim, int h, int& i, int& j) {
   }
 }
 
-__device__ __forceinline__ ddc twiddle(const ddc* __restrict__ tw, int k, bool inv) {
-  ddc w = tw[k];
+template <class R> __device__ __forceinline__ cplx<R> twiddle(const cplx<R>* __restrict__ tw, int k, bool inv) {
+  cplx<R> w = tw[k];
   if (inv) w.im = ddm::neg(w.im);
   return w;
 }
@@ -71,24 +74,24 @@ __device__ __forceinline__ ddc twiddle(const ddc* __restrict__ tw, int k, bool i
 // LDS round trips and barriers; an odd last stage runs alone.  NL lines of
 // M elements stored back to back are transformed together (the same
 // arithmetic per line).
-template <bool INV, int NL = 1>
-__device__ __forceinline__ void fft_dit(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+template <class R, bool INV, int NL = 1>
+__device__ __forceinline__ void fft_dit(cplx<R>* buf, int M, int logM, const cplx<R>* __restrict__ tw) {
   int s = 1;
   for (; s + 1 <= logM; s += 2) {
     const int half = 1 << (s - 1);
     for (int qa = threadIdx.x; qa < NL * (M >> 2); qa += blockDim.x) {
-      ddc* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);   // line qa / (M / 4)
+      cplx<R>* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);   // line qa / (M / 4)
       const int q = NL == 1 ? qa : qa & ((M >> 2) - 1);
       const int j = q & (half - 1);
       const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
-      const ddc wa = twiddle(tw, j * (M >> s), INV);
-      const ddc wb = twiddle(tw, j * (M >> (s + 1)), INV);
-      const ddc wc = twiddle(tw, (j + half) * (M >> (s + 1)), INV);
-      const ddc a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
-      const ddc t1 = ddm::cmul(a1, wa), t3 = ddm::cmul(a3, wa);
-      const ddc x0 = ddm::cadd(a0, t1), x1 = ddm::csub(a0, t1);
-      const ddc x2 = ddm::cadd(a2, t3), x3 = ddm::csub(a2, t3);
-      const ddc u2 = ddm::cmul(x2, wb), u3 = ddm::cmul(x3, wc);
+      const cplx<R> wa = twiddle(tw, j * (M >> s), INV);
+      const cplx<R> wb = twiddle(tw, j * (M >> (s + 1)), INV);
+      const cplx<R> wc = twiddle(tw, (j + half) * (M >> (s + 1)), INV);
+      const cplx<R> a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
+      const cplx<R> t1 = ddm::cmul(a1, wa), t3 = ddm::cmul(a3, wa);
+      const cplx<R> x0 = ddm::cadd(a0, t1), x1 = ddm::csub(a0, t1);
+      const cplx<R> x2 = ddm::cadd(a2, t3), x3 = ddm::csub(a2, t3);
+      const cplx<R> u2 = ddm::cmul(x2, wb), u3 = ddm::cmul(x3, wc);
       b[i0] = ddm::cadd(x0, u2);
       b[i0 + 2 * half] = ddm::csub(x0, u2);
       b[i0 + half] = ddm::cadd(x1, u3);
@@ -99,12 +102,12 @@ __device__ __forceinline__ void fft_dit(ddc* buf, int M, int logM, const ddc* __
   if (s == logM) {
     const int half = 1 << (s - 1);
     for (int ba = threadIdx.x; ba < NL * (M >> 1); ba += blockDim.x) {
-      ddc* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
+      cplx<R>* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
       const int bb = NL == 1 ? ba : ba & ((M >> 1) - 1);
       const int j = bb & (half - 1);
       const int i0 = ((bb >> (s - 1)) << s) + j;
-      const ddc v = ddm::cmul(bu[i0 + half], twiddle(tw, j * (M >> s), INV));
-      const ddc u = bu[i0];
+      const cplx<R> v = ddm::cmul(bu[i0 + half], twiddle(tw, j * (M >> s), INV));
+      const cplx<R> u = bu[i0];
       bu[i0] = ddm::cadd(u, v);
       bu[i0 + half] = ddm::csub(u, v);
     }
@@ -115,17 +118,17 @@ __device__ __forceinline__ void fft_dit(ddc* buf, int M, int logM, const ddc* __
 // In-place radix-2 decimation in frequency over natural-order input;
 // bit-reversed order out.  An odd top stage runs alone, then stages t and
 // t - 1 are taken together as in fft_dit; NL lines as in fft_dit.
-template <bool INV, int NL = 1>
-__device__ __forceinline__ void fft_dif(ddc* buf, int M, int logM, const ddc* __restrict__ tw) {
+template <class R, bool INV, int NL = 1>
+__device__ __forceinline__ void fft_dif(cplx<R>* buf, int M, int logM, const cplx<R>* __restrict__ tw) {
   int t = logM;
   if (logM & 1) {
     const int half = 1 << (t - 1);
     for (int ba = threadIdx.x; ba < NL * (M >> 1); ba += blockDim.x) {
-      ddc* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
+      cplx<R>* bu = NL == 1 ? buf : buf + ((ba >> (logM - 1)) << logM);
       const int bb = NL == 1 ? ba : ba & ((M >> 1) - 1);
       const int j = bb & (half - 1);
       const int i0 = ((bb >> (t - 1)) << t) + j;
-      const ddc u = bu[i0], v = bu[i0 + half];
+      const cplx<R> u = bu[i0], v = bu[i0 + half];
       bu[i0] = ddm::cadd(u, v);
       bu[i0 + half] = ddm::cmul(ddm::csub(u, v), twiddle(tw, j * (M >> t), INV));
     }
@@ -136,16 +139,16 @@ __device__ __forceinline__ void fft_dif(ddc* buf, int M, int logM, const ddc* __
     const int s = t - 1;              // lower stage of the pair
     const int half = 1 << (s - 1);
     for (int qa = threadIdx.x; qa < NL * (M >> 2); qa += blockDim.x) {
-      ddc* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);
+      cplx<R>* b = NL == 1 ? buf : buf + ((qa >> (logM - 2)) << logM);
       const int q = NL == 1 ? qa : qa & ((M >> 2) - 1);
       const int j = q & (half - 1);
       const int i0 = ((q >> (s - 1)) << (s + 1)) + j;
-      const ddc wb = twiddle(tw, j * (M >> t), INV);
-      const ddc wc = twiddle(tw, (j + half) * (M >> t), INV);
-      const ddc wa = twiddle(tw, j * (M >> s), INV);
-      const ddc a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
-      const ddc y0 = ddm::cadd(a0, a2), y2 = ddm::cmul(ddm::csub(a0, a2), wb);
-      const ddc y1 = ddm::cadd(a1, a3), y3 = ddm::cmul(ddm::csub(a1, a3), wc);
+      const cplx<R> wb = twiddle(tw, j * (M >> t), INV);
+      const cplx<R> wc = twiddle(tw, (j + half) * (M >> t), INV);
+      const cplx<R> wa = twiddle(tw, j * (M >> s), INV);
+      const cplx<R> a0 = b[i0], a1 = b[i0 + half], a2 = b[i0 + 2 * half], a3 = b[i0 + 3 * half];
+      const cplx<R> y0 = ddm::cadd(a0, a2), y2 = ddm::cmul(ddm::csub(a0, a2), wb);
+      const cplx<R> y1 = ddm::cadd(a1, a3), y3 = ddm::cmul(ddm::csub(a1, a3), wc);
       b[i0] = ddm::cadd(y0, y1);
       b[i0 + half] = ddm::cmul(ddm::csub(y0, y1), wa);
       b[i0 + 2 * half] = ddm::cadd(y2, y3);
@@ -157,7 +160,8 @@ __device__ __forceinline__ void fft_dif(ddc* buf, int M, int logM, const ddc* __
 
 // exp(-2 pi i k / M) for 0 <= k < M/2, M a power of two >= 8: the angle is
 // reduced to an octant so that the series sees |a| <= pi/4.
-__global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
+template <class R>
+__global__ void k_dd_twiddles(cplx<R>* __restrict__ tw, int M) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M / 2) return;
   int j, oct;
@@ -174,10 +178,10 @@ __global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
     j = M / 2 - k;
     oct = 3;
   }
-  const dd a = ddm::mul_d({ddm::kTwoPiHi, ddm::kTwoPiLo}, (double)j / (double)M);
-  dd s, c;
+  const R a = ddm::mul_d(xp<R>::two_pi(), (double)j / (double)M);
+  R s, c;
   ddm::sincos_reduced(a, s, c);
-  dd cs, sn;
+  R cs, sn;
   switch (oct) {
     case 0: cs = c; sn = s; break;
     case 1: cs = s; sn = c; break;
@@ -192,35 +196,36 @@ __global__ void k_dd_twiddles(ddc* __restrict__ tw, int M) {
 // f = exp(-r / tau), kind 1 + a the gradient kernel (h_a d_a / r) f, 0 at
 // r = 0 (eq. SxSyconv).  The displacement h d is an exact double-double
 // product.
-__global__ void k_dd_tab_sample(ddc* __restrict__ G, DDGeom g, int kind) {
+template <class R>
+__global__ void k_dd_tab_sample(cplx<R>* __restrict__ G, DDGeom g, int kind) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)g.Mx * g.My * g.Mz) return;
   const int x = (int)(i % g.Mx), y = (int)((i / g.Mx) % g.My), z = (int)(i / ((int64_t)g.Mx * g.My));
-  ddc v = zero_c();
+  cplx<R> v = zero_c<R>();
   if (x != g.Mx / 2 && y != g.My / 2 && (g.ndim == 2 || z != g.Mz / 2)) {
     const int dx = x < g.Mx / 2 ? x : x - g.Mx;
     const int dy = y < g.My / 2 ? y : y - g.My;
     const int dz = z < g.Mz / 2 ? z : z - g.Mz;
-    const dd px = ddm::two_prod(g.hx, (double)dx), py = ddm::two_prod(g.hy, (double)dy);
-    const dd pz = g.ndim == 3 ? ddm::two_prod(g.hz, (double)dz) : dd{0.0, 0.0};
-    dd r2 = ddm::add(ddm::mul(px, px), ddm::mul(py, py));
+    const R px = xp<R>::prod(g.hx, (double)dx), py = xp<R>::prod(g.hy, (double)dy);
+    const R pz = g.ndim == 3 ? xp<R>::prod(g.hz, (double)dz) : xp<R>::zero();
+    R r2 = ddm::add(ddm::mul(px, px), ddm::mul(py, py));
     if (g.ndim == 3) r2 = ddm::add(r2, ddm::mul(pz, pz));
-    const dd r = ddm::sqrt(r2);
-    const dd f = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
-    const dd p[3] = {px, py, pz};
+    const R r = ddm::sqrt(r2);
+    const R f = ddm::exp_nonpos(ddm::neg(ddm::div_d(r, g.tau)));
+    const R p[3] = {px, py, pz};
     if (kind == 0) {
       v.re = f;
     } else if (kind == kDDKindRF) {
       v.re = ddm::mul(r, f);                     // r f (the adjoint's tau kernel), 0 at r = 0
-    } else if (r.hi > 0.0 && kind <= g.ndim) {
+    } else if (xp<R>::lead(r) > 0.0 && kind <= g.ndim) {
       v.re = ddm::mul(ddm::div(p[kind - 1], r), f);
-    } else if (r.hi > 0.0) {
+    } else if (xp<R>::lead(r) > 0.0) {
       // Hessian kernel (-n_i n_j / tau + (delta_ij - n_i n_j) / r) f
       int a, b;
       dd_hess_pair(g.ndim, kind - 1 - g.ndim, a, b);
-      const dd nn = ddm::mul(ddm::div(p[a], r), ddm::div(p[b], r));
-      const dd t1 = ddm::neg(ddm::div_d(nn, g.tau));
-      const dd t2 = ddm::div(a == b ? ddm::sub(dd{1.0, 0.0}, nn) : ddm::neg(nn), r);
+      const R nn = ddm::mul(ddm::div(p[a], r), ddm::div(p[b], r));
+      const R t1 = ddm::neg(ddm::div_d(nn, g.tau));
+      const R t2 = ddm::div(a == b ? ddm::sub(xp<R>::from(1.0), nn) : ddm::neg(nn), r);
       v.re = ddm::mul(ddm::add(t1, t2), f);
     }
   }
@@ -241,33 +246,33 @@ struct DDLines {
 // index is the fastest in memory, so element j of the LB lines is one
 // contiguous run) and reads them whole before writing, so in and out may be
 // the same array.
-template <int MODE, int LB>
-__global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const ddc* __restrict__ in, ddc* __restrict__ out,
-                                                          dd* __restrict__ tab, const ddc* __restrict__ tw,
+template <class R, int MODE, int LB>
+__global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                          R* __restrict__ tab, const cplx<R>* __restrict__ tw,
                                                           DDLines L, int scale_e) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   constexpr int lb = LB;
   const int64_t l = (int64_t)blockIdx.x << L.log_lb;
   const int64_t o = l / L.n_inner, i = l % L.n_inner;
-  const ddc* src = in + o * L.in_outer + i;
+  const cplx<R>* src = in + o * L.in_outer + i;
   for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
     const int t = u & (lb - 1), j = u >> L.log_lb;
-    buf[(t << L.logM) + brev(j, L.logM)] = j < L.n_in ? src[(int64_t)j * L.in_stride + t] : zero_c();
+    buf[(t << L.logM) + brev(j, L.logM)] = j < L.n_in ? src[(int64_t)j * L.in_stride + t] : zero_c<R>();
   }
   __syncthreads();
-  fft_dit<false, LB>(buf, L.M, L.logM, tw);
+  fft_dit<R, false, LB>(buf, L.M, L.logM, tw);
   if (MODE == 0) {
-    ddc* dst = out + o * L.out_outer + i;
+    cplx<R>* dst = out + o * L.out_outer + i;
     for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
       const int t = u & (lb - 1), k = u >> L.log_lb;
       dst[(int64_t)k * L.out_stride + t] = buf[(t << L.logM) + k];
     }
   } else {
-    dd* dst = tab + o * L.out_outer + i;
+    R* dst = tab + o * L.out_outer + i;
     for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
       const int t = u & (lb - 1), k = u >> L.log_lb;
-      const ddc v = buf[(t << L.logM) + k];
+      const cplx<R> v = buf[(t << L.logM) + k];
       dst[(int64_t)k * L.out_stride + t] = ddm::scale2(MODE == 2 ? v.im : v.re, scale_e);
     }
   }
@@ -275,22 +280,22 @@ __global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const ddc* __restrict_
 
 // Inverse (unnormalised) transform of each line from its natural-order
 // spectrum; the first n_out samples are kept.  LB adjacent lines per block.
-template <int LB>
-__global__ __launch_bounds__(kThreads) void k_dd_line_inv(const ddc* __restrict__ in, ddc* __restrict__ out,
-                                                          const ddc* __restrict__ tw, DDLines L) {
+template <class R, int LB>
+__global__ __launch_bounds__(kThreads) void k_dd_line_inv(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                          const cplx<R>* __restrict__ tw, DDLines L) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   constexpr int lb = LB;
   const int64_t l = (int64_t)blockIdx.x << L.log_lb;
   const int64_t o = l / L.n_inner, i = l % L.n_inner;
-  const ddc* src = in + o * L.in_outer + i;
+  const cplx<R>* src = in + o * L.in_outer + i;
   for (int u = threadIdx.x; u < (L.M << L.log_lb); u += blockDim.x) {
     const int t = u & (lb - 1), k = u >> L.log_lb;
     buf[(t << L.logM) + k] = src[(int64_t)k * L.in_stride + t];
   }
   __syncthreads();
-  fft_dif<true, LB>(buf, L.M, L.logM, tw);
-  ddc* dst = out + o * L.out_outer + i;
+  fft_dif<R, true, LB>(buf, L.M, L.logM, tw);
+  cplx<R>* dst = out + o * L.out_outer + i;
   for (int u = threadIdx.x; u < (L.n_out << L.log_lb); u += blockDim.x) {
     const int t = u & (lb - 1), y = u >> L.log_lb;
     dst[(int64_t)y * L.out_stride + t] = buf[(t << L.logM) + brev(y, L.logM)];
@@ -299,41 +304,41 @@ __global__ __launch_bounds__(kThreads) void k_dd_line_inv(const ddc* __restrict_
 
 // Forward transform of rows.  REAL_IN: row y of the ny x nx multiplicities,
 // zero-padded to Mx; else row y of G in place.
-template <bool REAL_IN>
-__global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restrict__ cnt, ddc* __restrict__ G,
-                                                         const ddc* __restrict__ tw, DDGeom g) {
+template <class R, bool REAL_IN>
+__global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restrict__ cnt, cplx<R>* __restrict__ G,
+                                                         const cplx<R>* __restrict__ tw, DDGeom g) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   const int y = blockIdx.x;
   const int M = g.Mx;
   for (int x = threadIdx.x; x < M; x += blockDim.x) {
-    ddc v;
+    cplx<R> v;
     if (REAL_IN) {
-      v = zero_c();
-      if (x < g.nx) v.re.hi = cnt[(int64_t)y * g.nx + x];
+      v = zero_c<R>();
+      if (x < g.nx) v.re = xp<R>::from(cnt[(int64_t)y * g.nx + x]);
     } else {
       v = G[(int64_t)y * M + x];
     }
     buf[brev(x, g.logMx)] = v;
   }
   __syncthreads();
-  fft_dit<false>(buf, M, g.logMx, tw);
+  fft_dit<R, false>(buf, M, g.logMx, tw);
   for (int x = threadIdx.x; x < M; x += blockDim.x) G[(int64_t)y * M + x] = buf[x];
 }
 
 // Table mode (plan time): column kx of the row-transformed samples in G,
 // forward transform, and the real (IMAG = false) or imaginary part of the
 // spectrum, scaled by 1/(Mx My), into tab.
-template <bool IMAG>
-__global__ __launch_bounds__(kThreads) void k_dd_col_table(const ddc* __restrict__ G, dd* __restrict__ tab,
-                                                           const ddc* __restrict__ tw, DDGeom g) {
+template <class R, bool IMAG>
+__global__ __launch_bounds__(kThreads) void k_dd_col_table(const cplx<R>* __restrict__ G, R* __restrict__ tab,
+                                                           const cplx<R>* __restrict__ tw, DDGeom g) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   const int kx = blockIdx.x;
   const int M = g.My;
   for (int y = threadIdx.x; y < M; y += blockDim.x) buf[brev(y, g.logMy)] = G[(int64_t)y * g.Mx + kx];
   __syncthreads();
-  fft_dit<false>(buf, M, g.logMy, tw);
+  fft_dit<R, false>(buf, M, g.logMy, tw);
   const int e = -(g.logMx + g.logMy);
   for (int ky = threadIdx.x; ky < M; ky += blockDim.x)
     tab[(int64_t)ky * g.Mx + kx] = ddm::scale2(IMAG ? buf[ky].im : buf[ky].re, e);
@@ -357,12 +362,12 @@ struct DDFused {
   int log_lb;   // a block takes 2^log_lb adjacent lines
 };
 
-template <bool MULTI, int LB, int SPT = kSpecPerThread>
-__global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict__ Gin, ddc* __restrict__ Gout,
-                                                           const dd* __restrict__ tabs, const ddc* __restrict__ tw,
+template <class R, bool MULTI, int LB, int SPT = kSpecPerThread>
+__global__ __launch_bounds__(kThreads) void k_dd_col_fused(const cplx<R>* __restrict__ Gin, cplx<R>* __restrict__ Gout,
+                                                           const R* __restrict__ tabs, const cplx<R>* __restrict__ tw,
                                                            DDFused F, int C) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   constexpr int lb = LB;
   const int64_t kx = (int64_t)blockIdx.x << F.log_lb;   // the block's first line
   const int M = F.M;
@@ -370,11 +375,11 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
   const int64_t npad = F.tab_chan, plane = F.plane;
   for (int u = threadIdx.x; u < ML; u += blockDim.x) {
     const int t = u & (lb - 1), y = u >> F.log_lb;
-    buf[(t << F.logM) + brev(y, F.logM)] = y < F.n ? Gin[(int64_t)y * F.stride + kx + t] : zero_c();
+    buf[(t << F.logM) + brev(y, F.logM)] = y < F.n ? Gin[(int64_t)y * F.stride + kx + t] : zero_c<R>();
   }
   __syncthreads();
-  fft_dit<false, LB>(buf, M, F.logM, tw);
-  ddc sp[MULTI ? SPT : 1];
+  fft_dit<R, false, LB>(buf, M, F.logM, tw);
+  cplx<R> sp[MULTI ? SPT : 1];
   if (MULTI) {
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
@@ -383,15 +388,15 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
     }
   }
   for (int c = 0; c < C; ++c) {
-    const dd* tab = tabs + F.ch.tab_of[c] * npad;
+    const R* tab = tabs + F.ch.tab_of[c] * npad;
     if (MULTI) __syncthreads();   // every thread has read its spectrum bins (or its last outputs)
     // (a.re + i a.im) t, or (a.re + i a.im) (i t) = -a.im t + i a.re t; each
     // thread rewrites only the slots whose spectrum it holds
     const bool imag = (F.ch.imag >> c) & 1u;
-    auto product = [&](int u, const ddc& a) {
+    auto product = [&](int u, const cplx<R>& a) {
       const int t = u & (lb - 1), ky = u >> F.log_lb;
-      const dd tv = tab[(int64_t)ky * F.stride + kx + t];
-      buf[(t << F.logM) + ky] = !imag ? ddm::cmul_real(a, tv) : ddc{ddm::neg(ddm::mul(a.im, tv)), ddm::mul(a.re, tv)};
+      const R tv = tab[(int64_t)ky * F.stride + kx + t];
+      buf[(t << F.logM) + ky] = !imag ? ddm::cmul_real(a, tv) : cplx<R>{ddm::neg(ddm::mul(a.im, tv)), ddm::mul(a.re, tv)};
     };
     if (MULTI) {
 #pragma unroll
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
         product(u, buf[((u & (lb - 1)) << F.logM) + (u >> F.log_lb)]);
     }
     __syncthreads();
-    fft_dif<true, LB>(buf, M, F.logM, tw);
+    fft_dif<R, true, LB>(buf, M, F.logM, tw);
     for (int u = threadIdx.x; u < (F.n << F.log_lb); u += blockDim.x) {
       const int t = u & (lb - 1), y = u >> F.log_lb;
       Gout[c * plane + (int64_t)y * F.stride + kx + t] = buf[(t << F.logM) + brev(y, F.logM)];
@@ -424,12 +429,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const ddc* __restrict
 // transformed.
 constexpr int kMaxPerThread = 4;
 
-__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
                                                              double* __restrict__ S, double* __restrict__ grad,
                                                              double* __restrict__ hess, double* __restrict__ curv,
                                                              const double* __restrict__ scal, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   const int y = blockIdx.x;
   const int M = g.Mx;
   const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
@@ -438,30 +444,31 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
   for (int c = 0; c < C; ++c) {
     for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
     __syncthreads();
-    fft_dif<true>(buf, M, g.logMx, tw);
+    fft_dif<R, true>(buf, M, g.logMx, tw);
 #pragma unroll
     for (int k = 0; k < kMaxPerThread; ++k) {
       const int x = threadIdx.x + k * blockDim.x;
       if (x >= g.nx) break;
-      const dd v = buf[brev(x, g.logMx)].re;
+      const R v = buf[brev(x, g.logMx)].re;
+      const double vh = xp<R>::lead(v), vl = xp<R>::next(v);
       if (c == 0) {
-        phi[k] = v.hi;
+        phi[k] = vh;
         if (S) {
           // log(hi + lo) = log(hi) + lo / hi to float64 accuracy
-          const bool ok0 = v.hi > 0.0 && v.hi >= theta;
-          S[(int64_t)y * g.nx + x] = ok0 ? -g.tau * (log(v.hi) + v.lo / v.hi) : smax;
+          const bool ok0 = vh > 0.0 && vh >= theta;
+          S[(int64_t)y * g.nx + x] = ok0 ? -g.tau * (log(vh) + vl / vh) : smax;
         }
       } else {
         const bool ok = phi[k] > 0.0 && phi[k] >= theta;
         if (c <= g.ndim) {
-          const double gv = ok ? v.hi / phi[k] : 0.0;
+          const double gv = ok ? vh / phi[k] : 0.0;
           gs[k][c - 1] = gv;
           if (grad) grad[(c - 1) * nodes + (int64_t)y * g.nx + x] = gv;
         } else {
           const int hh = c - 1 - g.ndim;
           int a, b;
           dd_hess_pair(g.ndim, hh, a, b);
-          const double hv = ok ? v.hi / phi[k] + gs[k][a] * gs[k][b] / g.tau : 0.0;
+          const double hv = ok ? vh / phi[k] + gs[k][a] * gs[k][b] / g.tau : 0.0;
           hs[k][hh] = hv;
           if (hess) hess[hh * nodes + (int64_t)y * g.nx + x] = hv;
         }
@@ -485,18 +492,19 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const ddc* __restri
 // Inverse transforms of row y of C channels into plain fields (the float64
 // leading part of the real part), out[c][row][x] for x < nx (the adjoint's
 // convolutions w * u_a and w * r f).
-__global__ __launch_bounds__(kThreads) void k_dd_row_inv_plain(const ddc* __restrict__ Gc, const ddc* __restrict__ tw,
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_dd_row_inv_plain(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
                                                                double* __restrict__ out, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
-  ddc* buf = (ddc*)smem;
+  cplx<R>* buf = (cplx<R>*)smem;
   const int y = blockIdx.x;
   const int M = g.Mx;
   const int64_t plane = (int64_t)g.ny * M, nodes = (int64_t)g.nx * g.ny;
   for (int c = 0; c < C; ++c) {
     for (int x = threadIdx.x; x < M; x += blockDim.x) buf[x] = Gc[c * plane + (int64_t)y * M + x];
     __syncthreads();
-    fft_dif<true>(buf, M, g.logMx, tw);
-    for (int x = threadIdx.x; x < g.nx; x += blockDim.x) out[c * nodes + (int64_t)y * g.nx + x] = buf[brev(x, g.logMx)].re.hi;
+    fft_dif<R, true>(buf, M, g.logMx, tw);
+    for (int x = threadIdx.x; x < g.nx; x += blockDim.x) out[c * nodes + (int64_t)y * g.nx + x] = xp<R>::lead(buf[brev(x, g.logMx)].re);
     __syncthreads();
   }
 }
@@ -593,88 +601,102 @@ hipError_t allow_lds(F kern, size_t lds) {
 
 // Adjacent lines per block of the strided line passes, as a power of two:
 // four (a 128-byte run of double-double complex values per row) where the
-// block's lines stay within 64 KiB of LDS, else one.
-static int dd_log_lb(int M, int64_t n_inner) { return (M <= 512 && n_inner % 4 == 0) ? 2 : 0; }
+// block's four lines stay within 64 KiB of LDS, else one.
+template <class R> static int dd_log_lb(int M, int64_t n_inner) {
+  return ((size_t)M * 4 * sizeof(cplx<R>) <= 65536 && n_inner % 4 == 0) ? 2 : 0;
+}
 
 // Launches of the strided line passes with L.log_lb adjacent lines per block.
-template <int MODE>
-static hipError_t launch_line_fwd(const ddc* in, ddc* out, dd* tab, const ddc* tw, const DDLines& L, int scale_e,
-                                  hipStream_t st) {
-  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(ddc);
+template <class R, int MODE>
+static hipError_t launch_line_fwd(const cplx<R>* in, cplx<R>* out, R* tab, const cplx<R>* tw, const DDLines& L,
+                                  int scale_e, hipStream_t st) {
+  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(cplx<R>);
   const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
   hipError_t e;
   if (L.log_lb == 2) {
-    if ((e = allow_lds(k_dd_line_fwd<MODE, 4>, lds)) != hipSuccess) return e;
-    k_dd_line_fwd<MODE, 4><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+    if ((e = allow_lds(k_dd_line_fwd<R, MODE, 4>, lds)) != hipSuccess) return e;
+    k_dd_line_fwd<R, MODE, 4><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
   } else {
-    if ((e = allow_lds(k_dd_line_fwd<MODE, 1>, lds)) != hipSuccess) return e;
-    k_dd_line_fwd<MODE, 1><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+    if ((e = allow_lds(k_dd_line_fwd<R, MODE, 1>, lds)) != hipSuccess) return e;
+    k_dd_line_fwd<R, MODE, 1><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
   }
   return hipSuccess;
 }
-static hipError_t launch_line_inv(const ddc* in, ddc* out, const ddc* tw, const DDLines& L, hipStream_t st) {
-  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(ddc);
+template <class R>
+static hipError_t launch_line_inv(const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const DDLines& L,
+                                  hipStream_t st) {
+  const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(cplx<R>);
   const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
   hipError_t e;
   if (L.log_lb == 2) {
-    if ((e = allow_lds(k_dd_line_inv<4>, lds)) != hipSuccess) return e;
-    k_dd_line_inv<4><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+    if ((e = allow_lds(k_dd_line_inv<R, 4>, lds)) != hipSuccess) return e;
+    k_dd_line_inv<R, 4><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
   } else {
-    if ((e = allow_lds(k_dd_line_inv<1>, lds)) != hipSuccess) return e;
-    k_dd_line_inv<1><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+    if ((e = allow_lds(k_dd_line_inv<R, 1>, lds)) != hipSuccess) return e;
+    k_dd_line_inv<R, 1><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
   }
   return hipSuccess;
 }
 
 // 3D tables: rows of the Mz x My sample rows in place, then the y lines in
 // place, then the z lines into the real or imaginary spectrum.
-hipError_t dd_build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
-                              const DDGeom& g, hipStream_t st) {
-  k_dd_twiddles<<<(g.Mz / 2 + 255) / 256, 256, 0, st>>>((ddc*)twz, g.Mz);
+template <class R>
+static hipError_t build_tables_3d(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
+                                  const DDGeom& g, hipStream_t st) {
+  using C = cplx<R>;
+  k_dd_twiddles<R><<<(g.Mz / 2 + 255) / 256, 256, 0, st>>>((C*)twz, g.Mz);
   const int64_t plane = (int64_t)g.Mx * g.My, total = plane * g.Mz;
-  const size_t lx = (size_t)g.Mx * sizeof(ddc);
-  hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
+  const size_t lx = (size_t)g.Mx * sizeof(C);
+  hipError_t e = allow_lds(k_dd_row_fwd<R, false>, lx);
   if (e != hipSuccess) return e;
   DDGeom rows = g;
   rows.ny = g.My * g.Mz;   // every sample row
-  DDLines ly_{g.My, g.logMy, g.Mx, g.My, g.My, (int64_t)g.Mz * g.Mx, plane, g.Mx, plane, g.Mx, dd_log_lb(g.My, g.Mx)};
-  DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane, dd_log_lb(g.Mz, plane)};
+  DDLines ly_{g.My, g.logMy, g.Mx, g.My, g.My, (int64_t)g.Mz * g.Mx, plane, g.Mx, plane, g.Mx, dd_log_lb<R>(g.My, g.Mx)};
+  DDLines lz_{g.Mz, g.logMz, (int)plane, g.Mz, g.Mz, plane, 0, plane, 0, plane, dd_log_lb<R>(g.Mz, plane)};
   for (int t = 0; t < n_tabs; ++t) {
-    dd* tab = (dd*)tabs + t * total;
-    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t == rf_tab ? kDDKindRF : t);
-    k_dd_row_fwd<false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, rows);
-    if ((e = launch_line_fwd<0>((const ddc*)G, (ddc*)G, nullptr, (const ddc*)twy, ly_, 0, st)) != hipSuccess) return e;
+    R* tab = (R*)tabs + t * total;
+    k_dd_tab_sample<R><<<(unsigned)((total + 255) / 256), 256, 0, st>>>((C*)G, g, t == rf_tab ? kDDKindRF : t);
+    k_dd_row_fwd<R, false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (C*)G, (const C*)twx, rows);
+    if ((e = launch_line_fwd<R, 0>((const C*)G, (C*)G, nullptr, (const C*)twy, ly_, 0, st)) != hipSuccess) return e;
     const int e_scale = -(g.logMx + g.logMy + g.logMz);
     if (t == rf_tab || !dd_imag_channel(t, g.ndim))
-      e = launch_line_fwd<1>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_, e_scale, st);
+      e = launch_line_fwd<R, 1>((const C*)G, nullptr, tab, (const C*)twz, lz_, e_scale, st);
     else
-      e = launch_line_fwd<2>((const ddc*)G, nullptr, tab, (const ddc*)twz, lz_, e_scale, st);
+      e = launch_line_fwd<R, 2>((const C*)G, nullptr, tab, (const C*)twz, lz_, e_scale, st);
     if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+template <class R>
+static hipError_t build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
+                               const DDGeom& g, hipStream_t st) {
+  using C = cplx<R>;
+  k_dd_twiddles<R><<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((C*)twx, g.Mx);
+  k_dd_twiddles<R><<<(g.My / 2 + 255) / 256, 256, 0, st>>>((C*)twy, g.My);
+  if (g.ndim == 3) return build_tables_3d<R>(twx, twy, twz, tabs, n_tabs, rf_tab, G, g, st);
+  const int64_t total = (int64_t)g.Mx * g.My;
+  const size_t lx = (size_t)g.Mx * sizeof(C), ly = (size_t)g.My * sizeof(C);
+  hipError_t e = allow_lds(k_dd_row_fwd<R, false>, lx);
+  if (e == hipSuccess) e = allow_lds(k_dd_col_table<R, false>, ly);
+  if (e == hipSuccess) e = allow_lds(k_dd_col_table<R, true>, ly);
+  if (e != hipSuccess) return e;
+  for (int t = 0; t < n_tabs; ++t) {
+    R* tab = (R*)tabs + t * total;
+    k_dd_tab_sample<R><<<(unsigned)((total + 255) / 256), 256, 0, st>>>((C*)G, g, t == rf_tab ? kDDKindRF : t);
+    k_dd_row_fwd<R, false><<<g.My, kThreads, lx, st>>>(nullptr, (C*)G, (const C*)twx, g);
+    if (t == rf_tab || !dd_imag_channel(t, g.ndim))
+      k_dd_col_table<R, false><<<g.Mx, kThreads, ly, st>>>((const C*)G, tab, (const C*)twy, g);
+    else
+      k_dd_col_table<R, true><<<g.Mx, kThreads, ly, st>>>((const C*)G, tab, (const C*)twy, g);
   }
   return hipGetLastError();
 }
 
 hipError_t dd_build_tables(void* twx, void* twy, void* twz, void* tabs, int n_tabs, int rf_tab, void* G,
                            const DDGeom& g, hipStream_t st) {
-  k_dd_twiddles<<<(g.Mx / 2 + 255) / 256, 256, 0, st>>>((ddc*)twx, g.Mx);
-  k_dd_twiddles<<<(g.My / 2 + 255) / 256, 256, 0, st>>>((ddc*)twy, g.My);
-  if (g.ndim == 3) return dd_build_tables_3d(twx, twy, twz, tabs, n_tabs, rf_tab, G, g, st);
-  const int64_t total = (int64_t)g.Mx * g.My;
-  const size_t lx = (size_t)g.Mx * sizeof(ddc), ly = (size_t)g.My * sizeof(ddc);
-  hipError_t e = allow_lds(k_dd_row_fwd<false>, lx);
-  if (e == hipSuccess) e = allow_lds(k_dd_col_table<false>, ly);
-  if (e == hipSuccess) e = allow_lds(k_dd_col_table<true>, ly);
-  if (e != hipSuccess) return e;
-  for (int t = 0; t < n_tabs; ++t) {
-    dd* tab = (dd*)tabs + t * total;
-    k_dd_tab_sample<<<(unsigned)((total + 255) / 256), 256, 0, st>>>((ddc*)G, g, t == rf_tab ? kDDKindRF : t);
-    k_dd_row_fwd<false><<<g.My, kThreads, lx, st>>>(nullptr, (ddc*)G, (const ddc*)twx, g);
-    if (t == rf_tab || !dd_imag_channel(t, g.ndim))
-      k_dd_col_table<false><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
-    else
-      k_dd_col_table<true><<<g.Mx, kThreads, ly, st>>>((const ddc*)G, tab, (const ddc*)twy, g);
-  }
-  return hipGetLastError();
+  return g.quad ? build_tables<qd>(twx, twy, twz, tabs, n_tabs, rf_tab, G, g, st)
+                : build_tables<dd>(twx, twy, twz, tabs, n_tabs, rf_tab, G, g, st);
 }
 
 hipError_t dd_launch_splat(const float* Y, int64_t K, double* cnt, double* msq, uint32_t* err, const DDGeom& g,
@@ -689,48 +711,55 @@ hipError_t dd_launch_finalize(double* msq, double* scal, const DDGeom& g, double
   return hipGetLastError();
 }
 
-hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
-  const size_t lds = (size_t)g.Mx * sizeof(ddc);
-  const hipError_t e = allow_lds(k_dd_row_fwd<true>, lds);
+template <class R>
+static hipError_t row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
+  using C = cplx<R>;
+  const size_t lds = (size_t)g.Mx * sizeof(C);
+  const hipError_t e = allow_lds(k_dd_row_fwd<R, true>, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_fwd<true><<<g.ny, kThreads, lds, st>>>(cnt, (ddc*)G, (const ddc*)twx, g);
+  k_dd_row_fwd<R, true><<<g.ny, kThreads, lds, st>>>(cnt, (C*)G, (const C*)twx, g);
   return hipGetLastError();
 }
+hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
+  return g.quad ? row_fwd<qd>(cnt, G, twx, g, st) : row_fwd<dd>(cnt, G, twx, g, st);
+}
 
+template <class R>
 static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, const void* tw, const DDFused& F0,
                                int64_t lines, hipStream_t st) {
+  using C = cplx<R>;
   DDFused F = F0;
-  F.log_lb = dd_log_lb(F.M, lines);
-  const size_t lds = ((size_t)F.M << F.log_lb) * sizeof(ddc);
+  F.log_lb = dd_log_lb<R>(F.M, lines);
+  const size_t lds = ((size_t)F.M << F.log_lb) * sizeof(C);
   const unsigned blocks = (unsigned)(lines >> F.log_lb);
-  const int C = F.ch.C;
-  const ddc* gi = (const ddc*)Gin;
-  ddc* go = (ddc*)Gout;
-  const dd* tb = (const dd*)tabs;
-  const ddc* w = (const ddc*)tw;
+  const int nc = F.ch.C;
+  const C* gi = (const C*)Gin;
+  C* go = (C*)Gout;
+  const R* tb = (const R*)tabs;
+  const C* w = (const C*)tw;
   hipError_t e;
-  if (C > 1) {
+  if (nc > 1) {
     if ((F.M << F.log_lb) > kSpecPerThread * kThreads) return hipErrorInvalidValue;
     if (F.log_lb == 2 && (F.M << 2) <= 4 * kThreads) {   // four spectrum bins per thread suffice
-      if ((e = allow_lds(k_dd_col_fused<true, 4, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<true, 4, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, true, 4, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, true, 4, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     } else if (F.log_lb == 2) {
-      if ((e = allow_lds(k_dd_col_fused<true, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<true, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, true, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, true, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     } else if (F.M <= 4 * kThreads) {
-      if ((e = allow_lds(k_dd_col_fused<true, 1, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<true, 1, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, true, 1, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, true, 1, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     } else {
-      if ((e = allow_lds(k_dd_col_fused<true, 1>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<true, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, true, 1>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, true, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     }
   } else {
     if (F.log_lb == 2) {
-      if ((e = allow_lds(k_dd_col_fused<false, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<false, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, false, 4>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, false, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     } else {
-      if ((e = allow_lds(k_dd_col_fused<false, 1>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<false, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, C);
+      if ((e = allow_lds(k_dd_col_fused<R, false, 1>, lds)) != hipSuccess) return e;
+      k_dd_col_fused<R, false, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
     }
   }
   return hipGetLastError();
@@ -742,53 +771,73 @@ hipError_t dd_convolve_rows(const double* img, void* G, const void* twx, const D
   return dd_launch_row_fwd(img, G, twx, rows, st);
 }
 
-hipError_t dd_convolve_columns(void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twy,
-                               const void* twz, const DDGeom& g, hipStream_t st) {
-  if (ch.C < 1 || ch.C > kDDMaxChannels) return hipErrorInvalidValue;
+template <class R>
+static hipError_t convolve_columns(void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twy,
+                                   const void* twz, const DDGeom& g, hipStream_t st) {
+  using C = cplx<R>;
   hipError_t e = hipSuccess;
   if (g.ndim == 2) {
     const DDFused F{g.My, g.logMy, g.ny, g.Mx, (int64_t)g.ny * g.Mx, (int64_t)g.Mx * g.My, ch};
-    return launch_fused(G, Gc, tabs, twy, F, g.Mx, st);
+    return launch_fused<R>(G, Gc, tabs, twy, F, g.Mx, st);
   }
   const int64_t MyMx = (int64_t)g.My * g.Mx;
   // forward y: G [z][y < ny][kx] -> Gc [z][ky][kx]
-  const int log_lb = dd_log_lb(g.My, g.Mx);
+  const int log_lb = dd_log_lb<R>(g.My, g.Mx);
   const DDLines yf{g.My, g.logMy, g.Mx, g.ny, g.My, (int64_t)g.nz * g.Mx, (int64_t)g.ny * g.Mx, g.Mx, MyMx, g.Mx,
                    log_lb};
-  if ((e = launch_line_fwd<0>((const ddc*)G, (ddc*)Gc, nullptr, (const ddc*)twy, yf, 0, st)) != hipSuccess) return e;
+  if ((e = launch_line_fwd<R, 0>((const C*)G, (C*)Gc, nullptr, (const C*)twy, yf, 0, st)) != hipSuccess) return e;
   // z lines (ky, kx): forward, times each spectrum, inverse -> G [c][z < nz][ky][kx]
   const DDFused F{g.Mz, g.logMz, g.nz, MyMx, (int64_t)g.nz * MyMx, MyMx * g.Mz, ch};
-  e = launch_fused(Gc, G, tabs, twz, F, MyMx, st);
+  e = launch_fused<R>(Gc, G, tabs, twz, F, MyMx, st);
   if (e != hipSuccess) return e;
   // inverse y: G [c z][ky][kx] -> Gc [c z][y < ny][kx]
   const DDLines yi{g.My, g.logMy, g.Mx, g.My, g.ny, (int64_t)ch.C * g.nz * g.Mx, MyMx, g.Mx, (int64_t)g.ny * g.Mx,
                    g.Mx, log_lb};
-  if ((e = launch_line_inv((const ddc*)G, (ddc*)Gc, (const ddc*)twy, yi, st)) != hipSuccess) return e;
+  if ((e = launch_line_inv<R>((const C*)G, (C*)Gc, (const C*)twy, yi, st)) != hipSuccess) return e;
   return hipGetLastError();
 }
+hipError_t dd_convolve_columns(void* G, void* Gc, const void* tabs, const DDChannels& ch, const void* twy,
+                               const void* twz, const DDGeom& g, hipStream_t st) {
+  if (ch.C < 1 || ch.C > kDDMaxChannels) return hipErrorInvalidValue;
+  return g.quad ? convolve_columns<qd>(G, Gc, tabs, ch, twy, twz, g, st)
+                : convolve_columns<dd>(G, Gc, tabs, ch, twy, twz, g, st);
+}
 
+template <class R>
+static hipError_t row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
+                              double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
+  using Cx = cplx<R>;
+  DDGeom rows = g;
+  rows.ny = g.ny * g.nz;
+  const size_t lds = (size_t)g.Mx * sizeof(Cx);
+  const hipError_t e = allow_lds(k_dd_row_inv_epi<R>, lds);
+  if (e != hipSuccess) return e;
+  k_dd_row_inv_epi<R><<<(unsigned)rows.ny, kThreads, lds, st>>>((const Cx*)Gc, (const Cx*)twx, S, grad, hess, curv,
+                                                                 scal, rows, C);
+  return hipGetLastError();
+}
 hipError_t dd_launch_row_inv_epi(const void* Gc, int C, const void* twx, double* S, double* grad, double* hess,
                                  double* curv, const double* scal, const DDGeom& g, hipStream_t st) {
   if (g.nx > kMaxPerThread * kThreads) return hipErrorInvalidValue;
-  DDGeom rows = g;
-  rows.ny = g.ny * g.nz;
-  const size_t lds = (size_t)g.Mx * sizeof(ddc);
-  const hipError_t e = allow_lds(k_dd_row_inv_epi, lds);
-  if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<<<(unsigned)rows.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, S, grad, hess, curv,
-                                                              scal, rows, C);
-  return hipGetLastError();
+  return g.quad ? row_inv_epi<qd>(Gc, C, twx, S, grad, hess, curv, scal, g, st)
+                : row_inv_epi<dd>(Gc, C, twx, S, grad, hess, curv, scal, g, st);
 }
 
-hipError_t dd_launch_row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
-                                   hipStream_t st) {
+template <class R>
+static hipError_t row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
+                                hipStream_t st) {
+  using Cx = cplx<R>;
   DDGeom rows = g;
   rows.ny = g.ny * g.nz;
-  const size_t lds = (size_t)g.Mx * sizeof(ddc);
-  const hipError_t e = allow_lds(k_dd_row_inv_plain, lds);
+  const size_t lds = (size_t)g.Mx * sizeof(Cx);
+  const hipError_t e = allow_lds(k_dd_row_inv_plain<R>, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_plain<<<(unsigned)rows.ny, kThreads, lds, st>>>((const ddc*)Gc, (const ddc*)twx, out, rows, C);
+  k_dd_row_inv_plain<R><<<(unsigned)rows.ny, kThreads, lds, st>>>((const Cx*)Gc, (const Cx*)twx, out, rows, C);
   return hipGetLastError();
+}
+hipError_t dd_launch_row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
+                                   hipStream_t st) {
+  return g.quad ? row_inv_plain<qd>(Gc, C, twx, out, g, st) : row_inv_plain<dd>(Gc, C, twx, out, g, st);
 }
 
 hipError_t dd_launch_gather(const float* Y, int64_t K, const double* fields, const double* scal, float* dY,

@@ -46,6 +46,7 @@ const char* precision_name(int precision) {
     case DT_FP32_SCALED: return "fp32-scaled";
     case DT_FP64: return "fp64";
     case DT_FP64X2: return "fp64x2";
+    case DT_FP64X4: return "fp64x4";
     default: return "auto";
   }
 }

@@ -107,8 +107,10 @@ struct dt_plan_s {
     static_dev = -1;
     static_token = 0;
   }
-  // double-double plans (S, grad S, Hessian, curvatures) use their own workspace regions
+  // double-double and quad-double plans (S, grad S, Hessian, curvatures,
+  // adjoint) use their own workspace regions; quad marks quad-double
   bool dd = false;
+  bool quad = false;
   DDGeom ddg{};
   int dd_tabs = 1;       // 1: f; 1 + ndim: and the gradient kernels; + ndim (ndim + 1) / 2: and the Hessian's
   int dd_rf_tab = -1;    // table of r f (adjoint plans), else -1
@@ -140,7 +142,8 @@ struct dt_plan_s {
   int64_t nodes() const { return n[0] * n[1] * n[2]; }
   int64_t rows() const { return n[1] * n[2]; }
   double npad() const { return (double)M[0] * (double)M[1] * (double)M[2]; }
-  double unit() const { return dd ? std::ldexp(1.0, -104) : fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24); }
+  double unit() const { return std::ldexp(1.0, unit_log2()); }
+  int unit_log2() const { return dd ? (quad ? -208 : -104) : fp64 ? -53 : -24; }
   double* scal() const { return (double*)(ws + off_scal); }
   double* msq() const { return scal() + 16; }   // splat accumulator of sum m^2 (cleared by the finalize)
   uint32_t* err() const { return (uint32_t*)(ws + off_err); }
@@ -266,6 +269,18 @@ int log2_exact(int64_t m) {
 // as the other precisions, so the stats calls are shared), twiddles, the
 // spectra, the multiplicities, the complex work grid and the column-pass
 // outputs.
+// The outputs and sizes the extended-precision pipelines serve: every output
+// but the sign; 3D up to 256 nodes per axis in double-double (512^3 padded:
+// about 22 GB of workspace) and 128 in quad-double.
+bool xp_supported(int precision, int ndim, const int64_t* dims, unsigned out_mask) {
+  if (out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV | DT_OUT_BACKWARD)) return false;
+  const int64_t cap = precision == DT_FP64X4 ? 128 : 256;
+  if (ndim == 3)
+    for (int a = 0; a < 3; ++a)
+      if (dims[a] > cap) return false;
+  return true;
+}
+
 void setup_dd(dt_plan p) {
   p->dd = true;
   const bool d3 = p->ndim == 3;
@@ -295,7 +310,9 @@ void setup_dd(dt_plan p) {
   g.oy = p->o[1];
   g.oz = d3 ? p->o[2] : 0.0;
   g.tau = p->tau;
+  g.quad = p->quad ? 1 : 0;
   const size_t npad = (size_t)g.Mx * g.My * g.Mz, C = (size_t)p->dd_tabs;
+  const size_t cb = dd_complex_bytes(g), rb = dd_real_bytes(g);
   // 2D: G holds the row spectra, Gc the column-pass outputs.  3D: G holds
   // the table samples, the row spectra and the z-pass outputs; Gc the y-pass
   // outputs in both directions.
@@ -307,13 +324,13 @@ void setup_dd(dt_plan p) {
   p->off_partA = off; off = align_up(off + kPartials * sizeof(double));
   p->off_partB = off; off = align_up(off + kPartials * sizeof(double));
   p->off_R1 = off;  // end of the region cleared at attach
-  p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * kDDComplexBytes);
-  p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * kDDComplexBytes);
-  p->off_dd_twz = off; off = align_up(off + (size_t)std::max(g.Mz / 2, 1) * kDDComplexBytes);
-  p->off_dd_tab = off; off = align_up(off + C * npad * kDDRealBytes);
+  p->off_dd_twx = off; off = align_up(off + (size_t)g.Mx / 2 * cb);
+  p->off_dd_twy = off; off = align_up(off + (size_t)g.My / 2 * cb);
+  p->off_dd_twz = off; off = align_up(off + (size_t)std::max(g.Mz / 2, 1) * cb);
+  p->off_dd_tab = off; off = align_up(off + C * npad * rb);
   p->off_dd_cnt = off; off = align_up(off + (size_t)g.nx * g.ny * g.nz * sizeof(double));
-  p->off_dd_G = off; off = align_up(off + Gsz * kDDComplexBytes);
-  p->off_dd_Gc = off; off = align_up(off + Gcsz * kDDComplexBytes);
+  p->off_dd_G = off; off = align_up(off + Gsz * cb);
+  p->off_dd_Gc = off; off = align_up(off + Gcsz * cb);
   p->ws_bytes = off;
 }
 
@@ -361,7 +378,7 @@ void log_created(dt_plan p) {
   logf("plan %p created: %dD grid %s, h = %s, origin = %s, tau = %.6g (%.3g h_x), precision %s (u = 2^-%d), "
        "outputs %s, c_theta = %g",
        (void*)p, D, axes_i(p->n, D).c_str(), axes_d(p->h, D).c_str(), axes_d(p->o, D).c_str(), p->tau,
-       p->tau / p->h[0], precision_name(p->prec), p->dd ? 104 : p->fp64 ? 53 : 24, mask_names(p->mask, mb, sizeof(mb)),
+       p->tau / p->h[0], precision_name(p->prec), -p->unit_log2(), mask_names(p->mask, mb, sizeof(mb)),
        p->c_theta);
   if (p->k_max > 0) {
     int64_t cut[3] = {p->cut[0], p->cut[1], p->cut[2]};
@@ -422,7 +439,8 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
   if (ndim != 2 && ndim != 3) return DT_E_ARG;
   if (!dims || !spacing || !origin) return DT_E_ARG;
   if (!finite_pos(tau)) return DT_E_ARG;
-  if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO && precision != DT_FP64X2)
+  if (precision != DT_FP32_SCALED && precision != DT_FP64 && precision != DT_AUTO && precision != DT_FP64X2 &&
+      precision != DT_FP64X4)
     return DT_E_ARG;
   const unsigned known = DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_SIGN | DT_OUT_BACKWARD | DT_OUT_CURV;
   if (out_mask == 0 || (out_mask & ~known)) return DT_E_ARG;
@@ -488,15 +506,12 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     const double l1 = host_kernel_l1(p->M, p->h, ndim, tau);
     const double np = p->npad();
     int chosen = -1;
-    // double-double is a candidate wherever it is built: every output but the sign
-    // (3D up to 256 nodes per axis)
-    bool dd_ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV | DT_OUT_BACKWARD));
-    if (ndim == 3)
-      for (int a = 0; a < 3; ++a) dd_ok = dd_ok && dims[a] <= 256;
-    const int n_cand = dd_ok ? 3 : 2;
-    const int cands[3] = {DT_FP32_SCALED, DT_FP64, DT_FP64X2};
-    const int ubits[3] = {24, 53, 104};
-    for (int c = 0; c < n_cand && chosen < 0; ++c) {
+    // double-double and quad-double are candidates wherever they are built:
+    // every output but the sign (3D up to 256, resp. 128, nodes per axis)
+    const int cands[4] = {DT_FP32_SCALED, DT_FP64, DT_FP64X2, DT_FP64X4};
+    const int ubits[4] = {24, 53, 104, 208};
+    for (int c = 0; c < 4 && chosen < 0; ++c) {
+      if (c >= 2 && !xp_supported(cands[c], ndim, dims, out_mask)) continue;
       const double u = std::ldexp(1.0, -ubits[c]);
       const double theta = p->c_theta * u * std::log2(np) * l1 * std::sqrt((double)k_hint) / std::sqrt(np);
       if (trunc_dist <= -tau * std::log(theta)) chosen = cands[c];
@@ -508,14 +523,12 @@ static dt_status create_plan(dt_plan* out, int ndim, const int64_t* dims, const 
     precision = chosen;
   }
   p->prec = precision;
-  if (precision == DT_FP64X2) {
-    bool ok = !(out_mask & ~(unsigned)(DT_OUT_S | DT_OUT_GRAD | DT_OUT_HESS | DT_OUT_CURV | DT_OUT_BACKWARD));
-    if (ndim == 3)
-      for (int a = 0; a < 3; ++a) ok = ok && dims[a] <= 256;   // 512^3 padded: about 22 GB of workspace
-    if (!ok) {
+  if (precision == DT_FP64X2 || precision == DT_FP64X4) {
+    if (!xp_supported(precision, ndim, dims, out_mask)) {
       delete p;
       return DT_E_UNSUPPORTED;
     }
+    p->quad = precision == DT_FP64X4;
     setup_dd(p);
     log_created(p);
     *out = p;

@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 
 PRECISIONS = {"fp32": L.DT_FP32_SCALED, "fp32_scaled": L.DT_FP32_SCALED, "fp64": L.DT_FP64, "auto": L.DT_AUTO,
-              "fp64x2": L.DT_FP64X2}
+              "fp64x2": L.DT_FP64X2, "fp64x4": L.DT_FP64X4}
 OUTPUT_BITS = {"S": L.DT_OUT_S, "grad": L.DT_OUT_GRAD, "hess": L.DT_OUT_HESS, "sign": L.DT_OUT_SIGN,
                "backward": L.DT_OUT_BACKWARD, "curv": L.DT_OUT_CURV}
 
@@ -82,7 +82,7 @@ class Plan:
             L.check(lib.dt_plan_set_workspace(self._h, ctypes.c_void_p(base + off), int(nbytes.value),
                                               _stream(self.device)), "dt_plan_set_workspace")
         self.info = self._info()
-        self.dtype = torch.float64 if self.info.precision in (L.DT_FP64, L.DT_FP64X2) else torch.float32
+        self.dtype = torch.float64 if self.info.precision in (L.DT_FP64, L.DT_FP64X2, L.DT_FP64X4) else torch.float32
 
     def rebuild(self):
         """Attach the same workspace again: the kernel spectra are sampled and
@@ -128,7 +128,7 @@ class Plan:
 
     @property
     def precision(self):
-        return {L.DT_FP64: "fp64", L.DT_FP64X2: "fp64x2"}.get(self.info.precision, "fp32")
+        return {L.DT_FP64: "fp64", L.DT_FP64X2: "fp64x2", L.DT_FP64X4: "fp64x4"}.get(self.info.precision, "fp32")
 
     def _points(self, Y):
         if Y is None:

@@ -118,7 +118,7 @@ void plans_random(int count) {
       o[a] = unit() - 0.5;
     }
     const double tau = h[0] * (0.25 + 8 * unit());
-    const int prec = (int)uniform(0, 3);
+    const int prec = (int)uniform(0, 4);
     const unsigned mask = masks[uniform(0, 8)];
     const bool reduced = uniform(0, 2) == 0;
     const int64_t k_max = reduced ? log_uniform(1, 1000000) : 0;
@@ -135,10 +135,11 @@ void plans_random(int count) {
       CHECK(st == DT_E_UNSUPPORTED || st == DT_E_ARG, "reduced sign plan: %d", st);
     } else if (reduced && prec != DT_FP32_SCALED && prec != DT_FP64) {
       CHECK(st == DT_E_ARG, "reduced precision %d: %d", prec, st);
-    } else if (prec == DT_FP64X2) {
+    } else if (prec == DT_FP64X2 || prec == DT_FP64X4) {
       bool ok = !(mask & DT_OUT_SIGN);
-      for (int a = 0; a < ndim && ndim == 3; ++a) ok = ok && dims[a] <= 256;
-      CHECK(ok ? st == DT_OK : st == DT_E_UNSUPPORTED, "fp64x2 mask %u: %d", mask, st);
+      const int64_t cap = prec == DT_FP64X4 ? 128 : 256;
+      for (int a = 0; a < ndim && ndim == 3; ++a) ok = ok && dims[a] <= cap;
+      CHECK(ok ? st == DT_OK : st == DT_E_UNSUPPORTED, "extended precision %d mask %u: %d", prec, mask, st);
     } else if (prec == DT_AUTO) {
       CHECK(st == DT_OK || st == DT_E_PRECISION, "auto: %d", st);
     } else {
@@ -166,7 +167,7 @@ void plans_refused() {
   CHECK(dt_create_plan(&p, 2, d2, h, nullptr, 0.02, 0, 1, 0, 0, 0) == DT_E_ARG, "null origin");
   for (double tau : {0.0, -1.0, kNaN, kInf})
     CHECK(dt_create_plan(&p, 2, d2, h, o, tau, 0, 1, 0, 0, 0) == DT_E_ARG && !p, "tau %g", tau);
-  for (int prec : {-1, 4, 99}) CHECK(dt_create_plan(&p, 2, d2, h, o, 0.02, prec, 1, 0, 0, 0) == DT_E_ARG, "prec");
+  for (int prec : {-1, 5, 99}) CHECK(dt_create_plan(&p, 2, d2, h, o, 0.02, prec, 1, 0, 0, 0) == DT_E_ARG, "prec");
   for (unsigned m : {0u, 64u, 128u | 1u}) CHECK(dt_create_plan(&p, 2, d2, h, o, 0.02, 0, m, 0, 0, 0) == DT_E_ARG, "mask");
   for (double c : {kNaN, kInf}) CHECK(dt_create_plan(&p, 2, d2, h, o, 0.02, 0, 1, 0, 0, c) == DT_E_ARG, "c_theta");
   const int64_t small[2] = {1, 48}, big[3] = {32, 1025, 24};

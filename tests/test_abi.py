@@ -70,7 +70,17 @@ def test_auto_precision(lib):
     assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
     assert info.precision == 1
     lib.dt_destroy_plan(h)
-    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=1, trunc=80 * tau, khint=1000)[0] == 3
+    # beyond the float64 band: double-double (band about 60 tau here), then
+    # quad-double (about 130 tau), then no precision resolves it
+    for trunc, want in ((40, 3), (80, 4)):
+        st, h = _plan(lib, dims=dims, tau=tau, prec=2, mask=1, trunc=trunc * tau, khint=1000)
+        assert st == 0
+        assert lib.dt_plan_info(h, ctypes.byref(info)) == 0
+        assert info.precision == want, (trunc, info.precision)
+        lib.dt_destroy_plan(h)
+    assert _plan(lib, dims=dims, tau=tau, prec=2, mask=1, trunc=200 * tau, khint=1000)[0] == 3
+    # quad-double is not offered for the sign (as double-double)
+    assert _plan(lib, dims=dims, tau=tau, prec=4, mask=8)[0] == 6
 
 
 def test_workspace_and_call_checks(lib):
