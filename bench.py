@@ -426,7 +426,8 @@ def batch_bytes(dims, padded, w, C):
 def run_protocol(trials):
     """Example 1 of Sec. 6.1 on the float64 path: 129 x 129 nodes at spacing
     1/512 on [-0.125, 0.125]^2, 5000 distinct random nodes per trial, the
-    nine tau of Table 2.  Timed: the dt_distance calls with the points on the
+    nine tau of Table 2; the three smallest again in double-double and
+    quad-double.  Timed: the dt_distance calls with the points on the
     device.  Reported per tau: max and mean percentage error over the trials
     (true distance by KD-tree) and the fraction of nodes inside the valid
     band.  A 2D grid of this size is cache-resident: no roofline claim."""
@@ -445,9 +446,9 @@ def run_protocol(trials):
         Rs.append(cKDTree(Y.astype(np.float64)).query(X)[0])
     printed = [0.5728, 1.1482, 1.7461, 2.4046, 3.1550, 4.0146, 4.9959, 6.1033, 7.3380]   # Table 2
     taus = [5e-5 * (i + 1) for i in range(9)]
-    rows, total_ms = [], 0.0
-    for tau, pr in zip(taus, printed):
-        plan = dt.Plan((n, n), (h, h), (lo - h / 2, lo - h / 2), tau, precision="fp64", outputs=["S"])
+
+    def run_tau(tau, pr, precision):
+        plan = dt.Plan((n, n), (h, h), (lo - h / 2, lo - h / 2), tau, precision=precision, outputs=["S"])
         S = plan._empty()
         for Yd in pts[:3]:
             plan.distance_into(S, Yd)
@@ -461,7 +462,6 @@ def run_protocol(trials):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        total_ms += ms
         smax = plan.last_stats()["s_max"]
         E, valid = [], []
         for o, R in zip(outs, Rs):
@@ -469,16 +469,27 @@ def run_protocol(trials):
             keep = R > 0
             E.append(100.0 * np.sum(np.abs(Sv[keep] - R[keep]) / R[keep]) / len(R))   # eq. percentError
             valid.append(np.mean(Sv < smax))
-        rows.append({"tau": tau, "max_percent_error": round(max(E), 4), "printed_max": pr,
-                     "ratio": round(max(E) / pr, 4), "mean_percent_error": round(float(np.mean(E)), 4),
-                     "valid_fraction": round(float(np.mean(valid)), 5), "ms_per_trial": round(ms / trials, 4)})
         del plan
+        return ms, {"tau": tau, "precision": precision, "max_percent_error": round(max(E), 4), "printed_max": pr,
+                    "ratio": round(max(E) / pr, 4), "mean_percent_error": round(float(np.mean(E)), 4),
+                    "valid_fraction": round(float(np.mean(valid)), 5), "ms_per_trial": round(ms / trials, 4)}
+
+    rows, total_ms = [], 0.0
+    for tau, pr in zip(taus, printed):
+        ms, row = run_tau(tau, pr, "fp64")
+        total_ms += ms
+        rows.append(row)
+    # the three smallest tau, where the float64 band stops short of the farthest
+    # nodes, in the precision whose band reaches them
+    extended = [run_tau(tau, pr, prec)[1] for tau, pr, prec in
+                ((5e-5, printed[0], "fp64x4"), (1e-4, printed[1], "fp64x2"), (1.5e-4, printed[2], "fp64x2"))]
     line = {"metric": "Sec. 6.1 Example 1 trials/s (129^2, K=5000, float64) with Table 2 maxima",
             "value": round(trials * len(taus) / (total_ms * 1e-3), 1), "unit": "trials/s", "n_gpus": 1,
             "steps": trials * len(taus), "warmup": 3, "ms_per_step": round(total_ms / (trials * len(taus)), 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "example1_2d_129_K5000_table2_taus", "trials_per_tau": trials},
-            "roofline": None, "note": "cache-resident 2D size: no roofline claim", "table2": rows}
+            "roofline": None, "note": "cache-resident 2D size: no roofline claim", "table2": rows,
+            "table2_extended_precision": extended}
     print(json.dumps(line), flush=True)
 
 
@@ -564,8 +575,9 @@ def dd_col_ops(Mx, My):
 def run_dd(steps, warmup, no_cpu, cpu_cells):
     """The double-double path on the 1024^2 polygon workload (K = 8000,
     tau = 0.5 h: the smallest tau of that workload, where float64 loses the
-    most of the grid), S only, timed beside the float64 path on the same
-    input.  ALU-bound: the roofline counts float64 operations."""
+    most of the grid), S only, timed beside the quad-double and float64 paths
+    on the same input.  ALU-bound: the roofline counts float64 operations of
+    the double-double column pass."""
     import torch
     import paper_1112_3010_amd as dt
     import synth
@@ -575,7 +587,7 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
     tau = w.taus[0]
     Yd = torch.from_numpy(w.points).cuda()
     res = {}
-    for prec in ("fp64x2", "fp64"):
+    for prec in ("fp64x2", "fp64x4", "fp64"):
         plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S"])
         S = plan._empty()
         for _ in range(warmup):
@@ -625,7 +637,7 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
     Y3 = torch.from_numpy(synth.jittered_sphere_points(4096, 0.3, 2.0 / n3, seed=11)).cuda()
     d3 = {}
     for prec, outs in (("fp64x2", ["S"]), ("fp64x2", ["S", "grad"]), ("fp64", ["S", "grad"]),
-                       ("fp64x2", ["S", "backward"])):
+                       ("fp64x2", ["S", "backward"]), ("fp64x4", ["S"]), ("fp64x4", ["S", "grad"])):
         plan = dt.Plan(dims3, h3, None, h3[0], precision=prec, outputs=outs)
         if outs == ["S"]:
             fwd = lambda: plan.distance(Y3)
@@ -670,7 +682,9 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
             "with_grad_ms_per_step": round(grad_ms, 4),
             "3d_128cube_sphere4096_tau1h": d3,
             "fp64": {"ms_per_step": round(res["fp64"]["ms"], 4), "pass_ms": res["fp64"]["pass_ms"],
-                     "s_max_over_tau": round(res["fp64"]["s_max_over_tau"], 2)}}
+                     "s_max_over_tau": round(res["fp64"]["s_max_over_tau"], 2)},
+            "fp64x4": {"ms_per_step": round(res["fp64x4"]["ms"], 4), "pass_ms": res["fp64x4"]["pass_ms"],
+                       "s_max_over_tau": round(res["fp64x4"]["s_max_over_tau"], 2)}}
     if not no_cpu:
         import oracle
         from threadpoolctl import threadpool_limits
@@ -689,7 +703,7 @@ def run_dd(steps, warmup, no_cpu, cpu_cells):
                                 "sample": f"{len(cells)} random nodes of the 1024^2 grid, all {int(valid.sum())} "
                                           f"sources each, S in float64 ({dt_s:.1f} s)"}
         acc = {}
-        for prec in ("fp64x2", "fp64"):
+        for prec in ("fp64x2", "fp64x4", "fp64"):
             smax = res[prec]["s_max_over_tau"] * tau
             ref = np.minimum(f["S"], smax)
             Sg = res[prec]["S"][cells]
