@@ -41,6 +41,15 @@ using ddm::qd;
 using ddm::xp;
 
 constexpr int kThreads = 256;
+// Threads per block of the transform kernels (their launch bound): 256 for
+// double-double; up to 512 for quad-double, whose 2048-point lines fill
+// 128 KB of LDS (one block per CU) and whose kernels fit two waves per SIMD
+// in registers, so the larger block doubles the waves that share a CU.
+template <class R> constexpr int threads_of() { return sizeof(R) > 16 ? 512 : 256; }
+// Threads of one launch whose blocks hold `elems` values: the larger block
+// only where it has work for every thread (shorter blocks would leave half
+// of it idle in each radix-4 stage).
+template <class R> int block_threads(int elems) { return elems >= 2048 ? threads_of<R>() : kThreads; }
 
 __device__ __forceinline__ int brev(int x, int logM) { return (int)(__builtin_bitreverse32((uint32_t)x) >> (32 - logM)); }
 
@@ -247,7 +256,7 @@ struct DDLines {
 // contiguous run) and reads them whole before writing, so in and out may be
 // the same array.
 template <class R, int MODE, int LB>
-__global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_line_fwd(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                           R* __restrict__ tab, const cplx<R>* __restrict__ tw,
                                                           DDLines L, int scale_e) {
   extern __shared__ __align__(16) char smem[];
@@ -281,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_line_fwd(const cplx<R>* __restr
 // Inverse (unnormalised) transform of each line from its natural-order
 // spectrum; the first n_out samples are kept.  LB adjacent lines per block.
 template <class R, int LB>
-__global__ __launch_bounds__(kThreads) void k_dd_line_inv(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_line_inv(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                           const cplx<R>* __restrict__ tw, DDLines L) {
   extern __shared__ __align__(16) char smem[];
   cplx<R>* buf = (cplx<R>*)smem;
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_line_inv(const cplx<R>* __restr
 // Forward transform of rows.  REAL_IN: row y of the ny x nx multiplicities,
 // zero-padded to Mx; else row y of G in place.
 template <class R, bool REAL_IN>
-__global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restrict__ cnt, cplx<R>* __restrict__ G,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_row_fwd(const double* __restrict__ cnt, cplx<R>* __restrict__ G,
                                                          const cplx<R>* __restrict__ tw, DDGeom g) {
   extern __shared__ __align__(16) char smem[];
   cplx<R>* buf = (cplx<R>*)smem;
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_fwd(const double* __restric
 // forward transform, and the real (IMAG = false) or imaginary part of the
 // spectrum, scaled by 1/(Mx My), into tab.
 template <class R, bool IMAG>
-__global__ __launch_bounds__(kThreads) void k_dd_col_table(const cplx<R>* __restrict__ G, R* __restrict__ tab,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_col_table(const cplx<R>* __restrict__ G, R* __restrict__ tab,
                                                            const cplx<R>* __restrict__ tw, DDGeom g) {
   extern __shared__ __align__(16) char smem[];
   cplx<R>* buf = (cplx<R>*)smem;
@@ -363,7 +372,7 @@ struct DDFused {
 };
 
 template <class R, bool MULTI, int LB, int SPT = kSpecPerThread>
-__global__ __launch_bounds__(kThreads) void k_dd_col_fused(const cplx<R>* __restrict__ Gin, cplx<R>* __restrict__ Gout,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_col_fused(const cplx<R>* __restrict__ Gin, cplx<R>* __restrict__ Gout,
                                                            const R* __restrict__ tabs, const cplx<R>* __restrict__ tw,
                                                            DDFused F, int C) {
   extern __shared__ __align__(16) char smem[];
@@ -430,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_col_fused(const cplx<R>* __rest
 constexpr int kMaxPerThread = 4;
 
 template <class R>
-__global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_row_inv_epi(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
                                                              double* __restrict__ S, double* __restrict__ grad,
                                                              double* __restrict__ hess, double* __restrict__ curv,
                                                              const double* __restrict__ scal, DDGeom g, int C) {
@@ -493,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_row_inv_epi(const cplx<R>* __re
 // leading part of the real part), out[c][row][x] for x < nx (the adjoint's
 // convolutions w * u_a and w * r f).
 template <class R>
-__global__ __launch_bounds__(kThreads) void k_dd_row_inv_plain(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
+__global__ __launch_bounds__(threads_of<R>()) void k_dd_row_inv_plain(const cplx<R>* __restrict__ Gc, const cplx<R>* __restrict__ tw,
                                                                double* __restrict__ out, DDGeom g, int C) {
   extern __shared__ __align__(16) char smem[];
   cplx<R>* buf = (cplx<R>*)smem;
@@ -612,13 +621,14 @@ static hipError_t launch_line_fwd(const cplx<R>* in, cplx<R>* out, R* tab, const
                                   int scale_e, hipStream_t st) {
   const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(cplx<R>);
   const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
+  const int nt = block_threads<R>(L.M << L.log_lb);
   hipError_t e;
   if (L.log_lb == 2) {
     if ((e = allow_lds(k_dd_line_fwd<R, MODE, 4>, lds)) != hipSuccess) return e;
-    k_dd_line_fwd<R, MODE, 4><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+    k_dd_line_fwd<R, MODE, 4><<<blocks, nt, lds, st>>>(in, out, tab, tw, L, scale_e);
   } else {
     if ((e = allow_lds(k_dd_line_fwd<R, MODE, 1>, lds)) != hipSuccess) return e;
-    k_dd_line_fwd<R, MODE, 1><<<blocks, kThreads, lds, st>>>(in, out, tab, tw, L, scale_e);
+    k_dd_line_fwd<R, MODE, 1><<<blocks, nt, lds, st>>>(in, out, tab, tw, L, scale_e);
   }
   return hipSuccess;
 }
@@ -627,13 +637,14 @@ static hipError_t launch_line_inv(const cplx<R>* in, cplx<R>* out, const cplx<R>
                                   hipStream_t st) {
   const size_t lds = ((size_t)L.M << L.log_lb) * sizeof(cplx<R>);
   const unsigned blocks = (unsigned)(L.n_lines >> L.log_lb);
+  const int nt = block_threads<R>(L.M << L.log_lb);
   hipError_t e;
   if (L.log_lb == 2) {
     if ((e = allow_lds(k_dd_line_inv<R, 4>, lds)) != hipSuccess) return e;
-    k_dd_line_inv<R, 4><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+    k_dd_line_inv<R, 4><<<blocks, nt, lds, st>>>(in, out, tw, L);
   } else {
     if ((e = allow_lds(k_dd_line_inv<R, 1>, lds)) != hipSuccess) return e;
-    k_dd_line_inv<R, 1><<<blocks, kThreads, lds, st>>>(in, out, tw, L);
+    k_dd_line_inv<R, 1><<<blocks, nt, lds, st>>>(in, out, tw, L);
   }
   return hipSuccess;
 }
@@ -656,7 +667,7 @@ static hipError_t build_tables_3d(void* twx, void* twy, void* twz, void* tabs, i
   for (int t = 0; t < n_tabs; ++t) {
     R* tab = (R*)tabs + t * total;
     k_dd_tab_sample<R><<<(unsigned)((total + 255) / 256), 256, 0, st>>>((C*)G, g, t == rf_tab ? kDDKindRF : t);
-    k_dd_row_fwd<R, false><<<(unsigned)rows.ny, kThreads, lx, st>>>(nullptr, (C*)G, (const C*)twx, rows);
+    k_dd_row_fwd<R, false><<<(unsigned)rows.ny, block_threads<R>(g.Mx), lx, st>>>(nullptr, (C*)G, (const C*)twx, rows);
     if ((e = launch_line_fwd<R, 0>((const C*)G, (C*)G, nullptr, (const C*)twy, ly_, 0, st)) != hipSuccess) return e;
     const int e_scale = -(g.logMx + g.logMy + g.logMz);
     if (t == rf_tab || !dd_imag_channel(t, g.ndim))
@@ -684,11 +695,11 @@ static hipError_t build_tables(void* twx, void* twy, void* twz, void* tabs, int 
   for (int t = 0; t < n_tabs; ++t) {
     R* tab = (R*)tabs + t * total;
     k_dd_tab_sample<R><<<(unsigned)((total + 255) / 256), 256, 0, st>>>((C*)G, g, t == rf_tab ? kDDKindRF : t);
-    k_dd_row_fwd<R, false><<<g.My, kThreads, lx, st>>>(nullptr, (C*)G, (const C*)twx, g);
+    k_dd_row_fwd<R, false><<<g.My, block_threads<R>(g.Mx), lx, st>>>(nullptr, (C*)G, (const C*)twx, g);
     if (t == rf_tab || !dd_imag_channel(t, g.ndim))
-      k_dd_col_table<R, false><<<g.Mx, kThreads, ly, st>>>((const C*)G, tab, (const C*)twy, g);
+      k_dd_col_table<R, false><<<g.Mx, block_threads<R>(g.My), ly, st>>>((const C*)G, tab, (const C*)twy, g);
     else
-      k_dd_col_table<R, true><<<g.Mx, kThreads, ly, st>>>((const C*)G, tab, (const C*)twy, g);
+      k_dd_col_table<R, true><<<g.Mx, block_threads<R>(g.My), ly, st>>>((const C*)G, tab, (const C*)twy, g);
   }
   return hipGetLastError();
 }
@@ -717,7 +728,7 @@ static hipError_t row_fwd(const double* cnt, void* G, const void* twx, const DDG
   const size_t lds = (size_t)g.Mx * sizeof(C);
   const hipError_t e = allow_lds(k_dd_row_fwd<R, true>, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_fwd<R, true><<<g.ny, kThreads, lds, st>>>(cnt, (C*)G, (const C*)twx, g);
+  k_dd_row_fwd<R, true><<<g.ny, block_threads<R>(g.Mx), lds, st>>>(cnt, (C*)G, (const C*)twx, g);
   return hipGetLastError();
 }
 hipError_t dd_launch_row_fwd(const double* cnt, void* G, const void* twx, const DDGeom& g, hipStream_t st) {
@@ -733,33 +744,42 @@ static hipError_t launch_fused(const void* Gin, void* Gout, const void* tabs, co
   const size_t lds = ((size_t)F.M << F.log_lb) * sizeof(C);
   const unsigned blocks = (unsigned)(lines >> F.log_lb);
   const int nc = F.ch.C;
+  const int nt = block_threads<R>(F.M << F.log_lb);
   const C* gi = (const C*)Gin;
   C* go = (C*)Gout;
   const R* tb = (const R*)tabs;
   const C* w = (const C*)tw;
   hipError_t e;
   if (nc > 1) {
-    if ((F.M << F.log_lb) > kSpecPerThread * kThreads) return hipErrorInvalidValue;
-    if (F.log_lb == 2 && (F.M << 2) <= 4 * kThreads) {   // four spectrum bins per thread suffice
+    if ((F.M << F.log_lb) > kSpecPerThread * nt) return hipErrorInvalidValue;
+    // four spectrum bins per thread where they suffice; eight otherwise
+    // (double-double only: quad-double blocks of 256 threads up to 1024
+    // elements and of 512 above cover every length up to 2048 with four)
+    constexpr bool kEight = threads_of<R>() == kThreads;
+    if (F.log_lb == 2 && (F.M << 2) <= 4 * nt) {
       if ((e = allow_lds(k_dd_col_fused<R, true, 4, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, true, 4, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
-    } else if (F.log_lb == 2) {
-      if ((e = allow_lds(k_dd_col_fused<R, true, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, true, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
-    } else if (F.M <= 4 * kThreads) {
+      k_dd_col_fused<R, true, 4, 4><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
+    } else if (F.log_lb != 2 && F.M <= 4 * nt) {
       if ((e = allow_lds(k_dd_col_fused<R, true, 1, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, true, 1, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
+      k_dd_col_fused<R, true, 1, 4><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
+    } else if constexpr (kEight) {
+      if (F.log_lb == 2) {
+        if ((e = allow_lds(k_dd_col_fused<R, true, 4>, lds)) != hipSuccess) return e;
+        k_dd_col_fused<R, true, 4><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
+      } else {
+        if ((e = allow_lds(k_dd_col_fused<R, true, 1>, lds)) != hipSuccess) return e;
+        k_dd_col_fused<R, true, 1><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
+      }
     } else {
-      if ((e = allow_lds(k_dd_col_fused<R, true, 1>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, true, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
+      return hipErrorInvalidValue;
     }
   } else {
     if (F.log_lb == 2) {
       if ((e = allow_lds(k_dd_col_fused<R, false, 4>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, false, 4><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
+      k_dd_col_fused<R, false, 4><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
     } else {
       if ((e = allow_lds(k_dd_col_fused<R, false, 1>, lds)) != hipSuccess) return e;
-      k_dd_col_fused<R, false, 1><<<blocks, kThreads, lds, st>>>(gi, go, tb, w, F, nc);
+      k_dd_col_fused<R, false, 1><<<blocks, nt, lds, st>>>(gi, go, tb, w, F, nc);
     }
   }
   return hipGetLastError();
@@ -812,7 +832,7 @@ static hipError_t row_inv_epi(const void* Gc, int C, const void* twx, double* S,
   const size_t lds = (size_t)g.Mx * sizeof(Cx);
   const hipError_t e = allow_lds(k_dd_row_inv_epi<R>, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_epi<R><<<(unsigned)rows.ny, kThreads, lds, st>>>((const Cx*)Gc, (const Cx*)twx, S, grad, hess, curv,
+  k_dd_row_inv_epi<R><<<(unsigned)rows.ny, block_threads<R>(g.Mx), lds, st>>>((const Cx*)Gc, (const Cx*)twx, S, grad, hess, curv,
                                                                  scal, rows, C);
   return hipGetLastError();
 }
@@ -832,7 +852,7 @@ static hipError_t row_inv_plain(const void* Gc, int C, const void* twx, double* 
   const size_t lds = (size_t)g.Mx * sizeof(Cx);
   const hipError_t e = allow_lds(k_dd_row_inv_plain<R>, lds);
   if (e != hipSuccess) return e;
-  k_dd_row_inv_plain<R><<<(unsigned)rows.ny, kThreads, lds, st>>>((const Cx*)Gc, (const Cx*)twx, out, rows, C);
+  k_dd_row_inv_plain<R><<<(unsigned)rows.ny, block_threads<R>(g.Mx), lds, st>>>((const Cx*)Gc, (const Cx*)twx, out, rows, C);
   return hipGetLastError();
 }
 hipError_t dd_launch_row_inv_plain(const void* Gc, int C, const void* twx, double* out, const DDGeom& g,
