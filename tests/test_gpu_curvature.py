@@ -65,7 +65,8 @@ def _check(res, ref, tau, h, prec, tag, D):
 @pytest.mark.parametrize("dims,K,tau_h,prec", [((90, 70), 40, 2.0, "fp32"), ((90, 70), 40, 2.0, "fp64"),
                                                ((200, 130), 300, 3.0, "fp32"),
                                                ((34, 30, 28), 40, 2.0, "fp32"), ((34, 30, 28), 40, 2.0, "fp64"),
-                                               ((90, 70), 5, 0.5, "fp64x2"), ((34, 30, 28), 6, 0.5, "fp64x2")])
+                                               ((90, 70), 5, 0.5, "fp64x2"), ((34, 30, 28), 6, 0.5, "fp64x2"),
+                                               ((90, 70), 5, 0.35, "fp64x4"), ((34, 30, 28), 6, 0.3, "fp64x4")])
 def test_curvature(dt, dims, K, tau_h, prec):
     D = len(dims)
     pts = synth.generators.uniform_points(D, K, seed=401 + D + K)
@@ -79,13 +80,19 @@ def test_curvature(dt, dims, K, tau_h, prec):
     assert plan.last_error() == 0
     # the curvature outputs do not depend on which other outputs are written
     assert torch.equal(res["curv"], both["curv"])
-    if prec == "fp64x2":
-        # the double-double band reaches nodes that float64 reports as S_max
-        ref64 = oracle.theta("fp64", tuple(parity.padded(n) for n in dims),
-                             oracle.kernel_l1(tuple(parity.padded(n) for n in dims), h, tau),
-                             float(plan.last_stats()["g_l2"]))
-        assert plan.last_stats()["s_max"] > 1.8 * oracle.s_max(tau, ref64)
+    if prec in ("fp64x2", "fp64x4"):
+        # the extended band reaches nodes that the next narrower format
+        # (float64, double-double) reports as S_max
+        lower = "fp64" if prec == "fp64x2" else "fp64x2"
+        ref_low = oracle.theta(lower, tuple(parity.padded(n) for n in dims),
+                               oracle.kernel_l1(tuple(parity.padded(n) for n in dims), h, tau),
+                               float(plan.last_stats()["g_l2"]))
+        assert plan.last_stats()["s_max"] > 1.8 * oracle.s_max(tau, ref_low)
     ref = parity.reference(dims, h, (0.0,) * D, tau, pts, prec, grad=True, hess=True)
+    if prec in ("fp64x2", "fp64x4"):
+        # checked nodes (phi >= 10 Theta) exist beyond the narrower band
+        beyond = (ref["lnphi"] >= np.log(10 * ref["theta"])) & (ref["lnphi"] < np.log(ref_low))
+        assert beyond.sum() > 100, beyond.sum()
     _check(res, ref, tau, h, prec, f"{dims} {prec}", D)
 
 

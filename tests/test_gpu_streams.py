@@ -25,11 +25,12 @@ ROUNDS = 6
 
 
 def test_plans_on_concurrent_streams(dt):
-    # three plans of different kinds: 3D float32, 2D float64 with the Hessian,
-    # 2D double-double; and a batched plan
+    # plans of different kinds: 3D float32, 2D float64 with the Hessian, 2D
+    # double-double, 2D quad-double with the gradient; and a batched plan
     a = dt.Plan((48, 40, 36), None, None, 2.0 / 48, precision="fp32", outputs=["S", "grad"])
     b = dt.Plan((200, 160), None, None, 2.0 / 200, precision="fp64", outputs=["S", "grad", "hess"])
     c = dt.Plan((96, 80), None, None, 2.0 / 96, precision="fp64x2", outputs=["S"])
+    e = dt.Plan((64, 48), None, None, 1.0 / 64, precision="fp64x4", outputs=["S", "grad"])
     bdims = [(97, 130), (64, 64), (150, 40)]
     bp = dt.BatchPlan(bdims, [2.0 / d[0] for d in bdims], precision="fp32", graph=False)
 
@@ -37,19 +38,21 @@ def test_plans_on_concurrent_streams(dt):
         ya = torch.from_numpy(synth.generators.uniform_points(3, 300, seed=7000 + r)).cuda()
         yb = torch.from_numpy(synth.generators.uniform_points(2, 500, seed=7100 + r)).cuda()
         yc = torch.from_numpy(synth.generators.uniform_points(2, 40, seed=7200 + r)).cuda()
+        ye = torch.from_numpy(synth.generators.uniform_points(2, 8, seed=7400 + r)).cuda()
         pts = [torch.from_numpy(synth.generators.uniform_points(2, 50 + 10 * i, seed=7300 + 10 * r + i))
                for i in range(len(bdims))]
         yd, offs = dt.BatchPlan.pack(pts)
-        return ya, yb, yc, yd.cuda(), offs
+        return ya, yb, yc, yd.cuda(), offs, ye
 
     ins = [inputs(r) for r in range(ROUNDS)]
     torch.cuda.synchronize()
 
     def run_all(r, streams):
-        ya, yb, yc, yd, offs = ins[r]
+        ya, yb, yc, yd, offs, ye = ins[r]
         outs = {}
         with torch.cuda.stream(streams[0]):
             outs["a"] = a.forward(ya, S=True, grad=True)
+            outs["e"] = e.forward(ye, S=True, grad=True)
         with torch.cuda.stream(streams[1]):
             outs["b"] = b.forward(yb, S=True, grad=True, hess=True)
         with torch.cuda.stream(streams[2]):
@@ -70,10 +73,10 @@ def test_plans_on_concurrent_streams(dt):
     got = [run_all(r, streams) for r in range(ROUNDS)]
     torch.cuda.synchronize()
     for r in range(ROUNDS):
-        for key in ("a", "b", "c", "d"):
+        for key in ("a", "b", "c", "d", "e"):
             for field, t in ref[r][key].items():
                 assert torch.equal(got[r][key][field], t), (r, key, field)
-    for p in (a, b, c):
+    for p in (a, b, c, e):
         assert p.last_error() == 0
     assert bp.last_error() == 0
     # the fields are not trivially equal between rounds
