@@ -187,7 +187,8 @@ def _clustered3(n_pts, frac, seed):
     return p.astype(np.float32)
 
 
-@pytest.mark.parametrize("dims,K,tau_h", [((40, 36, 33), 5, 1.0), ((96, 40, 30), 12, 0.5)])
+# (40, 36, 150): 512-point z lines, four per block, eight spectrum bins per thread
+@pytest.mark.parametrize("dims,K,tau_h", [((40, 36, 33), 5, 1.0), ((96, 40, 30), 12, 0.5), ((40, 36, 150), 6, 1.0)])
 def test_dd3d_distance_and_gradient_vs_oracle(dt, dims, K, tau_h):
     """3D (rows, strided y lines, fused z lines, all in double-double): S and
     grad S on every node against the oracle, to the float64 per-node bound

@@ -250,3 +250,41 @@ def test_qd_rejects_what_it_does_not_build(dt):
         dt.Plan((64, 64), None, None, 0.02, precision="fp64x4", outputs=["S", "sign"])
     with pytest.raises(RuntimeError):
         dt.Plan((160, 32, 32), None, None, 0.05, precision="fp64x4", outputs=["S"])
+
+
+@pytest.mark.parametrize("prec", ["fp64x2", "fp64x4"])
+@pytest.mark.parametrize("dims", [(200, 400), (300, 700)])
+def test_xp_long_columns_gradient(dt, prec, dims):
+    """S + grad S with long padded columns (1024 and 2048 points: one line per
+    block; double-double keeps four or eight spectrum bins per thread,
+    quad-double four, on 256 or 512 threads): every resolved node against
+    the oracle, S equal to the S-only plan's."""
+    K, tau_h = 5, 2.0
+    pts = _clustered(K, 0.3, seed=880 + dims[1])
+    pts[:, [0, 1]] = pts[:, [1, 0]]   # the sources near y = 0: long distances along the columns
+    h = tuple(1.0 / n for n in dims)
+    tau = tau_h * h[0]
+    Y = torch.from_numpy(pts).cuda()
+    plan = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S", "grad"])
+    assert plan.padded == tuple(parity.padded(n) for n in dims)
+    S, g = plan.gradient(Y)
+    S_only = dt.Plan(dims, h, None, tau, precision=prec, outputs=["S"]).distance(Y)
+    torch.cuda.synchronize()
+    assert plan.last_error() == 0
+    assert torch.equal(S, S_only)
+    ref = parity.reference(dims, h, (0.0, 0.0), tau, pts, prec, grad=True)
+    S = S.cpu().numpy().ravel()
+    g = g.cpu().numpy().reshape(2, -1)
+    dS = np.abs(S - ref["S_ref"])
+    dG = np.abs(g - ref["grad"].T)
+    deep, valid = ref["deep"], ref["valid"]
+    lower = "fp64" if prec == "fp64x2" else "fp64x2"
+    theta_low = oracle.theta(lower, ref["padded"], ref["kernel_l1"], ref["g_l2"])
+    beyond = deep & (ref["lnphi"] < np.log(theta_low))
+    print(f"\n[{prec} long columns {dims} -> {plan.padded}] max|dS|/tau deep={dS[deep].max() / tau:.3e} "
+          f"max|dgrad| deep={dG[:, deep].max():.3e} beyond {lower}={beyond.sum()}")
+    assert beyond.sum() > 0
+    assert dS.max() <= parity.TOL_S_TAU * tau
+    assert np.all(dS[deep] <= parity.bound(ref, TOL_S_TAU_XP, tau)[deep])
+    assert np.all(dG[:, deep] <= parity.bound(ref, TOL_GRAD_XP)[deep])
+    assert dG[:, valid].max() <= parity.TOL_GRAD
