@@ -309,7 +309,8 @@ void batch_refused() {
   CHECK(dt_create_batch_plan(nullptr, 1, &q, 0, 3, 0) == DT_E_ARG, "null out");
   CHECK(dt_create_batch_plan(&p, 0, &q, 0, 3, 0) == DT_E_ARG && !p, "no instances");
   CHECK(dt_create_batch_plan(&p, 1, nullptr, 0, 3, 0) == DT_E_ARG, "null desc");
-  for (int prec : {(int)DT_AUTO, (int)DT_FP64X2, 9}) CHECK(dt_create_batch_plan(&p, 1, &q, prec, 3, 0) == DT_E_ARG, "prec");
+  for (int prec : {(int)DT_AUTO, (int)DT_FP64X2, (int)DT_FP64X4, 9})
+    CHECK(dt_create_batch_plan(&p, 1, &q, prec, 3, 0) == DT_E_ARG, "prec");
   for (unsigned m : {0u, (unsigned)DT_OUT_HESS, 7u}) CHECK(dt_create_batch_plan(&p, 1, &q, 0, m, 0) == DT_E_ARG, "mask");
   CHECK(dt_create_batch_plan(&p, 1, &q, 0, 3, kNaN) == DT_E_ARG, "c_theta NaN");
   q.dims[1] = 1;
