@@ -89,7 +89,7 @@ def counters_for(kernel_file_hash, precision, pass_name):
 
 
 # sources of the double-double pipeline only (no float32/float64 launch uses them)
-DD_SOURCES = ("dd.hpp", "dt_dd.hpp", "k_dd.hip")
+DD_SOURCES = ("dd.hpp", "qd.hpp", "dt_dd.hpp", "k_dd.hip")
 # sources of the batched 2D path and of the fixed workspace only (the 3D
 # passes of the headline workload do not use them)
 OTHER_SOURCES = ("batch.cpp", "dt_batch.hpp", "fft_mixed.hpp", "k_batch.hip", "k_static_ws.hip", "dt_static.hpp")
