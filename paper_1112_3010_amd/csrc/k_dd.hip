@@ -1,21 +1,25 @@
-// Extended-precision (double-double) pipeline for 2D and 3D distance fields.
+// Extended-precision pipelines (double-double and quad-double) for 2D and 3D
+// distance fields.
 //
 // The same zero-padded FFT convolution as the float32/float64 paths
 // (Sec. 3, Table 1: splat the indicator, transform, multiply by the kernel
-// spectrum, transform back, S = -tau log phi of eq. STilde), carried in
-// double-double so that the FFT's absolute error floor drops from about
-// 2^-53 to 2^-104 of the largest term.  Sec. 3.2 observes that the float64
+// spectrum, transform back, S = -tau log phi of eq. STilde), carried in an
+// extended real type R so that the FFT's absolute error floor drops from
+// about 2^-53 of the largest term to 2^-104 (R = dd, pairs of float64) or
+// 2^-208 (R = qd, four float64 parts).  Sec. 3.2 observes that the float64
 // convolution fails far from the sources for small tau and resorts to
-// multiple-precision arithmetic; this pipeline plays that role on the GPU.
+// multiple-precision arithmetic; these pipelines play that role on the GPU.
+// Every kernel below is a template over R; the exported launchers pick the
+// instantiation from DDGeom::quad.
 //
 // Layout in the plan's workspace (x fastest, M = padded lengths; 2D):
-//   twx, twy  M/2 complex double-double twiddles exp(-2 pi i k / M)
-//   tabs      C spectra, My x Mx double-double each, scaled by 1/(Mx My): the
+//   twx, twy  M/2 complex twiddles exp(-2 pi i k / M) in R
+//   tabs      C spectra, My x Mx values of R each, scaled by 1/(Mx My): the
 //             real spectrum of f, then the imaginary parts of the gradient
 //             kernels' (C = 3 when the gradient is prepared)
 //   cnt       ny x nx float64 multiplicities (the indicator g)
-//   G         My x Mx complex double-double work grid (row spectra)
-//   Gc        C x ny x Mx complex double-double (column-pass outputs)
+//   G         My x Mx complex work grid in R (row spectra)
+//   Gc        C x ny x Mx complex values in R (column-pass outputs)
 // 3D plans add twz, take Mz x My x Mx spectra (C = 4 with the gradient) and
 // run the y and z axes as strided line passes (dd_convolve_columns).
 // The transforms are radix-2 in LDS (stages fused in pairs), one row or
