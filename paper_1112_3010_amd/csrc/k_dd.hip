@@ -207,8 +207,8 @@ __global__ void k_dd_twiddles(cplx<R>* __restrict__ tw, int M) {
 // Kernel samples at every displacement d of the padded grid (minimum image;
 // the Nyquist lines are set to 0 as in the other precisions): kind 0 is
 // f = exp(-r / tau), kind 1 + a the gradient kernel (h_a d_a / r) f, 0 at
-// r = 0 (eq. SxSyconv).  The displacement h d is an exact double-double
-// product.
+// r = 0 (eq. SxSyconv).  The displacement h d is an exact product (its
+// float64 rounding error carried as the second part).
 template <class R>
 __global__ void k_dd_tab_sample(cplx<R>* __restrict__ G, DDGeom g, int kind) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -613,8 +613,9 @@ hipError_t allow_lds(F kern, size_t lds) {
 }  // namespace
 
 // Adjacent lines per block of the strided line passes, as a power of two:
-// four (a 128-byte run of double-double complex values per row) where the
-// block's four lines stay within 64 KiB of LDS, else one.
+// four (a 128-byte run of double-double complex values per row, 256 bytes
+// in quad-double) where the block's four lines stay within 64 KiB of LDS,
+// else one.
 template <class R> static int dd_log_lb(int M, int64_t n_inner) {
   return ((size_t)M * 4 * sizeof(cplx<R>) <= 65536 && n_inner % 4 == 0) ? 2 : 0;
 }

@@ -265,7 +265,7 @@ int log2_exact(int64_t m) {
   return e;
 }
 
-// Workspace of a double-double plan: scalars and error word (same offsets
+// Workspace of an extended-precision plan: scalars and error word (same offsets
 // as the other precisions, so the stats calls are shared), twiddles, the
 // spectra, the multiplicities, the complex work grid and the column-pass
 // outputs.
@@ -388,9 +388,10 @@ void log_created(dt_plan p) {
     logf("  padded %s (full zero padding)", axes_i(p->M, D).c_str());
   }
   if (p->dd) {
-    logf("  passes: double-double radix-2 transforms staged in LDS (rows %lld, columns %s); %d spectra; "
+    logf("  passes: %s radix-2 transforms staged in LDS (rows %lld, columns %s); %d spectra; "
          "workspace %.1f MB",
-         (long long)p->M[0], axes_i(p->M + 1, D - 1).c_str(), p->dd_tabs, p->ws_bytes / 1e6);
+         p->quad ? "quad-double" : "double-double", (long long)p->M[0], axes_i(p->M + 1, D - 1).c_str(),
+         p->dd_tabs, p->ws_bytes / 1e6);
     return;
   }
   const int Q = (int)(p->M[0] / 2);
@@ -1143,7 +1144,8 @@ dt_status run_backward(dt_plan p, const float* Y, int64_t K, const void* S, cons
 
 }  // namespace
 
-// The double-double pipeline: S, grad S, the Hessian and curvatures from explicit sources.
+// The extended-precision pipeline (double-double or quad-double): S, grad S,
+// the Hessian and curvatures from explicit sources.
 static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_shape* shape, const dt_outputs* out,
                          hipStream_t st) {
   if (out->label || out->mu || out->signed_outputs || shape) return DT_E_UNSUPPORTED;
@@ -1190,9 +1192,9 @@ static dt_status run_forward_dd(dt_plan p, const float* Y, int64_t K, const dt_s
   return hip_status(e);
 }
 
-// The double-double adjoint (as run_backward): w = G exp(S / tau) p2 on valid
-// nodes, its convolutions with the gradient kernels and with r f in
-// double-double, their values at the sources' nodes.
+// The extended-precision adjoint (as run_backward): w = G exp(S / tau) p2 on
+// valid nodes, its convolutions with the gradient kernels and with r f in
+// the plan's extended type, their values at the sources' nodes.
 static dt_status run_backward_dd(dt_plan p, const float* Y, int64_t K, const double* S, const double* Gr, float* dY,
                                  double* dtau, hipStream_t st) {
   const DDGeom& g = p->ddg;
