@@ -248,18 +248,21 @@ template <typename B> std::vector<B> xcd_runs(const std::vector<B>& v) {
   return out;
 }
 
-// Default tiles: 512 threads per column block and the widest power-of-two
-// tile whose longest column set fits 8 elements per thread (the lightest
-// instantiation in registers) and the LDS.
+// Default tiles: 1024 threads per column block (512 if nothing fits) and
+// the widest power-of-two tile whose longest column set fits 8 elements per
+// thread (the lightest instantiation in registers) and the LDS; 512 threads
+// per row block.
 dt_batch_tiles default_tiles(dt_batch_plan p) {
   int64_t my = 0;
   for (const auto& I : p->inst) my = std::max<int64_t>(my, I.My);
-  dt_batch_tiles t{1, 512, 256};
-  for (int nb : {16, 8, 4, 2, 1})
-    if (my * nb <= 8 * 512 && (size_t)(2 * my * nb + my) * 2 * p->wsz() <= (size_t)p->lds_max) {
-      t.col_nb = nb;
-      break;
-    }
+  dt_batch_tiles t{1, 512, 512};
+  for (int nt : {1024, 512})
+    for (int nb : {16, 8, 4, 2, 1})
+      if (my * nb <= 8 * nt && (size_t)(2 * my * nb + my) * 2 * p->wsz() <= (size_t)p->lds_max) {
+        t.col_nb = nb;
+        t.col_threads = nt;
+        return t;
+      }
   return t;
 }
 
