@@ -70,16 +70,19 @@ def test_reduced_plan_reports_cut(lib, capfd, monkeypatch):
     assert "precision fp64" in out
 
 
-def test_dd_and_batch_plans(lib, capfd, monkeypatch):
+def test_extended_and_batch_plans(lib, capfd, monkeypatch):
     from tests.test_batch_host import _desc
     monkeypatch.setenv("DT_LOG", "1")
     h = _create(lib, (128, 96), 2.0, 3, mask=1)
+    lib.dt_destroy_plan(h)
+    h = _create(lib, (64, 40, 36), 2.0, 4, mask=3)
     lib.dt_destroy_plan(h)
     hb = ctypes.c_void_p()
     assert lib.dt_create_batch_plan(ctypes.byref(hb), 2, _desc([(128, 200), (97, 64)]), 1, 3, 0.0) == 0
     lib.dt_destroy_batch_plan(hb)
     out = "\n".join(_lines(capfd.readouterr().err))
     assert "precision fp64x2 (u = 2^-104)" in out and "double-double radix-2" in out
+    assert "precision fp64x4 (u = 2^-208)" in out and "quad-double radix-2" in out
     assert "batch plan" in out and "2 2D instances, precision fp64" in out
     # the batched padding: 2 x the 7-smooth length at least n along x, 2 x that of n along y
     assert "inst 0: grid 128x200" in out and "padded 256x400" in out
