@@ -35,7 +35,11 @@ class Plan:
     prepare; "curv" prepares the gradient and Hessian kernels).  k_max (None
     or 0: full padding): the most sources a call will bring; a smaller
     padded grid with truncated kernels, which changes results only below the
-    validity threshold (calls with more sources are refused).
+    validity threshold (calls with more sources are refused).  precision:
+    "fp32" (float32 with exact power-of-two scaling), "fp64", "fp64x2"
+    (double-double), "fp64x4" (quad-double) or "auto" (the narrowest of
+    these whose band reaches trunc_dist for k_hint sources); the extended
+    formats return float64 fields.
     """
 
     def __init__(self, dims, spacing=None, origin=None, tau=None, precision="fp32", outputs=("S", "grad"),
