@@ -159,7 +159,6 @@ template <class R> __device__ __forceinline__ cplx<R> cmul_real(cplx<R> a, R b) 
 // part and the part after it.
 template <class R> struct xp;
 template <> struct xp<dd> {
-  static constexpr double kUnitLog2 = -104;   // unit roundoff 2^-104
   __device__ static dd zero() { return {0.0, 0.0}; }
   __device__ static dd from(double a) { return {a, 0.0}; }
   __device__ static dd prod(double a, double b) { return two_prod(a, b); }

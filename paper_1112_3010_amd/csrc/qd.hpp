@@ -221,7 +221,6 @@ __host__ __device__ inline void sincos_reduced(qd a, qd& s, qd& c) {
 }
 
 template <> struct xp<qd> {
-  static constexpr double kUnitLog2 = -208;   // unit roundoff taken as 2^-208 (212 bits less a few for the operations)
   __device__ static qd zero() { return {0.0, 0.0, 0.0, 0.0}; }
   __device__ static qd from(double a) { return {a, 0.0, 0.0, 0.0}; }
   __device__ static qd prod(double a, double b) {
